@@ -1,0 +1,67 @@
+"""Discretised curvature regulariser (Sec. 2.2, eq. CURV_discretized and
+eq. laplace_discretized) and its derivatives (Sec. 3.1, eq. curvatureMF;
+Sec. 4.2, eq. curv_hessMult).
+
+L is the 7-point Laplacian on the nodal grid with homogeneous Neumann
+boundary conditions realised by clamped neighbours (entries of coinciding
+columns summed); it acts on each displacement component separately.
+S(u) = hbar^y sum_d ||L u_d||^2, grad S = 2 hbar^y L^T L u, and the
+(constant) Hessian is 2 hbar^y L^T L.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def laplacian(grid):
+    """L (nbar x nbar) with rows sum_k (u_{n-k} - 2 u_n + u_{n+k}) / hy_k^2."""
+    n = np.arange(grid.nbar)
+    a, b, c = grid.node_abc(n)
+    hy = grid.hy
+    ri, ci, vi = [], [], []
+    for k, (lo, hi) in enumerate((
+        (grid.node_id(np.maximum(a - 1, 0), b, c), grid.node_id(np.minimum(a + 1, grid.my[0] - 1), b, c)),
+        (grid.node_id(a, np.maximum(b - 1, 0), c), grid.node_id(a, np.minimum(b + 1, grid.my[1] - 1), c)),
+        (grid.node_id(a, b, np.maximum(c - 1, 0)), grid.node_id(a, b, np.minimum(c + 1, grid.my[2] - 1))),
+    )):
+        w = 1.0 / hy[k] ** 2
+        ri += [n, n, n]
+        ci += [lo, n, hi]
+        vi += [np.full(len(n), w), np.full(len(n), -2.0 * w), np.full(len(n), w)]
+    L = sp.coo_matrix((np.concatenate(vi), (np.concatenate(ri), np.concatenate(ci))),
+                      shape=(grid.nbar, grid.nbar)).tocsr()
+    L.sum_duplicates()
+    L.eliminate_zeros()
+    return L
+
+
+def _comps(grid, u):
+    return np.asarray(u, dtype=np.float64).reshape(3, grid.nbar)
+
+
+def energy(grid, u, L=None):
+    """S(u) = hbar^y sum_n sum_d (L u_d)_n^2."""
+    L = laplacian(grid) if L is None else L
+    uc = _comps(grid, u)
+    return grid.hybar * float(sum(np.sum((L @ uc[d]) ** 2) for d in range(3)))
+
+
+def gradient(grid, u, L=None):
+    """grad S = 2 hbar^y L^T L u, shaped (3, nz, ny, nx)."""
+    L = laplacian(grid) if L is None else L
+    uc = _comps(grid, u)
+    g = np.stack([2.0 * grid.hybar * (L.T @ (L @ uc[d])) for d in range(3)])
+    return g.reshape(3, grid.my[2], grid.my[1], grid.my[0])
+
+
+def hess_vec(grid, p, L=None):
+    """(nabla^2 S) p = 2 hbar^y L^T L p."""
+    return gradient(grid, p, L)
+
+
+def hessian_diag(grid, L=None):
+    """diag(2 hbar^y L^T L) = 2 hbar^y (column sums of L o L), per component."""
+    L = laplacian(grid) if L is None else L
+    d = 2.0 * grid.hybar * np.asarray(L.multiply(L).sum(axis=0)).ravel()
+    return np.stack([d, d, d]).reshape(3, grid.my[2], grid.my[1], grid.my[0])
