@@ -1,0 +1,171 @@
+/*
+ * mfr.h -- matrix-free NGF + curvature image registration on MI355X (gfx950).
+ *
+ * C ABI of the library libmfr.so.  It evaluates the discretised objective
+ * J(y) = D(y) + alpha S(y) of Sec. 2.2 (eq. discreteenergy: the normalized
+ * gradient fields distance D of eq. NGF_discretized and the curvature
+ * regulariser S of eq. CURV_discretized), its gradient and the Gauss-Newton
+ * Hessian-vector product of Sec. 3-4 (eq. NGF_discretized_gradient,
+ * eq. NGF_discretized_hessian, eq. curvatureMF, eq. curv_hessMult), and runs
+ * the Gauss-Newton / conjugate-gradient loop of Sec. 2.3 on a coarse-to-fine
+ * pyramid.  Every arithmetic step runs in hand-written HIP kernels.
+ *
+ * Conventions (all calls):
+ *  - Images are contiguous float32 arrays [m_z][m_y][m_x] (x fastest): the
+ *    lexicographic order of Sec. 2.2.  Voxel (a,b,c) has centre
+ *    ((a+1/2)h_x, (b+1/2)h_y, (c+1/2)h_z).
+ *  - Node vectors (displacement u, directions p, results) are contiguous
+ *    float32 arrays [3][n_z][n_y][n_x]: all x components, then y, then z
+ *    (the component-major order of Sec. 2.2).  Node (i,j,k) sits at
+ *    (i hy_x, j hy_y, k hy_z) with hy = m h / (n - 1): the nodal grid spans
+ *    the image domain.
+ *  - The unknown is the DISPLACEMENT u = y - x^y (Sec. 2.2); derivatives with
+ *    respect to u and y coincide.
+ *  - Every pointer argument named R, T, u, p, q, g, b, s, diag or workspace is
+ *    a DEVICE pointer (hipMalloc / torch CUDA memory), 4-byte aligned (the
+ *    workspace 256-byte aligned), owned by the caller and only borrowed for the
+ *    duration of the call -- except R and T, borrowed until the next
+ *    mfr_set_images or mfr_destroy.  Pointers to mfr_* structs and to double
+ *    results are HOST pointers.  The library never allocates device memory.
+ *  - Work is enqueued on the HIP stream given to mfr_create.  Calls that return
+ *    host scalars (J, D, S, PCG info) synchronise that stream; the others
+ *    return once their kernels are enqueued.
+ *  - A context is not thread-safe; separate contexts on separate streams are.
+ *  - Every call validates its arguments before any launch and returns an
+ *    mfr_status; mfr_last_error() gives a thread-local message for the last
+ *    non-OK status.  No C++ exception crosses the ABI.
+ */
+#ifndef MFR_H
+#define MFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFR_ABI_VERSION 1
+
+typedef enum {
+  MFR_OK = 0,
+  MFR_EINVAL = -1,        /* invalid argument (sizes, parameters, null or misaligned pointer) */
+  MFR_ENOMEM = -2,        /* workspace smaller than the size query returned                   */
+  MFR_EHIP = -3,          /* a HIP runtime call or kernel launch failed                       */
+  MFR_ENONFINITE = -4,    /* a scalar result (J, D, S, dot product) is NaN or infinite       */
+  MFR_ELINESEARCH = -5,   /* Armijo line search found no sufficient decrease                  */
+  MFR_EBREAKDOWN = -6     /* reserved: CG breakdown is reported in mfr_pcg_info.flag          */
+} mfr_status;
+
+/* Problem description (Sec. 2.2; notation table).  Sizes and spacings are
+ * given per dimension in the order x, y, z. */
+typedef struct {
+  int32_t m[3];     /* image grid cells; 2 <= m                                              */
+  double h[3];      /* image grid spacing; > 0                                                */
+  int32_t my[3];    /* deformation grid NODES; 2 <= my and my - 1 <= m (Sec. 2.2)             */
+  int32_t mT[3];    /* template grid cells (all 0: same as m)                                 */
+  double hT[3];     /* template grid spacing (all 0: same as h)                               */
+  double tau;       /* NGF edge parameter of the template, > 0 (eq. ngf)                     */
+  double rho;       /* NGF edge parameter of the reference, > 0 (eq. ngf)                    */
+  double alpha;     /* curvature weight, >= 0 (eq. optimizationProblem)                       */
+} mfr_grid;
+
+typedef struct mfr_ctx mfr_ctx;   /* opaque host-side context; owns no device memory */
+
+int mfr_abi_version(void);
+const char* mfr_last_error(void);
+
+/* Bytes of device workspace a context for `grid` needs (tile partial sums,
+ * reduction partials, lookup tables, the template copy with a zero border
+ * that realises its Dirichlet extension, and the six node vectors of PCG). */
+mfr_status mfr_workspace_size(const mfr_grid* grid, size_t* bytes);
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = default
+ * stream) and to a caller-owned device workspace of at least
+ * mfr_workspace_size bytes.  *out receives the context. */
+mfr_status mfr_create(const mfr_grid* grid, void* hip_stream, void* workspace, size_t ws_bytes,
+                      mfr_ctx** out);
+void mfr_destroy(mfr_ctx* ctx);
+
+/* Bind the reference R [m_z][m_y][m_x] and template T [mT_z][mT_y][mT_x]
+ * (device, float32).  Copies T into the workspace with a two-cell zero border
+ * (the template's zero Dirichlet extension, Sec. 2.2). */
+mfr_status mfr_set_images(mfr_ctx* ctx, const float* R, const float* T);
+
+/* J = D + alpha S at displacement u (eq. discreteenergy).  D follows
+ * eq. NGF_discretized_ri, S eq. CURV_discretized.  Any of J, D, S may be
+ * NULL.  Sums are accumulated in float64.  Synchronises the stream. */
+mfr_status mfr_objective(mfr_ctx* ctx, const float* u, double* J, double* D, double* S);
+
+/* g = grad D + alpha grad S at u (eq. gradNGF with the transposed grid
+ * conversion of Sec. 4.3, and eq. curvatureMF).  g: device [3][n].  If J is
+ * not NULL it receives J(u) (and the stream is synchronised). */
+mfr_status mfr_gradient(mfr_ctx* ctx, const float* u, float* g, double* J);
+
+/* q = (H + alpha nabla^2 S) p with H the Gauss-Newton matrix of D at u
+ * (eq. NGF_discretized_hessian, evaluated matrix-free as in eq. hessMult /
+ * eq. drTdr) and nabla^2 S = 2 hbar^y L^T L (eq. curv_hessMult).
+ * q must not alias u or p.  Asynchronous. */
+mfr_status mfr_hess_vec(mfr_ctx* ctx, const float* u, const float* p, float* q);
+
+/* diag = diag(H + alpha nabla^2 S) at u, exactly (the Jacobi preconditioner
+ * of the conjugate-gradient solve; the paper leaves CG unpreconditioned).
+ * Asynchronous. */
+mfr_status mfr_jacobi_diag(mfr_ctx* ctx, const float* u, float* diag);
+
+typedef struct {
+  int32_t max_iter;   /* >= 0                                                   */
+  double rtol;        /* stop when ||b - A s_k|| / ||b|| <= rtol (recursive residual) */
+  int32_t precond;    /* 0 none (plain CG), 1 Jacobi                             */
+} mfr_pcg_opts;
+
+typedef struct {
+  int32_t iters;      /* iterations performed                                    */
+  double relres;      /* final relative residual                                 */
+  int32_t flag;       /* 0 converged, 1 max_iter reached, 2 breakdown (p^T A p <= 0 or not finite) */
+} mfr_pcg_info;
+
+/* Solve (H + alpha nabla^2 S) s = b at u by (Jacobi-)preconditioned CG from
+ * s = 0 (Sec. 2.3.1: the Newton equation solved with CG).  Vectors in float32,
+ * dot products and step lengths in float64.  s: device [3][n].
+ * Synchronises once per iteration (convergence test on the host). */
+mfr_status mfr_pcg_solve(mfr_ctx* ctx, const float* u, const float* b, float* s,
+                         const mfr_pcg_opts* opts, mfr_pcg_info* info);
+
+typedef struct {
+  int32_t levels;      /* pyramid levels, 1..8                                     */
+  int32_t gn_iters;    /* Gauss-Newton iterations per level                        */
+  int32_t pcg_max;     /* CG iterations per Gauss-Newton step                      */
+  double pcg_rtol;     /* CG relative residual tolerance                            */
+  double armijo_c1;    /* sufficient-decrease constant (e.g. 1e-4)                  */
+  int32_t armijo_max;  /* step halvings before the line search gives up             */
+  int32_t precond;     /* 0 none, 1 Jacobi                                          */
+} mfr_ml_opts;
+
+typedef struct {
+  double J_final;          /* objective at the returned u on the finest level         */
+  int32_t gn_done[8];      /* accepted Gauss-Newton steps per level (coarsest first)  */
+  int32_t pcg_total[8];    /* CG iterations per level                                */
+  int32_t status[8];       /* 0, or MFR_ELINESEARCH if that level stopped early       */
+  double seconds;          /* wall time of the whole call                             */
+} mfr_ml_report;
+
+/* Bytes of device workspace mfr_register_multilevel needs for `finest`. */
+mfr_status mfr_ml_workspace_size(const mfr_grid* finest, int32_t levels, size_t* bytes);
+
+/* Coarse-to-fine Gauss-Newton registration (Sec. 2.3): image pyramid of
+ * 2x2x2 means (ceil(m/2) cells, spacing doubled), deformation grids with
+ * ceil((my-1)/2) cells per coarser level, Gauss-Newton with (P)CG and Armijo
+ * line search on each level, linear prolongation of u to the next level.
+ * u: device [3][n] of the finest grid; in: initial displacement at the
+ * finest level is ignored unless levels == 1 (coarsest level starts at 0);
+ * out: the registered finest displacement.  Synchronises the stream. */
+mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* opts, void* hip_stream,
+                                   void* workspace, size_t ws_bytes, const float* R, const float* T,
+                                   float* u, mfr_ml_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFR_H */

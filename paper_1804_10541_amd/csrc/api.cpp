@@ -1,0 +1,813 @@
+// libmfr host side: argument validation, workspace layout, lookup tables, the
+// C ABI of include/mfr.h, the conjugate-gradient solver and the multilevel
+// Gauss-Newton driver (Sec. 2.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mfr.h"
+#include "mfr_internal.h"
+
+using namespace mfr;
+
+namespace {
+
+thread_local std::string g_err;
+
+mfr_status fail(mfr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(MFR_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+#define MFR_TRY(expr)                \
+  do {                               \
+    mfr_status s_ = (expr);          \
+    if (s_ != MFR_OK) return s_;     \
+  } while (0)
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Derived, validated problem description.
+struct Geo {
+  int m[3], n[3], mT[3];
+  double h[3], hT[3], hy[3];
+  double tau, rho, alpha;
+  size_t mbar, nbar;
+  double hbar() const { return h[0] * h[1] * h[2]; }
+  double hybar() const { return hy[0] * hy[1] * hy[2]; }
+};
+
+mfr_status make_geo(const mfr_grid* g, Geo* o) {
+  if (!g) return fail(MFR_EINVAL, "grid is NULL");
+  const bool tdef = g->mT[0] == 0 && g->mT[1] == 0 && g->mT[2] == 0;
+  const bool hdef = g->hT[0] == 0 && g->hT[1] == 0 && g->hT[2] == 0;
+  for (int k = 0; k < 3; ++k) {
+    o->m[k] = g->m[k];
+    o->n[k] = g->my[k];
+    o->h[k] = g->h[k];
+    o->mT[k] = tdef ? g->m[k] : g->mT[k];
+    o->hT[k] = hdef ? g->h[k] : g->hT[k];
+    if (o->m[k] < 2 || o->m[k] > (1 << 20)) return fail(MFR_EINVAL, "m[%d] = %d out of range [2, 2^20]", k, o->m[k]);
+    if (o->n[k] < 2 || o->n[k] - 1 > o->m[k])
+      return fail(MFR_EINVAL, "my[%d] = %d: need 2 <= my <= m + 1", k, o->n[k]);
+    if (o->mT[k] < 1 || o->mT[k] > (1 << 20)) return fail(MFR_EINVAL, "mT[%d] = %d out of range", k, o->mT[k]);
+    if (!(o->h[k] > 0) || !std::isfinite(o->h[k])) return fail(MFR_EINVAL, "h[%d] must be > 0", k);
+    if (!(o->hT[k] > 0) || !std::isfinite(o->hT[k])) return fail(MFR_EINVAL, "hT[%d] must be > 0", k);
+    o->hy[k] = o->m[k] * o->h[k] / (o->n[k] - 1);
+  }
+  if (!(g->tau > 0) || !(g->rho > 0) || !std::isfinite(g->tau) || !std::isfinite(g->rho))
+    return fail(MFR_EINVAL, "tau and rho must be > 0");
+  if (!(g->alpha >= 0) || !std::isfinite(g->alpha)) return fail(MFR_EINVAL, "alpha must be >= 0");
+  o->tau = g->tau;
+  o->rho = g->rho;
+  o->alpha = g->alpha;
+  o->mbar = (size_t)o->m[0] * o->m[1] * o->m[2];
+  o->nbar = (size_t)o->n[0] * o->n[1] * o->n[2];
+  const size_t tpad = (size_t)(o->mT[0] + 4) * (o->mT[1] + 4) * (o->mT[2] + 4);
+  if (o->mbar >= (size_t)1 << 31 || 3 * o->nbar >= (size_t)1 << 31 || tpad >= (size_t)1 << 32)
+    return fail(MFR_EINVAL, "problem too large for 32-bit voxel / node indexing");
+  return MFR_OK;
+}
+
+// ---- lookup tables -----------------------------------------------------------
+// Grid conversion along one axis: c = (a + 1/2)(n - 1)/m in exact integer
+// arithmetic, lower node min(floor(c), n - 2), fraction c - lower.
+std::vector<Conv1> conv_table(int m, int n) {
+  std::vector<Conv1> t(m);
+  const long long den = 2LL * m;
+  for (int a = 0; a < m; ++a) {
+    const long long num = (2LL * a + 1) * (n - 1);
+    long long n0 = std::min<long long>(num / den, n - 2);
+    t[a].n0 = (int)n0;
+    t[a].f = (float)((double)(num - n0 * den) / (double)den);
+  }
+  return t;
+}
+
+// Template coordinate of voxel centres: (a + 1/2) h / hT - 1/2 = base + frac.
+std::vector<Samp1> samp_table(int m, double h, double hT) {
+  std::vector<Samp1> t(m);
+  for (int a = 0; a < m; ++a) {
+    const double q = (a + 0.5) * h / hT - 0.5;
+    const double b = std::floor(q);
+    t[a].base = (int)b;
+    t[a].frac = (float)(q - b);
+  }
+  return t;
+}
+
+// Voxel range contributing to each node (lower node n-1 or n).
+std::vector<Range1> node_cols(const std::vector<Conv1>& c, int n) {
+  std::vector<Range1> r(n, Range1{1 << 30, -1});
+  for (int a = 0; a < (int)c.size(); ++a) {
+    for (int j = c[a].n0; j <= c[a].n0 + 1; ++j) {
+      r[j].lo = std::min(r[j].lo, a);
+      r[j].hi = std::max(r[j].hi, a);
+    }
+  }
+  return r;
+}
+
+// Prolongation: coarse node values at the positions of the fine nodes.
+std::vector<Conv1> prolong_table(int nf, double hyf, int nc, double hyc) {
+  std::vector<Conv1> t(nf);
+  for (int j = 0; j < nf; ++j) {
+    double s = std::min(std::max(j * hyf / hyc, 0.0), (double)(nc - 1));
+    int k0 = std::min((int)std::floor(s), nc - 2);
+    t[j].n0 = k0;
+    t[j].f = (float)(s - k0);
+  }
+  return t;
+}
+
+// ---- tiling -----------------------------------------------------------------
+struct Tiling {
+  TileShape shape;
+  int tiles_x, tiles_y, chunks, chunk_len;
+  int nxt, nyt, nzt;
+  int grid() const { return tiles_x * tiles_y * chunks; }
+};
+
+Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector<Conv1>& cy,
+                   const std::vector<Conv1>& cz) {
+  Tiling t;
+  t.shape = TileShape{32, 16};
+  if (const char* e = std::getenv("MFR_TILE")) {
+    int bx = 0, by = 0;
+    if (sscanf(e, "%dx%d", &bx, &by) == 2) t.shape = TileShape{bx, by};
+  }
+  const int TX = t.shape.bx - 4, TY = t.shape.by - 4;
+  t.tiles_x = (g.m[0] + TX - 1) / TX;
+  t.tiles_y = (g.m[1] + TY - 1) / TY;
+  const int xy = t.tiles_x * t.tiles_y;
+  int chunks = std::max(1, (2048 + xy - 1) / xy);
+  chunks = std::min(chunks, std::max(1, g.m[2] / 16));
+  int clen = (g.m[2] + chunks - 1) / chunks;
+  if (const char* e = std::getenv("MFR_CHUNK")) clen = std::max(1, atoi(e));
+  t.chunk_len = std::min(clen, g.m[2]);
+  t.chunks = (g.m[2] + t.chunk_len - 1) / t.chunk_len;
+  t.nxt = t.nyt = t.nzt = 0;
+  for (int i = 0; i < t.tiles_x; ++i) {
+    const int a0 = i * TX, a1 = std::min(a0 + TX, g.m[0]) - 1;
+    t.nxt = std::max(t.nxt, cx[a1].n0 + 2 - cx[a0].n0);
+  }
+  for (int i = 0; i < t.tiles_y; ++i) {
+    const int a0 = i * TY, a1 = std::min(a0 + TY, g.m[1]) - 1;
+    t.nyt = std::max(t.nyt, cy[a1].n0 + 2 - cy[a0].n0);
+  }
+  for (int i = 0; i < t.chunks; ++i) {
+    const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[2]) - 1;
+    t.nzt = std::max(t.nzt, cz[a1].n0 + 2 - cz[a0].n0);
+  }
+  return t;
+}
+
+bool valid_shape(const TileShape& s) {
+  return (s.bx == 32 && s.by == 16) || (s.bx == 64 && s.by == 8) || (s.bx == 32 && s.by == 32) ||
+         (s.bx == 64 && s.by == 16);
+}
+
+// ---- workspace layout ---------------------------------------------------------
+struct Layout {
+  size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
+  size_t part, red_tile, red_node, sc, vec;
+  size_t n_red_node;
+  size_t total;
+};
+
+Layout make_layout(const Geo& g, const Tiling& t) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.Tp = take(sizeof(float) * (size_t)(g.mT[0] + 4) * (g.mT[1] + 4) * (g.mT[2] + 4));
+  L.cx = take(sizeof(Conv1) * g.m[0]);
+  L.cy = take(sizeof(Conv1) * g.m[1]);
+  L.cz = take(sizeof(Conv1) * g.m[2]);
+  L.sx = take(sizeof(Samp1) * g.m[0]);
+  L.sy = take(sizeof(Samp1) * g.m[1]);
+  L.sz = take(sizeof(Samp1) * g.m[2]);
+  L.ntx = take(sizeof(Range1) * g.n[0]);
+  L.nty = take(sizeof(Range1) * g.n[1]);
+  L.ntz = take(sizeof(Range1) * g.n[2]);
+  L.orgx = take(sizeof(int) * t.tiles_x);
+  L.orgy = take(sizeof(int) * t.tiles_y);
+  L.orgz = take(sizeof(int) * t.chunks);
+  L.rx = take(sizeof(Range1) * g.n[0]);
+  L.ry = take(sizeof(Range1) * g.n[1]);
+  L.rz = take(sizeof(Range1) * g.n[2]);
+  L.part = take(sizeof(float) * (size_t)t.grid() * 3 * t.nzt * t.nyt * t.nxt);
+  L.red_tile = take(sizeof(double) * (size_t)t.grid());
+  const size_t node_blocks = (g.nbar + kNodeBlock - 1) / kNodeBlock;
+  L.n_red_node = std::max<size_t>(node_blocks, 2 * 1024);
+  L.red_node = take(sizeof(double) * L.n_red_node);
+  L.sc = take(sizeof(double) * SC_COUNT);
+  L.vec = take(sizeof(float) * 3 * g.nbar * 7);   // PCG: s r z p q diag + GN trial
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct mfr_ctx {
+  Geo geo;
+  Tiling tiling;
+  Layout lay;
+  hipStream_t stream;
+  char* ws;
+  const float* R;
+  bool have_images;
+  TileParams tp;
+  NodeParams np;
+  DiagParams dp;
+  double* sc;
+  double* red_tile;
+  double* red_node;
+  float* vec[7];
+  int vec_blocks;
+};
+
+namespace {
+
+template <class T>
+T* at(char* base, size_t off) {
+  return reinterpret_cast<T*>(base + off);
+}
+
+mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes) {
+  MFR_TRY(make_geo(grid, &c->geo));
+  const Geo& g = c->geo;
+  auto cx = conv_table(g.m[0], g.n[0]);
+  auto cy = conv_table(g.m[1], g.n[1]);
+  auto cz = conv_table(g.m[2], g.n[2]);
+  c->tiling = make_tiling(g, cx, cy, cz);
+  if (!valid_shape(c->tiling.shape)) return fail(MFR_EINVAL, "unsupported tile shape %dx%d", c->tiling.shape.bx, c->tiling.shape.by);
+  c->lay = make_layout(g, c->tiling);
+  if (!ws) return fail(MFR_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(MFR_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < c->lay.total)
+    return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", ws_bytes, c->lay.total);
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(ws);
+  c->R = nullptr;
+  c->have_images = false;
+  const Tiling& t = c->tiling;
+  const int TX = t.shape.bx - 4, TY = t.shape.by - 4;
+
+  auto sx = samp_table(g.m[0], g.h[0], g.hT[0]);
+  auto sy = samp_table(g.m[1], g.h[1], g.hT[1]);
+  auto sz = samp_table(g.m[2], g.h[2], g.hT[2]);
+  auto colx = node_cols(cx, g.n[0]), coly = node_cols(cy, g.n[1]), colz = node_cols(cz, g.n[2]);
+  std::vector<Range1> ntx(g.n[0]), nty(g.n[1]), ntz(g.n[2]), rx(g.n[0]), ry(g.n[1]), rz(g.n[2]);
+  for (int i = 0; i < g.n[0]; ++i) {
+    ntx[i] = Range1{colx[i].lo / TX, colx[i].hi / TX};
+    rx[i] = Range1{std::max(colx[i].lo - 1, 0), std::min(colx[i].hi + 1, g.m[0] - 1)};
+  }
+  for (int i = 0; i < g.n[1]; ++i) {
+    nty[i] = Range1{coly[i].lo / TY, coly[i].hi / TY};
+    ry[i] = Range1{std::max(coly[i].lo - 1, 0), std::min(coly[i].hi + 1, g.m[1] - 1)};
+  }
+  for (int i = 0; i < g.n[2]; ++i) {
+    ntz[i] = Range1{colz[i].lo / t.chunk_len, colz[i].hi / t.chunk_len};
+    rz[i] = Range1{std::max(colz[i].lo - 1, 0), std::min(colz[i].hi + 1, g.m[2] - 1)};
+  }
+  std::vector<int> orgx(t.tiles_x), orgy(t.tiles_y), orgz(t.chunks);
+  for (int i = 0; i < t.tiles_x; ++i) orgx[i] = cx[i * TX].n0;
+  for (int i = 0; i < t.tiles_y; ++i) orgy[i] = cy[i * TY].n0;
+  for (int i = 0; i < t.chunks; ++i) orgz[i] = cz[i * t.chunk_len].n0;
+
+  const Layout& L = c->lay;
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  HIP_TRY(up(L.cx, cx.data(), sizeof(Conv1) * cx.size()));
+  HIP_TRY(up(L.cy, cy.data(), sizeof(Conv1) * cy.size()));
+  HIP_TRY(up(L.cz, cz.data(), sizeof(Conv1) * cz.size()));
+  HIP_TRY(up(L.sx, sx.data(), sizeof(Samp1) * sx.size()));
+  HIP_TRY(up(L.sy, sy.data(), sizeof(Samp1) * sy.size()));
+  HIP_TRY(up(L.sz, sz.data(), sizeof(Samp1) * sz.size()));
+  HIP_TRY(up(L.ntx, ntx.data(), sizeof(Range1) * ntx.size()));
+  HIP_TRY(up(L.nty, nty.data(), sizeof(Range1) * nty.size()));
+  HIP_TRY(up(L.ntz, ntz.data(), sizeof(Range1) * ntz.size()));
+  HIP_TRY(up(L.orgx, orgx.data(), sizeof(int) * orgx.size()));
+  HIP_TRY(up(L.orgy, orgy.data(), sizeof(int) * orgy.size()));
+  HIP_TRY(up(L.orgz, orgz.data(), sizeof(int) * orgz.size()));
+  HIP_TRY(up(L.rx, rx.data(), sizeof(Range1) * rx.size()));
+  HIP_TRY(up(L.ry, ry.data(), sizeof(Range1) * ry.size()));
+  HIP_TRY(up(L.rz, rz.data(), sizeof(Range1) * rz.size()));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+
+  TileParams& p = c->tp;
+  p.mx = g.m[0];
+  p.my = g.m[1];
+  p.mz = g.m[2];
+  p.nx = g.n[0];
+  p.ny = g.n[1];
+  p.nz = g.n[2];
+  p.nbar = (int)g.nbar;
+  p.mTx = g.mT[0];
+  p.mTy = g.mT[1];
+  p.mTz = g.mT[2];
+  p.PX = g.mT[0] + 4;
+  p.PY = g.mT[1] + 4;
+  p.PXY = (long long)p.PX * p.PY;
+  p.ih2x = (float)(1.0 / (g.h[0] * g.h[0]));
+  p.ih2y = (float)(1.0 / (g.h[1] * g.h[1]));
+  p.ih2z = (float)(1.0 / (g.h[2] * g.h[2]));
+  p.hhx = (float)(0.5 / (g.h[0] * g.h[0]));
+  p.hhy = (float)(0.5 / (g.h[1] * g.h[1]));
+  p.hhz = (float)(0.5 / (g.h[2] * g.h[2]));
+  p.ihTx = (float)(1.0 / g.hT[0]);
+  p.ihTy = (float)(1.0 / g.hT[1]);
+  p.ihTz = (float)(1.0 / g.hT[2]);
+  p.tau2 = (float)(g.tau * g.tau);
+  p.rho2 = (float)(g.rho * g.rho);
+  p.taurho = (float)(g.tau * g.rho);
+  p.R = nullptr;
+  p.Tp = at<float>(c->ws, L.Tp);
+  p.cx = at<Conv1>(c->ws, L.cx);
+  p.cy = at<Conv1>(c->ws, L.cy);
+  p.cz = at<Conv1>(c->ws, L.cz);
+  p.sx = at<Samp1>(c->ws, L.sx);
+  p.sy = at<Samp1>(c->ws, L.sy);
+  p.sz = at<Samp1>(c->ws, L.sz);
+  p.tiles_x = t.tiles_x;
+  p.tiles_y = t.tiles_y;
+  p.chunks = t.chunks;
+  p.chunk_len = t.chunk_len;
+  p.nxt = t.nxt;
+  p.nyt = t.nyt;
+  p.nzt = t.nzt;
+  p.part = at<float>(c->ws, L.part);
+  p.red = at<double>(c->ws, L.red_tile);
+
+  NodeParams& q = c->np;
+  q.nx = g.n[0];
+  q.ny = g.n[1];
+  q.nz = g.n[2];
+  q.nbar = (int)g.nbar;
+  q.ihy2x = (float)(1.0 / (g.hy[0] * g.hy[0]));
+  q.ihy2y = (float)(1.0 / (g.hy[1] * g.hy[1]));
+  q.ihy2z = (float)(1.0 / (g.hy[2] * g.hy[2]));
+  q.s_ngf = 0.0f;
+  q.s_curv = (float)(2.0 * g.alpha * g.hybar());
+  q.tiles_x = t.tiles_x;
+  q.tiles_y = t.tiles_y;
+  q.nxt = t.nxt;
+  q.nyt = t.nyt;
+  q.nzt = t.nzt;
+  q.part = p.part;
+  q.ntx = at<Range1>(c->ws, L.ntx);
+  q.nty = at<Range1>(c->ws, L.nty);
+  q.ntz = at<Range1>(c->ws, L.ntz);
+  q.orgx = at<int>(c->ws, L.orgx);
+  q.orgy = at<int>(c->ws, L.orgy);
+  q.orgz = at<int>(c->ws, L.orgz);
+  q.red = at<double>(c->ws, L.red_node);
+
+  DiagParams& d = c->dp;
+  d.t = p;
+  d.rx = at<Range1>(c->ws, L.rx);
+  d.ry = at<Range1>(c->ws, L.ry);
+  d.rz = at<Range1>(c->ws, L.rz);
+  d.s_ngf = (float)(2.0 * g.hbar());
+  d.s_curv = q.s_curv;
+  d.ihy2x = q.ihy2x;
+  d.ihy2y = q.ihy2y;
+  d.ihy2z = q.ihy2z;
+
+  c->sc = at<double>(c->ws, L.sc);
+  c->red_tile = p.red;
+  c->red_node = q.red;
+  for (int k = 0; k < 7; ++k) c->vec[k] = at<float>(c->ws, L.vec) + (size_t)k * 3 * g.nbar;
+  c->vec_blocks = (int)std::min<size_t>((3 * g.nbar + kVecBlock - 1) / kVecBlock, 1024);
+  return MFR_OK;
+}
+
+int node_blocks(const mfr_ctx* c) { return (int)((c->geo.nbar + kNodeBlock - 1) / kNodeBlock); }
+
+mfr_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(MFR_EINVAL, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(p) % 4 != 0) return fail(MFR_EINVAL, "%s is not 4-byte aligned", name);
+  return MFR_OK;
+}
+
+mfr_status need_images(const mfr_ctx* c) {
+  if (!c) return fail(MFR_EINVAL, "context is NULL");
+  if (!c->have_images) return fail(MFR_EINVAL, "mfr_set_images has not been called");
+  return MFR_OK;
+}
+
+// Enqueue: D and S sums into sc[SC_D], sc[SC_S].
+mfr_status enqueue_objective(mfr_ctx* c, const float* u) {
+  const Tiling& t = c->tiling;
+  HIP_TRY(launch_tile(t.shape, MODE_OBJ, c->tp, u, nullptr, t.grid(), c->stream));
+  HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
+  NodeParams q = c->np;
+  HIP_TRY(launch_node_pass(NP_S, q, u, nullptr, node_blocks(c), c->stream));
+  HIP_TRY(launch_sum(c->red_node, node_blocks(c), c->sc + SC_S, c->stream));
+  return MFR_OK;
+}
+
+mfr_status read_objective(mfr_ctx* c, double* J, double* D, double* S) {
+  double h[SC_COUNT];
+  HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double Dv = c->geo.hbar() * h[SC_D];
+  const double Sv = c->geo.hybar() * h[SC_S];
+  const double Jv = Dv + c->geo.alpha * Sv;
+  if (J) *J = Jv;
+  if (D) *D = Dv;
+  if (S) *S = Sv;
+  if (!std::isfinite(Jv)) return fail(MFR_ENONFINITE, "objective is not finite (D = %g, S = %g)", Dv, Sv);
+  return MFR_OK;
+}
+
+mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
+  const Tiling& t = c->tiling;
+  HIP_TRY(launch_tile(t.shape, MODE_GRAD, c->tp, u, nullptr, t.grid(), c->stream));
+  HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
+  NodeParams q = c->np;
+  q.s_ngf = (float)(-2.0 * c->geo.hbar());
+  HIP_TRY(launch_node_pass(NP_GRAD, q, u, g, node_blocks(c), c->stream));
+  HIP_TRY(launch_sum(c->red_node, node_blocks(c), c->sc + SC_S, c->stream));
+  return MFR_OK;
+}
+
+// q = A p; p . q partials left in red_node
+mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q) {
+  const Tiling& t = c->tiling;
+  HIP_TRY(launch_tile(t.shape, MODE_HV, c->tp, u, p, t.grid(), c->stream));
+  NodeParams np = c->np;
+  np.s_ngf = (float)(2.0 * c->geo.hbar());
+  HIP_TRY(launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream));
+  return MFR_OK;
+}
+
+mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
+                   mfr_pcg_info* info) {
+  const int n3 = (int)(3 * c->geo.nbar);
+  float* s = s_out;
+  float* r = c->vec[0];
+  float* z = c->vec[1];
+  float* p = c->vec[2];
+  float* q = c->vec[3];
+  float* diag = nullptr;
+  if (o->precond == 1) {
+    diag = c->vec[4];
+    HIP_TRY(launch_jacobi_diag(c->dp, u, diag, c->stream));
+  }
+  const int vb = c->vec_blocks;
+  HIP_TRY(launch_pcg_init(n3, b, diag, s, r, z, p, c->red_node, vb, c->stream));
+  HIP_TRY(launch_pcg_init_finish(c->red_node, vb, c->sc, c->stream));
+  double h[SC_COUNT];
+  HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double bn = std::sqrt(h[SC_BB]);
+  mfr_pcg_info inf{0, 0.0, 1};
+  if (!std::isfinite(bn)) return fail(MFR_ENONFINITE, "right-hand side is not finite");
+  if (bn == 0.0) {
+    inf.flag = 0;
+    if (info) *info = inf;
+    return MFR_OK;
+  }
+  inf.relres = 1.0;
+  for (int it = 1; it <= o->max_iter; ++it) {
+    MFR_TRY(enqueue_hess_vec(c, u, p, q));
+    HIP_TRY(launch_pcg_alpha(c->red_node, node_blocks(c), c->sc, c->stream));
+    HIP_TRY(launch_pcg_update(n3, diag, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
+    HIP_TRY(launch_pcg_beta(c->red_node, vb, c->sc, c->stream));
+    HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double pq = h[SC_PQ];
+    if (!(pq > 0.0) || !std::isfinite(pq)) {
+      inf.flag = 2;
+      inf.iters = it - 1;
+      break;
+    }
+    inf.iters = it;
+    inf.relres = std::sqrt(h[SC_RR]) / bn;
+    if (inf.relres <= o->rtol) {
+      inf.flag = 0;
+      break;
+    }
+    if (it == o->max_iter) break;
+    HIP_TRY(launch_pcg_direction(n3, z, p, c->sc, vb, c->stream));
+  }
+  if (info) *info = inf;
+  return MFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfr_abi_version(void) { return MFR_ABI_VERSION; }
+
+const char* mfr_last_error(void) { return g_err.c_str(); }
+
+mfr_status mfr_workspace_size(const mfr_grid* grid, size_t* bytes) {
+  Geo g;
+  MFR_TRY(make_geo(grid, &g));
+  if (!bytes) return fail(MFR_EINVAL, "bytes is NULL");
+  auto cx = conv_table(g.m[0], g.n[0]);
+  auto cy = conv_table(g.m[1], g.n[1]);
+  auto cz = conv_table(g.m[2], g.n[2]);
+  Tiling t = make_tiling(g, cx, cy, cz);
+  if (!valid_shape(t.shape)) return fail(MFR_EINVAL, "unsupported tile shape %dx%d", t.shape.bx, t.shape.by);
+  *bytes = make_layout(g, t).total;
+  return MFR_OK;
+}
+
+mfr_status mfr_create(const mfr_grid* grid, void* hip_stream, void* workspace, size_t ws_bytes, mfr_ctx** out) {
+  if (!out) return fail(MFR_EINVAL, "out is NULL");
+  *out = nullptr;
+  mfr_ctx* c = new (std::nothrow) mfr_ctx();
+  if (!c) return fail(MFR_EINVAL, "host allocation failed");
+  mfr_status s = ctx_init(c, grid, hip_stream, workspace, ws_bytes);
+  if (s != MFR_OK) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return MFR_OK;
+}
+
+void mfr_destroy(mfr_ctx* ctx) { delete ctx; }
+
+mfr_status mfr_set_images(mfr_ctx* c, const float* R, const float* T) {
+  if (!c) return fail(MFR_EINVAL, "context is NULL");
+  MFR_TRY(check_ptr(R, "R"));
+  MFR_TRY(check_ptr(T, "T"));
+  const Geo& g = c->geo;
+  HIP_TRY(launch_pad_template(T, at<float>(c->ws, c->lay.Tp), g.mT[0], g.mT[1], g.mT[2], c->stream));
+  c->R = R;
+  c->tp.R = R;
+  c->dp.t.R = R;
+  c->have_images = true;
+  return MFR_OK;
+}
+
+mfr_status mfr_objective(mfr_ctx* c, const float* u, double* J, double* D, double* S) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(enqueue_objective(c, u));
+  return read_objective(c, J, D, S);
+}
+
+mfr_status mfr_gradient(mfr_ctx* c, const float* u, float* g, double* J) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(check_ptr(g, "g"));
+  if (g == u) return fail(MFR_EINVAL, "g must not alias u");
+  MFR_TRY(enqueue_gradient(c, u, g));
+  if (J) return read_objective(c, J, nullptr, nullptr);
+  return MFR_OK;
+}
+
+mfr_status mfr_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(check_ptr(p, "p"));
+  MFR_TRY(check_ptr(q, "q"));
+  if (q == u || q == p) return fail(MFR_EINVAL, "q must not alias u or p");
+  return enqueue_hess_vec(c, u, p, q);
+}
+
+mfr_status mfr_jacobi_diag(mfr_ctx* c, const float* u, float* diag) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(check_ptr(diag, "diag"));
+  HIP_TRY(launch_jacobi_diag(c->dp, u, diag, c->stream));
+  return MFR_OK;
+}
+
+mfr_status mfr_pcg_solve(mfr_ctx* c, const float* u, const float* b, float* s, const mfr_pcg_opts* opts,
+                         mfr_pcg_info* info) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(check_ptr(b, "b"));
+  MFR_TRY(check_ptr(s, "s"));
+  if (!opts) return fail(MFR_EINVAL, "opts is NULL");
+  if (opts->max_iter < 0 || !(opts->rtol >= 0) || opts->precond < 0 || opts->precond > 1)
+    return fail(MFR_EINVAL, "invalid PCG options");
+  if (s == u || s == b) return fail(MFR_EINVAL, "s must not alias u or b");
+  return pcg_run(c, u, b, s, opts, info);
+}
+
+// ---- multilevel ---------------------------------------------------------------
+namespace {
+
+struct Level {
+  mfr_grid grid;
+  Geo geo;
+  size_t off_R, off_T, off_u;   // coarse images / displacement (finest: caller buffers)
+};
+
+mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out, size_t* total) {
+  if (levels < 1 || levels > 8) return fail(MFR_EINVAL, "levels must be in 1..8");
+  std::vector<Level> L(levels);
+  L[levels - 1].grid = *finest;
+  MFR_TRY(make_geo(finest, &L[levels - 1].geo));
+  for (int l = levels - 2; l >= 0; --l) {
+    const Geo& f = L[l + 1].geo;
+    mfr_grid g{};
+    for (int k = 0; k < 3; ++k) {
+      g.m[k] = (f.m[k] + 1) / 2;
+      g.h[k] = 2.0 * f.h[k];
+      g.my[k] = (f.n[k] - 1 + 1) / 2 + 1;
+      g.mT[k] = (f.mT[k] + 1) / 2;
+      g.hT[k] = 2.0 * f.hT[k];
+    }
+    g.tau = f.tau;
+    g.rho = f.rho;
+    g.alpha = f.alpha;
+    L[l].grid = g;
+    MFR_TRY(make_geo(&g, &L[l].geo));
+  }
+  size_t o = 0;
+  size_t ctx_ws = 0;
+  for (int l = 0; l < levels; ++l) {
+    size_t b = 0;
+    MFR_TRY(mfr_workspace_size(&L[l].grid, &b));
+    ctx_ws = std::max(ctx_ws, b);
+  }
+  o = align_up(ctx_ws);
+  for (int l = 0; l < levels; ++l) {
+    const Geo& g = L[l].geo;
+    L[l].off_R = o;
+    o = align_up(o + sizeof(float) * g.mbar);
+    L[l].off_T = o;
+    o = align_up(o + sizeof(float) * (size_t)g.mT[0] * g.mT[1] * g.mT[2]);
+    L[l].off_u = o;
+    o = align_up(o + sizeof(float) * 3 * g.nbar);
+  }
+  const Geo& c = L[levels - 1].geo;  // finest level: search direction + prolongation tables
+  o = align_up(o + sizeof(float) * 3 * c.nbar);
+  o = align_up(o + sizeof(Conv1) * (c.n[0] + c.n[1] + c.n[2]));
+  *out = L;
+  *total = o;
+  return MFR_OK;
+}
+
+}  // namespace
+
+mfr_status mfr_ml_workspace_size(const mfr_grid* finest, int32_t levels, size_t* bytes) {
+  if (!bytes) return fail(MFR_EINVAL, "bytes is NULL");
+  std::vector<Level> L;
+  return ml_levels(finest, levels, &L, bytes);
+}
+
+mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o, void* hip_stream, void* workspace,
+                                   size_t ws_bytes, const float* R, const float* T, float* u,
+                                   mfr_ml_report* report) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!o) return fail(MFR_EINVAL, "opts is NULL");
+  if (o->gn_iters < 0 || o->pcg_max < 0 || !(o->pcg_rtol >= 0) || !(o->armijo_c1 >= 0 && o->armijo_c1 < 1) ||
+      o->armijo_max < 1 || o->precond < 0 || o->precond > 1)
+    return fail(MFR_EINVAL, "invalid multilevel options");
+  MFR_TRY(check_ptr(R, "R"));
+  MFR_TRY(check_ptr(T, "T"));
+  MFR_TRY(check_ptr(u, "u"));
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(MFR_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  std::vector<Level> L;
+  size_t need = 0;
+  MFR_TRY(ml_levels(finest, o->levels, &L, &need));
+  if (ws_bytes < need) return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", ws_bytes, need);
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace);
+  const int nl = o->levels;
+  mfr_ml_report rep{};
+
+  // image pyramid (finest level copies the caller's images)
+  const Geo& gf = L[nl - 1].geo;
+  HIP_TRY(hipMemcpyAsync(ws + L[nl - 1].off_R, R, sizeof(float) * gf.mbar, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ws + L[nl - 1].off_T, T, sizeof(float) * (size_t)gf.mT[0] * gf.mT[1] * gf.mT[2],
+                         hipMemcpyDeviceToDevice, st));
+  for (int l = nl - 2; l >= 0; --l) {
+    const Geo& f = L[l + 1].geo;
+    HIP_TRY(launch_restrict(at<float>(ws, L[l + 1].off_R), f.m[0], f.m[1], f.m[2], at<float>(ws, L[l].off_R), st));
+    HIP_TRY(launch_restrict(at<float>(ws, L[l + 1].off_T), f.mT[0], f.mT[1], f.mT[2], at<float>(ws, L[l].off_T), st));
+  }
+  size_t ctx_ws = 0;
+  for (int l = 0; l < nl; ++l) {
+    size_t b = 0;
+    MFR_TRY(mfr_workspace_size(&L[l].grid, &b));
+    ctx_ws = std::max(ctx_ws, b);
+  }
+  size_t off_dir = 0;
+  {
+    const Level& lf = L[nl - 1];
+    off_dir = align_up(lf.off_u + sizeof(float) * 3 * lf.geo.nbar);
+  }
+  const size_t off_ptab = align_up(off_dir + sizeof(float) * 3 * gf.nbar);
+
+  double Jfinal = 0.0;
+  for (int l = 0; l < nl; ++l) {
+    const Geo& g = L[l].geo;
+    float* ul = at<float>(ws, L[l].off_u);
+    if (l == 0) {
+      if (nl == 1)
+        HIP_TRY(hipMemcpyAsync(ul, u, sizeof(float) * 3 * g.nbar, hipMemcpyDeviceToDevice, st));
+      else
+        HIP_TRY(hipMemsetAsync(ul, 0, sizeof(float) * 3 * g.nbar, st));
+    } else {
+      const Geo& gc = L[l - 1].geo;
+      auto px = prolong_table(g.n[0], g.hy[0], gc.n[0], gc.hy[0]);
+      auto py = prolong_table(g.n[1], g.hy[1], gc.n[1], gc.hy[1]);
+      auto pz = prolong_table(g.n[2], g.hy[2], gc.n[2], gc.hy[2]);
+      Conv1* dt = at<Conv1>(ws, off_ptab);
+      HIP_TRY(hipMemcpyAsync(dt, px.data(), sizeof(Conv1) * px.size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(dt + g.n[0], py.data(), sizeof(Conv1) * py.size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(dt + g.n[0] + g.n[1], pz.data(), sizeof(Conv1) * pz.size(), hipMemcpyHostToDevice, st));
+      HIP_TRY(launch_prolong(at<float>(ws, L[l - 1].off_u), gc.n[0], gc.n[1], gc.n[2], ul, g.n[0], g.n[1], g.n[2],
+                             dt, dt + g.n[0], dt + g.n[0] + g.n[1], st));
+      HIP_TRY(hipStreamSynchronize(st));   // host tables must outlive the copies
+    }
+    mfr_ctx* c = nullptr;
+    MFR_TRY(mfr_create(&L[l].grid, st, ws, ctx_ws, &c));
+    struct Guard {
+      mfr_ctx* c;
+      ~Guard() { mfr_destroy(c); }
+    } guard{c};
+    MFR_TRY(mfr_set_images(c, at<float>(ws, L[l].off_R), at<float>(ws, L[l].off_T)));
+    float* grad = c->vec[5];
+    float* trial = c->vec[6];
+    float* dir = at<float>(ws, off_dir);
+    const int n3 = (int)(3 * g.nbar);
+    mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond};
+    int gn_done = 0, pcg_tot = 0, status = 0;
+    double Jv = 0.0;
+    MFR_TRY(mfr_objective(c, ul, &Jv, nullptr, nullptr));
+    for (int k = 0; k < o->gn_iters; ++k) {
+      // gradient (its J equals the objective at ul), PCG on -grad
+      MFR_TRY(enqueue_gradient(c, ul, grad));
+      HIP_TRY(launch_axpy(n3, grad, -2.0f, grad, grad, st));   // grad <- -grad
+      mfr_pcg_info info{};
+      MFR_TRY(pcg_run(c, ul, grad, dir, &po, &info));
+      pcg_tot += info.iters;
+      // slope = grad J . s = -(b . s) with b = -grad J
+      std::vector<float> hb(n3), hs(n3);
+      HIP_TRY(hipMemcpyAsync(hb.data(), grad, sizeof(float) * n3, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(hs.data(), dir, sizeof(float) * n3, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double slope = 0.0;
+      for (int i = 0; i < n3; ++i) slope -= (double)hb[i] * hs[i];
+      double eta = 1.0;
+      bool ok = false;
+      double Jn = 0.0;
+      for (int ls = 0; ls < o->armijo_max; ++ls) {
+        HIP_TRY(launch_axpy(n3, ul, (float)eta, dir, trial, st));
+        MFR_TRY(mfr_objective(c, trial, &Jn, nullptr, nullptr));
+        if (Jn <= Jv + o->armijo_c1 * eta * slope) {
+          ok = true;
+          break;
+        }
+        eta *= 0.5;
+      }
+      if (!ok) {
+        status = MFR_ELINESEARCH;
+        break;
+      }
+      HIP_TRY(hipMemcpyAsync(ul, trial, sizeof(float) * n3, hipMemcpyDeviceToDevice, st));
+      Jv = Jn;
+      ++gn_done;
+    }
+    rep.gn_done[l] = gn_done;
+    rep.pcg_total[l] = pcg_tot;
+    rep.status[l] = status;
+    Jfinal = Jv;
+  }
+  const Level& lf = L[nl - 1];
+  HIP_TRY(hipMemcpyAsync(u, ws + lf.off_u, sizeof(float) * 3 * lf.geo.nbar, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  rep.J_final = Jfinal;
+  rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (report) *report = rep;
+  return MFR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Internal declarations of libmfr: kernel parameter blocks, lookup-table
+// records and the host-side launch wrappers implemented in the .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mfr {
+
+// Grid conversion along one axis (Sec. 4.3, eq. grid_conversion): voxel index
+// a lies between nodes n0 and n0 + 1 with weights (1 - f, f).
+struct Conv1 {
+  int n0;
+  float f;
+};
+
+// Template coordinate of a voxel centre along one axis: the continuous
+// template index (a + 1/2) h / hT - 1/2 split into an integer and a fraction.
+struct Samp1 {
+  int base;
+  float frac;
+};
+
+// Inclusive index range.
+struct Range1 {
+  int lo;
+  int hi;
+};
+
+// The three computations the fused voxel-tile kernel performs.
+enum TileMode : int {
+  MODE_OBJ = 0,   // sum of 1 - r_i^2
+  MODE_GRAD = 1,  // dr^T r, scaled by the template derivative, transposed conversion
+  MODE_HV = 2     // dr^T dr (g . P p), scaled by the template derivative, transposed conversion
+};
+
+// Node-pass variants.
+enum NodeMode : int {
+  NP_S = 0,     // curvature energy only
+  NP_GRAD = 1,  // gather + 2 alpha hbar^y L^T L u, and the curvature energy
+  NP_HV = 2     // gather + 2 alpha hbar^y L^T L p, and p . q partials
+};
+
+// Parameters of the fused voxel-tile kernel (passed by value).
+struct TileParams {
+  int mx, my, mz;         // image cells
+  int nx, ny, nz, nbar;   // deformation nodes
+  int mTx, mTy, mTz;      // template cells
+  int PX, PY;             // padded template row / plane pitch (mT + 4)
+  long long PXY;          // padded template plane size
+  float ih2x, ih2y, ih2z; // 1 / h^2
+  float hhx, hhy, hhz;    // 1 / (2 h^2)
+  float ihTx, ihTy, ihTz; // 1 / hT
+  float tau2, rho2, taurho;
+  const float* R;         // reference [mz][my][mx]
+  const float* Tp;        // padded template [mTz+4][mTy+4][mTx+4]
+  const Conv1* cx;        // per-voxel conversion tables (x, y, z)
+  const Conv1* cy;
+  const Conv1* cz;
+  const Samp1* sx;        // per-voxel template coordinates (x, y, z)
+  const Samp1* sy;
+  const Samp1* sz;
+  int tiles_x, tiles_y, chunks, chunk_len;
+  int nxt, nyt, nzt;      // node extents of one tile's partial block
+  float* part;            // transposed-conversion partial blocks
+  double* red;            // one float64 partial per work-group
+};
+
+// Parameters of the node pass.
+struct NodeParams {
+  int nx, ny, nz, nbar;
+  float ihy2x, ihy2y, ihy2z;  // 1 / hy^2
+  float s_ngf;                // scale of the gathered voxel contributions (+-2 hbar)
+  float s_curv;               // 2 alpha hbar^y
+  int tiles_x, tiles_y;
+  int nxt, nyt, nzt;
+  const float* part;
+  const Range1* ntx;          // per node index: range of x tiles / y tiles / z chunks
+  const Range1* nty;
+  const Range1* ntz;
+  const int* orgx;            // per tile: first node index of its partial block
+  const int* orgy;
+  const int* orgz;
+  double* red;
+};
+
+// Parameters of the Jacobi-diagonal kernel.
+struct DiagParams {
+  TileParams t;
+  const Range1* rx;   // per node index: voxel rows whose dr row touches the node's support
+  const Range1* ry;
+  const Range1* rz;
+  float s_ngf;        // 2 hbar
+  float s_curv;       // 2 alpha hbar^y
+  float ihy2x, ihy2y, ihy2z;
+};
+
+// Tile shape of the voxel kernel: the work-group covers BX x BY columns; the
+// inner (BX-4) x (BY-4) are its output voxels, the rest a two-voxel halo.
+struct TileShape {
+  int bx, by;
+};
+
+// ---- launch wrappers (return hipError_t of the launch) ----------------------
+hipError_t launch_tile(const TileShape& s, int mode, const TileParams& p, const float* u,
+                       const float* pv, int grid, hipStream_t st);
+hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float* out, int blocks,
+                            hipStream_t st);
+hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st);
+hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, hipStream_t st);
+hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, hipStream_t st);
+
+// PCG vector kernels.  sc: device scalars (see PcgSlot).
+enum PcgSlot : int {
+  SC_BB = 0, SC_RZ = 1, SC_PQ = 2, SC_RR = 3, SC_RZNEW = 4, SC_ALPHA = 5, SC_BETA = 6,
+  SC_D = 8, SC_S = 9, SC_J = 10, SC_COUNT = 16
+};
+hipError_t launch_pcg_init(int n3, const float* b, const float* diag, float* s, float* r, float* z,
+                           float* p, double* red, int blocks, hipStream_t st);
+hipError_t launch_pcg_alpha(const double* red_pq, int nred, double* sc, hipStream_t st);
+hipError_t launch_pcg_update(int n3, const float* diag, const float* p, const float* q, float* s,
+                             float* r, float* z, const double* sc, double* red, int blocks,
+                             hipStream_t st);
+hipError_t launch_pcg_beta(const double* red, int nred, double* sc, hipStream_t st);
+hipError_t launch_pcg_direction(int n3, const float* z, float* p, const double* sc, int blocks,
+                                hipStream_t st);
+hipError_t launch_pcg_init_finish(const double* red, int nred, double* sc, hipStream_t st);
+
+// y = x + eta * s (GN trial points / updates).
+hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* y, hipStream_t st);
+// Image restriction (2 x 2 x 2 mean, ceil(m/2) cells).
+hipError_t launch_restrict(const float* fine, int mx, int my, int mz, float* coarse, hipStream_t st);
+// Node-field prolongation with per-axis (lower index, fraction) tables.
+hipError_t launch_prolong(const float* coarse, int cnx, int cny, int cnz, float* fine, int fnx,
+                          int fny, int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz,
+                          hipStream_t st);
+
+constexpr int kVecBlock = 256;
+constexpr int kNodeBlock = 256;
+
+}  // namespace mfr

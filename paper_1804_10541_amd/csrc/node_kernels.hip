@@ -1,0 +1,510 @@
+// Node-grid kernels: the gather that completes the transposed grid conversion
+// (Sec. 4.3), the curvature stencils (Sec. 3.1 eq. curvatureMF, Sec. 4.2
+// eq. curv_hessMult), fixed-order float64 reductions, the zero-bordered
+// template copy, the exact Jacobi diagonal, and image / displacement
+// pyramid transfers.
+#include <algorithm>
+
+#include "mfr_internal.h"
+
+namespace mfr {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sum in a fixed order (lane tree, then waves in index order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sred[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += sred[w];
+  }
+  return s;
+}
+
+// 7-point Laplacian with clamped (Neumann) neighbours at node (i, j, k)
+// (eq. laplace_discretized).
+__device__ __forceinline__ float lap7(const float* __restrict__ f, int i, int j, int k, int nx, int ny,
+                                      int nz, float ix2, float iy2, float iz2) {
+  const int nxy = nx * ny;
+  const int c = i + nx * j + nxy * k;
+  const float f0 = f[c];
+  const float fxm = f[c - (i > 0)], fxp = f[c + (i < nx - 1)];
+  const float fym = f[c - nx * (j > 0)], fyp = f[c + nx * (j < ny - 1)];
+  const float fzm = f[c - nxy * (k > 0)], fzp = f[c + nxy * (k < nz - 1)];
+  const float m2 = -2.0f * f0;
+  return fmaf(fxm + fxp + m2, ix2, fmaf(fym + fyp + m2, iy2, (fzm + fzp + m2) * iz2));
+}
+
+}  // namespace
+
+// One thread per node: q_d = s_ngf * (sum of the tile partials) + s_curv * (L L f_d).
+template <int MODE>
+__global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams Q,
+                                                               const float* __restrict__ f,
+                                                               float* __restrict__ out) {
+  __shared__ double sred[kNodeBlock / 64];
+  const int n = blockIdx.x * kNodeBlock + threadIdx.x;
+  double local = 0.0;
+  if (n < Q.nbar) {
+    const int i = n % Q.nx;
+    const int j = (n / Q.nx) % Q.ny;
+    const int k = n / (Q.nx * Q.ny);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float* fd = f + (size_t)d * Q.nbar;
+      const float L0 = lap7(fd, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z);
+      if (MODE == NP_S) {
+        local += (double)L0 * (double)L0;
+        continue;
+      }
+      const float Lxm = i > 0 ? lap7(fd, i - 1, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float Lxp = i < Q.nx - 1 ? lap7(fd, i + 1, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float Lym = j > 0 ? lap7(fd, i, j - 1, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float Lyp = j < Q.ny - 1 ? lap7(fd, i, j + 1, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float Lzm = k > 0 ? lap7(fd, i, j, k - 1, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float Lzp = k < Q.nz - 1 ? lap7(fd, i, j, k + 1, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float m2 = -2.0f * L0;
+      const float LL = fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
+      // gather of the transposed conversion: every tile slot overlapping node n
+      const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
+      float s = 0.0f;
+      for (int cz = rz.lo; cz <= rz.hi; ++cz) {
+        const int kz = k - Q.orgz[cz];
+        for (int cy = ry.lo; cy <= ry.hi; ++cy) {
+          const int iy = j - Q.orgy[cy];
+          for (int cx = rx.lo; cx <= rx.hi; ++cx) {
+            const int jx = i - Q.orgx[cx];
+            const size_t slot = (size_t)cx + (size_t)Q.tiles_x * ((size_t)cy + (size_t)Q.tiles_y * cz);
+            s += Q.part[(((slot * 3 + d) * Q.nzt + kz) * Q.nyt + iy) * Q.nxt + jx];
+          }
+        }
+      }
+      const float q = fmaf(Q.s_ngf, s, Q.s_curv * LL);
+      out[(size_t)d * Q.nbar + n] = q;
+      if (MODE == NP_GRAD) local += (double)L0 * (double)L0;
+      if (MODE == NP_HV) local += (double)fd[n] * (double)q;
+    }
+  }
+  const double s = block_sum<kNodeBlock>(local, sred);
+  if (threadIdx.x == 0) Q.red[blockIdx.x] = s;
+}
+
+hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float* out, int blocks,
+                            hipStream_t st) {
+  if (mode == NP_S)
+    hipLaunchKernelGGL(node_pass_kernel<NP_S>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
+  else if (mode == NP_GRAD)
+    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
+  else
+    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
+  return hipGetLastError();
+}
+
+// Fixed-order sum of n float64 partials by one work-group.
+__global__ __launch_bounds__(256) void sum_kernel(const double* __restrict__ parts, int n,
+                                                  double* __restrict__ out) {
+  __shared__ double sred[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += parts[i];
+  s = block_sum<256>(s, sred);
+  if (threadIdx.x == 0) *out = s;
+}
+
+hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, parts, n, out);
+  return hipGetLastError();
+}
+
+// Copy T into a (m + 4)^3 array with a two-cell zero border.
+__global__ void pad_template_kernel(const float* __restrict__ T, float* __restrict__ Tp, int mx, int my,
+                                    int mz) {
+  const int PX = mx + 4, PY = my + 4, PZ = mz + 4;
+  const size_t total = (size_t)PX * PY * PZ;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(idx % PX) - 2;
+    const int y = (int)((idx / PX) % PY) - 2;
+    const int z = (int)(idx / ((size_t)PX * PY)) - 2;
+    float v = 0.0f;
+    if (x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz) v = T[((size_t)z * my + y) * mx + x];
+    Tp[idx] = v;
+  }
+}
+
+hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, hipStream_t st) {
+  const size_t total = (size_t)(mx + 4) * (my + 4) * (mz + 4);
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(pad_template_kernel, dim3(blocks), dim3(256), 0, st, T, Tp, mx, my, mz);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact Jacobi diagonal: diag_{(d,n)} = 2 hbar sum_l (sum_k drow_l(k) g_{l+k,d}
+// W_n(l+k))^2 + 2 alpha hbar^y (L^T L)_{nn}; one thread per node, rows l of
+// dr whose 7-point stencil meets the node's support, everything recomputed.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct VoxelEval {
+  float T, g[3];
+};
+
+__device__ __forceinline__ VoxelEval eval_voxel(const TileParams& P, const float* __restrict__ u, int x,
+                                                int y, int z) {
+  const Conv1 cx = P.cx[x], cy = P.cy[y], cz = P.cz[z];
+  const int nxy = P.nx * P.ny;
+  float dsp[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float* b = u + (size_t)d * P.nbar + cz.n0 * nxy + cy.n0 * P.nx + cx.n0;
+    const float l00 = fmaf(cx.f, b[1] - b[0], b[0]);
+    const float l10 = fmaf(cx.f, b[P.nx + 1] - b[P.nx], b[P.nx]);
+    const float l01 = fmaf(cx.f, b[nxy + 1] - b[nxy], b[nxy]);
+    const float l11 = fmaf(cx.f, b[nxy + P.nx + 1] - b[nxy + P.nx], b[nxy + P.nx]);
+    const float m0 = fmaf(cy.f, l10 - l00, l00), m1 = fmaf(cy.f, l11 - l01, l01);
+    dsp[d] = fmaf(cz.f, m1 - m0, m0);
+  }
+  const Samp1 sx = P.sx[x], sy = P.sy[y], sz = P.sz[z];
+  const float qx = fminf(fmaxf(fmaf(dsp[0], P.ihTx, sx.frac), -1.0e7f), 1.0e7f);
+  const float qy = fminf(fmaxf(fmaf(dsp[1], P.ihTy, sy.frac), -1.0e7f), 1.0e7f);
+  const float qz = fminf(fmaxf(fmaf(dsp[2], P.ihTz, sz.frac), -1.0e7f), 1.0e7f);
+  const float flx = floorf(qx), fly = floorf(qy), flz = floorf(qz);
+  int kx = min(max(sx.base + (int)flx, -2), P.mTx);
+  int ky = min(max(sy.base + (int)fly, -2), P.mTy);
+  int kz = min(max(sz.base + (int)flz, -2), P.mTz);
+  const float fx = qx - flx, fy = qy - fly, fz = qz - flz;
+  const float* b0 = P.Tp + (size_t)(kz + 2) * (size_t)P.PXY + (size_t)((ky + 2) * P.PX + (kx + 2));
+  const float* b1 = b0 + P.PXY;
+  const float t000 = b0[0], t100 = b0[1], t010 = b0[P.PX], t110 = b0[P.PX + 1];
+  const float t001 = b1[0], t101 = b1[1], t011 = b1[P.PX], t111 = b1[P.PX + 1];
+  const float d00 = t100 - t000, d10 = t110 - t010, d01 = t101 - t001, d11 = t111 - t011;
+  const float e00 = fmaf(fx, d00, t000), e10 = fmaf(fx, d10, t010);
+  const float e01 = fmaf(fx, d01, t001), e11 = fmaf(fx, d11, t011);
+  const float dy0 = e10 - e00, dy1 = e11 - e01;
+  const float f0 = fmaf(fy, dy0, e00), f1 = fmaf(fy, dy1, e01);
+  const float dxa = fmaf(fy, d10 - d00, d00), dxb = fmaf(fy, d11 - d01, d01);
+  VoxelEval o;
+  o.T = fmaf(fz, f1 - f0, f0);
+  o.g[2] = (f1 - f0) * P.ihTz;
+  o.g[1] = fmaf(fz, dy1 - dy0, dy0) * P.ihTy;
+  o.g[0] = fmaf(fz, dxb - dxa, dxa) * P.ihTx;
+  return o;
+}
+
+// weight of node index n for voxel index a along one axis
+__device__ __forceinline__ float w1(const Conv1 c, int n) {
+  return (c.n0 == n) ? 1.0f - c.f : ((c.n0 + 1 == n) ? c.f : 0.0f);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kNodeBlock) void jacobi_diag_kernel(const DiagParams D,
+                                                                 const float* __restrict__ u,
+                                                                 float* __restrict__ diag) {
+  const TileParams& P = D.t;
+  const int n = blockIdx.x * kNodeBlock + threadIdx.x;
+  if (n >= P.nbar) return;
+  const int ni = n % P.nx, nj = (n / P.nx) % P.ny, nk = n / (P.nx * P.ny);
+  const Range1 rx = D.rx[ni], ry = D.ry[nj], rz = D.rz[nk];
+  const size_t plane = (size_t)P.mx * P.my;
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int z = rz.lo; z <= rz.hi; ++z) {
+    for (int y = ry.lo; y <= ry.hi; ++y) {
+      for (int x = rx.lo; x <= rx.hi; ++x) {
+        // the seven stencil points of row l = (x, y, z); clamped ones carry no weight
+        const int px[7] = {x, x - 1, x + 1, x, x, x, x};
+        const int py[7] = {y, y, y, y - 1, y + 1, y, y};
+        const int pz[7] = {z, z, z, z, z, z - 1, z + 1};
+        bool ok[7];
+        VoxelEval ev[7];
+        float Rv[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          ok[k] = px[k] >= 0 && px[k] < P.mx && py[k] >= 0 && py[k] < P.my && pz[k] >= 0 && pz[k] < P.mz;
+          const int qx = ok[k] ? px[k] : x, qy = ok[k] ? py[k] : y, qz = ok[k] ? pz[k] : z;
+          ev[k] = eval_voxel(P, u, qx, qy, qz);
+          Rv[k] = P.R[(size_t)qz * plane + (size_t)qy * P.mx + qx];
+        }
+        float dT[7], dR[7];
+#pragma unroll
+        for (int k = 1; k < 7; ++k) {
+          dT[k] = ev[k].T - ev[0].T;
+          dR[k] = Rv[k] - Rv[0];
+        }
+        const float sTT = fmaf(fmaf(dT[1], dT[1], dT[2] * dT[2]), P.ih2x,
+                               fmaf(fmaf(dT[3], dT[3], dT[4] * dT[4]), P.ih2y, fmaf(dT[5], dT[5], dT[6] * dT[6]) * P.ih2z));
+        const float sRR = fmaf(fmaf(dR[1], dR[1], dR[2] * dR[2]), P.ih2x,
+                               fmaf(fmaf(dR[3], dR[3], dR[4] * dR[4]), P.ih2y, fmaf(dR[5], dR[5], dR[6] * dR[6]) * P.ih2z));
+        const float sTR = fmaf(fmaf(dT[1], dR[1], dT[2] * dR[2]), P.ih2x,
+                               fmaf(fmaf(dT[3], dR[3], dT[4] * dR[4]), P.ih2y, fmaf(dT[5], dR[5], dT[6] * dR[6]) * P.ih2z));
+        const float rnT = rsqrtf(fmaf(0.5f, sTT, P.tau2)), rnR = rsqrtf(fmaf(0.5f, sRR, P.rho2));
+        const float r1 = fmaf(0.5f, sTR, P.taurho);
+        const float c1 = rnT * rnR, c2 = r1 * rnT * rnT;
+        const float hh[7] = {0.f, P.hhx, P.hhx, P.hhy, P.hhy, P.hhz, P.hhz};
+        float rh[7];
+        rh[0] = 0.f;
+#pragma unroll
+        for (int k = 1; k < 7; ++k) {
+          rh[k] = hh[k] * c1 * fmaf(-c2, dT[k], dR[k]);
+          rh[0] -= rh[k];
+        }
+        float zd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          if (!ok[k]) continue;
+          const float W = w1(P.cx[px[k]], ni) * w1(P.cy[py[k]], nj) * w1(P.cz[pz[k]], nk);
+          const float c = rh[k] * W;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) zd[d] = fmaf(c, ev[k].g[d], zd[d]);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[d] = fmaf(zd[d], zd[d], acc[d]);
+      }
+    }
+  }
+  // curvature part: (L^T L)_{nn} = (L_nn)^2 + sum over in-range neighbours 1/hy_k^4
+  const int cxn = (ni > 0) + (ni < P.nx - 1), cyn = (nj > 0) + (nj < P.ny - 1), czn = (nk > 0) + (nk < P.nz - 1);
+  const float Lnn = -(cxn * D.ihy2x + cyn * D.ihy2y + czn * D.ihy2z);
+  const float LL = Lnn * Lnn + cxn * D.ihy2x * D.ihy2x + cyn * D.ihy2y * D.ihy2y + czn * D.ihy2z * D.ihy2z;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) diag[(size_t)d * P.nbar + n] = fmaf(D.s_ngf, acc[d], D.s_curv * LL);
+}
+
+hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, hipStream_t st) {
+  const int blocks = (d.t.nbar + kNodeBlock - 1) / kNodeBlock;
+  hipLaunchKernelGGL(jacobi_diag_kernel, dim3(blocks), dim3(kNodeBlock), 0, st, d, u, diag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector kernels (float32 vectors, float64 dots and step lengths)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kVecBlock) void pcg_init_kernel(int n3, const float* __restrict__ b,
+                                                             const float* __restrict__ diag,
+                                                             float* __restrict__ s, float* __restrict__ r,
+                                                             float* __restrict__ z, float* __restrict__ p,
+                                                             double* __restrict__ red) {
+  __shared__ double sred[kVecBlock / 64];
+  double bb = 0.0, rz = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
+    const float bi = b[i];
+    const float zi = diag ? bi / diag[i] : bi;
+    s[i] = 0.0f;
+    r[i] = bi;
+    z[i] = zi;
+    p[i] = zi;
+    bb += (double)bi * bi;
+    rz += (double)bi * zi;
+  }
+  const double sb = block_sum<kVecBlock>(bb, sred);
+  __syncthreads();
+  const double sz = block_sum<kVecBlock>(rz, sred);
+  if (threadIdx.x == 0) {
+    red[2 * blockIdx.x] = sb;
+    red[2 * blockIdx.x + 1] = sz;
+  }
+}
+
+hipError_t launch_pcg_init(int n3, const float* b, const float* diag, float* s, float* r, float* z,
+                           float* p, double* red, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(blocks), dim3(kVecBlock), 0, st, n3, b, diag, s, r, z, p, red);
+  return hipGetLastError();
+}
+
+// sums pairs of partials (bb, rz) -> sc[SC_BB], sc[SC_RZ]
+__global__ __launch_bounds__(256) void pcg_init_finish_kernel(const double* __restrict__ red, int nred,
+                                                              double* __restrict__ sc) {
+  __shared__ double sred[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nred; i += 256) {
+    a += red[2 * i];
+    b += red[2 * i + 1];
+  }
+  const double sa = block_sum<256>(a, sred);
+  __syncthreads();
+  const double sb = block_sum<256>(b, sred);
+  if (threadIdx.x == 0) {
+    sc[SC_BB] = sa;
+    sc[SC_RZ] = sb;
+    sc[SC_RR] = sa;
+  }
+}
+
+hipError_t launch_pcg_init_finish(const double* red, int nred, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(1), dim3(256), 0, st, red, nred, sc);
+  return hipGetLastError();
+}
+
+// pq = sum of node-pass partials; alpha = rz / pq (0 on breakdown)
+__global__ __launch_bounds__(256) void pcg_alpha_kernel(const double* __restrict__ red, int nred,
+                                                        double* __restrict__ sc) {
+  __shared__ double sred[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nred; i += 256) a += red[i];
+  const double pq = block_sum<256>(a, sred);
+  if (threadIdx.x == 0) {
+    sc[SC_PQ] = pq;
+    sc[SC_ALPHA] = (pq > 0.0 && isfinite(pq)) ? sc[SC_RZ] / pq : 0.0;
+  }
+}
+
+hipError_t launch_pcg_alpha(const double* red_pq, int nred, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_alpha_kernel, dim3(1), dim3(256), 0, st, red_pq, nred, sc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecBlock) void pcg_update_kernel(int n3, const float* __restrict__ diag,
+                                                               const float* __restrict__ p,
+                                                               const float* __restrict__ q,
+                                                               float* __restrict__ s, float* __restrict__ r,
+                                                               float* __restrict__ z,
+                                                               const double* __restrict__ sc,
+                                                               double* __restrict__ red) {
+  __shared__ double sred[kVecBlock / 64];
+  const float alpha = (float)sc[SC_ALPHA];
+  double rr = 0.0, rz = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
+    const float ri = fmaf(-alpha, q[i], r[i]);
+    s[i] = fmaf(alpha, p[i], s[i]);
+    r[i] = ri;
+    const float zi = diag ? ri / diag[i] : ri;
+    z[i] = zi;
+    rr += (double)ri * ri;
+    rz += (double)ri * zi;
+  }
+  const double a = block_sum<kVecBlock>(rr, sred);
+  __syncthreads();
+  const double b = block_sum<kVecBlock>(rz, sred);
+  if (threadIdx.x == 0) {
+    red[2 * blockIdx.x] = a;
+    red[2 * blockIdx.x + 1] = b;
+  }
+}
+
+hipError_t launch_pcg_update(int n3, const float* diag, const float* p, const float* q, float* s,
+                             float* r, float* z, const double* sc, double* red, int blocks,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(pcg_update_kernel, dim3(blocks), dim3(kVecBlock), 0, st, n3, diag, p, q, s, r, z, sc,
+                     red);
+  return hipGetLastError();
+}
+
+// rr, rz_new; beta = rz_new / rz; rz <- rz_new
+__global__ __launch_bounds__(256) void pcg_beta_kernel(const double* __restrict__ red, int nred,
+                                                       double* __restrict__ sc) {
+  __shared__ double sred[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nred; i += 256) {
+    a += red[2 * i];
+    b += red[2 * i + 1];
+  }
+  const double rr = block_sum<256>(a, sred);
+  __syncthreads();
+  const double rz = block_sum<256>(b, sred);
+  if (threadIdx.x == 0) {
+    sc[SC_RR] = rr;
+    sc[SC_RZNEW] = rz;
+    sc[SC_BETA] = rz / sc[SC_RZ];
+    sc[SC_RZ] = rz;
+  }
+}
+
+hipError_t launch_pcg_beta(const double* red, int nred, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_beta_kernel, dim3(1), dim3(256), 0, st, red, nred, sc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecBlock) void pcg_direction_kernel(int n3, const float* __restrict__ z,
+                                                                  float* __restrict__ p,
+                                                                  const double* __restrict__ sc) {
+  const float beta = (float)sc[SC_BETA];
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock)
+    p[i] = fmaf(beta, p[i], z[i]);
+}
+
+hipError_t launch_pcg_direction(int n3, const float* z, float* p, const double* sc, int blocks,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(pcg_direction_kernel, dim3(blocks), dim3(kVecBlock), 0, st, n3, z, p, sc);
+  return hipGetLastError();
+}
+
+__global__ void axpy_kernel(int n, const float* __restrict__ x, float eta, const float* __restrict__ s,
+                            float* __restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    y[i] = fmaf(eta, s[i], x[i]);
+}
+
+hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* y, hipStream_t st) {
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(axpy_kernel, dim3(blocks), dim3(256), 0, st, n, x, eta, s, y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pyramid transfers
+// ---------------------------------------------------------------------------
+__global__ void restrict_kernel(const float* __restrict__ f, int mx, int my, int mz, float* __restrict__ c) {
+  const int cx = (mx + 1) / 2, cy = (my + 1) / 2, cz = (mz + 1) / 2;
+  const size_t total = (size_t)cx * cy * cz;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(idx % cx), b = (int)((idx / cx) % cy), k = (int)(idx / ((size_t)cx * cy));
+    const int x0 = 2 * a, x1 = min(2 * a + 1, mx - 1);
+    const int y0 = 2 * b, y1 = min(2 * b + 1, my - 1);
+    const int z0 = 2 * k, z1 = min(2 * k + 1, mz - 1);
+    auto at = [&](int x, int y, int z) { return f[((size_t)z * my + y) * mx + x]; };
+    const float s = ((at(x0, y0, z0) + at(x1, y0, z0)) + (at(x0, y1, z0) + at(x1, y1, z0))) +
+                    ((at(x0, y0, z1) + at(x1, y0, z1)) + (at(x0, y1, z1) + at(x1, y1, z1)));
+    c[idx] = 0.125f * s;
+  }
+}
+
+hipError_t launch_restrict(const float* fine, int mx, int my, int mz, float* coarse, hipStream_t st) {
+  const size_t total = (size_t)((mx + 1) / 2) * ((my + 1) / 2) * ((mz + 1) / 2);
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(restrict_kernel, dim3(blocks), dim3(256), 0, st, fine, mx, my, mz, coarse);
+  return hipGetLastError();
+}
+
+__global__ void prolong_kernel(const float* __restrict__ c, int cnx, int cny, int cnz, float* __restrict__ f,
+                               int fnx, int fny, int fnz, const Conv1* __restrict__ tx,
+                               const Conv1* __restrict__ ty, const Conv1* __restrict__ tz) {
+  const size_t fb = (size_t)fnx * fny * fnz, cb = (size_t)cnx * cny * cnz;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < fb;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % fnx), j = (int)((idx / fnx) % fny), k = (int)(idx / ((size_t)fnx * fny));
+    const Conv1 a = tx[i], b = ty[j], e = tz[k];
+    for (int d = 0; d < 3; ++d) {
+      const float* s = c + d * cb + ((size_t)e.n0 * cny + b.n0) * cnx + a.n0;
+      const size_t sy = cnx, sz = (size_t)cnx * cny;
+      const float l00 = fmaf(a.f, s[1] - s[0], s[0]);
+      const float l10 = fmaf(a.f, s[sy + 1] - s[sy], s[sy]);
+      const float l01 = fmaf(a.f, s[sz + 1] - s[sz], s[sz]);
+      const float l11 = fmaf(a.f, s[sz + sy + 1] - s[sz + sy], s[sz + sy]);
+      const float m0 = fmaf(b.f, l10 - l00, l00), m1 = fmaf(b.f, l11 - l01, l01);
+      f[d * fb + idx] = fmaf(e.f, m1 - m0, m0);
+    }
+  }
+}
+
+hipError_t launch_prolong(const float* coarse, int cnx, int cny, int cnz, float* fine, int fnx, int fny,
+                          int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz, hipStream_t st) {
+  const size_t total = (size_t)fnx * fny * fnz;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(prolong_kernel, dim3(blocks), dim3(256), 0, st, coarse, cnx, cny, cnz, fine, fnx, fny,
+                     fnz, tx, ty, tz);
+  return hipGetLastError();
+}
+
+}  // namespace mfr

@@ -1,0 +1,248 @@
+"""ctypes binding of libmfr (include/mfr.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor
+devices, dtypes, shapes and contiguity, passes raw device pointers and the
+current HIP stream, and converts status codes into exceptions.  Device
+memory (workspaces, outputs) is allocated through torch.  There is no CPU
+fallback: if the library is missing, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmfr.so")
+
+MFR_OK = 0
+STATUS = {0: "MFR_OK", -1: "MFR_EINVAL", -2: "MFR_ENOMEM", -3: "MFR_EHIP", -4: "MFR_ENONFINITE",
+          -5: "MFR_ELINESEARCH", -6: "MFR_EBREAKDOWN"}
+
+
+class MfrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CGrid(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("my", ctypes.c_int32 * 3),
+                ("mT", ctypes.c_int32 * 3), ("hT", ctypes.c_double * 3),
+                ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class CPcgOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double), ("precond", ctypes.c_int32)]
+
+
+class CPcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double), ("flag", ctypes.c_int32)]
+
+
+class CMlOpts(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32), ("pcg_max", ctypes.c_int32),
+                ("pcg_rtol", ctypes.c_double), ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
+
+
+class CMlReport(ctypes.Structure):
+    _fields_ = [("J_final", ctypes.c_double), ("gn_done", ctypes.c_int32 * 8), ("pcg_total", ctypes.c_int32 * 8),
+                ("status", ctypes.c_int32 * 8), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+# exported function -> (restype, argtypes)
+_VP, _SZ, _D, _I = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32
+SIGNATURES = {
+    "mfr_abi_version": (ctypes.c_int, []),
+    "mfr_last_error": (ctypes.c_char_p, []),
+    "mfr_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(_SZ)]),
+    "mfr_create": (ctypes.c_int, [ctypes.POINTER(CGrid), _VP, _VP, _SZ, ctypes.POINTER(_VP)]),
+    "mfr_destroy": (None, [_VP]),
+    "mfr_set_images": (ctypes.c_int, [_VP, _VP, _VP]),
+    "mfr_objective": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "mfr_gradient": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_D)]),
+    "mfr_hess_vec": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mfr_jacobi_diag": (ctypes.c_int, [_VP, _VP, _VP]),
+    "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
+    "mfr_ml_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
+    "mfr_register_multilevel": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CMlOpts), _VP, _VP, _SZ,
+                                               _VP, _VP, _VP, ctypes.POINTER(CMlReport)]),
+}
+
+
+def load():
+    """Load libmfr.so and bind every exported entry point (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmfr.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != MFR_OK:
+        raise MfrError(status, _lib.mfr_last_error().decode())
+
+
+def make_grid(spec):
+    """CGrid from any object with m, h, my, tau, rho, alpha (optional mT, hT)."""
+    g = CGrid()
+    for k in range(3):
+        g.m[k] = int(spec.m[k])
+        g.h[k] = float(spec.h[k])
+        g.my[k] = int(spec.my[k])
+        mT = getattr(spec, "mT", None)
+        hT = getattr(spec, "hT", None)
+        g.mT[k] = int(mT[k]) if mT is not None else 0
+        g.hT[k] = float(hT[k]) if hT is not None else 0.0
+    g.tau, g.rho, g.alpha = float(spec.tau), float(spec.rho), float(spec.alpha)
+    return g
+
+
+def _dev_tensor(x, numel, name, device):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.device.type != "cuda" or (device is not None and x.device != device):
+        raise ValueError(f"{name} must live on {device}")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.numel() != numel:
+        raise ValueError(f"{name} has {x.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_size(spec):
+    lib = load()
+    g = make_grid(spec)
+    n = ctypes.c_size_t()
+    _check(lib.mfr_workspace_size(ctypes.byref(g), ctypes.byref(n)))
+    return n.value
+
+
+def _alloc_workspace(nbytes, device):
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws, ws.data_ptr() + off
+
+
+class Context:
+    """One registration problem bound to a device, a stream and a workspace."""
+
+    def __init__(self, spec, device="cuda:0"):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.spec = spec
+        self.grid = make_grid(spec)
+        self.m = tuple(int(k) for k in spec.m)
+        self.my = tuple(int(k) for k in spec.my)
+        mT = getattr(spec, "mT", None)
+        self.mT = tuple(int(k) for k in (mT if mT is not None else spec.m))
+        self.nbar = self.my[0] * self.my[1] * self.my[2]
+        self.mbar = self.m[0] * self.m[1] * self.m[2]
+        self.ws_bytes = workspace_size(spec)
+        self._ws, ptr = _alloc_workspace(self.ws_bytes, self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.mfr_create(ctypes.byref(self.grid), _stream(self.device), ctypes.c_void_p(ptr),
+                                   self.ws_bytes, ctypes.byref(h)))
+        self._h = h
+        self._images = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.mfr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def node_shape(self):
+        return (3, self.my[2], self.my[1], self.my[0])
+
+    def set_images(self, R, T):
+        r = _dev_tensor(R, self.mbar, "R", self.device)
+        t = _dev_tensor(T, self.mT[0] * self.mT[1] * self.mT[2], "T", self.device)
+        _check(self.lib.mfr_set_images(self._h, r, t))
+        self._images = (R, T)   # keep the borrowed buffers alive
+
+    def objective(self, u):
+        J, D, S = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.mfr_objective(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+                                      ctypes.byref(J), ctypes.byref(D), ctypes.byref(S)))
+        return J.value, D.value, S.value
+
+    def gradient(self, u, out=None, want_J=True):
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        J = ctypes.c_double()
+        _check(self.lib.mfr_gradient(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+                                     _dev_tensor(out, 3 * self.nbar, "g", self.device),
+                                     ctypes.byref(J) if want_J else None))
+        return out, (J.value if want_J else None)
+
+    def hess_vec(self, u, p, out=None):
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        _check(self.lib.mfr_hess_vec(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+                                     _dev_tensor(p, 3 * self.nbar, "p", self.device),
+                                     _dev_tensor(out, 3 * self.nbar, "q", self.device)))
+        return out
+
+    def jacobi_diag(self, u, out=None):
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        _check(self.lib.mfr_jacobi_diag(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+                                        _dev_tensor(out, 3 * self.nbar, "diag", self.device)))
+        return out
+
+    def pcg_solve(self, u, b, max_iter=50, rtol=1e-3, precond=1, out=None):
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        opts = CPcgOpts(int(max_iter), float(rtol), int(precond))
+        info = CPcgInfo()
+        _check(self.lib.mfr_pcg_solve(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+                                      _dev_tensor(b, 3 * self.nbar, "b", self.device),
+                                      _dev_tensor(out, 3 * self.nbar, "s", self.device),
+                                      ctypes.byref(opts), ctypes.byref(info)))
+        return out, dict(iters=info.iters, relres=info.relres, flag=info.flag)
+
+
+def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=1e-3, armijo_c1=1e-4,
+                        armijo_max=10, precond=1, u0=None, device="cuda:0"):
+    """Coarse-to-fine Gauss-Newton registration; returns (u_finest, report dict)."""
+    lib = load()
+    device = torch.device(device)
+    g = make_grid(spec)
+    n = ctypes.c_size_t()
+    _check(lib.mfr_ml_workspace_size(ctypes.byref(g), int(levels), ctypes.byref(n)))
+    ws, ptr = _alloc_workspace(n.value, device)
+    my = tuple(int(k) for k in spec.my)
+    nb = my[0] * my[1] * my[2]
+    u = torch.zeros((3, my[2], my[1], my[0]), dtype=torch.float32, device=device) if u0 is None else u0.clone()
+    mbar = int(spec.m[0]) * int(spec.m[1]) * int(spec.m[2])
+    mT = getattr(spec, "mT", None) or spec.m
+    opts = CMlOpts(int(levels), int(gn_iters), int(pcg_max), float(pcg_rtol), float(armijo_c1), int(armijo_max),
+                   int(precond))
+    rep = CMlReport()
+    _check(lib.mfr_register_multilevel(ctypes.byref(g), ctypes.byref(opts), _stream(device), ctypes.c_void_p(ptr),
+                                       n.value, _dev_tensor(R, mbar, "R", device),
+                                       _dev_tensor(T, int(mT[0]) * int(mT[1]) * int(mT[2]), "T", device),
+                                       _dev_tensor(u, 3 * nb, "u", device), ctypes.byref(rep)))
+    del ws
+    return u, dict(J_final=rep.J_final, gn_done=list(rep.gn_done)[:levels], pcg_total=list(rep.pcg_total)[:levels],
+                   status=list(rep.status)[:levels], seconds=rep.seconds)

@@ -1,0 +1,81 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/*.h declares, and its host-only logic (argument validation, workspace
+sizing) behaves as documented.  No compute call is made here."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_1804_10541_amd import mfr
+from synth import GridSpec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(mfr_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mfr.LIB_PATH):
+        pytest.fail("libmfr.so is not built; run __graft_entry__.build()")
+    return mfr.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names == set(mfr.SIGNATURES), "binding and header disagree"
+
+
+def test_abi_version(lib):
+    assert lib.mfr_abi_version() == 1
+
+
+def _ws(spec):
+    return mfr.workspace_size(spec)
+
+
+def test_workspace_size_and_validation(lib):
+    spec = GridSpec(m=(32, 32, 32), h=(1, 1, 1), my=(17, 17, 17), tau=0.1, rho=0.1, alpha=1.0)
+    n = _ws(spec)
+    padded = 36 ** 3 * 4
+    assert n > padded
+    # derivative storage does not grow with the voxel count beyond the template copy
+    big = GridSpec(m=(64, 64, 64), h=(1, 1, 1), my=(17, 17, 17), tau=0.1, rho=0.1, alpha=1.0)
+    assert _ws(big) - 68 ** 3 * 4 < 4 * (n - padded)
+    bad = [
+        dict(my=(34, 17, 17)),                   # more than m + 1 nodes
+        dict(my=(1, 17, 17)),                    # fewer than 2 nodes
+        dict(h=(0.0, 1, 1)),                     # zero spacing
+        dict(tau=0.0),                           # tau must be > 0
+        dict(alpha=-1.0),                        # alpha must be >= 0
+    ]
+    for kw in bad:
+        args = dict(m=(32, 32, 32), h=(1, 1, 1), my=(17, 17, 17), tau=0.1, rho=0.1, alpha=1.0)
+        args.update(kw)
+        with pytest.raises(mfr.MfrError) as e:
+            _ws(GridSpec(**args))
+        assert e.value.status == -1
+        assert len(str(e.value)) > 12
+
+
+def test_null_arguments_rejected(lib):
+    g = mfr.make_grid(GridSpec(m=(8, 8, 8), h=(1, 1, 1), my=(5, 5, 5), tau=1, rho=1, alpha=1))
+    out = ctypes.c_void_p()
+    st = lib.mfr_create(ctypes.byref(g), None, None, 0, ctypes.byref(out))
+    assert st == -1 and b"workspace" in lib.mfr_last_error()
+    assert lib.mfr_workspace_size(None, None) == -1
+    assert lib.mfr_objective(None, None, None, None, None) == -1
+    assert lib.mfr_hess_vec(None, None, None, None) == -1
