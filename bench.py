@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free NGF + curvature Gauss-Newton step on one MI355X.
+
+Workload (default): the large single-level Gauss-Newton step -- a 512 x 512 x
+900 CT-like float32 volume pair, deformation grid 129 x 129 x 225 nodes, eps
+50 HU, alpha 0.1, smooth initial displacement of max 0.5 voxel.  One step is
+one call of the library's Gauss-Newton step: objective and gradient, exact
+Jacobi diagonal, Jacobi-PCG with exactly 20 Hessian-vector products
+(rtol 0), Armijo line search (one or more objective evaluations) and the
+update.  All inputs are synthetic and resident in HBM before timing starts.
+
+Output: one JSON line.  ``value`` = voxel-Hessian-vector products per second
+over whole steps (image voxels x 20 / step time, in Gvoxel/s).  ``roofline``
+refers to the dominant kernel (the voxel-tile kernel in Hessian-vector mode),
+timed with HIP events on the stream it runs on.  ``cpu_baseline`` times the
+float64 oracle on a bounded crop of the same volume on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HV_PER_STEP = 20
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, 8 TB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz)
+
+# Algorithmic work of one Hessian-vector product (per image voxel / per node).
+# Flops: the per-voxel arithmetic of the fused matrix-free scheme for one
+# output voxel (grid conversion of u and p, trilinear template value and
+# gradient, six short differences of T and R, residual and the rho-hat row,
+# dr a, the column gather of dr^T, g w, transposed conversion), FMA = 2 flops,
+# no halo recomputation counted.  Bytes: R and T read once (8 B/voxel); u, p
+# read and q written once (36 B/node).
+HV_FLOP_PER_VOXEL = 217
+HV_BYTES_PER_VOXEL = 8
+HV_BYTES_PER_NODE = 36
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload_spec(name):
+    from synth import GridSpec
+
+    if name == "c3":
+        return GridSpec(m=(512, 512, 900), h=(1.0, 1.0, 1.0), my=(129, 129, 225), tau=50.0, rho=50.0, alpha=0.1)
+    if name == "c3-half":
+        return GridSpec(m=(512, 512, 450), h=(1.0, 1.0, 1.0), my=(129, 129, 113), tau=50.0, rho=50.0, alpha=0.1)
+    if name == "small":
+        return GridSpec(m=(128, 128, 96), h=(1.0, 1.0, 1.0), my=(33, 33, 25), tau=50.0, rho=50.0, alpha=0.1)
+    raise ValueError(name)
+
+
+def cpu_baseline(R, T, u0, spec, budget_s=25.0):
+    """The float64 oracle, as it stands, on a crop of the same volume: one
+    Gauss-Newton step's derivative work (objective, gradient, Jacobi diagonal,
+    and HV_PER_STEP Hessian-vector products reusing the assembled Jacobian)."""
+    import numpy as np
+
+    from oracle import Grid, solver
+
+    # crop: 128 x 128 x 64 voxels from the centre, deformation ratio 4 as in the workload
+    cm = (128, 128, 64)
+    cn = (33, 33, 17)
+    mx, my_, mz = spec.m
+    x0, y0, z0 = (mx - cm[0]) // 2, (my_ - cm[1]) // 2, (mz - cm[2]) // 2
+    Rc = R[z0:z0 + cm[2], y0:y0 + cm[1], x0:x0 + cm[0]].double().cpu().numpy()
+    Tc = T[z0:z0 + cm[2], y0:y0 + cm[1], x0:x0 + cm[0]].double().cpu().numpy()
+    rng = np.random.default_rng(1)
+    from synth import smooth_field
+
+    u = smooth_field(rng, cn, 0.5)
+    g = Grid(cm, spec.h, cn, spec.tau, spec.rho, spec.alpha)
+    t0 = time.perf_counter()
+    prob = solver.Problem(g, Rc, Tc)
+    prob.objective(u)
+    _, grad = prob.gradient(u)
+    Jac = prob.jacobian(u)
+    prob.jacobi_diag(u, Jac)
+    p = -grad
+    n_hv = 0
+    for _ in range(HV_PER_STEP):
+        p = prob.hess_vec(u, p, Jac)
+        p /= np.linalg.norm(p)
+        n_hv += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    vox = cm[0] * cm[1] * cm[2]
+    return {"value": vox * n_hv / dt / 1e9, "unit": "Gvoxel/s", "cores": 1, "kind": "oracle",
+            "sample": f"crop {cm[0]}x{cm[1]}x{cm[2]} voxels / {cn[0]}x{cn[1]}x{cn[2]} nodes of the same volume; "
+                      f"objective + gradient + Jacobi diagonal + {n_hv} Hessian-vector products "
+                      f"(assembled float64 Jacobian, scipy.sparse, single thread) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c3-half", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the multi-GPU path is not part of this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1804_10541_amd import mfr
+    from synth import ct_pair, smooth_field
+
+    dev = torch.device("cuda:0")
+    spec = workload_spec(args.workload)
+    log(f"[bench] generating {args.workload}: {spec.m} voxels, {spec.my} nodes")
+    t0 = time.perf_counter()
+    R, T, _, rng = ct_pair(0, spec.m, device=dev)
+    u0 = torch.from_numpy(smooth_field(rng, spec.my, 0.5).astype("float32")).to(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    ctx = mfr.Context(spec, dev)
+    ctx.set_images(R, T)
+    u = u0.clone()
+    gn = dict(pcg_max=HV_PER_STEP, pcg_rtol=0.0, precond=1, armijo_c1=1e-4, armijo_max=10)
+    for i in range(args.warmup):
+        info = ctx.gn_step(u, **gn)
+        log(f"[bench] warmup {i}: J {info['J_before']:.6e} -> {info['J_after']:.6e}, eta {info['eta']}")
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        infos.append(ctx.gn_step(u, **gn))
+        log(f"[bench] step {i}: J {infos[-1]['J_before']:.6e} -> {infos[-1]['J_after']:.6e}, "
+            f"pcg {infos[-1]['pcg_iters']} relres {infos[-1]['pcg_relres']:.3e}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    peak_mem = torch.cuda.max_memory_allocated(dev)
+
+    mbar = spec.voxels
+    nbar = spec.nodes
+    n_hv = sum(i["pcg_iters"] for i in infos)
+    ms_step = dt * 1e3 / args.steps
+    value = mbar * n_hv / dt / 1e9
+    hv_launches, hv_ms = prof["tile_hv"]
+    np_launches, np_ms = prof["node_pass"]
+    hv_avg_ms = hv_ms / max(hv_launches, 1)
+    flops = HV_FLOP_PER_VOXEL * mbar
+    achieved_tflops = flops / (hv_avg_ms * 1e-3) / 1e12
+    alg_bytes = HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar
+    hv_hbm_gbs = alg_bytes / (hv_avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "GN Hessian-vector Gvoxel/s + % HBM peak; PCG solve time, learned vs Jacobi",
+        "value": round(value, 3),
+        "unit": "Gvoxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"large single-level Gauss-Newton step, {spec.m[0]}x{spec.m[1]}x{spec.m[2]} "
+                               f"CT-like float32 pair, {spec.my[0]}x{spec.my[1]}x{spec.my[2]} nodes, "
+                               f"{HV_PER_STEP} Hessian-vector products per step (Jacobi-PCG, rtol 0)",
+                   "voxels": mbar, "nodes": nbar, "hv_per_step": HV_PER_STEP},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None,
+                     "kernel": "ngf_tile_kernel<HV>", "avg_ms": round(hv_avg_ms, 4), "launches": hv_launches,
+                     "flop_per_voxel": HV_FLOP_PER_VOXEL},
+        "hv": {"kernel_gvoxel_s": round(mbar / (hv_avg_ms * 1e-3) / 1e9, 2),
+               "with_node_pass_gvoxel_s": round(mbar / ((hv_avg_ms + np_ms / max(np_launches, 1)) * 1e-3) / 1e9, 2),
+               "hbm_algorithmic_gbs": round(hv_hbm_gbs, 1),
+               "hbm_frac": round(hv_hbm_gbs / HBM_PEAK_GBS, 4)},
+        "kernel_ms": {k: (v[0], round(v[1] / max(v[0], 1), 4)) for k, v in prof.items()},
+        "peak_device_bytes": int(peak_mem),
+        "workspace_bytes": int(ctx.ws_bytes),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
+        out["cpu_baseline"] = cpu_baseline(R, T, u0, spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

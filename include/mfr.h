@@ -133,6 +133,33 @@ mfr_status mfr_pcg_solve(mfr_ctx* ctx, const float* u, const float* b, float* s,
                          const mfr_pcg_opts* opts, mfr_pcg_info* info);
 
 typedef struct {
+  int32_t pcg_max;     /* CG iterations                                              */
+  double pcg_rtol;     /* CG relative residual tolerance (0: always pcg_max steps)   */
+  int32_t precond;     /* 0 none, 1 Jacobi                                           */
+  double armijo_c1;    /* sufficient-decrease constant in [0, 1) (e.g. 1e-4)         */
+  int32_t armijo_max;  /* trial step lengths 1, 1/2, 1/4, ... before giving up, >= 1 */
+} mfr_gn_opts;
+
+typedef struct {
+  double J_before;     /* J(u) on entry                                              */
+  double J_after;      /* J at the accepted point (= J_before if none accepted)      */
+  double eta;          /* accepted step length (0 if the line search failed)         */
+  double slope;        /* grad J . s                                                 */
+  int32_t pcg_iters;
+  double pcg_relres;
+  int32_t pcg_flag;
+  int32_t accepted;    /* 1 if u was updated                                         */
+  int32_t ls_trials;   /* objective evaluations spent in the line search             */
+} mfr_gn_info;
+
+/* One Gauss-Newton step at u (Sec. 2.3.1): gradient, (H + alpha nabla^2 S) s =
+ * -grad J by (P)CG, Armijo line search eta = 1, 1/2, ... on J(u + eta s), and
+ * u <- u + eta s if a step is accepted.  u: device [3][n], updated in place.
+ * A failed line search is not an error: info->accepted = 0 and u is unchanged.
+ * Synchronises the stream. */
+mfr_status mfr_gn_step(mfr_ctx* ctx, float* u, const mfr_gn_opts* opts, mfr_gn_info* info);
+
+typedef struct {
   int32_t levels;      /* pyramid levels, 1..8                                     */
   int32_t gn_iters;    /* Gauss-Newton iterations per level                        */
   int32_t pcg_max;     /* CG iterations per Gauss-Newton step                      */
@@ -163,6 +190,21 @@ mfr_status mfr_ml_workspace_size(const mfr_grid* finest, int32_t levels, size_t*
 mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* opts, void* hip_stream,
                                    void* workspace, size_t ws_bytes, const float* R, const float* T,
                                    float* u, mfr_ml_report* report);
+
+/* Kernel timing for measurement.  While enabled, the library records a pair
+ * of HIP events on the context's stream around every launch of its main
+ * kernels; mfr_profile_read synchronises the stream and returns the launch
+ * counts and summed event times in milliseconds, per kernel:
+ * [0] voxel-tile kernel, objective mode; [1] gradient mode; [2] Hessian-vector
+ * mode; [3] Jacobi diagonal; [4] node pass (all modes).  Timing adds two event
+ * records per launch; it is off after mfr_create. */
+typedef struct {
+  int32_t launches[5];
+  double ms[5];
+} mfr_profile_stats;
+
+mfr_status mfr_profile_enable(mfr_ctx* ctx, int32_t enable);
+mfr_status mfr_profile_read(mfr_ctx* ctx, mfr_profile_stats* stats, int32_t reset);
 
 #ifdef __cplusplus
 }

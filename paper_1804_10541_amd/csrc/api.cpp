@@ -139,6 +139,35 @@ std::vector<Conv1> prolong_table(int nf, double hyf, int nc, double hyc) {
   return t;
 }
 
+// Node blocks along x or y for the Jacobi kernel: consecutive nodes whose voxel
+// rows (plus a one-voxel halo) fit into `width` columns.  Returns false if a
+// single node does not fit.
+bool node_blocks_xy(const std::vector<Range1>& rows, int width, std::vector<NodeBlock>* out) {
+  out->clear();
+  const int n = (int)rows.size();
+  int lo = 0;
+  while (lo < n) {
+    if (rows[lo].hi - rows[lo].lo + 3 > width) return false;
+    int hi = lo;
+    while (hi + 1 < n && rows[hi + 1].hi - rows[lo].lo + 3 <= width) ++hi;
+    out->push_back(NodeBlock{lo, hi, rows[lo].lo - 1, 0});
+    lo = hi + 1;
+  }
+  return true;
+}
+
+// Node-plane chunks along z: `per` planes each; a0 = first voxel plane - 1,
+// pad = last voxel plane of the rows touching the chunk.
+std::vector<NodeBlock> node_blocks_z(const std::vector<Range1>& rows, int per) {
+  std::vector<NodeBlock> out;
+  const int n = (int)rows.size();
+  for (int lo = 0; lo < n; lo += per) {
+    const int hi = std::min(lo + per, n) - 1;
+    out.push_back(NodeBlock{lo, hi, rows[lo].lo - 1, rows[hi].hi});
+  }
+  return out;
+}
+
 // ---- tiling -----------------------------------------------------------------
 struct Tiling {
   TileShape shape;
@@ -189,7 +218,7 @@ bool valid_shape(const TileShape& s) {
 // ---- workspace layout ---------------------------------------------------------
 struct Layout {
   size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
-  size_t part, red_tile, red_node, sc, vec;
+  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz;
   size_t n_red_node;
   size_t total;
 };
@@ -218,13 +247,16 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.rx = take(sizeof(Range1) * g.n[0]);
   L.ry = take(sizeof(Range1) * g.n[1]);
   L.rz = take(sizeof(Range1) * g.n[2]);
+  L.jbx = take(sizeof(NodeBlock) * g.n[0]);
+  L.jby = take(sizeof(NodeBlock) * g.n[1]);
+  L.jbz = take(sizeof(NodeBlock) * g.n[2]);
   L.part = take(sizeof(float) * (size_t)t.grid() * 3 * t.nzt * t.nyt * t.nxt);
   L.red_tile = take(sizeof(double) * (size_t)t.grid());
   const size_t node_blocks = (g.nbar + kNodeBlock - 1) / kNodeBlock;
   L.n_red_node = std::max<size_t>(node_blocks, 2 * 1024);
   L.red_node = take(sizeof(double) * L.n_red_node);
   L.sc = take(sizeof(double) * SC_COUNT);
-  L.vec = take(sizeof(float) * 3 * g.nbar * 7);   // PCG: s r z p q diag + GN trial
+  L.vec = take(sizeof(float) * 3 * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
   L.total = o;
   return L;
 }
@@ -242,11 +274,26 @@ struct mfr_ctx {
   TileParams tp;
   NodeParams np;
   DiagParams dp;
+  JacParams jp;
+  bool jac_tiled;
   double* sc;
   double* red_tile;
   double* red_node;
-  float* vec[7];
+  float* vec[8];
   int vec_blocks;
+  // kernel timing (mfr_profile_*)
+  bool prof_on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  int prof_launches[5] = {0, 0, 0, 0, 0};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  ~mfr_ctx() {
+    for (auto& p : prof_pending) {
+      hipEventDestroy(p.second.first);
+      hipEventDestroy(p.second.second);
+    }
+    for (auto e : prof_pool) hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -293,6 +340,14 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
     ntz[i] = Range1{colz[i].lo / t.chunk_len, colz[i].hi / t.chunk_len};
     rz[i] = Range1{std::max(colz[i].lo - 1, 0), std::min(colz[i].hi + 1, g.m[2] - 1)};
   }
+  std::vector<NodeBlock> jbx, jby;
+  c->jac_tiled = node_blocks_xy(rx, kJacAX, &jbx) && node_blocks_xy(ry, kJacAY, &jby);
+  std::vector<NodeBlock> jbz;
+  if (c->jac_tiled) {
+    const int nxy = (int)(jbx.size() * jby.size());
+    const int nbz = std::max(1, std::min(g.n[2], (2048 + nxy - 1) / nxy));
+    jbz = node_blocks_z(rz, (g.n[2] + nbz - 1) / nbz);
+  }
   std::vector<int> orgx(t.tiles_x), orgy(t.tiles_y), orgz(t.chunks);
   for (int i = 0; i < t.tiles_x; ++i) orgx[i] = cx[i * TX].n0;
   for (int i = 0; i < t.tiles_y; ++i) orgy[i] = cy[i * TY].n0;
@@ -317,6 +372,11 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   HIP_TRY(up(L.rx, rx.data(), sizeof(Range1) * rx.size()));
   HIP_TRY(up(L.ry, ry.data(), sizeof(Range1) * ry.size()));
   HIP_TRY(up(L.rz, rz.data(), sizeof(Range1) * rz.size()));
+  if (c->jac_tiled) {
+    HIP_TRY(up(L.jbx, jbx.data(), sizeof(NodeBlock) * jbx.size()));
+    HIP_TRY(up(L.jby, jby.data(), sizeof(NodeBlock) * jby.size()));
+    HIP_TRY(up(L.jbz, jbz.data(), sizeof(NodeBlock) * jbz.size()));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
 
   TileParams& p = c->tp;
@@ -398,12 +458,60 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   d.ihy2y = q.ihy2y;
   d.ihy2z = q.ihy2z;
 
+  JacParams& jp = c->jp;
+  jp.t = p;
+  jp.bx = at<NodeBlock>(c->ws, L.jbx);
+  jp.by = at<NodeBlock>(c->ws, L.jby);
+  jp.bz = at<NodeBlock>(c->ws, L.jbz);
+  jp.nbx = (int)jbx.size();
+  jp.nby = (int)jby.size();
+  jp.nbz = (int)jbz.size();
+  jp.rx = d.rx;
+  jp.ry = d.ry;
+  jp.s_ngf = d.s_ngf;
+  jp.s_curv = d.s_curv;
+  jp.ihy2x = d.ihy2x;
+  jp.ihy2y = d.ihy2y;
+  jp.ihy2z = d.ihy2z;
+
   c->sc = at<double>(c->ws, L.sc);
   c->red_tile = p.red;
   c->red_node = q.red;
-  for (int k = 0; k < 7; ++k) c->vec[k] = at<float>(c->ws, L.vec) + (size_t)k * 3 * g.nbar;
+  for (int k = 0; k < 8; ++k) c->vec[k] = at<float>(c->ws, L.vec) + (size_t)k * 3 * g.nbar;
   c->vec_blocks = (int)std::min<size_t>((3 * g.nbar + kVecBlock - 1) / kVecBlock, 1024);
   return MFR_OK;
+}
+
+hipEvent_t prof_event(mfr_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs `launch` between two event records when timing is on (slot: kernel id).
+template <class F>
+hipError_t timed(mfr_ctx* c, int slot, F&& launch) {
+  if (!c->prof_on) return launch();
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, c->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, c->stream);
+  if (e != hipSuccess) return e;
+  c->prof_pending.push_back({slot, {a, b}});
+  return hipSuccess;
+}
+
+hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
+  if (c->jac_tiled) return launch_jacobi_tile(c->jp, u, diag, c->stream);
+  return launch_jacobi_diag(c->dp, u, diag, c->stream);
 }
 
 int node_blocks(const mfr_ctx* c) { return (int)((c->geo.nbar + kNodeBlock - 1) / kNodeBlock); }
@@ -423,10 +531,10 @@ mfr_status need_images(const mfr_ctx* c) {
 // Enqueue: D and S sums into sc[SC_D], sc[SC_S].
 mfr_status enqueue_objective(mfr_ctx* c, const float* u) {
   const Tiling& t = c->tiling;
-  HIP_TRY(launch_tile(t.shape, MODE_OBJ, c->tp, u, nullptr, t.grid(), c->stream));
+  HIP_TRY(timed(c, 0, [&] { return launch_tile(t.shape, MODE_OBJ, c->tp, u, nullptr, t.grid(), c->stream); }));
   HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
   NodeParams q = c->np;
-  HIP_TRY(launch_node_pass(NP_S, q, u, nullptr, node_blocks(c), c->stream));
+  HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_S, q, u, nullptr, node_blocks(c), c->stream); }));
   HIP_TRY(launch_sum(c->red_node, node_blocks(c), c->sc + SC_S, c->stream));
   return MFR_OK;
 }
@@ -447,11 +555,11 @@ mfr_status read_objective(mfr_ctx* c, double* J, double* D, double* S) {
 
 mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
   const Tiling& t = c->tiling;
-  HIP_TRY(launch_tile(t.shape, MODE_GRAD, c->tp, u, nullptr, t.grid(), c->stream));
+  HIP_TRY(timed(c, 1, [&] { return launch_tile(t.shape, MODE_GRAD, c->tp, u, nullptr, t.grid(), c->stream); }));
   HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
   NodeParams q = c->np;
   q.s_ngf = (float)(-2.0 * c->geo.hbar());
-  HIP_TRY(launch_node_pass(NP_GRAD, q, u, g, node_blocks(c), c->stream));
+  HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_GRAD, q, u, g, node_blocks(c), c->stream); }));
   HIP_TRY(launch_sum(c->red_node, node_blocks(c), c->sc + SC_S, c->stream));
   return MFR_OK;
 }
@@ -459,10 +567,10 @@ mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
 // q = A p; p . q partials left in red_node
 mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q) {
   const Tiling& t = c->tiling;
-  HIP_TRY(launch_tile(t.shape, MODE_HV, c->tp, u, p, t.grid(), c->stream));
+  HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, c->tp, u, p, t.grid(), c->stream); }));
   NodeParams np = c->np;
   np.s_ngf = (float)(2.0 * c->geo.hbar());
-  HIP_TRY(launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream));
+  HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream); }));
   return MFR_OK;
 }
 
@@ -477,7 +585,7 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
   float* diag = nullptr;
   if (o->precond == 1) {
     diag = c->vec[4];
-    HIP_TRY(launch_jacobi_diag(c->dp, u, diag, c->stream));
+    HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
   }
   const int vb = c->vec_blocks;
   HIP_TRY(launch_pcg_init(n3, b, diag, s, r, z, p, c->red_node, vb, c->stream));
@@ -517,6 +625,55 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
     HIP_TRY(launch_pcg_direction(n3, z, p, c->sc, vb, c->stream));
   }
   if (info) *info = inf;
+  return MFR_OK;
+}
+
+// One Gauss-Newton step (Sec. 2.3.1).  Vectors: vec[5] right-hand side -grad J,
+// vec[6] trial point, vec[7] search direction.
+mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out) {
+  const int n3 = (int)(3 * c->geo.nbar);
+  float* b = c->vec[5];
+  float* trial = c->vec[6];
+  float* dir = c->vec[7];
+  mfr_gn_info inf{};
+  MFR_TRY(enqueue_gradient(c, u, b));
+  double Jv = 0.0;
+  MFR_TRY(read_objective(c, &Jv, nullptr, nullptr));
+  inf.J_before = Jv;
+  inf.J_after = Jv;
+  HIP_TRY(launch_axpy(n3, b, -2.0f, b, b, c->stream));   // b <- -grad J
+  mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond};
+  mfr_pcg_info pinf{};
+  MFR_TRY(pcg_run(c, u, b, dir, &po, &pinf));
+  inf.pcg_iters = pinf.iters;
+  inf.pcg_relres = pinf.relres;
+  inf.pcg_flag = pinf.flag;
+  // slope = grad J . s = -(b . s)
+  HIP_TRY(launch_dot(n3, b, dir, c->red_node, c->vec_blocks, c->stream));
+  HIP_TRY(launch_sum(c->red_node, c->vec_blocks, c->sc + SC_DOT, c->stream));
+  double h[SC_COUNT];
+  HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double slope = -h[SC_DOT];
+  inf.slope = slope;
+  double eta = 1.0;
+  for (int ls = 0; ls < o->armijo_max; ++ls) {
+    HIP_TRY(launch_axpy(n3, u, (float)eta, dir, trial, c->stream));
+    double Jn = 0.0;
+    MFR_TRY(enqueue_objective(c, trial));
+    mfr_status st = read_objective(c, &Jn, nullptr, nullptr);
+    inf.ls_trials = ls + 1;
+    if (st == MFR_OK && Jn <= Jv + o->armijo_c1 * eta * slope) {
+      inf.accepted = 1;
+      inf.eta = eta;
+      inf.J_after = Jn;
+      HIP_TRY(hipMemcpyAsync(u, trial, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      break;
+    }
+    eta *= 0.5;
+  }
+  if (out) *out = inf;
   return MFR_OK;
 }
 
@@ -566,6 +723,7 @@ mfr_status mfr_set_images(mfr_ctx* c, const float* R, const float* T) {
   c->R = R;
   c->tp.R = R;
   c->dp.t.R = R;
+  c->jp.t.R = R;
   c->have_images = true;
   return MFR_OK;
 }
@@ -600,7 +758,49 @@ mfr_status mfr_jacobi_diag(mfr_ctx* c, const float* u, float* diag) {
   MFR_TRY(need_images(c));
   MFR_TRY(check_ptr(u, "u"));
   MFR_TRY(check_ptr(diag, "diag"));
-  HIP_TRY(launch_jacobi_diag(c->dp, u, diag, c->stream));
+  HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
+  return MFR_OK;
+}
+
+mfr_status mfr_gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* info) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  if (!o) return fail(MFR_EINVAL, "opts is NULL");
+  if (o->pcg_max < 0 || !(o->pcg_rtol >= 0) || o->precond < 0 || o->precond > 1 ||
+      !(o->armijo_c1 >= 0 && o->armijo_c1 < 1) || o->armijo_max < 1)
+    return fail(MFR_EINVAL, "invalid Gauss-Newton options");
+  for (int k = 5; k < 8; ++k)
+    if (u == c->vec[k]) return fail(MFR_EINVAL, "u must not point into the context workspace");
+  return gn_step(c, u, o, info);
+}
+
+mfr_status mfr_profile_enable(mfr_ctx* c, int32_t enable) {
+  if (!c) return fail(MFR_EINVAL, "context is NULL");
+  c->prof_on = enable != 0;
+  return MFR_OK;
+}
+
+mfr_status mfr_profile_read(mfr_ctx* c, mfr_profile_stats* st, int32_t reset) {
+  if (!c) return fail(MFR_EINVAL, "context is NULL");
+  if (!st) return fail(MFR_EINVAL, "stats is NULL");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& p : c->prof_pending) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    c->prof_ms[p.first] += ms;
+    c->prof_launches[p.first] += 1;
+    c->prof_pool.push_back(p.second.first);
+    c->prof_pool.push_back(p.second.second);
+  }
+  c->prof_pending.clear();
+  for (int k = 0; k < 5; ++k) {
+    st->launches[k] = c->prof_launches[k];
+    st->ms[k] = c->prof_ms[k];
+    if (reset) {
+      c->prof_launches[k] = 0;
+      c->prof_ms[k] = 0.0;
+    }
+  }
   return MFR_OK;
 }
 
@@ -664,8 +864,7 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
     L[l].off_u = o;
     o = align_up(o + sizeof(float) * 3 * g.nbar);
   }
-  const Geo& c = L[levels - 1].geo;  // finest level: search direction + prolongation tables
-  o = align_up(o + sizeof(float) * 3 * c.nbar);
+  const Geo& c = L[levels - 1].geo;  // prolongation tables of the finest level
   o = align_up(o + sizeof(Conv1) * (c.n[0] + c.n[1] + c.n[2]));
   *out = L;
   *total = o;
@@ -718,12 +917,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     MFR_TRY(mfr_workspace_size(&L[l].grid, &b));
     ctx_ws = std::max(ctx_ws, b);
   }
-  size_t off_dir = 0;
-  {
-    const Level& lf = L[nl - 1];
-    off_dir = align_up(lf.off_u + sizeof(float) * 3 * lf.geo.nbar);
-  }
-  const size_t off_ptab = align_up(off_dir + sizeof(float) * 3 * gf.nbar);
+  const size_t off_ptab = align_up(L[nl - 1].off_u + sizeof(float) * 3 * gf.nbar);
 
   double Jfinal = 0.0;
   for (int l = 0; l < nl; ++l) {
@@ -754,46 +948,19 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
       ~Guard() { mfr_destroy(c); }
     } guard{c};
     MFR_TRY(mfr_set_images(c, at<float>(ws, L[l].off_R), at<float>(ws, L[l].off_T)));
-    float* grad = c->vec[5];
-    float* trial = c->vec[6];
-    float* dir = at<float>(ws, off_dir);
-    const int n3 = (int)(3 * g.nbar);
-    mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond};
+    mfr_gn_opts go{o->pcg_max, o->pcg_rtol, o->precond, o->armijo_c1, o->armijo_max};
     int gn_done = 0, pcg_tot = 0, status = 0;
     double Jv = 0.0;
     MFR_TRY(mfr_objective(c, ul, &Jv, nullptr, nullptr));
     for (int k = 0; k < o->gn_iters; ++k) {
-      // gradient (its J equals the objective at ul), PCG on -grad
-      MFR_TRY(enqueue_gradient(c, ul, grad));
-      HIP_TRY(launch_axpy(n3, grad, -2.0f, grad, grad, st));   // grad <- -grad
-      mfr_pcg_info info{};
-      MFR_TRY(pcg_run(c, ul, grad, dir, &po, &info));
-      pcg_tot += info.iters;
-      // slope = grad J . s = -(b . s) with b = -grad J
-      std::vector<float> hb(n3), hs(n3);
-      HIP_TRY(hipMemcpyAsync(hb.data(), grad, sizeof(float) * n3, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipMemcpyAsync(hs.data(), dir, sizeof(float) * n3, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      double slope = 0.0;
-      for (int i = 0; i < n3; ++i) slope -= (double)hb[i] * hs[i];
-      double eta = 1.0;
-      bool ok = false;
-      double Jn = 0.0;
-      for (int ls = 0; ls < o->armijo_max; ++ls) {
-        HIP_TRY(launch_axpy(n3, ul, (float)eta, dir, trial, st));
-        MFR_TRY(mfr_objective(c, trial, &Jn, nullptr, nullptr));
-        if (Jn <= Jv + o->armijo_c1 * eta * slope) {
-          ok = true;
-          break;
-        }
-        eta *= 0.5;
-      }
-      if (!ok) {
+      mfr_gn_info gi{};
+      MFR_TRY(gn_step(c, ul, &go, &gi));
+      pcg_tot += gi.pcg_iters;
+      if (!gi.accepted) {
         status = MFR_ELINESEARCH;
         break;
       }
-      HIP_TRY(hipMemcpyAsync(ul, trial, sizeof(float) * n3, hipMemcpyDeviceToDevice, st));
-      Jv = Jn;
+      Jv = gi.J_after;
       ++gn_done;
     }
     rep.gn_done[l] = gn_done;

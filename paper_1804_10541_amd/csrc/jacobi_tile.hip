@@ -1,0 +1,260 @@
+// Exact diagonal of the Gauss-Newton system, diag(H + alpha nabla^2 S), on
+// node blocks (the Jacobi preconditioner of the conjugate-gradient solve).
+//
+// With J = dr dT P (eq. NGF_discretized_hessian), the NGF part is
+//   diag_{(d,n)} = 2 hbar sum_l ( sum_{k in K} rho-hat_l(k) g_{l+k,d} W_n(l+k) )^2,
+// a sum over the rows l of dr (eq. dr, eq. hatRho) whose 7-point stencil
+// meets the support of node n; W_n is the trilinear conversion weight of the
+// node (eq. grid_conversion) and g the template derivative (eq. dT).
+//
+// Each work-group owns a block of node columns (nodes in x and y) and a range
+// of node planes, so every diagonal entry is written by exactly one group.  It
+// covers the voxel rows of that block plus a one-voxel halo with one thread
+// per voxel column, and marches through the voxel planes: per plane it
+// samples the template (T(P y) and g) and computes the rho-hat rows of its
+// voxels into LDS; then the threads assigned to each node column gather their
+// rows' squared stencil sums from LDS into per-node-plane accumulators, and a
+// node plane is reduced (fixed order) and written once no later voxel plane
+// can touch it.
+#include "tile_common.h"
+
+namespace mfr {
+
+template <int AX, int AY>
+__global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, const float* __restrict__ u,
+                                                             float* __restrict__ diag) {
+  constexpr int NT = AX * AY;
+  const TileParams& P = J.t;
+  __shared__ float sTw[2][NT];
+  __shared__ float sR[2][NT];
+  __shared__ float sG[3][3][NT];   // template derivative, 3 plane slots
+  __shared__ float sRho[7][NT];    // rho-hat rows: k = 0, -x, +x, -y, +y, -z, +z
+  __shared__ float sPart[3][NT];
+  __shared__ Conv1 sCx[AX], sCy[AY];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % AX, ty = tid / AX;
+  const int bid = xcd_block_id();
+  const int ib = bid % J.nbx;
+  const int rest = bid / J.nbx;
+  const int jb = rest % J.nby, kb = rest / J.nby;
+  const NodeBlock BX = J.bx[ib], BY = J.by[jb], BZ = J.bz[kb];
+  const int gx = BX.a0 + tx, gy = BY.a0 + ty;
+  const bool in_img = (gx >= 0) && (gx < P.mx) && (gy >= 0) && (gy < P.my);
+  const bool inB = (tx >= 1) && (tx < AX - 1) && (ty >= 1) && (ty < AY - 1);
+  if (tid < AX) sCx[tid] = P.cx[min(max(BX.a0 + tid, 0), P.mx - 1)];
+  if (tid < AY) sCy[tid] = P.cy[min(max(BY.a0 + tid, 0), P.my - 1)];
+
+  // own column for the template samples
+  const int cxi = min(max(gx, 0), P.mx - 1), cyi = min(max(gy, 0), P.my - 1);
+  const Conv1 cvx = P.cx[cxi], cvy = P.cy[cyi];
+  const Samp1 spx = P.sx[cxi], spy = P.sy[cyi];
+  const float wx0 = 1.0f - cvx.f, wx1 = cvx.f, wy0 = 1.0f - cvy.f, wy1 = cvy.f;
+  const int nodexy = cvy.n0 * P.nx + cvx.n0;
+  const int nxy = P.nx * P.ny;
+  const size_t plane = (size_t)P.mx * (size_t)P.my;
+  const int colxy = gy * P.mx + gx;
+
+  // node column of this thread for the gather
+  const int ncx = BX.hi - BX.lo + 1, ncy = BY.hi - BY.lo + 1, NC = ncx * ncy;
+  const int G = NT / NC;
+  const int jcol = tid % NC, kgrp = tid / NC;
+  const bool gathers = kgrp < G;
+  const int nxn = BX.lo + jcol % ncx, nyn = BY.lo + jcol / ncx;
+  const Range1 rxr = J.rx[nxn], ryr = J.ry[nyn];
+  const int rw = rxr.hi - rxr.lo + 1;
+  const int nrows = rw * (ryr.hi - ryr.lo + 1);
+
+  // acc[q] accumulates node plane kflush + q (kflush: lowest plane not yet written)
+  float acc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0f;
+  int kflush = BZ.lo;
+
+  auto flush = [&](int K) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      sPart[d][tid] = gathers ? acc[0][d] : 0.0f;
+      acc[0][d] = acc[1][d];
+      acc[1][d] = acc[2][d];
+      acc[2][d] = acc[3][d];
+      acc[3][d] = 0.0f;
+    }
+    __syncthreads();
+    if (tid < NC) {
+      const int i = BX.lo + tid % ncx, j = BY.lo + tid / ncx;
+      const int cxn = (i > 0) + (i < P.nx - 1), cyn = (j > 0) + (j < P.ny - 1), czn = (K > 0) + (K < P.nz - 1);
+      const float Lnn = -(cxn * J.ihy2x + cyn * J.ihy2y + czn * J.ihy2z);
+      const float LL = Lnn * Lnn + cxn * J.ihy2x * J.ihy2x + cyn * J.ihy2y * J.ihy2y + czn * J.ihy2z * J.ihy2z;
+      const size_t n = (size_t)K * nxy + (size_t)j * P.nx + i;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float s = 0.0f;
+        for (int k = 0; k < G; ++k) s += sPart[d][tid + k * NC];
+        diag[(size_t)d * P.nbar + n] = fmaf(J.s_ngf, s, J.s_curv * LL);
+      }
+    }
+    __syncthreads();
+  };
+
+  float Tw_p = 0.f, Tw_c = 0.f, Tw_n = 0.f, R_p = 0.f, R_c = 0.f, R_n = 0.f;
+  int Kp = -0x7fffffff;
+  float ulo[3] = {0.f, 0.f, 0.f}, uhi[3] = {0.f, 0.f, 0.f};
+  auto xy_interp = [&](int k, float (&o)[3]) {
+    const int i00 = k * nxy + nodexy;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float* b = u + (size_t)d * P.nbar + i00;
+      const float lo = fmaf(wx1, b[1], wx0 * b[0]);
+      const float hi = fmaf(wx1, b[P.nx + 1], wx0 * b[P.nx]);
+      o[d] = fmaf(wy1, hi, wy0 * lo);
+    }
+  };
+
+  const int zr0 = BZ.a0 + 1, zr1 = BZ.pad;   // voxel planes of the rows
+  for (int t = zr0 - 1; t <= zr1 + 1; ++t) {
+    // ---- A: template value and derivative at plane t ----
+    {
+      float Tv = 0.f, Rv = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+      if (t >= 0 && t < P.mz && in_img) {
+        const Conv1 cvz = P.cz[t];
+        if (cvz.n0 != Kp) {
+          if (cvz.n0 == Kp + 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ulo[d] = uhi[d];
+          } else {
+            xy_interp(cvz.n0, ulo);
+          }
+          xy_interp(cvz.n0 + 1, uhi);
+          Kp = cvz.n0;
+        }
+        const float fz = cvz.f;
+        float fx, fy, fzz;
+        const int kx = template_cell(spx, fmaf(fz, uhi[0] - ulo[0], ulo[0]), P.ihTx, fx);
+        const int ky = template_cell(spy, fmaf(fz, uhi[1] - ulo[1], ulo[1]), P.ihTy, fy);
+        const int kz = template_cell(P.sz[t], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, fzz);
+        const Tri s = sample_template(P, kx, ky, kz, fx, fy, fzz);
+        Tv = s.v;
+        g0 = s.gx;
+        g1 = s.gy;
+        g2 = s.gz;
+        Rv = P.R[(size_t)t * plane + colxy];
+      }
+      const int sl = t & 1, s3 = (t + 3) % 3;
+      sTw[sl][tid] = Tv;
+      sR[sl][tid] = Rv;
+      sG[s3][0][tid] = g0;
+      sG[s3][1][tid] = g1;
+      sG[s3][2][tid] = g2;
+      Tw_n = Tv;
+      R_n = Rv;
+    }
+    __syncthreads();
+
+    const int c = t - 1;
+    const bool row_plane = c >= zr0 && c <= zr1;
+    // ---- B: rho-hat rows at plane c ----
+    if (row_plane) {
+      float rh[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (inB && in_img) {
+        const int s1 = c & 1;
+        const float Tc = Tw_c, Rc = R_c;
+        const bool hxm = gx > 0, hxp = gx < P.mx - 1, hym = gy > 0, hyp = gy < P.my - 1;
+        const bool hzm = c > 0, hzp = c < P.mz - 1;
+        const float dT[6] = {(hxm ? sTw[s1][tid - 1] : Tc) - Tc, (hxp ? sTw[s1][tid + 1] : Tc) - Tc,
+                             (hym ? sTw[s1][tid - AX] : Tc) - Tc, (hyp ? sTw[s1][tid + AX] : Tc) - Tc,
+                             (hzm ? Tw_p : Tc) - Tc, (hzp ? Tw_n : Tc) - Tc};
+        const float dR[6] = {(hxm ? sR[s1][tid - 1] : Rc) - Rc, (hxp ? sR[s1][tid + 1] : Rc) - Rc,
+                             (hym ? sR[s1][tid - AX] : Rc) - Rc, (hyp ? sR[s1][tid + AX] : Rc) - Rc,
+                             (hzm ? R_p : Rc) - Rc, (hzp ? R_n : Rc) - Rc};
+        const float ih2[3] = {P.ih2x, P.ih2y, P.ih2z};
+        float sTT = 0.f, sRR = 0.f, sTR = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          sTT = fmaf(fmaf(dT[2 * a], dT[2 * a], dT[2 * a + 1] * dT[2 * a + 1]), ih2[a], sTT);
+          sRR = fmaf(fmaf(dR[2 * a], dR[2 * a], dR[2 * a + 1] * dR[2 * a + 1]), ih2[a], sRR);
+          sTR = fmaf(fmaf(dT[2 * a], dR[2 * a], dT[2 * a + 1] * dR[2 * a + 1]), ih2[a], sTR);
+        }
+        const float rnT = rsqrtf(fmaf(0.5f, sTT, P.tau2)), rnR = rsqrtf(fmaf(0.5f, sRR, P.rho2));
+        const float r1 = fmaf(0.5f, sTR, P.taurho);
+        const float c1 = rnT * rnR, c2 = r1 * rnT * rnT;
+        const float hh[3] = {P.hhx, P.hhy, P.hhz};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          rh[1 + k] = hh[k / 2] * c1 * fmaf(-c2, dT[k], dR[k]);
+          rh[0] -= rh[1 + k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 7; ++k) sRho[k][tid] = rh[k];
+    }
+    __syncthreads();
+
+    // ---- gather of the rows at plane c into the node planes they touch ----
+    if (row_plane) {
+      const bool hzm = c > 0, hzp = c < P.mz - 1;
+      const Conv1 czm = P.cz[max(c - 1, 0)], cz0 = P.cz[c], czp = P.cz[min(c + 1, P.mz - 1)];
+      float wz0[4], wzp[4], wzm[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int nz = kflush + q;
+        const bool ok = nz <= BZ.hi;
+        wz0[q] = ok ? conv_weight(cz0, nz) : 0.0f;
+        wzp[q] = (ok && hzp) ? conv_weight(czp, nz) : 0.0f;
+        wzm[q] = (ok && hzm) ? conv_weight(czm, nz) : 0.0f;
+      }
+      const int sc = (c + 3) % 3, sp = (c + 4) % 3, sm = (c + 2) % 3;
+      if (gathers) {
+        for (int r = kgrp; r < nrows; r += G) {
+          const int a = rxr.lo + r % rw, b = ryr.lo + r / rw;
+          const int la = a - BX.a0, lb = b - BY.a0;
+          const int li = lb * AX + la;
+          const float vx0 = conv_weight(sCx[la], nxn);
+          const float vxm = a > 0 ? conv_weight(sCx[la - 1], nxn) : 0.0f;
+          const float vxp = a < P.mx - 1 ? conv_weight(sCx[la + 1], nxn) : 0.0f;
+          const float vy0 = conv_weight(sCy[lb], nyn);
+          const float vym = b > 0 ? conv_weight(sCy[lb - 1], nyn) : 0.0f;
+          const float vyp = b < P.my - 1 ? conv_weight(sCy[lb + 1], nyn) : 0.0f;
+          const float w00 = vx0 * vy0;
+          const float al0 = sRho[0][li] * w00;
+          const float alxm = sRho[1][li] * vxm * vy0, alxp = sRho[2][li] * vxp * vy0;
+          const float alym = sRho[3][li] * vx0 * vym, alyp = sRho[4][li] * vx0 * vyp;
+          const float alzm = sRho[5][li] * w00, alzp = sRho[6][li] * w00;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const float* gc = sG[sc][d];
+            float pxy = al0 * gc[li];
+            pxy = fmaf(alxm, gc[li - 1], pxy);
+            pxy = fmaf(alxp, gc[li + 1], pxy);
+            pxy = fmaf(alym, gc[li - AX], pxy);
+            pxy = fmaf(alyp, gc[li + AX], pxy);
+            const float zp = alzp * sG[sp][d][li];
+            const float zm = alzm * sG[sm][d][li];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
+              acc[q][d] = fmaf(zz, zz, acc[q][d]);
+            }
+          }
+        }
+      }
+      // node planes below the window of the next row plane are complete
+      while (kflush <= BZ.hi && kflush < cz0.n0) flush(kflush++);
+    }
+
+    Tw_p = Tw_c;
+    Tw_c = Tw_n;
+    R_p = R_c;
+    R_c = R_n;
+    __syncthreads();
+  }
+  while (kflush <= BZ.hi) flush(kflush++);
+}
+
+hipError_t launch_jacobi_tile(const JacParams& j, const float* u, float* diag, hipStream_t st) {
+  const int blocks = j.nbx * j.nby * j.nbz;
+  hipLaunchKernelGGL((jacobi_tile_kernel<32, 32>), dim3(blocks), dim3(1024), 0, st, j, u, diag);
+  return hipGetLastError();
+}
+
+}  // namespace mfr

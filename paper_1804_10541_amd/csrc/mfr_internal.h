@@ -97,6 +97,26 @@ struct DiagParams {
   float ihy2x, ihy2y, ihy2z;
 };
 
+// A block of nodes along one axis for the Jacobi-diagonal kernel: node range
+// [lo, hi] and a0, the voxel index of the block's first column (x, y) or, for
+// z, one before its first voxel plane; for z, pad holds its last voxel plane.
+struct NodeBlock {
+  int lo, hi, a0, pad;
+};
+
+struct JacParams {
+  TileParams t;
+  const NodeBlock* bx;
+  const NodeBlock* by;
+  const NodeBlock* bz;
+  int nbx, nby, nbz;
+  const Range1* rx;   // per node index: voxel rows whose dr row touches the node's support
+  const Range1* ry;
+  float s_ngf;        // 2 hbar
+  float s_curv;       // 2 alpha hbar^y
+  float ihy2x, ihy2y, ihy2z;
+};
+
 // Tile shape of the voxel kernel: the work-group covers BX x BY columns; the
 // inner (BX-4) x (BY-4) are its output voxels, the rest a two-voxel halo.
 struct TileShape {
@@ -111,11 +131,13 @@ hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float
 hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st);
 hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, hipStream_t st);
 hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, hipStream_t st);
+hipError_t launch_jacobi_tile(const JacParams& j, const float* u, float* diag, hipStream_t st);
+constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi work-group
 
 // PCG vector kernels.  sc: device scalars (see PcgSlot).
 enum PcgSlot : int {
   SC_BB = 0, SC_RZ = 1, SC_PQ = 2, SC_RR = 3, SC_RZNEW = 4, SC_ALPHA = 5, SC_BETA = 6,
-  SC_D = 8, SC_S = 9, SC_J = 10, SC_COUNT = 16
+  SC_D = 8, SC_S = 9, SC_J = 10, SC_DOT = 11, SC_COUNT = 16
 };
 hipError_t launch_pcg_init(int n3, const float* b, const float* diag, float* s, float* r, float* z,
                            float* p, double* red, int blocks, hipStream_t st);
@@ -128,6 +150,8 @@ hipError_t launch_pcg_direction(int n3, const float* z, float* p, const double* 
                                 hipStream_t st);
 hipError_t launch_pcg_init_finish(const double* red, int nred, double* sc, hipStream_t st);
 
+// float64 partial sums of x . y, one per block (then launch_sum).
+hipError_t launch_dot(int n, const float* x, const float* y, double* red, int blocks, hipStream_t st);
 // y = x + eta * s (GN trial points / updates).
 hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* y, hipStream_t st);
 // Image restriction (2 x 2 x 2 mean, ceil(m/2) cells).

@@ -439,6 +439,21 @@ hipError_t launch_pcg_direction(int n3, const float* z, float* p, const double* 
   return hipGetLastError();
 }
 
+// partial sums of x . y per work-group
+__global__ __launch_bounds__(kVecBlock) void dot_kernel(int n, const float* __restrict__ x,
+                                                        const float* __restrict__ y, double* __restrict__ red) {
+  __shared__ double sred[kVecBlock / 64];
+  double a = 0.0;
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n; i += gridDim.x * kVecBlock) a += (double)x[i] * y[i];
+  const double s = block_sum<kVecBlock>(a, sred);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+hipError_t launch_dot(int n, const float* x, const float* y, double* red, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(dot_kernel, dim3(blocks), dim3(kVecBlock), 0, st, n, x, y, red);
+  return hipGetLastError();
+}
+
 __global__ void axpy_kernel(int n, const float* __restrict__ x, float eta, const float* __restrict__ s,
                             float* __restrict__ y) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)

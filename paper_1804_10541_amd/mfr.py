@@ -41,6 +41,17 @@ class CPcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double), ("flag", ctypes.c_int32)]
 
 
+class CGnOpts(ctypes.Structure):
+    _fields_ = [("pcg_max", ctypes.c_int32), ("pcg_rtol", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32)]
+
+
+class CGnInfo(ctypes.Structure):
+    _fields_ = [("J_before", ctypes.c_double), ("J_after", ctypes.c_double), ("eta", ctypes.c_double),
+                ("slope", ctypes.c_double), ("pcg_iters", ctypes.c_int32), ("pcg_relres", ctypes.c_double),
+                ("pcg_flag", ctypes.c_int32), ("accepted", ctypes.c_int32), ("ls_trials", ctypes.c_int32)]
+
+
 class CMlOpts(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32), ("pcg_max", ctypes.c_int32),
                 ("pcg_rtol", ctypes.c_double), ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32),
@@ -51,6 +62,12 @@ class CMlReport(ctypes.Structure):
     _fields_ = [("J_final", ctypes.c_double), ("gn_done", ctypes.c_int32 * 8), ("pcg_total", ctypes.c_int32 * 8),
                 ("status", ctypes.c_int32 * 8), ("seconds", ctypes.c_double)]
 
+
+class CProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int32 * 5), ("ms", ctypes.c_double * 5)]
+
+
+PROFILE_KERNELS = ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass")
 
 _lib = None
 
@@ -68,9 +85,12 @@ SIGNATURES = {
     "mfr_hess_vec": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mfr_jacobi_diag": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
+    "mfr_gn_step": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(CGnOpts), ctypes.POINTER(CGnInfo)]),
     "mfr_ml_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_register_multilevel": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CMlOpts), _VP, _VP, _SZ,
                                                _VP, _VP, _VP, ctypes.POINTER(CMlReport)]),
+    "mfr_profile_enable": (ctypes.c_int, [_VP, _I]),
+    "mfr_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(CProfile), _I]),
 }
 
 
@@ -210,6 +230,24 @@ class Context:
         _check(self.lib.mfr_jacobi_diag(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
                                         _dev_tensor(out, 3 * self.nbar, "diag", self.device)))
         return out
+
+    def gn_step(self, u, pcg_max=50, pcg_rtol=1e-3, precond=1, armijo_c1=1e-4, armijo_max=10):
+        """One Gauss-Newton step; u (device, float32) is updated in place."""
+        opts = CGnOpts(int(pcg_max), float(pcg_rtol), int(precond), float(armijo_c1), int(armijo_max))
+        info = CGnInfo()
+        _check(self.lib.mfr_gn_step(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device), ctypes.byref(opts),
+                                    ctypes.byref(info)))
+        return {f[0]: getattr(info, f[0]) for f in CGnInfo._fields_}
+
+    def profile(self, enable=True):
+        """Turn kernel timing (HIP events on this context's stream) on or off."""
+        _check(self.lib.mfr_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset=True):
+        """{kernel: (launches, total ms)} accumulated since the last reset."""
+        st = CProfile()
+        _check(self.lib.mfr_profile_read(self._h, ctypes.byref(st), 1 if reset else 0))
+        return {k: (st.launches[i], st.ms[i]) for i, k in enumerate(PROFILE_KERNELS)}
 
     def pcg_solve(self, u, b, max_iter=50, rtol=1e-3, precond=1, out=None):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
