@@ -128,10 +128,11 @@ def main():
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
 
     if args.copy_calibration:
+        # a plain streaming kernel of known size: 1 GiB read, 1 GiB written (torch's neg kernel)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

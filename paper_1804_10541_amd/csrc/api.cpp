@@ -83,8 +83,9 @@ mfr_status make_geo(const mfr_grid* g, Geo* o) {
   o->mbar = (size_t)o->m[0] * o->m[1] * o->m[2];
   o->nbar = (size_t)o->n[0] * o->n[1] * o->n[2];
   const size_t tpad = (size_t)(o->mT[0] + 4) * (o->mT[1] + 4) * (o->mT[2] + 4);
-  if (o->mbar >= (size_t)1 << 31 || 3 * o->nbar >= (size_t)1 << 31 || tpad >= (size_t)1 << 32)
-    return fail(MFR_EINVAL, "problem too large for 32-bit voxel / node indexing");
+  // kernels address images, the padded template and node vectors with 32-bit byte offsets
+  if (o->mbar >= (size_t)1 << 30 || 3 * o->nbar >= (size_t)1 << 30 || tpad >= (size_t)1 << 30)
+    return fail(MFR_EINVAL, "problem too large: images, padded template and node vectors must stay below 2^30 elements");
   return MFR_OK;
 }
 

@@ -111,34 +111,45 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
     }
   };
 
+  // stage-A inputs of the next plane, loaded one step ahead
+  bool nx_ok = false;
+  float nx_t[8];
+  float nx_fx = 0.f, nx_fy = 0.f, nx_fz = 0.f, nx_R = 0.f;
+  auto issue = [&](int tt) {
+    nx_ok = tt >= 0 && tt < P.mz && in_img;
+    if (!nx_ok) return;
+    const Conv1 cvz = P.cz[tt];
+    if (cvz.n0 != Kp) {
+      if (cvz.n0 == Kp + 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ulo[d] = uhi[d];
+      } else {
+        xy_interp(cvz.n0, ulo);
+      }
+      xy_interp(cvz.n0 + 1, uhi);
+      Kp = cvz.n0;
+    }
+    const float fz = cvz.f;
+    const int kx = template_cell(spx, fmaf(fz, uhi[0] - ulo[0], ulo[0]), P.ihTx, nx_fx);
+    const int ky = template_cell(spy, fmaf(fz, uhi[1] - ulo[1], ulo[1]), P.ihTy, nx_fy);
+    const int kz = template_cell(P.sz[tt], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, nx_fz);
+    template_corners(P, kx, ky, kz, nx_t);
+    nx_R = P.R[(size_t)tt * plane + colxy];
+  };
+
   const int zr0 = BZ.a0 + 1, zr1 = BZ.pad;   // voxel planes of the rows
+  issue(zr0 - 1);
   for (int t = zr0 - 1; t <= zr1 + 1; ++t) {
-    // ---- A: template value and derivative at plane t ----
+    // ---- A: template value and derivative at plane t (inputs prefetched) ----
     {
       float Tv = 0.f, Rv = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-      if (t >= 0 && t < P.mz && in_img) {
-        const Conv1 cvz = P.cz[t];
-        if (cvz.n0 != Kp) {
-          if (cvz.n0 == Kp + 1) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) ulo[d] = uhi[d];
-          } else {
-            xy_interp(cvz.n0, ulo);
-          }
-          xy_interp(cvz.n0 + 1, uhi);
-          Kp = cvz.n0;
-        }
-        const float fz = cvz.f;
-        float fx, fy, fzz;
-        const int kx = template_cell(spx, fmaf(fz, uhi[0] - ulo[0], ulo[0]), P.ihTx, fx);
-        const int ky = template_cell(spy, fmaf(fz, uhi[1] - ulo[1], ulo[1]), P.ihTy, fy);
-        const int kz = template_cell(P.sz[t], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, fzz);
-        const Tri s = sample_template(P, kx, ky, kz, fx, fy, fzz);
+      if (nx_ok) {
+        const Tri s = trilinear(P, nx_t, nx_fx, nx_fy, nx_fz);
         Tv = s.v;
         g0 = s.gx;
         g1 = s.gy;
         g2 = s.gz;
-        Rv = P.R[(size_t)t * plane + colxy];
+        Rv = nx_R;
       }
       const int sl = t & 1, s3 = (t + 3) % 3;
       sTw[sl][tid] = Tv;
@@ -149,7 +160,9 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
       Tw_n = Tv;
       R_n = Rv;
     }
-    __syncthreads();
+    if (t < zr1 + 1) issue(t + 1);
+    // No barrier here: stage B reads the plane t-1 slots written in the
+    // previous step; the gather below waits (barrier after B) for this step's writes.
 
     const int c = t - 1;
     const bool row_plane = c >= zr0 && c <= zr1;

@@ -21,11 +21,20 @@
 //         eq. drTdr / eq. hessMult as a gather over the rows of dr), v = g w,
 //         accumulated into the node planes of the transposed conversion P^T.
 //
+// Columns and planes outside the image sample the template at the clamped
+// position, so every neighbour read in stage B already holds the clamped
+// value of eq. boundary_conditions (differences across the border are 0).
+// The stage-A inputs of plane t+1 (template corners, reference value) are
+// loaded during step t.  The march is unrolled by three so the per-column
+// register windows (planes t, t-1, t-2) sit in fixed registers.
+//
 // P^T is a gather: each column accumulates its z contributions in registers;
 // when a node plane is complete the group reduces it over x and y in LDS and
 // writes the node block to its own slot of a partial buffer.  A node pass sums
 // the slots that overlap each node in a fixed order, so results are
 // deterministic and no atomics are used.  Nothing per voxel reaches HBM.
+#include <type_traits>
+
 #include "tile_common.h"
 
 namespace mfr {
@@ -39,6 +48,8 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
   constexpr int MAXNX = TX + 1, MAXNY = TY + 1;
   constexpr bool HV = (MODE == MODE_HV);
   constexpr bool NEED_C = (MODE != MODE_OBJ);
+  static_assert(MAXNX * TY <= NT && MAXNX * MAXNY <= NT, "flush mapping needs more threads");
+  static_assert(NT >= 64 + MAXNY, "node-range setup needs more threads");
 
   __shared__ float sTw[2][NT];
   __shared__ float sR[2][NT];
@@ -68,14 +79,16 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
   const bool inner = (tx >= 2) && (tx < BX - 2) && (ty >= 2) && (ty < BY - 2);
   const bool inC = inner && in_img;
 
+  // own column, clamped into the image
   const int cxi = min(max(gx, 0), P.mx - 1), cyi = min(max(gy, 0), P.my - 1);
   const Conv1 cvx = P.cx[cxi], cvy = P.cy[cyi];
   const Samp1 spx = P.sx[cxi], spy = P.sy[cyi];
   const float wx0 = 1.0f - cvx.f, wx1 = cvx.f, wy0 = 1.0f - cvy.f, wy1 = cvy.f;
-  const int nodexy = cvy.n0 * P.nx + cvx.n0;
-  const int nxy = P.nx * P.ny;
-  const size_t plane = (size_t)P.mx * (size_t)P.my;
-  const int colxy = gy * P.mx + gx;
+  const unsigned nxy = (unsigned)(P.nx * P.ny);
+  const unsigned nodexy = (unsigned)(cvy.n0 * P.nx + cvx.n0);
+  const unsigned plane = (unsigned)(P.mx * P.my);
+  const unsigned colxy = (unsigned)(cyi * P.mx + cxi);
+  const unsigned nb = (unsigned)P.nbar, nxu = (unsigned)P.nx;
 
   // Tile node origins and the column / row ranges of each local node.
   const int TXv = min(TX, P.mx - x0), TYv = min(TY, P.my - y0);
@@ -119,6 +132,7 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
 
   // Writes one node plane (local index kloc) of the transposed conversion:
   // reduce the per-column sums acc over x, then y, into the slot's node block.
+  const int fj = tid % MAXNX, fr = tid / MAXNX;   // flush roles (compile-time divisor)
   auto flush = [&](const float (&acc)[3], int kloc) {
     if (inner) {
       const int l = (ty - 2) * TX + (tx - 2);
@@ -127,42 +141,46 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
       sV[2][l] = acc[2];
     }
     __syncthreads();
-    for (int it = tid; it < nxl * TYv * 3; it += NT) {
-      const int j = it % nxl;
-      const int r = it / nxl;
-      const int ly = r % TYv, d = r / TYv;
-      const int jg = nox + j;
-      float s = 0.0f;
-      for (int l = sColLo[j]; l <= sColHi[j]; ++l) {
+    if (fj < nxl && fr < TYv) {   // x reduction: node column fj, voxel row fr
+      const int jg = nox + fj;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      for (int l = sColLo[fj]; l <= sColHi[fj]; ++l) {
         const Conv1 c = sCx[l];
         const float w = (c.n0 == jg) ? 1.0f - c.f : c.f;
-        s = fmaf(w, sV[d][ly * TX + l], s);
+        const int q = fr * TX + l;
+        s0 = fmaf(w, sV[0][q], s0);
+        s1 = fmaf(w, sV[1][q], s1);
+        s2 = fmaf(w, sV[2][q], s2);
       }
-      sW[d][ly * MAXNX + j] = s;
+      sW[0][fr * MAXNX + fj] = s0;
+      sW[1][fr * MAXNX + fj] = s1;
+      sW[2][fr * MAXNX + fj] = s2;
     }
     __syncthreads();
-    for (int it = tid; it < nxl * nyl * 3; it += NT) {
-      const int j = it % nxl;
-      const int r = it / nxl;
-      const int i = r % nyl, d = r / nyl;
-      const int ig = noy + i;
-      float s = 0.0f;
-      for (int l = sRowLo[i]; l <= sRowHi[i]; ++l) {
+    if (fj < nxl && fr < nyl) {   // y reduction: node (fj, fr)
+      const int ig = noy + fr;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      for (int l = sRowLo[fr]; l <= sRowHi[fr]; ++l) {
         const Conv1 c = sCy[l];
         const float w = (c.n0 == ig) ? 1.0f - c.f : c.f;
-        s = fmaf(w, sW[d][l * MAXNX + j], s);
+        const int q = l * MAXNX + fj;
+        s0 = fmaf(w, sW[0][q], s0);
+        s1 = fmaf(w, sW[1][q], s1);
+        s2 = fmaf(w, sW[2][q], s2);
       }
-      part[(((size_t)d * P.nzt + kloc) * P.nyt + i) * P.nxt + j] = s;
+      const size_t o = ((size_t)kloc * P.nyt + fr) * P.nxt + fj;
+      const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
+      part[o] = s0;
+      part[o + dstride] = s1;
+      part[o + 2 * dstride] = s2;
     }
     __syncthreads();
   };
 
-  // Register state of the own column.
-  float Tw_p = 0.f, Tw_c = 0.f, Tw_n = 0.f;   // T(P y) at planes t-2, t-1, t
-  float R_p = 0.f, R_c = 0.f, R_n = 0.f;
-  float a_p = 0.f, a_c = 0.f, a_n = 0.f;      // g . P p (Hessian only)
-  float g_p[3] = {0.f, 0.f, 0.f}, g_c[3] = {0.f, 0.f, 0.f}, g_n[3] = {0.f, 0.f, 0.f};
-  float e0_prev = 0.f, ezp_p = 0.f, ezp_pp = 0.f;
+  // Register windows of the own column; slot (t - tfirst) mod 3.
+  float Tw[3] = {0.f, 0.f, 0.f}, Rv[3] = {0.f, 0.f, 0.f}, av[3] = {0.f, 0.f, 0.f};
+  float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  float e0[3] = {0.f, 0.f, 0.f}, ezp[3] = {0.f, 0.f, 0.f};
   float acc_lo[3] = {0.f, 0.f, 0.f}, acc_hi[3] = {0.f, 0.f, 0.f};
   int KL = noz;
   double obj = 0.0;
@@ -172,95 +190,92 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
   float ulo[3] = {0.f, 0.f, 0.f}, uhi[3] = {0.f, 0.f, 0.f};
   float plo[3] = {0.f, 0.f, 0.f}, phi[3] = {0.f, 0.f, 0.f};
   auto xy_interp = [&](const float* __restrict__ f, int k, float (&o)[3]) {
-    const int i00 = k * nxy + nodexy;
+    const unsigned i00 = (unsigned)k * nxy + nodexy;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float* b = f + (size_t)d * P.nbar + i00;
-      const float lo = fmaf(wx1, b[1], wx0 * b[0]);
-      const float hi = fmaf(wx1, b[P.nx + 1], wx0 * b[P.nx]);
+      const unsigned b = (unsigned)d * nb + i00;
+      const float lo = fmaf(wx1, ld32(f, b + 1), wx0 * ld32(f, b));
+      const float hi = fmaf(wx1, ld32(f, b + nxu + 1), wx0 * ld32(f, b + nxu));
       o[d] = fmaf(wy1, hi, wy0 * lo);
     }
   };
 
+  // Stage A inputs of the next plane, loaded one step ahead.
+  float nx_t[8];
+  float nx_fx = 0.f, nx_fy = 0.f, nx_fz = 0.f, nx_R = 0.f;
+  float nx_pp[3] = {0.f, 0.f, 0.f};
+  auto issue = [&](int tt) {
+    const int tc = min(max(tt, 0), P.mz - 1);
+    const Conv1 cvz = P.cz[tc];
+    if (cvz.n0 != Kp) {
+      if (cvz.n0 == Kp + 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          ulo[d] = uhi[d];
+          if (HV) plo[d] = phi[d];
+        }
+      } else {
+        xy_interp(u, cvz.n0, ulo);
+        if (HV) xy_interp(pv, cvz.n0, plo);
+      }
+      xy_interp(u, cvz.n0 + 1, uhi);
+      if (HV) xy_interp(pv, cvz.n0 + 1, phi);
+      Kp = cvz.n0;
+    }
+    const float fz = cvz.f;
+    const int kx = template_cell(spx, fmaf(fz, uhi[0] - ulo[0], ulo[0]), P.ihTx, nx_fx);
+    const int ky = template_cell(spy, fmaf(fz, uhi[1] - ulo[1], ulo[1]), P.ihTy, nx_fy);
+    const int kz = template_cell(P.sz[tc], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, nx_fz);
+    template_corners32(P, kx, ky, kz, nx_t);
+    nx_R = ld32(P.R, (unsigned)tc * plane + colxy);
+    if (HV) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) nx_pp[d] = fmaf(fz, phi[d] - plo[d], plo[d]);
+    }
+  };
+
   const int tfirst = zb - 2, tlast = ze + 1;
-  for (int t = tfirst; t <= tlast; ++t) {
+
+  auto step = [&](auto Kc, int t) {
+    constexpr int K = decltype(Kc)::value;   // slot of plane t
+    constexpr int K1 = (K + 2) % 3;          // slot of plane t-1
+    constexpr int K2 = (K + 1) % 3;          // slot of plane t-2
+
     // ---------------- stage A: plane t ----------------
     {
-      float Tv = 0.f, Rv = 0.f, av = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-      if (t >= 0 && t < P.mz && in_img) {
-        const Conv1 cvz = P.cz[t];
-        if (cvz.n0 != Kp) {
-          if (cvz.n0 == Kp + 1) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              ulo[d] = uhi[d];
-              if (HV) plo[d] = phi[d];
-            }
-          } else {
-            xy_interp(u, cvz.n0, ulo);
-            if (HV) xy_interp(pv, cvz.n0, plo);
-          }
-          xy_interp(u, cvz.n0 + 1, uhi);
-          if (HV) xy_interp(pv, cvz.n0 + 1, phi);
-          Kp = cvz.n0;
-        }
-        const float fz = cvz.f;
-        const float dux = fmaf(fz, uhi[0] - ulo[0], ulo[0]);
-        const float duy = fmaf(fz, uhi[1] - ulo[1], ulo[1]);
-        const float duz = fmaf(fz, uhi[2] - ulo[2], ulo[2]);
-        const Samp1 spz = P.sz[t];
-        float fx, fy, fz2;
-        const int kx = template_cell(spx, dux, P.ihTx, fx);
-        const int ky = template_cell(spy, duy, P.ihTy, fy);
-        const int kz = template_cell(spz, duz, P.ihTz, fz2);
-        const Tri s = sample_template(P, kx, ky, kz, fx, fy, fz2);
-        Tv = s.v;
-        g0 = s.gx;
-        g1 = s.gy;
-        g2 = s.gz;
-        Rv = P.R[(size_t)t * plane + colxy];
-        if (HV) {
-          const float ppx = fmaf(fz, phi[0] - plo[0], plo[0]);
-          const float ppy = fmaf(fz, phi[1] - plo[1], plo[1]);
-          const float ppz = fmaf(fz, phi[2] - plo[2], plo[2]);
-          av = fmaf(g0, ppx, fmaf(g1, ppy, g2 * ppz));
-        }
-      }
+      const Tri s = trilinear(P, nx_t, nx_fx, nx_fy, nx_fz);
+      Tw[K] = s.v;
+      g[K][0] = s.gx;
+      g[K][1] = s.gy;
+      g[K][2] = s.gz;
+      Rv[K] = nx_R;
+      if (HV) av[K] = fmaf(s.gx, nx_pp[0], fmaf(s.gy, nx_pp[1], s.gz * nx_pp[2]));
       const int sl = t & 1;
-      sTw[sl][tid] = Tv;
-      sR[sl][tid] = Rv;
-      if (HV) sA[sl][tid] = av;
-      Tw_n = Tv;
-      R_n = Rv;
-      a_n = av;
-      g_n[0] = g0;
-      g_n[1] = g1;
-      g_n[2] = g2;
+      sTw[sl][tid] = Tw[K];
+      sR[sl][tid] = Rv[K];
+      if (HV) sA[sl][tid] = av[K];
     }
-    __syncthreads();
+    if (t < tlast) issue(t + 1);
+    // No barrier here: stage B reads only LDS slots of plane t-1 (written in the
+    // previous step) and the slots written above were last read before the
+    // barrier that ends the previous step.
 
     // ---------------- stage B: plane zc = t-1 ----------------
     const int zc = t - 1;
-    float e0_new = 0.f, ezp_new = 0.f, ezm_new = 0.f;
+    float ezm = 0.f;
+    e0[K1] = 0.f;
+    ezp[K1] = 0.f;
     if (zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
       const int s1 = zc & 1;
       float ex_p = 0.f, ex_m = 0.f, ey_p = 0.f, ey_m = 0.f;
       if (inB && in_img) {
-        const float Tc = Tw_c, Rc = R_c;
-        const bool hxm = gx > 0, hxp = gx < P.mx - 1, hym = gy > 0, hyp = gy < P.my - 1;
-        const bool hzm = zc > 0, hzp = zc < P.mz - 1;
-        const float dTxm = (hxm ? sTw[s1][tid - 1] : Tc) - Tc;
-        const float dTxp = (hxp ? sTw[s1][tid + 1] : Tc) - Tc;
-        const float dTym = (hym ? sTw[s1][tid - BX] : Tc) - Tc;
-        const float dTyp = (hyp ? sTw[s1][tid + BX] : Tc) - Tc;
-        const float dTzm = (hzm ? Tw_p : Tc) - Tc;
-        const float dTzp = (hzp ? Tw_n : Tc) - Tc;
-        const float dRxm = (hxm ? sR[s1][tid - 1] : Rc) - Rc;
-        const float dRxp = (hxp ? sR[s1][tid + 1] : Rc) - Rc;
-        const float dRym = (hym ? sR[s1][tid - BX] : Rc) - Rc;
-        const float dRyp = (hyp ? sR[s1][tid + BX] : Rc) - Rc;
-        const float dRzm = (hzm ? R_p : Rc) - Rc;
-        const float dRzp = (hzp ? R_n : Rc) - Rc;
+        const float Tc = Tw[K1], Rc = Rv[K1];
+        const float dTxm = sTw[s1][tid - 1] - Tc, dTxp = sTw[s1][tid + 1] - Tc;
+        const float dTym = sTw[s1][tid - BX] - Tc, dTyp = sTw[s1][tid + BX] - Tc;
+        const float dTzm = Tw[K2] - Tc, dTzp = Tw[K] - Tc;
+        const float dRxm = sR[s1][tid - 1] - Rc, dRxp = sR[s1][tid + 1] - Rc;
+        const float dRym = sR[s1][tid - BX] - Rc, dRyp = sR[s1][tid + BX] - Rc;
+        const float dRzm = Rv[K2] - Rc, dRzp = Rv[K] - Rc;
         const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x,
                                fmaf(fmaf(dTym, dTym, dTyp * dTyp), P.ih2y,
                                     fmaf(dTzm, dTzm, dTzp * dTzp) * P.ih2z));
@@ -277,7 +292,7 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
         const float c1 = rnT * rnR;
         const float r = r1 * c1;
         if (MODE != MODE_HV && inner && zc >= zb && zc < ze) obj += (double)fmaf(-r, r, 1.0f);
-        if (NEED_C) {
+        if constexpr (NEED_C) {
           const float c2 = r1 * rnT * rnT;
           const float kx = P.hhx * c1, ky = P.hhy * c1, kz = P.hhz * c1;
           const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
@@ -285,14 +300,14 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
           const float rzm = kz * fmaf(-c2, dTzm, dRzm), rzp = kz * fmaf(-c2, dTzp, dRzp);
           const float r0 = -(((rxm + rxp) + (rym + ryp)) + (rzm + rzp));
           float zl;
-          if (HV) {
-            zl = r0 * a_c;
+          if constexpr (HV) {
+            zl = r0 * av[K1];
             zl = fmaf(rxm, sA[s1][tid - 1], zl);
             zl = fmaf(rxp, sA[s1][tid + 1], zl);
             zl = fmaf(rym, sA[s1][tid - BX], zl);
             zl = fmaf(ryp, sA[s1][tid + BX], zl);
-            zl = fmaf(rzm, a_p, zl);
-            zl = fmaf(rzp, a_n, zl);
+            zl = fmaf(rzm, av[K2], zl);
+            zl = fmaf(rzp, av[K], zl);
           } else {
             zl = r;
           }
@@ -300,12 +315,12 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
           ex_m = rxm * zl;
           ey_p = ryp * zl;
           ey_m = rym * zl;
-          ezp_new = rzp * zl;
-          ezm_new = rzm * zl;
-          e0_new = r0 * zl;
+          ezp[K1] = rzp * zl;
+          ezm = rzm * zl;
+          e0[K1] = r0 * zl;
         }
       }
-      if (NEED_C) {
+      if constexpr (NEED_C) {
         sE[s1][0][tid] = ex_p;
         sE[s1][1][tid] = ex_m;
         sE[s1][2][tid] = ey_p;
@@ -329,40 +344,31 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
         }
         if (inC) {
           const int s2 = c & 1;
-          float w = e0_prev;
+          float w = e0[K2];
           w += sE[s2][1][tid + 1];
           w += sE[s2][0][tid - 1];
           w += sE[s2][3][tid + BX];
           w += sE[s2][2][tid - BX];
-          w += ezm_new;
-          w += ezp_pp;
+          w += ezm;
+          w += ezp[K];
           const float wz1 = cvz.f, wz0 = 1.0f - cvz.f;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const float v = g_p[d] * w;
+            const float v = g[K2][d] * w;
             acc_lo[d] = fmaf(wz0, v, acc_lo[d]);
             acc_hi[d] = fmaf(wz1, v, acc_hi[d]);
           }
         }
       }
     }
-
-    // rotate the register windows
-    Tw_p = Tw_c;
-    Tw_c = Tw_n;
-    R_p = R_c;
-    R_c = R_n;
-    a_p = a_c;
-    a_c = a_n;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      g_p[d] = g_c[d];
-      g_c[d] = g_n[d];
-    }
-    e0_prev = e0_new;
-    ezp_pp = ezp_p;
-    ezp_p = ezp_new;
     __syncthreads();
+  };
+
+  issue(tfirst);
+  for (int t = tfirst; t <= tlast; t += 3) {
+    step(std::integral_constant<int, 0>{}, t);
+    if (t + 1 <= tlast) step(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 <= tlast) step(std::integral_constant<int, 2>{}, t + 2);
   }
 
   if constexpr (NEED_C) {

@@ -36,22 +36,32 @@ struct Tri {
   float v, gx, gy, gz;
 };
 
-// Trilinear sample of the zero-bordered template and its exact derivative.
-// (kx, ky, kz) is the lower corner in template cells, (fx, fy, fz) the
-// fractions; indices are clamped to [-2, mT] which only ever maps fully
-// outside samples onto the zero border (value and derivative stay 0).
-__device__ __forceinline__ Tri sample_template(const TileParams& P, int kx, int ky, int kz, float fx,
-                                               float fy, float fz) {
+// Loads the 8 corner samples of the zero-bordered template for the cell with
+// lower corner (kx, ky, kz) (template cells).  Indices are clamped to [-2, mT],
+// which only ever maps fully outside samples onto the zero border, so value
+// and derivative stay exactly 0 there (the Dirichlet extension).
+__device__ __forceinline__ void template_corners(const TileParams& P, int kx, int ky, int kz, float (&t)[8]) {
   kx = min(max(kx, -2), P.mTx);
   ky = min(max(ky, -2), P.mTy);
   kz = min(max(kz, -2), P.mTz);
   const float* b0 = P.Tp + (size_t)(kz + 2) * (size_t)P.PXY + (size_t)((ky + 2) * P.PX + (kx + 2));
   const float* b1 = b0 + P.PXY;
-  const float t000 = b0[0], t100 = b0[1], t010 = b0[P.PX], t110 = b0[P.PX + 1];
-  const float t001 = b1[0], t101 = b1[1], t011 = b1[P.PX], t111 = b1[P.PX + 1];
-  const float d00 = t100 - t000, d10 = t110 - t010, d01 = t101 - t001, d11 = t111 - t011;
-  const float e00 = fmaf(fx, d00, t000), e10 = fmaf(fx, d10, t010);
-  const float e01 = fmaf(fx, d01, t001), e11 = fmaf(fx, d11, t011);
+  t[0] = b0[0];
+  t[1] = b0[1];
+  t[2] = b0[P.PX];
+  t[3] = b0[P.PX + 1];
+  t[4] = b1[0];
+  t[5] = b1[1];
+  t[6] = b1[P.PX];
+  t[7] = b1[P.PX + 1];
+}
+
+// Trilinear value and exact derivative from the 8 corners (x fastest) and
+// the fractions (fx, fy, fz); the derivative is scaled by 1/hT.
+__device__ __forceinline__ Tri trilinear(const TileParams& P, const float (&t)[8], float fx, float fy, float fz) {
+  const float d00 = t[1] - t[0], d10 = t[3] - t[2], d01 = t[5] - t[4], d11 = t[7] - t[6];
+  const float e00 = fmaf(fx, d00, t[0]), e10 = fmaf(fx, d10, t[2]);
+  const float e01 = fmaf(fx, d01, t[4]), e11 = fmaf(fx, d11, t[6]);
   const float dy0 = e10 - e00, dy1 = e11 - e01;
   const float f0 = fmaf(fy, dy0, e00), f1 = fmaf(fy, dy1, e01);
   const float dxa = fmaf(fy, d10 - d00, d00), dxb = fmaf(fy, d11 - d01, d01);
@@ -63,6 +73,36 @@ __device__ __forceinline__ Tri sample_template(const TileParams& P, int kx, int 
   return o;
 }
 
+// Loads of a float at a 32-bit byte offset from a uniform base pointer (the
+// library limits images and node vectors to < 2^32 bytes, checked on the host).
+__device__ __forceinline__ float ld32(const float* __restrict__ base, unsigned idx) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (idx << 2));
+}
+
+// template_corners with 32-bit offsets.
+__device__ __forceinline__ void template_corners32(const TileParams& P, int kx, int ky, int kz, float (&t)[8]) {
+  kx = min(max(kx, -2), P.mTx);
+  ky = min(max(ky, -2), P.mTy);
+  kz = min(max(kz, -2), P.mTz);
+  const unsigned PX = (unsigned)P.PX, PXY = (unsigned)P.PXY;
+  const unsigned i0 = (unsigned)(kz + 2) * PXY + (unsigned)__mul24(ky + 2, (int)PX) + (unsigned)(kx + 2);
+  const unsigned i1 = i0 + PXY;
+  t[0] = ld32(P.Tp, i0);
+  t[1] = ld32(P.Tp, i0 + 1);
+  t[2] = ld32(P.Tp, i0 + PX);
+  t[3] = ld32(P.Tp, i0 + PX + 1);
+  t[4] = ld32(P.Tp, i1);
+  t[5] = ld32(P.Tp, i1 + 1);
+  t[6] = ld32(P.Tp, i1 + PX);
+  t[7] = ld32(P.Tp, i1 + PX + 1);
+}
+
+__device__ __forceinline__ Tri sample_template(const TileParams& P, int kx, int ky, int kz, float fx, float fy,
+                                               float fz) {
+  float t[8];
+  template_corners(P, kx, ky, kz, t);
+  return trilinear(P, t, fx, fy, fz);
+}
 
 // Template coordinate along one axis for voxel-table entry s and displacement d:
 // returns the lower template cell and writes the fraction.
