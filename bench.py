@@ -56,6 +56,63 @@ def workload_spec(name):
     raise ValueError(name)
 
 
+def c4_specs():
+    """Ten CT-like pairs of uneven sizes (256^2 and 512^2 in-plane, 94-136
+    slices), quarter-resolution deformation grids ceil(m/4) + 1."""
+    from synth import GridSpec, config_c4_sizes, quarter_nodes
+
+    return [GridSpec(m=s, h=(1.0, 1.0, 1.0), my=quarter_nodes(s), tau=50.0, rho=50.0, alpha=0.1)
+            for s in config_c4_sizes()]
+
+
+def batch_leg(dev, tune):
+    """Multilevel registration of the ten uneven pairs: the batched path (one
+    persistent launch per phase for all pairs, CG iterations replayed from
+    captured HIP graphs) against per-pair runs of the single-pair path, and a
+    check that both return the same displacements bit for bit."""
+    import torch
+
+    from paper_1804_10541_amd import autotune, mfr
+    from synth import ct_pair
+
+    specs = c4_specs()
+    pairs = [ct_pair(k, s.m, device=dev)[:2] for k, s in enumerate(specs)]
+    torch.cuda.synchronize()
+    big = max(range(len(specs)), key=lambda k: specs[k].voxels)
+    cfg = None
+    if tune:
+        ub = torch.zeros((3,) + tuple(reversed(specs[big].my)), dtype=torch.float32, device=dev)
+        cfg = autotune.apply(specs[big], pairs[big][0], pairs[big][1], ub, device=dev)
+    opts = dict(gn_iters=10, pcg_max=50, pcg_rtol=1e-3, precond=1)
+    b = mfr.Batch(specs, levels=3, device=dev)
+    b.set_images([p[0] for p in pairs], [p[1] for p in pairs])
+    b.register(use_graph=True, gn_iters=1, pcg_max=8, pcg_rtol=1e-3, precond=1)   # warm-up and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ub_list, rep = b.register(use_graph=True, **opts)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"[bench] batched: {t_batch:.3f} s, gn {rep['gn_done']}, pcg {rep['pcg_total']}, "
+        f"graph replays {rep['graph_launches']}")
+    for k, s in enumerate(specs[:1]):   # warm-up of the single-pair path
+        mfr.register_multilevel(s, pairs[k][0], pairs[k][1], levels=3, gn_iters=1, pcg_max=8, pcg_rtol=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [mfr.register_multilevel(s, pairs[k][0], pairs[k][1], levels=3, **opts) for k, s in enumerate(specs)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = all(torch.equal(seq[k][0], ub_list[k]) for k in range(len(specs)))
+    log(f"[bench] sequential: {t_seq:.3f} s; identical displacements: {same}")
+    b.close()
+    vox = sum(s.voxels for s in specs)
+    return {"workload": f"{len(specs)} CT-like pairs, " + ", ".join("x".join(map(str, s.m)) for s in specs)
+                        + "; 3 levels, 10 Gauss-Newton steps per level, Jacobi-PCG <= 50 at rtol 1e-3",
+            "pairs": len(specs), "voxels": vox, "nodes": sum(s.nodes for s in specs),
+            "batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4), "speedup": round(t_seq / t_batch, 3),
+            "graph_replays": rep["graph_launches"], "gn_steps": rep["gn_done"], "pcg_iters": rep["pcg_total"],
+            "identical_to_sequential": bool(same), "tile_config": cfg}
+
+
 def cpu_baseline(R, T, u0, spec, budget_s=25.0):
     """The float64 oracle, as it stands, on a crop of the same volume: one
     Gauss-Newton step's derivative work (objective, gradient, Jacobi diagonal,
@@ -105,6 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=["c3", "c3-half", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ten-pair batched registration leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -136,6 +195,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    tile_cfg = None
+    if not args.no_autotune:
+        from paper_1804_10541_amd import autotune
+
+        tile_cfg = autotune.apply(spec, R, T, u0, device=dev)
+        log(f"[bench] tile configuration {tile_cfg}")
     ctx = mfr.Context(spec, dev)
     ctx.set_images(R, T)
     u = u0.clone()
@@ -199,7 +264,12 @@ def main():
         "kernel_ms": {k: (v[0], round(v[1] / max(v[0], 1), 4)) for k, v in prof.items()},
         "peak_device_bytes": int(peak_mem),
         "workspace_bytes": int(ctx.ws_bytes),
+        "tile_config": tile_cfg,
     }
+    del ctx, R, T
+    if not args.no_batch and args.workload != "small":
+        log("[bench] ten-pair batched registration")
+        out["batch"] = batch_leg(dev, not args.no_autotune)
     if not args.no_cpu_baseline:
         log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(R, T, u0, spec)

@@ -191,6 +191,68 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* op
                                    void* workspace, size_t ws_bytes, const float* R, const float* T,
                                    float* u, mfr_ml_report* report);
 
+/* ---- Batched registration of independent pairs ------------------------------
+ * Up to MFR_MAX_BATCH image pairs of different sizes advance together: every
+ * phase (voxel-tile kernels, node passes, sums, CG vector updates) is one
+ * launch for all pairs; the voxel-tile kernels are persistent (work-groups take
+ * tiles of any pair from a shared device counter).  The CG iteration is steered
+ * on the device (per-pair convergence flags), so a block of iterations is
+ * captured once into a HIP graph and replayed.  Results equal running each pair
+ * alone through mfr_register_multilevel, bit for bit.  This is an extension of
+ * the paper's single-pair method (Sec. 2.3) for throughput; it is not in the
+ * paper. */
+#define MFR_MAX_BATCH 12
+
+typedef struct mfr_batch mfr_batch;   /* opaque host-side batch context */
+
+typedef struct {
+  double J_final[MFR_MAX_BATCH];     /* objective at the returned u (finest level)         */
+  int32_t gn_done[MFR_MAX_BATCH];    /* accepted Gauss-Newton steps, all levels            */
+  int32_t pcg_total[MFR_MAX_BATCH];  /* CG iterations, all levels                           */
+  int32_t status[MFR_MAX_BATCH];     /* 0, or MFR_ELINESEARCH if a level stopped early     */
+  int32_t graph_launches;            /* replays of captured CG graphs                      */
+  double seconds;                    /* wall time of the call                              */
+} mfr_batch_report;
+
+/* Device workspace for `n` pairs (grids[i]: finest grid of pair i) with
+ * `levels` pyramid levels each. */
+mfr_status mfr_batch_workspace_size(int32_t n, const mfr_grid* grids, int32_t levels, size_t* bytes);
+
+/* Create a batch bound to `hip_stream` and a caller-owned workspace. */
+mfr_status mfr_batch_create(int32_t n, const mfr_grid* grids, int32_t levels, void* hip_stream,
+                            void* workspace, size_t ws_bytes, mfr_batch** out);
+void mfr_batch_destroy(mfr_batch* b);
+
+/* Bind the images of every pair (host arrays of n device pointers) and build
+ * the image pyramids in the workspace. */
+mfr_status mfr_batch_set_images(mfr_batch* b, const float* const* R, const float* const* T);
+
+/* q_i = (H_i + alpha nabla^2 S_i) p_i at u_i on the finest grids, every pair in
+ * one persistent launch (host arrays of n device pointers).  Asynchronous. */
+mfr_status mfr_batch_hess_vec(mfr_batch* b, const float* const* u, const float* const* p, float* const* q);
+
+/* Coarse-to-fine Gauss-Newton registration of every pair (options as in
+ * mfr_register_multilevel; opts->levels must equal the batch's levels).
+ * use_graph != 0 replays the CG iterations from captured HIP graphs.
+ * u: host array of n device pointers to the finest displacements (output).
+ * Synchronises the stream. */
+mfr_status mfr_batch_register(mfr_batch* b, const mfr_ml_opts* opts, int32_t use_graph, float* const* u,
+                              mfr_batch_report* report);
+
+/* ---- Tile configuration ---------------------------------------------------------
+ * Shape of the voxel-tile work-groups (bx x by threads: 32x16, 64x8, 32x32 or
+ * 64x16), the number of z planes per group (chunk_len; 0 = derived from
+ * target_groups) and the number of work-groups the derived split aims for
+ * (target_groups; 0 = 2048), for contexts and batches created afterwards in
+ * this process.  Returns MFR_EINVAL for an unsupported shape or a negative
+ * count.  The tile autotuner sets it from measured timings. */
+typedef struct {
+  int32_t bx, by, chunk_len, target_groups;
+} mfr_tile_config;
+
+mfr_status mfr_set_tile_config(const mfr_tile_config* cfg);
+mfr_status mfr_get_tile_config(mfr_tile_config* cfg);
+
 /* Kernel timing for measurement.  While enabled, the library records a pair
  * of HIP events on the context's stream around every launch of its main
  * kernels; mfr_profile_read synchronises the stream and returns the launch

@@ -14,11 +14,11 @@
 #include <vector>
 
 #include "../../include/mfr.h"
-#include "mfr_internal.h"
+#include "ctx_internal.h"
 
 using namespace mfr;
 
-namespace {
+namespace mfr {
 
 thread_local std::string g_err;
 
@@ -32,29 +32,8 @@ mfr_status fail(mfr_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess) return fail(MFR_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
-  } while (0)
 
-#define MFR_TRY(expr)                \
-  do {                               \
-    mfr_status s_ = (expr);          \
-    if (s_ != MFR_OK) return s_;     \
-  } while (0)
 
-size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
-
-// Derived, validated problem description.
-struct Geo {
-  int m[3], n[3], mT[3];
-  double h[3], hT[3], hy[3];
-  double tau, rho, alpha;
-  size_t mbar, nbar;
-  double hbar() const { return h[0] * h[1] * h[2]; }
-  double hybar() const { return hy[0] * hy[1] * hy[2]; }
-};
 
 mfr_status make_geo(const mfr_grid* g, Geo* o) {
   if (!g) return fail(MFR_EINVAL, "grid is NULL");
@@ -170,29 +149,40 @@ std::vector<NodeBlock> node_blocks_z(const std::vector<Range1>& rows, int per) {
 }
 
 // ---- tiling -----------------------------------------------------------------
-struct Tiling {
-  TileShape shape;
-  int tiles_x, tiles_y, chunks, chunk_len;
-  int nxt, nyt, nzt;
-  int grid() const { return tiles_x * tiles_y * chunks; }
-};
+
+// Process-wide tile configuration (mfr_set_tile_config); initialised from the
+// environment variables MFR_TILE ("BXxBY"), MFR_CHUNK and MFR_GROUPS if present.
+static mfr_tile_config g_tile_cfg = [] {
+  mfr_tile_config c{32, 16, 0, 0};
+  if (const char* e = std::getenv("MFR_TILE")) {
+    int bx = 0, by = 0;
+    if (sscanf(e, "%dx%d", &bx, &by) == 2) {
+      c.bx = bx;
+      c.by = by;
+    }
+  }
+  if (const char* e = std::getenv("MFR_CHUNK")) c.chunk_len = std::max(0, atoi(e));
+  if (const char* e = std::getenv("MFR_GROUPS")) c.target_groups = std::max(0, atoi(e));
+  return c;
+}();
+
+mfr_tile_config current_tile_config() { return g_tile_cfg; }
+void set_tile_config(const mfr_tile_config& c) { g_tile_cfg = c; }
 
 Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector<Conv1>& cy,
                    const std::vector<Conv1>& cz) {
   Tiling t;
-  t.shape = TileShape{32, 16};
-  if (const char* e = std::getenv("MFR_TILE")) {
-    int bx = 0, by = 0;
-    if (sscanf(e, "%dx%d", &bx, &by) == 2) t.shape = TileShape{bx, by};
-  }
+  const mfr_tile_config cfg = current_tile_config();
+  t.shape = TileShape{cfg.bx, cfg.by};
   const int TX = t.shape.bx - 4, TY = t.shape.by - 4;
   t.tiles_x = (g.m[0] + TX - 1) / TX;
   t.tiles_y = (g.m[1] + TY - 1) / TY;
   const int xy = t.tiles_x * t.tiles_y;
-  int chunks = std::max(1, (2048 + xy - 1) / xy);
+  const int target = cfg.target_groups > 0 ? cfg.target_groups : 2048;
+  int chunks = std::max(1, (target + xy - 1) / xy);
   chunks = std::min(chunks, std::max(1, g.m[2] / 16));
   int clen = (g.m[2] + chunks - 1) / chunks;
-  if (const char* e = std::getenv("MFR_CHUNK")) clen = std::max(1, atoi(e));
+  if (cfg.chunk_len > 0) clen = cfg.chunk_len;
   t.chunk_len = std::min(clen, g.m[2]);
   t.chunks = (g.m[2] + t.chunk_len - 1) / t.chunk_len;
   t.nxt = t.nyt = t.nzt = 0;
@@ -217,12 +207,6 @@ bool valid_shape(const TileShape& s) {
 }
 
 // ---- workspace layout ---------------------------------------------------------
-struct Layout {
-  size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
-  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz;
-  size_t n_red_node;
-  size_t total;
-};
 
 Layout make_layout(const Geo& g, const Tiling& t) {
   Layout L;
@@ -262,47 +246,11 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   return L;
 }
 
-}  // namespace
+}  // namespace mfr
 
-struct mfr_ctx {
-  Geo geo;
-  Tiling tiling;
-  Layout lay;
-  hipStream_t stream;
-  char* ws;
-  const float* R;
-  bool have_images;
-  TileParams tp;
-  NodeParams np;
-  DiagParams dp;
-  JacParams jp;
-  bool jac_tiled;
-  double* sc;
-  double* red_tile;
-  double* red_node;
-  float* vec[8];
-  int vec_blocks;
-  // kernel timing (mfr_profile_*)
-  bool prof_on = false;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
-  std::vector<hipEvent_t> prof_pool;
-  int prof_launches[5] = {0, 0, 0, 0, 0};
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  ~mfr_ctx() {
-    for (auto& p : prof_pending) {
-      hipEventDestroy(p.second.first);
-      hipEventDestroy(p.second.second);
-    }
-    for (auto e : prof_pool) hipEventDestroy(e);
-  }
-};
 
-namespace {
+namespace mfr {
 
-template <class T>
-T* at(char* base, size_t off) {
-  return reinterpret_cast<T*>(base + off);
-}
 
 mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes) {
   MFR_TRY(make_geo(grid, &c->geo));
@@ -678,7 +626,7 @@ mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out)
   return MFR_OK;
 }
 
-}  // namespace
+}  // namespace mfr
 
 extern "C" {
 
@@ -775,6 +723,21 @@ mfr_status mfr_gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* 
   return gn_step(c, u, o, info);
 }
 
+mfr_status mfr_set_tile_config(const mfr_tile_config* cfg) {
+  if (!cfg) return fail(MFR_EINVAL, "cfg is NULL");
+  if (!valid_shape(TileShape{cfg->bx, cfg->by}) || cfg->chunk_len < 0 || cfg->target_groups < 0)
+    return fail(MFR_EINVAL, "unsupported tile configuration %dx%d / %d / %d", cfg->bx, cfg->by, cfg->chunk_len,
+                cfg->target_groups);
+  set_tile_config(*cfg);
+  return MFR_OK;
+}
+
+mfr_status mfr_get_tile_config(mfr_tile_config* cfg) {
+  if (!cfg) return fail(MFR_EINVAL, "cfg is NULL");
+  *cfg = current_tile_config();
+  return MFR_OK;
+}
+
 mfr_status mfr_profile_enable(mfr_ctx* c, int32_t enable) {
   if (!c) return fail(MFR_EINVAL, "context is NULL");
   c->prof_on = enable != 0;
@@ -819,13 +782,10 @@ mfr_status mfr_pcg_solve(mfr_ctx* c, const float* u, const float* b, float* s, c
 }
 
 // ---- multilevel ---------------------------------------------------------------
-namespace {
+}  // extern "C"
 
-struct Level {
-  mfr_grid grid;
-  Geo geo;
-  size_t off_R, off_T, off_u;   // coarse images / displacement (finest: caller buffers)
-};
+namespace mfr {
+
 
 mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out, size_t* total) {
   if (levels < 1 || levels > 8) return fail(MFR_EINVAL, "levels must be in 1..8");
@@ -872,7 +832,9 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
   return MFR_OK;
 }
 
-}  // namespace
+}  // namespace mfr
+
+extern "C" {
 
 mfr_status mfr_ml_workspace_size(const mfr_grid* finest, int32_t levels, size_t* bytes) {
   if (!bytes) return fail(MFR_EINVAL, "bytes is NULL");

@@ -1,0 +1,134 @@
+// Host-side internals of libmfr shared by the single-problem API (api.cpp)
+// and the batched path (batch.cpp): validated geometry, tiling, workspace
+// layout, the context structure and the enqueue helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <utility>
+#include <vector>
+
+#include "../../include/mfr.h"
+#include "mfr_internal.h"
+
+namespace mfr {
+
+mfr_status fail(mfr_status s, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(MFR_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+#define MFR_TRY(expr)                \
+  do {                               \
+    mfr_status s_ = (expr);          \
+    if (s_ != MFR_OK) return s_;     \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Derived, validated problem description.
+struct Geo {
+  int m[3], n[3], mT[3];
+  double h[3], hT[3], hy[3];
+  double tau, rho, alpha;
+  size_t mbar, nbar;
+  double hbar() const { return h[0] * h[1] * h[2]; }
+  double hybar() const { return hy[0] * hy[1] * hy[2]; }
+};
+
+mfr_status make_geo(const mfr_grid* g, Geo* o);
+std::vector<Conv1> conv_table(int m, int n);
+std::vector<Samp1> samp_table(int m, double h, double hT);
+std::vector<Range1> node_cols(const std::vector<Conv1>& c, int n);
+std::vector<Conv1> prolong_table(int nf, double hyf, int nc, double hyc);
+
+struct Tiling {
+  TileShape shape;
+  int tiles_x, tiles_y, chunks, chunk_len;
+  int nxt, nyt, nzt;
+  int grid() const { return tiles_x * tiles_y * chunks; }
+};
+
+Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector<Conv1>& cy,
+                   const std::vector<Conv1>& cz);
+bool valid_shape(const TileShape& s);
+mfr_tile_config current_tile_config();
+void set_tile_config(const mfr_tile_config& c);
+
+struct Layout {
+  size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
+  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz;
+  size_t n_red_node;
+  size_t total;
+};
+
+Layout make_layout(const Geo& g, const Tiling& t);
+
+template <class T>
+T* at(char* base, size_t off) {
+  return reinterpret_cast<T*>(base + off);
+}
+
+struct Level {
+  mfr_grid grid;
+  Geo geo;
+  size_t off_R, off_T, off_u;   // coarse images / displacement (finest: caller buffers)
+};
+
+mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out, size_t* total);
+
+}  // namespace mfr
+
+// The opaque context of include/mfr.h.
+struct mfr_ctx {
+  mfr::Geo geo;
+  mfr::Tiling tiling;
+  mfr::Layout lay;
+  hipStream_t stream;
+  char* ws;
+  const float* R;
+  bool have_images;
+  mfr::TileParams tp;
+  mfr::NodeParams np;
+  mfr::DiagParams dp;
+  mfr::JacParams jp;
+  bool jac_tiled;
+  double* sc;
+  double* red_tile;
+  double* red_node;
+  float* vec[8];
+  int vec_blocks;
+  // kernel timing (mfr_profile_*)
+  bool prof_on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  int prof_launches[5] = {0, 0, 0, 0, 0};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  ~mfr_ctx() {
+    for (auto& p : prof_pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : prof_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace mfr {
+
+mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes);
+hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag);
+int node_blocks(const mfr_ctx* c);
+mfr_status check_ptr(const void* p, const char* name);
+mfr_status enqueue_objective(mfr_ctx* c, const float* u);
+mfr_status read_objective(mfr_ctx* c, double* J, double* D, double* S);
+mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g);
+mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q);
+mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
+                   mfr_pcg_info* info);
+mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out);
+
+}  // namespace mfr

@@ -9,6 +9,9 @@
 
 namespace mfr {
 
+constexpr int kVecBlock = 256;
+constexpr int kNodeBlock = 256;
+
 // Grid conversion along one axis (Sec. 4.3, eq. grid_conversion): voxel index
 // a lies between nodes n0 and n0 + 1 with weights (1 - f, f).
 struct Conv1 {
@@ -123,9 +126,94 @@ struct TileShape {
   int bx, by;
 };
 
+// One problem of a batched launch: its kernel parameters and vectors.
+struct BatchJob {
+  TileParams t;
+  const float* u;
+  const float* p;
+};
+
+// Work list of a persistent batched launch (passed by value, so the table
+// sits in kernel-argument memory): problem j owns tiles [prefix[j],
+// prefix[j+1]); counter is a device int the caller zeroes before the launch;
+// active (may be null) masks problems out.
+constexpr int kMaxBatch = 12;
+struct BatchJobs {
+  BatchJob jobs[kMaxBatch];
+  int prefix[kMaxBatch + 1];
+  int n, total;
+  int* counter;
+  const int* active;
+};
+
+// Node pass of one problem in a batched launch; problem j owns node blocks
+// [prefix[j], prefix[j+1]).
+struct NodeJob {
+  NodeParams q;
+  const float* f;
+  float* out;
+};
+struct NodeJobs {
+  NodeJob jobs[kMaxBatch];
+  int prefix[kMaxBatch + 1];
+  int n;
+  const int* active;
+};
+
+// Fixed-order sum of n partials (stride apart) into *out, one group per problem.
+struct SumJob {
+  const double* parts;
+  int n, stride;
+  double* out;
+};
+struct SumJobs {
+  SumJob jobs[kMaxBatch];
+  int n;
+  const int* active;
+};
+
+// y = x + eta s for one problem.
+struct AxpyJob {
+  const float* x;
+  const float* s;
+  float* y;
+  float eta;
+  int n;
+};
+struct AxpyJobs {
+  AxpyJob jobs[kMaxBatch];
+  int prefix[kMaxBatch + 1];
+  int n;
+  const int* active;
+};
+
+// Conjugate-gradient vectors and device-side control of one problem.
+// ST_MAXIT and SC_RTOL are copied from the job table by the start kernel, so
+// launches captured once stay valid for later solves with other limits.
+enum PcgState : int { ST_ACTIVE = 0, ST_ITERS = 1, ST_FLAG = 2, ST_MAXIT = 3, ST_COUNT = 4 };
+struct VecJob {
+  float *r, *z, *p, *q, *s;
+  const float* b;
+  const float* diag;
+  double* sc;
+  int* state;
+  double* red;
+  const double* red_pq;
+  int n_pq, n3, max_iter;
+  double rtol;
+};
+struct VecJobs {
+  VecJob jobs[kMaxBatch];
+  int prefix[kMaxBatch + 1];
+  int n;
+  int* active_out;
+};
+
 // ---- launch wrappers (return hipError_t of the launch) ----------------------
 hipError_t launch_tile(const TileShape& s, int mode, const TileParams& p, const float* u,
                        const float* pv, int grid, hipStream_t st);
+// groups <= 0: as many work-groups as fit on the device at once.
+hipError_t launch_tile_batch(const TileShape& s, int mode, const BatchJobs& j, int groups, hipStream_t st);
 hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float* out, int blocks,
                             hipStream_t st);
 hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st);
@@ -137,7 +225,7 @@ constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi
 // PCG vector kernels.  sc: device scalars (see PcgSlot).
 enum PcgSlot : int {
   SC_BB = 0, SC_RZ = 1, SC_PQ = 2, SC_RR = 3, SC_RZNEW = 4, SC_ALPHA = 5, SC_BETA = 6,
-  SC_D = 8, SC_S = 9, SC_J = 10, SC_DOT = 11, SC_COUNT = 16
+  SC_D = 8, SC_S = 9, SC_J = 10, SC_DOT = 11, SC_RELRES = 12, SC_RTOL = 13, SC_COUNT = 16
 };
 hipError_t launch_pcg_init(int n3, const float* b, const float* diag, float* s, float* r, float* z,
                            float* p, double* red, int blocks, hipStream_t st);
@@ -161,7 +249,16 @@ hipError_t launch_prolong(const float* coarse, int cnx, int cny, int cnz, float*
                           int fny, int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz,
                           hipStream_t st);
 
-constexpr int kVecBlock = 256;
-constexpr int kNodeBlock = 256;
+// batched path
+hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st);
+hipError_t launch_sum_batch(const SumJobs& j, hipStream_t st);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t st);
+hipError_t launch_axpy_batch(const AxpyJobs& j, hipStream_t st);
+hipError_t launch_dot_batch(const VecJobs& j, hipStream_t st);
+hipError_t launch_pcg_init_batch(const VecJobs& j, hipStream_t st);
+hipError_t launch_pcg_alpha_batch(const VecJobs& j, hipStream_t st);
+hipError_t launch_pcg_update_batch(const VecJobs& j, hipStream_t st);
+hipError_t launch_pcg_beta_batch(const VecJobs& j, hipStream_t st);
+hipError_t launch_pcg_direction_batch(const VecJobs& j, hipStream_t st);
 
 }  // namespace mfr

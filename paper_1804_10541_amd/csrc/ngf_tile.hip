@@ -39,10 +39,26 @@
 
 namespace mfr {
 
+// LDS of one work-group of the voxel-tile kernel.
 template <int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
-                                                          const float* __restrict__ u,
-                                                          const float* __restrict__ pv) {
+struct TileSmem {
+  static constexpr int NT = BX * BY, TX = BX - 4, TY = BY - 4, MAXNX = TX + 1, MAXNY = TY + 1;
+  static constexpr bool HV = (MODE == MODE_HV), NEED_C = (MODE != MODE_OBJ);
+  float sTw[2][NT];
+  float sR[2][NT];
+  float sA[HV ? 2 : 1][HV ? NT : 1];
+  float sE[NEED_C ? 2 : 1][4][NEED_C ? NT : 1];
+  float sV[3][TX * TY];
+  float sW[3][TY * MAXNX];
+  int sColLo[MAXNX], sColHi[MAXNX], sRowLo[MAXNY], sRowHi[MAXNY];
+  Conv1 sCx[TX], sCy[TY];
+  double sRed[NT / 64];
+};
+
+// One tile (work-group id `bid` of the problem P) of the fused kernel.
+template <int BX, int BY, int MODE>
+__device__ __forceinline__ void tile_body(const TileParams& P, const int bid, const float* __restrict__ u,
+                                          const float* __restrict__ pv, TileSmem<BX, BY, MODE>& S) {
   constexpr int NT = BX * BY;
   constexpr int TX = BX - 4, TY = BY - 4;
   constexpr int MAXNX = TX + 1, MAXNY = TY + 1;
@@ -50,21 +66,23 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
   constexpr bool NEED_C = (MODE != MODE_OBJ);
   static_assert(MAXNX * TY <= NT && MAXNX * MAXNY <= NT, "flush mapping needs more threads");
   static_assert(NT >= 64 + MAXNY, "node-range setup needs more threads");
-
-  __shared__ float sTw[2][NT];
-  __shared__ float sR[2][NT];
-  __shared__ float sA[HV ? 2 : 1][HV ? NT : 1];
-  __shared__ float sE[NEED_C ? 2 : 1][4][NEED_C ? NT : 1];
-  __shared__ float sV[3][TX * TY];
-  __shared__ float sW[3][TY * MAXNX];
-  __shared__ int sColLo[MAXNX], sColHi[MAXNX], sRowLo[MAXNY], sRowHi[MAXNY];
-  __shared__ Conv1 sCx[TX], sCy[TY];
-  __shared__ double sRed[NT / 64];
+  auto& sTw = S.sTw;
+  auto& sR = S.sR;
+  auto& sA = S.sA;
+  auto& sE = S.sE;
+  auto& sV = S.sV;
+  auto& sW = S.sW;
+  auto& sColLo = S.sColLo;
+  auto& sColHi = S.sColHi;
+  auto& sRowLo = S.sRowLo;
+  auto& sRowHi = S.sRowHi;
+  auto& sCx = S.sCx;
+  auto& sCy = S.sCy;
+  auto& sRed = S.sRed;
 
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
 
-  const int bid = xcd_block_id();
   const int tile_x = bid % P.tiles_x;
   const int rest = bid / P.tiles_x;
   const int tile_y = rest % P.tiles_y;
@@ -376,6 +394,36 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P,
     flush(acc_hi, KL + 1 - noz);
   }
   if constexpr (MODE != MODE_HV) block_sum_store<NT>(obj, P.red + bid, sRed);
+  __syncthreads();   // LDS may be reused by the next tile of a persistent group
+}
+
+template <int BX, int BY, int MODE>
+__global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P, const float* __restrict__ u,
+                                                          const float* __restrict__ pv) {
+  __shared__ TileSmem<BX, BY, MODE> S;
+  tile_body<BX, BY, MODE>(P, xcd_block_id(), u, pv, S);
+}
+
+// Persistent form over a batch of problems: every group takes tiles from a
+// shared work counter until all tiles of all active problems are done.  A
+// tile's results depend only on its problem and tile id, so the output equals
+// one launch per problem bit for bit.
+template <int BX, int BY, int MODE>
+__global__ __launch_bounds__(BX* BY) void ngf_tile_batch_kernel(const BatchJobs J) {
+  __shared__ TileSmem<BX, BY, MODE> S;
+  __shared__ int sItem;
+  for (;;) {
+    if (threadIdx.x == 0) sItem = atomicAdd(J.counter, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(sItem);   // uniform across the group
+    __syncthreads();
+    if (item >= J.total) break;
+    int pr = 0;
+    while (pr + 1 < J.n && J.prefix[pr + 1] <= item) ++pr;
+    if (J.active && !J.active[pr]) continue;
+    const BatchJob& jb = J.jobs[pr];
+    tile_body<BX, BY, MODE>(jb.t, item - J.prefix[pr], jb.u, jb.p, S);
+  }
 }
 
 template <int BX, int BY>
@@ -396,12 +444,60 @@ static hipError_t launch_tile_shape(int mode, const TileParams& p, const float* 
   return hipGetLastError();
 }
 
+static int resident_groups(const void* kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return 0;
+  return cus * per_cu;
+}
+
+template <int BX, int BY>
+static hipError_t launch_tile_batch_shape(int mode, const BatchJobs& j, int groups, hipStream_t st) {
+  if (groups <= 0) {
+    // resident capacity of each mode, queried once per process (one device)
+    static int cap[3] = {-1, -1, -1};
+    const int mi = mode == MODE_OBJ ? 0 : mode == MODE_GRAD ? 1 : 2;
+    if (cap[mi] < 0) {
+      const void* k = mi == 0   ? reinterpret_cast<const void*>(ngf_tile_batch_kernel<BX, BY, MODE_OBJ>)
+                      : mi == 1 ? reinterpret_cast<const void*>(ngf_tile_batch_kernel<BX, BY, MODE_GRAD>)
+                                : reinterpret_cast<const void*>(ngf_tile_batch_kernel<BX, BY, MODE_HV>);
+      cap[mi] = resident_groups(k, BX * BY);
+    }
+    groups = cap[mi] > 0 ? cap[mi] : 512;
+  }
+  groups = groups < j.total ? groups : j.total;
+  if (groups <= 0) return hipSuccess;
+  dim3 blk(BX * BY), grd(groups);
+  switch (mode) {
+    case MODE_OBJ:
+      hipLaunchKernelGGL((ngf_tile_batch_kernel<BX, BY, MODE_OBJ>), grd, blk, 0, st, j);
+      break;
+    case MODE_GRAD:
+      hipLaunchKernelGGL((ngf_tile_batch_kernel<BX, BY, MODE_GRAD>), grd, blk, 0, st, j);
+      break;
+    default:
+      hipLaunchKernelGGL((ngf_tile_batch_kernel<BX, BY, MODE_HV>), grd, blk, 0, st, j);
+      break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_tile(const TileShape& s, int mode, const TileParams& p, const float* u,
                        const float* pv, int grid, hipStream_t st) {
   if (s.bx == 32 && s.by == 16) return launch_tile_shape<32, 16>(mode, p, u, pv, grid, st);
   if (s.bx == 64 && s.by == 8) return launch_tile_shape<64, 8>(mode, p, u, pv, grid, st);
   if (s.bx == 32 && s.by == 32) return launch_tile_shape<32, 32>(mode, p, u, pv, grid, st);
   if (s.bx == 64 && s.by == 16) return launch_tile_shape<64, 16>(mode, p, u, pv, grid, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_batch(const TileShape& s, int mode, const BatchJobs& j, int groups, hipStream_t st) {
+  if (s.bx == 32 && s.by == 16) return launch_tile_batch_shape<32, 16>(mode, j, groups, st);
+  if (s.bx == 64 && s.by == 8) return launch_tile_batch_shape<64, 8>(mode, j, groups, st);
+  if (s.bx == 32 && s.by == 32) return launch_tile_batch_shape<32, 32>(mode, j, groups, st);
+  if (s.bx == 64 && s.by == 16) return launch_tile_batch_shape<64, 16>(mode, j, groups, st);
   return hipErrorInvalidValue;
 }
 

@@ -50,11 +50,9 @@ __device__ __forceinline__ float lap7(const float* __restrict__ f, int i, int j,
 
 // One thread per node: q_d = s_ngf * (sum of the tile partials) + s_curv * (L L f_d).
 template <int MODE>
-__global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams Q,
-                                                               const float* __restrict__ f,
-                                                               float* __restrict__ out) {
-  __shared__ double sred[kNodeBlock / 64];
-  const int n = blockIdx.x * kNodeBlock + threadIdx.x;
+__device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float* __restrict__ f,
+                                               float* __restrict__ out, const int blk, double* sred) {
+  const int n = blk * kNodeBlock + threadIdx.x;
   double local = 0.0;
   if (n < Q.nbar) {
     const int i = n % Q.nx;
@@ -97,8 +95,39 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams 
     }
   }
   const double s = block_sum<kNodeBlock>(local, sred);
-  if (threadIdx.x == 0) Q.red[blockIdx.x] = s;
+  if (threadIdx.x == 0) Q.red[blk] = s;
 }
+
+template <int MODE>
+__global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams Q,
+                                                               const float* __restrict__ f,
+                                                               float* __restrict__ out) {
+  __shared__ double sred[kNodeBlock / 64];
+  node_pass_body<MODE>(Q, f, out, blockIdx.x, sred);
+}
+
+// The same per-node arithmetic for a table of problems (batched path).
+template <int MODE>
+__global__ __launch_bounds__(kNodeBlock) void node_pass_batch_kernel(const NodeJobs J) {
+  __shared__ double sred[kNodeBlock / 64];
+  int pr = 0;
+  while (pr + 1 < J.n && J.prefix[pr + 1] <= (int)blockIdx.x) ++pr;
+  if (J.active && !J.active[pr]) return;
+  const NodeJob& jb = J.jobs[pr];
+  node_pass_body<MODE>(jb.q, jb.f, jb.out, blockIdx.x - J.prefix[pr], sred);
+}
+
+hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
+  const int blocks = j.prefix[j.n];
+  if (mode == NP_S)
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_S>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+  else if (mode == NP_GRAD)
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+  else
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float* out, int blocks,
                             hipStream_t st) {

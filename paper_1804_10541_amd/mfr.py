@@ -67,6 +67,20 @@ class CProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int32 * 5), ("ms", ctypes.c_double * 5)]
 
 
+class CTileConfig(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("chunk_len", ctypes.c_int32),
+                ("target_groups", ctypes.c_int32)]
+
+
+MAX_BATCH = 12
+
+
+class CBatchReport(ctypes.Structure):
+    _fields_ = [("J_final", ctypes.c_double * MAX_BATCH), ("gn_done", ctypes.c_int32 * MAX_BATCH),
+                ("pcg_total", ctypes.c_int32 * MAX_BATCH), ("status", ctypes.c_int32 * MAX_BATCH),
+                ("graph_launches", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
 PROFILE_KERNELS = ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass")
 
 _lib = None
@@ -89,6 +103,15 @@ SIGNATURES = {
     "mfr_ml_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_register_multilevel": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CMlOpts), _VP, _VP, _SZ,
                                                _VP, _VP, _VP, ctypes.POINTER(CMlReport)]),
+    "mfr_batch_workspace_size": (ctypes.c_int, [_I, ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
+    "mfr_batch_create": (ctypes.c_int, [_I, ctypes.POINTER(CGrid), _I, _VP, _VP, _SZ, ctypes.POINTER(_VP)]),
+    "mfr_batch_destroy": (None, [_VP]),
+    "mfr_batch_set_images": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
+    "mfr_batch_hess_vec": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
+    "mfr_batch_register": (ctypes.c_int, [_VP, ctypes.POINTER(CMlOpts), _I, ctypes.POINTER(_VP),
+                                          ctypes.POINTER(CBatchReport)]),
+    "mfr_set_tile_config": (ctypes.c_int, [ctypes.POINTER(CTileConfig)]),
+    "mfr_get_tile_config": (ctypes.c_int, [ctypes.POINTER(CTileConfig)]),
     "mfr_profile_enable": (ctypes.c_int, [_VP, _I]),
     "mfr_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(CProfile), _I]),
 }
@@ -284,3 +307,123 @@ def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=
     del ws
     return u, dict(J_final=rep.J_final, gn_done=list(rep.gn_done)[:levels], pcg_total=list(rep.pcg_total)[:levels],
                    status=list(rep.status)[:levels], seconds=rep.seconds)
+
+
+def set_tile_config(bx, by, chunk_len=0, target_groups=0):
+    """Tile shape (bx x by threads), z planes per work-group (0: derived) and
+    the work-group count the derived split aims for (0: library default), for
+    contexts and batches created afterwards in this process."""
+    lib = load()
+    c = CTileConfig(int(bx), int(by), int(chunk_len), int(target_groups))
+    _check(lib.mfr_set_tile_config(ctypes.byref(c)))
+
+
+def get_tile_config():
+    lib = load()
+    c = CTileConfig()
+    _check(lib.mfr_get_tile_config(ctypes.byref(c)))
+    return dict(bx=c.bx, by=c.by, chunk_len=c.chunk_len, target_groups=c.target_groups)
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p.value if isinstance(p, ctypes.c_void_p) else p
+    return arr
+
+
+class Batch:
+    """Independent registration problems (up to MAX_BATCH, sizes may differ)
+    advanced together by the batched library path on a stream of its own."""
+
+    def __init__(self, specs, levels=1, device="cuda:0"):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.specs = list(specs)
+        self.n = len(self.specs)
+        if not 1 <= self.n <= MAX_BATCH:
+            raise ValueError(f"batch size must be in 1..{MAX_BATCH}")
+        self.levels = int(levels)
+        self.grids = (CGrid * self.n)(*[make_grid(s) for s in self.specs])
+        self.my = [tuple(int(k) for k in s.my) for s in self.specs]
+        self.m = [tuple(int(k) for k in s.m) for s in self.specs]
+        self.mT = [tuple(int(k) for k in (getattr(s, "mT", None) or s.m)) for s in self.specs]
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.mfr_batch_workspace_size(self.n, self.grids, self.levels, ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        self._ws, ptr = _alloc_workspace(self.ws_bytes, self.device)
+        self.stream = torch.cuda.Stream(self.device)   # default priority; graphs need a non-null stream
+        h = ctypes.c_void_p()
+        _check(self.lib.mfr_batch_create(self.n, self.grids, self.levels, ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.c_void_p(ptr), self.ws_bytes, ctypes.byref(h)))
+        self._h = h
+        self._images = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.stream.synchronize()
+            self.lib.mfr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def node_shape(self, k):
+        my = self.my[k]
+        return (3, my[2], my[1], my[0])
+
+    def _nodes(self, k):
+        my = self.my[k]
+        return 3 * my[0] * my[1] * my[2]
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def set_images(self, Rs, Ts):
+        if len(Rs) != self.n or len(Ts) != self.n:
+            raise ValueError("one reference and one template image per pair")
+        r = [_dev_tensor(Rs[k], self.m[k][0] * self.m[k][1] * self.m[k][2], f"R[{k}]", self.device)
+             for k in range(self.n)]
+        t = [_dev_tensor(Ts[k], self.mT[k][0] * self.mT[k][1] * self.mT[k][2], f"T[{k}]", self.device)
+             for k in range(self.n)]
+        self._enter()
+        _check(self.lib.mfr_batch_set_images(self._h, _ptr_array(r), _ptr_array(t)))
+        self._leave()
+        self._images = (list(Rs), list(Ts))
+
+    def hess_vec(self, us, ps, outs=None):
+        """q_k = H_k p_k at u_k on the finest grids, all pairs in one pass."""
+        if outs is None:
+            outs = [torch.empty(self.node_shape(k), dtype=torch.float32, device=self.device) for k in range(self.n)]
+        u = [_dev_tensor(us[k], self._nodes(k), f"u[{k}]", self.device) for k in range(self.n)]
+        p = [_dev_tensor(ps[k], self._nodes(k), f"p[{k}]", self.device) for k in range(self.n)]
+        q = [_dev_tensor(outs[k], self._nodes(k), f"q[{k}]", self.device) for k in range(self.n)]
+        self._enter()
+        _check(self.lib.mfr_batch_hess_vec(self._h, _ptr_array(u), _ptr_array(p), _ptr_array(q)))
+        self._leave()
+        return outs
+
+    def register(self, gn_iters=10, pcg_max=50, pcg_rtol=1e-3, armijo_c1=1e-4, armijo_max=10, precond=1,
+                 use_graph=True, u0=None):
+        """Coarse-to-fine Gauss-Newton registration of every pair; returns
+        (list of finest displacements, report dict)."""
+        us = [torch.zeros(self.node_shape(k), dtype=torch.float32, device=self.device) if u0 is None
+              else u0[k].clone() for k in range(self.n)]
+        ptr = [_dev_tensor(us[k], self._nodes(k), f"u[{k}]", self.device) for k in range(self.n)]
+        opts = CMlOpts(self.levels, int(gn_iters), int(pcg_max), float(pcg_rtol), float(armijo_c1),
+                       int(armijo_max), int(precond))
+        rep = CBatchReport()
+        self._enter()
+        _check(self.lib.mfr_batch_register(self._h, ctypes.byref(opts), 1 if use_graph else 0, _ptr_array(ptr),
+                                           ctypes.byref(rep)))
+        self._leave()
+        n = self.n
+        return us, dict(J_final=list(rep.J_final)[:n], gn_done=list(rep.gn_done)[:n],
+                        pcg_total=list(rep.pcg_total)[:n], status=list(rep.status)[:n],
+                        graph_launches=rep.graph_launches, seconds=rep.seconds)
