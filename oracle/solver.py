@@ -96,6 +96,60 @@ def pcg(apply_A, b, diag=None, max_iter=50, rtol=1e-3):
     return s.reshape(shape), dict(iters=it, relres=relres, flag=flag)
 
 
+def fpcg(apply_A, b, precond, max_iter=50, rtol=1e-3, fallback=None, fallback_iters=0):
+    """Flexible preconditioned CG for A s = b from s = 0, for a preconditioner
+    z = precond(r) that may change from step to step or be nonlinear.
+
+    The direction update uses the Polak-Ribiere form
+    beta_k = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k), which equals the standard
+    PCG beta when precond is linear, symmetric and fixed (then z_{k+1}^T r_k = 0).
+    If ``fallback`` (a second preconditioner) is given and ``fallback_iters``
+    > 0, the solve switches to it after that many steps without convergence,
+    restarting the directions from the current iterate.  Stopping rule and
+    info as in pcg, plus used_fallback."""
+    b = np.asarray(b, dtype=np.float64)
+    shape = b.shape
+    b = b.ravel()
+    s = np.zeros_like(b)
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return s.reshape(shape), dict(iters=0, relres=0.0, flag=0, used_fallback=0)
+    M = lambda r: np.asarray(precond(r.reshape(shape)), dtype=np.float64).ravel()
+    r = b.copy()
+    z = M(r)
+    p = z.copy()
+    rz = float(r @ z)
+    relres, flag, it, used = 1.0, 1, 0, 0
+    for it in range(1, max_iter + 1):
+        q = np.asarray(apply_A(p.reshape(shape)), dtype=np.float64).ravel()
+        pq = float(p @ q)
+        if not np.isfinite(pq) or pq <= 0.0:
+            flag = 2
+            it -= 1
+            break
+        alpha = rz / pq
+        s += alpha * p
+        r_old = r
+        r = r - alpha * q
+        relres = float(np.linalg.norm(r)) / bn
+        if relres <= rtol:
+            flag = 0
+            break
+        if fallback is not None and fallback_iters > 0 and it == fallback_iters and not used:
+            used = 1
+            M = lambda r: np.asarray(fallback(r.reshape(shape)), dtype=np.float64).ravel()
+            z = M(r)
+            p = z.copy()
+            rz = float(r @ z)
+            continue
+        z = M(r)
+        rz_new = float(r @ z)
+        beta = (rz_new - float(r_old @ z)) / rz
+        p = z + beta * p
+        rz = rz_new
+    return s.reshape(shape), dict(iters=it, relres=relres, flag=flag, used_fallback=used)
+
+
 def gauss_newton(problem, u0, iters=10, pcg_max=50, pcg_rtol=1e-3, c1=1e-4, max_ls=10,
                  precond=True, callback=None):
     """Gauss-Newton with CG inner solves and Armijo line search.
