@@ -116,28 +116,36 @@ mfr_status mfr_jacobi_diag(mfr_ctx* ctx, const float* u, float* diag);
 typedef struct {
   int32_t max_iter;   /* >= 0                                                   */
   double rtol;        /* stop when ||b - A s_k|| / ||b|| <= rtol (recursive residual) */
-  int32_t precond;    /* 0 none (plain CG), 1 Jacobi                             */
+  int32_t precond;    /* 0 none (plain CG), 1 Jacobi, 2 learned (flexible CG; needs a
+                         preconditioner attached with mfr_attach_pc)            */
+  int32_t fallback_iters; /* precond 2 only: after this many iterations without
+                         convergence, continue with Jacobi-PCG from the current
+                         iterate (0: never)                                      */
 } mfr_pcg_opts;
 
 typedef struct {
   int32_t iters;      /* iterations performed                                    */
   double relres;      /* final relative residual                                 */
   int32_t flag;       /* 0 converged, 1 max_iter reached, 2 breakdown (p^T A p <= 0 or not finite) */
+  int32_t used_fallback; /* 1 if a learned solve switched to Jacobi              */
 } mfr_pcg_info;
 
-/* Solve (H + alpha nabla^2 S) s = b at u by (Jacobi-)preconditioned CG from
- * s = 0 (Sec. 2.3.1: the Newton equation solved with CG).  Vectors in float32,
- * dot products and step lengths in float64.  s: device [3][n].
- * Synchronises once per iteration (convergence test on the host). */
+/* Solve (H + alpha nabla^2 S) s = b at u by preconditioned CG from s = 0
+ * (Sec. 2.3.1: the Newton equation solved with CG).  Vectors in float32, dot
+ * products and step lengths in float64.  s: device [3][n].  With precond 2 the
+ * direction update is the flexible (Polak-Ribiere) one, since the learned
+ * preconditioner is nonlinear.  Synchronises once per iteration (convergence
+ * test on the host). */
 mfr_status mfr_pcg_solve(mfr_ctx* ctx, const float* u, const float* b, float* s,
                          const mfr_pcg_opts* opts, mfr_pcg_info* info);
 
 typedef struct {
   int32_t pcg_max;     /* CG iterations                                              */
   double pcg_rtol;     /* CG relative residual tolerance (0: always pcg_max steps)   */
-  int32_t precond;     /* 0 none, 1 Jacobi                                           */
+  int32_t precond;     /* 0 none, 1 Jacobi, 2 learned (attached preconditioner)      */
   double armijo_c1;    /* sufficient-decrease constant in [0, 1) (e.g. 1e-4)         */
   int32_t armijo_max;  /* trial step lengths 1, 1/2, 1/4, ... before giving up, >= 1 */
+  int32_t fallback_iters; /* as in mfr_pcg_opts                                      */
 } mfr_gn_opts;
 
 typedef struct {
@@ -238,6 +246,77 @@ mfr_status mfr_batch_hess_vec(mfr_batch* b, const float* const* u, const float* 
  * Synchronises the stream. */
 mfr_status mfr_batch_register(mfr_batch* b, const mfr_ml_opts* opts, int32_t use_graph, float* const* u,
                               mfr_batch_report* report);
+
+/* ---- Learned preconditioner -------------------------------------------------------
+ * An extension of the method (the paper solves the Newton equation with plain
+ * CG): a 3D CNN on the deformation-node grid maps the CG residual r to a search
+ * direction z for flexible CG,
+ *   y = r / diag (Jacobi),  z = y + rms(y) * CNN(features)[0..2],
+ * features per node = RMS-normalised y (3), r (3), diag (3) and |grad R| (1,
+ * the voxel gradient magnitude of R averaged onto the nodes with the weights of
+ * the grid conversion, eq. grid_conversion), zero-padded to 16 channels.
+ * Network: four 3x3x3 convolutions 16 -> 16 channels, zero padding, ReLU after
+ * the first three; bf16 weights and activations with fp32 accumulation on the
+ * matrix cores; the last layer's outputs 3..15 are unused (held at zero).
+ * Parameters (fp32 master copy): per layer [27 taps][16 in][16 out] weights,
+ * tap t = 9 (dz+1) + 3 (dy+1) + (dx+1), then 16 biases. */
+#define MFR_PC_PARAMS (4 * (27 * 16 * 16 + 16))
+
+typedef struct mfr_pc mfr_pc;   /* opaque, bound to one context (grid, stream, images) */
+
+/* Device workspace of a preconditioner for `grid`; train != 0 adds the
+ * gradient, optimiser and backward buffers. */
+mfr_status mfr_pc_workspace_size(const mfr_grid* grid, int32_t train, size_t* bytes);
+/* Create on ctx's stream (parameters zero: z = y until mfr_pc_set_params).
+ * The context must have images; |grad R| is recomputed when they change. */
+mfr_status mfr_pc_create(mfr_ctx* ctx, int32_t train, void* workspace, size_t ws_bytes, mfr_pc** out);
+void mfr_pc_destroy(mfr_pc* pc);
+/* Copy MFR_PC_PARAMS floats from / to host memory (synchronous). */
+mfr_status mfr_pc_set_params(mfr_pc* pc, const float* params);
+mfr_status mfr_pc_get_params(mfr_pc* pc, float* params);
+/* z = M(r) with the Jacobi diagonal taken at u (device [3][n] vectors). */
+mfr_status mfr_pc_apply(mfr_pc* pc, const float* u, const float* r, float* z);
+
+typedef struct {
+  double lr, beta1, beta2, eps;   /* Adam                                          */
+  int32_t pcg_iters;              /* Jacobi-PCG iterations run on the system       */
+  int32_t sample_every;           /* one training step on every k-th residual      */
+} mfr_pc_train_opts;
+
+typedef struct {
+  int32_t steps;                  /* training steps taken                          */
+  double loss_first, loss_last, loss_mean;
+} mfr_pc_train_info;
+
+/* Train on one Gauss-Newton system (H + alpha nabla^2 S) s = b at u: run
+ * Jacobi-PCG on it and take an Adam step on every sample_every-th residual r.
+ * Loss per residual: L = -((z.r)^2 / z.Az) / ((y.r)^2 / y.Ay), the energy
+ * decrease of the best step along z relative to the Jacobi direction y
+ * (-1 for z = y; lower is better); dL/dz = 2s(s Az - r)/E_J with s = z.r/z.Az.
+ * Needs a preconditioner created with train != 0.  Synchronises. */
+mfr_status mfr_pc_train_system(mfr_pc* pc, const float* u, const float* b, const mfr_pc_train_opts* opts,
+                               mfr_pc_train_info* info);
+
+/* Attach (or detach with NULL) the preconditioner used by precond = 2. */
+mfr_status mfr_attach_pc(mfr_ctx* ctx, mfr_pc* pc);
+
+/* The convolution kernels themselves, for testing and reuse: node grid nx x ny
+ * x nz, activations [z][y][x][16] bf16 (raw 16-bit patterns), weights
+ * [27][16][16] bf16, bias fp32[16] (nullable).  Asynchronous on `hip_stream`.
+ * mfr_cnn_conv: y = conv(x) + bias, ReLU if relu != 0; outputs y32 (fp32
+ * [n][16]) and/or y16 (bf16 [n][16]), either may be NULL.
+ * mfr_cnn_conv_bwd_data: dx = conv^T(g) (the gradient with respect to the
+ * input), zeroed where mask <= 0 (mask: the bf16 input activations, nullable).
+ * mfr_cnn_conv_bwd_weight: dwb = [dW (27*16*16) | db (16)] fp32 of sum(g * y)
+ * with respect to the weights and bias, with a device workspace of
+ * mfr_cnn_wgrad_workspace_size bytes. */
+mfr_status mfr_cnn_conv(int32_t nx, int32_t ny, int32_t nz, const uint16_t* x, const uint16_t* w,
+                        const float* bias, int32_t relu, float* y32, uint16_t* y16, void* hip_stream);
+mfr_status mfr_cnn_conv_bwd_data(int32_t nx, int32_t ny, int32_t nz, const uint16_t* g, const uint16_t* w,
+                                 const uint16_t* mask, float* dx32, uint16_t* dx16, void* hip_stream);
+mfr_status mfr_cnn_wgrad_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes);
+mfr_status mfr_cnn_conv_bwd_weight(int32_t nx, int32_t ny, int32_t nz, const uint16_t* x, const uint16_t* g,
+                                   float* dwb, void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---- Tile configuration ---------------------------------------------------------
  * Shape of the voxel-tile work-groups (bx x by threads: 32x16, 64x8, 32x32 or

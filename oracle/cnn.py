@@ -138,9 +138,14 @@ def features(r, diag, gR):
 
 
 def apply(params, r, diag, gR, round_hidden=False):
-    """z = D^-1 r + rms(D^-1 r) * CNN(features)[:3] (node vector [3, nz, ny, nx])."""
+    """z = D^-1 r + rms(D^-1 r) * CNN(features)[:3] (node vector [3, nz, ny, nx]).
+    round_hidden: the input features and hidden activations are rounded to
+    bfloat16, as the device network stores them."""
     y = np.asarray(r, dtype=np.float64) / np.asarray(diag, dtype=np.float64)
-    o = forward(params, features(r, diag, gR), round_hidden)[-1]
+    h0 = features(r, diag, gR)
+    if round_hidden:
+        h0 = bf16_round(h0)
+    o = forward(params, h0, round_hidden)[-1]
     return y + rms(y) * np.moveaxis(o[..., :OUT_USED], -1, 0)
 
 

@@ -523,6 +523,26 @@ mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q
   return MFR_OK;
 }
 
+// float64 dot products into context scalars: out[k] = a[k] . b[k] (b null: a . a).
+static mfr_status ctx_dots(mfr_ctx* c, double* red, int count, const float* const* a, const float* const* b,
+                           const int* slots) {
+  DotsArgs d{};
+  DotsOut o{};
+  d.n = 3 * c->geo.nbar;
+  d.count = count;
+  for (int k = 0; k < count; ++k) {
+    d.a[k] = a[k];
+    d.b[k] = b ? b[k] : nullptr;
+    o.out[k] = c->sc + slots[k];
+  }
+  HIP_TRY(launch_pc_dots(d, o, red, c->stream));
+  return MFR_OK;
+}
+
+// Preconditioned CG (Sec. 2.3.1; CG from s = 0, relative recursive residual).
+// precond 1: Jacobi.  precond 2: the attached learned preconditioner with the
+// flexible direction update beta = z_{k+1}.(r_{k+1} - r_k) / z_k.r_k, optionally
+// switching to Jacobi after fallback_iters iterations.
 mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
                    mfr_pcg_info* info) {
   const int n3 = (int)(3 * c->geo.nbar);
@@ -532,18 +552,31 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
   float* p = c->vec[2];
   float* q = c->vec[3];
   float* diag = nullptr;
-  if (o->precond == 1) {
+  bool flexible = o->precond == 2;
+  if (flexible && !c->pc) return fail(MFR_EINVAL, "precond 2 needs a preconditioner attached with mfr_attach_pc");
+  if (o->precond >= 1) {
     diag = c->vec[4];
     HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
   }
   const int vb = c->vec_blocks;
-  HIP_TRY(launch_pcg_init(n3, b, diag, s, r, z, p, c->red_node, vb, c->stream));
+  HIP_TRY(launch_pcg_init(n3, b, flexible ? nullptr : diag, s, r, z, p, c->red_node, vb, c->stream));
   HIP_TRY(launch_pcg_init_finish(c->red_node, vb, c->sc, c->stream));
+  double* fred = flexible ? pc_red(c->pc) : nullptr;
+  float* r_prev = flexible ? pc_scratch_vec(c->pc) : nullptr;
+  if (flexible) {
+    MFR_TRY(pc_begin_solve(c->pc, diag));
+    MFR_TRY(pc_forward(c->pc, r, diag, z));
+    HIP_TRY(hipMemcpyAsync(p, z, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
+    const float* a[1] = {z};
+    const float* bb[1] = {r};
+    const int sl[1] = {SC_RZ};
+    MFR_TRY(ctx_dots(c, fred, 1, a, bb, sl));
+  }
   double h[SC_COUNT];
   HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const double bn = std::sqrt(h[SC_BB]);
-  mfr_pcg_info inf{0, 0.0, 1};
+  mfr_pcg_info inf{0, 0.0, 1, 0};
   if (!std::isfinite(bn)) return fail(MFR_ENONFINITE, "right-hand side is not finite");
   if (bn == 0.0) {
     inf.flag = 0;
@@ -554,8 +587,16 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
   for (int it = 1; it <= o->max_iter; ++it) {
     MFR_TRY(enqueue_hess_vec(c, u, p, q));
     HIP_TRY(launch_pcg_alpha(c->red_node, node_blocks(c), c->sc, c->stream));
-    HIP_TRY(launch_pcg_update(n3, diag, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
-    HIP_TRY(launch_pcg_beta(c->red_node, vb, c->sc, c->stream));
+    if (flexible) {
+      HIP_TRY(hipMemcpyAsync(r_prev, r, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(launch_pcg_update(n3, nullptr, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
+      const float* a[1] = {r};
+      const int sl[1] = {SC_RR};
+      MFR_TRY(ctx_dots(c, fred, 1, a, nullptr, sl));
+    } else {
+      HIP_TRY(launch_pcg_update(n3, diag, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
+      HIP_TRY(launch_pcg_beta(c->red_node, vb, c->sc, c->stream));
+    }
     HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     const double pq = h[SC_PQ];
@@ -571,6 +612,26 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
       break;
     }
     if (it == o->max_iter) break;
+    if (flexible && o->fallback_iters > 0 && it >= o->fallback_iters) {
+      // continue as Jacobi-PCG from the current iterate: z = D^-1 r, p = z
+      flexible = false;
+      inf.used_fallback = 1;
+      HIP_TRY(launch_pc_jacobi(n3, r, diag, z, c->stream));
+      HIP_TRY(hipMemcpyAsync(p, z, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
+      const float* a[1] = {z};
+      const float* bb[1] = {r};
+      const int sl[1] = {SC_RZ};
+      MFR_TRY(ctx_dots(c, fred, 1, a, bb, sl));
+      continue;
+    }
+    if (flexible) {
+      MFR_TRY(pc_forward(c->pc, r, diag, z));
+      const float* a[2] = {z, z};
+      const float* bb[2] = {r, r_prev};
+      const int sl[2] = {SC_ZR, SC_ZRP};
+      MFR_TRY(ctx_dots(c, fred, 2, a, bb, sl));
+      HIP_TRY(launch_fpcg_beta(c->sc, c->stream));
+    }
     HIP_TRY(launch_pcg_direction(n3, z, p, c->sc, vb, c->stream));
   }
   if (info) *info = inf;
@@ -591,7 +652,7 @@ mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out)
   inf.J_before = Jv;
   inf.J_after = Jv;
   HIP_TRY(launch_axpy(n3, b, -2.0f, b, b, c->stream));   // b <- -grad J
-  mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond};
+  mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond, o->fallback_iters};
   mfr_pcg_info pinf{};
   MFR_TRY(pcg_run(c, u, b, dir, &po, &pinf));
   inf.pcg_iters = pinf.iters;
@@ -674,6 +735,7 @@ mfr_status mfr_set_images(mfr_ctx* c, const float* R, const float* T) {
   c->dp.t.R = R;
   c->jp.t.R = R;
   c->have_images = true;
+  ++c->image_version;
   return MFR_OK;
 }
 
@@ -715,9 +777,10 @@ mfr_status mfr_gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* 
   MFR_TRY(need_images(c));
   MFR_TRY(check_ptr(u, "u"));
   if (!o) return fail(MFR_EINVAL, "opts is NULL");
-  if (o->pcg_max < 0 || !(o->pcg_rtol >= 0) || o->precond < 0 || o->precond > 1 ||
-      !(o->armijo_c1 >= 0 && o->armijo_c1 < 1) || o->armijo_max < 1)
+  if (o->pcg_max < 0 || !(o->pcg_rtol >= 0) || o->precond < 0 || o->precond > 2 ||
+      !(o->armijo_c1 >= 0 && o->armijo_c1 < 1) || o->armijo_max < 1 || o->fallback_iters < 0)
     return fail(MFR_EINVAL, "invalid Gauss-Newton options");
+  if (o->precond == 2 && !c->pc) return fail(MFR_EINVAL, "precond 2 needs a preconditioner attached with mfr_attach_pc");
   for (int k = 5; k < 8; ++k)
     if (u == c->vec[k]) return fail(MFR_EINVAL, "u must not point into the context workspace");
   return gn_step(c, u, o, info);
@@ -775,7 +838,7 @@ mfr_status mfr_pcg_solve(mfr_ctx* c, const float* u, const float* b, float* s, c
   MFR_TRY(check_ptr(b, "b"));
   MFR_TRY(check_ptr(s, "s"));
   if (!opts) return fail(MFR_EINVAL, "opts is NULL");
-  if (opts->max_iter < 0 || !(opts->rtol >= 0) || opts->precond < 0 || opts->precond > 1)
+  if (opts->max_iter < 0 || !(opts->rtol >= 0) || opts->precond < 0 || opts->precond > 2 || opts->fallback_iters < 0)
     return fail(MFR_EINVAL, "invalid PCG options");
   if (s == u || s == b) return fail(MFR_EINVAL, "s must not alias u or b");
   return pcg_run(c, u, b, s, opts, info);
@@ -911,7 +974,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
       ~Guard() { mfr_destroy(c); }
     } guard{c};
     MFR_TRY(mfr_set_images(c, at<float>(ws, L[l].off_R), at<float>(ws, L[l].off_T)));
-    mfr_gn_opts go{o->pcg_max, o->pcg_rtol, o->precond, o->armijo_c1, o->armijo_max};
+    mfr_gn_opts go{o->pcg_max, o->pcg_rtol, o->precond, o->armijo_c1, o->armijo_max, 0};
     int gn_done = 0, pcg_tot = 0, status = 0;
     double Jv = 0.0;
     MFR_TRY(mfr_objective(c, ul, &Jv, nullptr, nullptr));

@@ -102,6 +102,8 @@ struct mfr_ctx {
   double* red_node;
   float* vec[8];
   int vec_blocks;
+  mfr_pc* pc = nullptr;          // learned preconditioner used by precond = 2
+  unsigned image_version = 0;    // bumped by mfr_set_images
   // kernel timing (mfr_profile_*)
   bool prof_on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
@@ -130,5 +132,11 @@ mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q
 mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
                    mfr_pcg_info* info);
 mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out);
+
+// learned preconditioner (pc.cpp) as used by the flexible CG of pcg_run
+mfr_status pc_begin_solve(mfr_pc* pc, const float* diag);
+mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z);
+float* pc_scratch_vec(mfr_pc* pc);
+double* pc_red(mfr_pc* pc);
 
 }  // namespace mfr

@@ -225,7 +225,8 @@ constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi
 // PCG vector kernels.  sc: device scalars (see PcgSlot).
 enum PcgSlot : int {
   SC_BB = 0, SC_RZ = 1, SC_PQ = 2, SC_RR = 3, SC_RZNEW = 4, SC_ALPHA = 5, SC_BETA = 6,
-  SC_D = 8, SC_S = 9, SC_J = 10, SC_DOT = 11, SC_RELRES = 12, SC_RTOL = 13, SC_COUNT = 16
+  SC_D = 8, SC_S = 9, SC_J = 10, SC_DOT = 11, SC_RELRES = 12, SC_RTOL = 13, SC_ZR = 14, SC_ZRP = 15,
+  SC_COUNT = 16
 };
 hipError_t launch_pcg_init(int n3, const float* b, const float* diag, float* s, float* r, float* z,
                            float* p, double* red, int blocks, hipStream_t st);
@@ -260,5 +261,86 @@ hipError_t launch_pcg_alpha_batch(const VecJobs& j, hipStream_t st);
 hipError_t launch_pcg_update_batch(const VecJobs& j, hipStream_t st);
 hipError_t launch_pcg_beta_batch(const VecJobs& j, hipStream_t st);
 hipError_t launch_pcg_direction_batch(const VecJobs& j, hipStream_t st);
+
+// ---- learned preconditioner (cnn_kernels.hip, pc_kernels.hip) ---------------------
+constexpr int kCnnLayers = 4;
+constexpr int kCnnWeights = 27 * 16 * 16;                 // per layer
+constexpr int kCnnLayerParams = kCnnWeights + 16;         // weights then biases
+constexpr int kCnnParams = kCnnLayers * kCnnLayerParams;
+
+// One 3x3x3 convolution launch.  x: input activations [n][16] bf16; w: [27][16][16]
+// bf16.  transpose = 1 computes the backward-data product (flipped taps, in/out
+// channels swapped).  Epilogue: + bias (nullable), ReLU, zero where mask <= 0
+// (nullable), then any of: bf16 output y16, fp32 output y32 (both [n][16]), and
+// the preconditioner output z[d][n] = r[d][n] / diag[d][n] + scale * out[d] (d < 3).
+struct ConvArgs {
+  int nx, ny, nz;
+  const uint16_t* x;
+  const uint16_t* w;
+  const float* bias;
+  int transpose, relu;
+  const uint16_t* mask;
+  uint16_t* y16;
+  float* y32;
+  float* z;
+  const float* r;
+  const float* diag;
+  const double* scale;
+};
+
+struct AdamArgs {
+  float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
+};
+
+hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st);
+
+// Scalars of the learned preconditioner (device doubles).
+enum PcSlot : int {
+  PC_RMS_Y = 0, PC_RMS_R = 1, PC_RMS_D = 2, PC_RMS_G = 3, PC_ZR = 4, PC_ZAZ = 5, PC_YR = 6, PC_YAY = 7,
+  PC_LOSS = 8, PC_CA = 9, PC_CR = 10, PC_COUNT = 16
+};
+
+// Up to four float64 dot products a_k . b_k over n floats (b_k null: a_k . a_k;
+// den_k non-null: a_k / den_k elementwise), summed in a fixed order into *out[k];
+// rms_scale[k] > 0 stores sqrt(sum * rms_scale[k]) instead.
+struct DotsArgs {
+  size_t n;
+  int count;
+  const float* a[4];
+  const float* b[4];
+  const float* den[4];
+};
+struct DotsOut {
+  double* out[4];
+  double rms_scale[4];
+};
+int pc_dots_blocks(size_t n);   // partials per product (red needs 4 x this many doubles)
+hipError_t launch_pc_dots(const DotsArgs& d, const DotsOut& o, double* red, hipStream_t st);
+hipError_t launch_pc_features(int n, const float* r, const float* diag, const float* gR, const double* sc,
+                              uint16_t* h0, hipStream_t st);
+hipError_t launch_pc_jacobi(int n3, const float* r, const float* diag, float* y, hipStream_t st);
+hipError_t launch_pc_loss(double* sc, hipStream_t st);
+hipError_t launch_pc_grad_out(int n, const float* Az, const float* r, const double* sc, uint16_t* g16,
+                              hipStream_t st);
+
+// |grad R| restricted to the nodes (separable transposed grid conversion).
+struct GmArgs {
+  int mx, my, mz, nx, ny, nz;
+  const float* R;
+  const Conv1 *cx, *cy, *cz;
+  const Range1 *rx, *ry, *rz;
+  const float *wsx, *wsy, *wsz;   // per node: sum of its conversion weights along the axis
+  float ih2x, ih2y, ih2z;
+};
+// tmp1: mz*my*nx floats, tmp2: mz*ny*nx floats, gR: nz*ny*nx floats
+hipError_t launch_pc_gradmag(const GmArgs& g, float* tmp1, float* tmp2, float* gR, hipStream_t st);
+hipError_t launch_fpcg_beta(double* sc, hipStream_t st);
+int cnn_wgrad_groups(int nx, int ny, int nz);
+// part: cnn_wgrad_groups(...) x kCnnLayerParams floats; out: kCnnLayerParams floats
+hipError_t launch_cnn_wgrad(int nx, int ny, int nz, const uint16_t* x, const uint16_t* g, float* part,
+                            float* out, hipStream_t st);
+hipError_t launch_cnn_cast(float* params, uint16_t* w16, hipStream_t st);
+hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, uint16_t* w16, const AdamArgs& h,
+                           hipStream_t st);
 
 }  // namespace mfr

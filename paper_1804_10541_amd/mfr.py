@@ -34,16 +34,18 @@ class CGrid(ctypes.Structure):
 
 
 class CPcgOpts(ctypes.Structure):
-    _fields_ = [("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double), ("precond", ctypes.c_int32)]
+    _fields_ = [("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("fallback_iters", ctypes.c_int32)]
 
 
 class CPcgInfo(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double), ("flag", ctypes.c_int32)]
+    _fields_ = [("iters", ctypes.c_int32), ("relres", ctypes.c_double), ("flag", ctypes.c_int32),
+                ("used_fallback", ctypes.c_int32)]
 
 
 class CGnOpts(ctypes.Structure):
     _fields_ = [("pcg_max", ctypes.c_int32), ("pcg_rtol", ctypes.c_double), ("precond", ctypes.c_int32),
-                ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32)]
+                ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32), ("fallback_iters", ctypes.c_int32)]
 
 
 class CGnInfo(ctypes.Structure):
@@ -81,6 +83,19 @@ class CBatchReport(ctypes.Structure):
                 ("graph_launches", ctypes.c_int32), ("seconds", ctypes.c_double)]
 
 
+PC_PARAMS = 4 * (27 * 16 * 16 + 16)
+
+
+class CPcTrainOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("pcg_iters", ctypes.c_int32), ("sample_every", ctypes.c_int32)]
+
+
+class CPcTrainInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("loss_mean", ctypes.c_double)]
+
+
 PROFILE_KERNELS = ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass")
 
 _lib = None
@@ -110,6 +125,18 @@ SIGNATURES = {
     "mfr_batch_hess_vec": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
     "mfr_batch_register": (ctypes.c_int, [_VP, ctypes.POINTER(CMlOpts), _I, ctypes.POINTER(_VP),
                                           ctypes.POINTER(CBatchReport)]),
+    "mfr_pc_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
+    "mfr_pc_create": (ctypes.c_int, [_VP, _I, _VP, _SZ, ctypes.POINTER(_VP)]),
+    "mfr_pc_destroy": (None, [_VP]),
+    "mfr_pc_set_params": (ctypes.c_int, [_VP, _VP]),
+    "mfr_pc_get_params": (ctypes.c_int, [_VP, _VP]),
+    "mfr_pc_apply": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mfr_pc_train_system": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(CPcTrainOpts), ctypes.POINTER(CPcTrainInfo)]),
+    "mfr_attach_pc": (ctypes.c_int, [_VP, _VP]),
+    "mfr_cnn_conv": (ctypes.c_int, [_I, _I, _I, _VP, _VP, _VP, _I, _VP, _VP, _VP]),
+    "mfr_cnn_conv_bwd_data": (ctypes.c_int, [_I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "mfr_cnn_wgrad_workspace_size": (ctypes.c_int, [_I, _I, _I, ctypes.POINTER(_SZ)]),
+    "mfr_cnn_conv_bwd_weight": (ctypes.c_int, [_I, _I, _I, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "mfr_set_tile_config": (ctypes.c_int, [ctypes.POINTER(CTileConfig)]),
     "mfr_get_tile_config": (ctypes.c_int, [ctypes.POINTER(CTileConfig)]),
     "mfr_profile_enable": (ctypes.c_int, [_VP, _I]),
@@ -254,9 +281,10 @@ class Context:
                                         _dev_tensor(out, 3 * self.nbar, "diag", self.device)))
         return out
 
-    def gn_step(self, u, pcg_max=50, pcg_rtol=1e-3, precond=1, armijo_c1=1e-4, armijo_max=10):
+    def gn_step(self, u, pcg_max=50, pcg_rtol=1e-3, precond=1, armijo_c1=1e-4, armijo_max=10, fallback_iters=0):
         """One Gauss-Newton step; u (device, float32) is updated in place."""
-        opts = CGnOpts(int(pcg_max), float(pcg_rtol), int(precond), float(armijo_c1), int(armijo_max))
+        opts = CGnOpts(int(pcg_max), float(pcg_rtol), int(precond), float(armijo_c1), int(armijo_max),
+                       int(fallback_iters))
         info = CGnInfo()
         _check(self.lib.mfr_gn_step(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device), ctypes.byref(opts),
                                     ctypes.byref(info)))
@@ -272,15 +300,20 @@ class Context:
         _check(self.lib.mfr_profile_read(self._h, ctypes.byref(st), 1 if reset else 0))
         return {k: (st.launches[i], st.ms[i]) for i, k in enumerate(PROFILE_KERNELS)}
 
-    def pcg_solve(self, u, b, max_iter=50, rtol=1e-3, precond=1, out=None):
+    def pcg_solve(self, u, b, max_iter=50, rtol=1e-3, precond=1, fallback_iters=0, out=None):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
-        opts = CPcgOpts(int(max_iter), float(rtol), int(precond))
+        opts = CPcgOpts(int(max_iter), float(rtol), int(precond), int(fallback_iters))
         info = CPcgInfo()
         _check(self.lib.mfr_pcg_solve(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
                                       _dev_tensor(b, 3 * self.nbar, "b", self.device),
                                       _dev_tensor(out, 3 * self.nbar, "s", self.device),
                                       ctypes.byref(opts), ctypes.byref(info)))
-        return out, dict(iters=info.iters, relres=info.relres, flag=info.flag)
+        return out, dict(iters=info.iters, relres=info.relres, flag=info.flag, used_fallback=info.used_fallback)
+
+    def attach_pc(self, pc):
+        """Use a LearnedPC of this context for precond = 2 (None detaches)."""
+        _check(self.lib.mfr_attach_pc(self._h, None if pc is None else pc._h))
+        self._pc = pc
 
 
 def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=1e-3, armijo_c1=1e-4,
@@ -427,3 +460,121 @@ class Batch:
         return us, dict(J_final=list(rep.J_final)[:n], gn_done=list(rep.gn_done)[:n],
                         pcg_total=list(rep.pcg_total)[:n], status=list(rep.status)[:n],
                         graph_launches=rep.graph_launches, seconds=rep.seconds)
+
+
+class LearnedPC:
+    """The learned preconditioner of one context (see include/mfr.h)."""
+
+    def __init__(self, ctx, train=False):
+        self.lib = load()
+        self.ctx = ctx
+        self.train = bool(train)
+        n = ctypes.c_size_t()
+        _check(self.lib.mfr_pc_workspace_size(ctypes.byref(ctx.grid), 1 if train else 0, ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self._ws, ptr = _alloc_workspace(self.ws_bytes, ctx.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.mfr_pc_create(ctx._h, 1 if train else 0, ctypes.c_void_p(ptr), self.ws_bytes,
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            if getattr(self.ctx, "_pc", None) is self:
+                self.ctx.attach_pc(None)
+            self.lib.mfr_pc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        if a.size != PC_PARAMS:
+            raise ValueError(f"expected {PC_PARAMS} parameters, got {a.size}")
+        _check(self.lib.mfr_pc_set_params(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        import numpy as np
+
+        a = np.empty(PC_PARAMS, dtype=np.float32)
+        _check(self.lib.mfr_pc_get_params(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def apply(self, u, r, out=None):
+        c = self.ctx
+        out = torch.empty(c.node_shape(), dtype=torch.float32, device=c.device) if out is None else out
+        _check(self.lib.mfr_pc_apply(self._h, _dev_tensor(u, 3 * c.nbar, "u", c.device),
+                                     _dev_tensor(r, 3 * c.nbar, "r", c.device),
+                                     _dev_tensor(out, 3 * c.nbar, "z", c.device)))
+        return out
+
+    def train_system(self, u, b, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, pcg_iters=20, sample_every=4):
+        c = self.ctx
+        opts = CPcTrainOpts(float(lr), float(beta1), float(beta2), float(eps), int(pcg_iters), int(sample_every))
+        info = CPcTrainInfo()
+        _check(self.lib.mfr_pc_train_system(self._h, _dev_tensor(u, 3 * c.nbar, "u", c.device),
+                                            _dev_tensor(b, 3 * c.nbar, "b", c.device), ctypes.byref(opts),
+                                            ctypes.byref(info)))
+        return {f[0]: getattr(info, f[0]) for f in CPcTrainInfo._fields_}
+
+
+def _bf16_tensor(x, numel, name, device):
+    if not isinstance(x, torch.Tensor) or x.dtype not in (torch.bfloat16, torch.int16):
+        raise TypeError(f"{name} must be a bfloat16 tensor")
+    if x.device != device or not x.is_contiguous() or x.numel() != numel:
+        raise ValueError(f"{name}: expected a contiguous tensor of {numel} elements on {device}")
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def cnn_conv(x, w, bias=None, relu=False, out32=True, out16=False):
+    """One 3x3x3 convolution on the device: x [nz, ny, nx, 16] bf16, w [27, 16, 16]
+    bf16, bias [16] float32.  Returns (y32 or None, y16 or None)."""
+    lib = load()
+    nz, ny, nx = (int(k) for k in x.shape[:3])
+    dev = x.device
+    n = nx * ny * nz
+    y32 = torch.empty((nz, ny, nx, 16), dtype=torch.float32, device=dev) if out32 else None
+    y16 = torch.empty((nz, ny, nx, 16), dtype=torch.bfloat16, device=dev) if out16 else None
+    b = None if bias is None else _dev_tensor(bias, 16, "bias", dev)
+    _check(lib.mfr_cnn_conv(nx, ny, nz, _bf16_tensor(x, 16 * n, "x", dev), _bf16_tensor(w, 27 * 256, "w", dev), b,
+                            1 if relu else 0, None if y32 is None else _dev_tensor(y32, 16 * n, "y32", dev),
+                            None if y16 is None else ctypes.c_void_p(y16.data_ptr()), _stream(dev)))
+    return y32, y16
+
+
+def cnn_conv_bwd_data(g, w, mask=None, out32=True, out16=False):
+    """Gradient with respect to the input of a convolution, zeroed where mask <= 0."""
+    lib = load()
+    nz, ny, nx = (int(k) for k in g.shape[:3])
+    dev = g.device
+    n = nx * ny * nz
+    d32 = torch.empty((nz, ny, nx, 16), dtype=torch.float32, device=dev) if out32 else None
+    d16 = torch.empty((nz, ny, nx, 16), dtype=torch.bfloat16, device=dev) if out16 else None
+    m = None if mask is None else _bf16_tensor(mask, 16 * n, "mask", dev)
+    _check(lib.mfr_cnn_conv_bwd_data(nx, ny, nz, _bf16_tensor(g, 16 * n, "g", dev), _bf16_tensor(w, 27 * 256, "w", dev),
+                                     m, None if d32 is None else _dev_tensor(d32, 16 * n, "dx32", dev),
+                                     None if d16 is None else ctypes.c_void_p(d16.data_ptr()), _stream(dev)))
+    return d32, d16
+
+
+def cnn_conv_bwd_weight(x, g):
+    """(dW [27, 16, 16], db [16]) float32 of sum(g * conv(x))."""
+    lib = load()
+    nz, ny, nx = (int(k) for k in x.shape[:3])
+    dev = x.device
+    n = nx * ny * nz
+    nb = ctypes.c_size_t()
+    _check(lib.mfr_cnn_wgrad_workspace_size(nx, ny, nz, ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value // 4, 1), dtype=torch.float32, device=dev)
+    out = torch.empty(27 * 256 + 16, dtype=torch.float32, device=dev)
+    _check(lib.mfr_cnn_conv_bwd_weight(nx, ny, nz, _bf16_tensor(x, 16 * n, "x", dev), _bf16_tensor(g, 16 * n, "g", dev),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                       _stream(dev)))
+    torch.cuda.current_stream(dev).synchronize()
+    return out[:27 * 256].view(27, 16, 16), out[27 * 256:]
