@@ -113,6 +113,27 @@ def batch_leg(dev, tune):
             "identical_to_sequential": bool(same), "tile_config": cfg}
 
 
+def pc_leg(dev):
+    """PCG solve time to relative residual 1e-3, flexible CG with the learned
+    preconditioner (Jacobi fallback after twice the Jacobi count) against
+    Jacobi-PCG on the same held-out Gauss-Newton systems."""
+    import numpy as np
+
+    from paper_1804_10541_amd import pc_train
+
+    if not os.path.exists(pc_train.WEIGHTS):
+        return {"skipped": f"no trained weights at {os.path.relpath(pc_train.WEIGHTS, ROOT)}"}
+    params = np.load(pc_train.WEIGHTS)
+    out = {"weights": os.path.relpath(pc_train.WEIGHTS, ROOT), "rtol": 1e-3}
+    for name, seeds, spec in (("128x128x96", [200], pc_train.workload_spec()),
+                              ("512x512x128", [201], pc_train.c4_specs()[8])):
+        rows = pc_train.evaluate(params, seeds, gn_iters=4, spec=spec, device=dev)
+        summ = pc_train.summarize(rows)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"[bench] learned preconditioner {name}: {out[name]}")
+    return out
+
+
 def cpu_baseline(R, T, u0, spec, budget_s=25.0):
     """The float64 oracle, as it stands, on a crop of the same volume: one
     Gauss-Newton step's derivative work (objective, gradient, Jacobi diagonal,
@@ -164,6 +185,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the ten-pair batched registration leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile configuration")
+    ap.add_argument("--no-pc", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -270,6 +292,9 @@ def main():
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
         out["batch"] = batch_leg(dev, not args.no_autotune)
+    if not args.no_pc and args.workload != "small":
+        log("[bench] learned preconditioner vs Jacobi")
+        out["pcg_learned_vs_jacobi"] = pc_leg(dev)
     if not args.no_cpu_baseline:
         log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(R, T, u0, spec)

@@ -271,6 +271,11 @@ mfr_status mfr_pc_workspace_size(const mfr_grid* grid, int32_t train, size_t* by
  * The context must have images; |grad R| is recomputed when they change. */
 mfr_status mfr_pc_create(mfr_ctx* ctx, int32_t train, void* workspace, size_t ws_bytes, mfr_pc** out);
 void mfr_pc_destroy(mfr_pc* pc);
+/* Rebind to another context (another grid size; the network parameters and
+ * optimiser state are kept).  The workspace must be large enough for that
+ * context's grid (MFR_ENOMEM otherwise).  Detaches the preconditioner from its
+ * previous context. */
+mfr_status mfr_pc_bind(mfr_pc* pc, mfr_ctx* ctx);
 /* Copy MFR_PC_PARAMS floats from / to host memory (synchronous). */
 mfr_status mfr_pc_set_params(mfr_pc* pc, const float* params);
 mfr_status mfr_pc_get_params(mfr_pc* pc, float* params);

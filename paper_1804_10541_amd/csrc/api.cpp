@@ -588,11 +588,9 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
     MFR_TRY(enqueue_hess_vec(c, u, p, q));
     HIP_TRY(launch_pcg_alpha(c->red_node, node_blocks(c), c->sc, c->stream));
     if (flexible) {
-      HIP_TRY(hipMemcpyAsync(r_prev, r, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
-      HIP_TRY(launch_pcg_update(n3, nullptr, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
-      const float* a[1] = {r};
-      const int sl[1] = {SC_RR};
-      MFR_TRY(ctx_dots(c, fred, 1, a, nullptr, sl));
+      // s += alpha p, r_prev = r, r -= alpha q, and the RMS scales of the next network input
+      HIP_TRY(launch_fpcg_update(n3, diag, p, q, s, r, r_prev, c->sc, c->red_node, vb, c->stream));
+      HIP_TRY(launch_fpcg_scales(c->red_node, vb, n3, c->sc, pc_scalars(c->pc), c->stream));
     } else {
       HIP_TRY(launch_pcg_update(n3, diag, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
       HIP_TRY(launch_pcg_beta(c->red_node, vb, c->sc, c->stream));
@@ -625,12 +623,9 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
       continue;
     }
     if (flexible) {
-      MFR_TRY(pc_forward(c->pc, r, diag, z));
-      const float* a[2] = {z, z};
-      const float* bb[2] = {r, r_prev};
-      const int sl[2] = {SC_ZR, SC_ZRP};
-      MFR_TRY(ctx_dots(c, fred, 2, a, bb, sl));
-      HIP_TRY(launch_fpcg_beta(c->sc, c->stream));
+      // z = M(r); the last layer leaves the partials of z.r and z.r_prev for beta
+      MFR_TRY(pc_forward(c->pc, r, diag, z, true, r_prev, fred));
+      HIP_TRY(launch_fpcg_beta_sum(fred, pc_conv_blocks(c->pc), c->sc, c->stream));
     }
     HIP_TRY(launch_pcg_direction(n3, z, p, c->sc, vb, c->stream));
   }

@@ -105,6 +105,14 @@ mfr_status enter_level(mfr_batch* b, int l) {
   return MFR_OK;
 }
 
+// Small device-to-host read after the batch stream has drained (a blocking copy
+// into pageable host memory).
+mfr_status read_back(mfr_batch* b, void* dst, const void* src, size_t bytes) {
+  HIP_TRY(hipStreamSynchronize(b->st));
+  HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  return MFR_OK;
+}
+
 // Fills the persistent work list of a voxel-tile launch.
 BatchJobs tile_jobs(mfr_batch* b, const float* const* u, const float* const* p, const int* active) {
   BatchJobs J{};
@@ -303,14 +311,13 @@ mfr_status batch_pcg(mfr_batch* b, const float* const* u, const mfr_ml_opts* o, 
       MFR_TRY(cg_iteration(b, V, u));
       done += 1;
     }
-    HIP_TRY(hipMemcpyAsync(act, b->active, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->st));
-    HIP_TRY(hipStreamSynchronize(b->st));
+    MFR_TRY(read_back(b, act, b->active, sizeof(int) * b->n));
     bool any = false;
     for (int k = 0; k < b->n; ++k) any = any || act[k] != 0;
     if (!any) break;
   }
   int stt[ST_COUNT * kMaxBatch];
-  HIP_TRY(hipMemcpy(stt, b->state, sizeof(int) * ST_COUNT * b->n, hipMemcpyDeviceToHost));
+  MFR_TRY(read_back(b, stt, b->state, sizeof(int) * ST_COUNT * b->n));
   for (int k = 0; k < b->n; ++k) iters[k] = stt[ST_COUNT * k + ST_ITERS];
   return MFR_OK;
 }

@@ -48,7 +48,7 @@ __device__ __forceinline__ int find_job(const int (&prefix)[N], int n, int item)
 __global__ __launch_bounds__(256) void sum_batch_kernel(const SumJobs J) {
   __shared__ double sred[4];
   const SumJob& s = J.jobs[blockIdx.x];
-  if (J.active && !J.active[blockIdx.x]) return;
+  if (J.active && !ld_coherent(J.active + blockIdx.x)) return;
   double a = 0.0;
   for (int i = threadIdx.x; i < s.n; i += 256) a += s.parts[i * s.stride];
   a = block_sum<256>(a, sred);
@@ -73,7 +73,7 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t st) {
 // y_j = x_j + eta_j s_j for active problems
 __global__ __launch_bounds__(kVecBlock) void axpy_batch_kernel(const AxpyJobs J) {
   const int pr = find_job(J.prefix, J.n, blockIdx.x);
-  if (J.active && !J.active[pr]) return;
+  if (J.active && !ld_coherent(J.active + pr)) return;
   const AxpyJob& a = J.jobs[pr];
   const int nb = J.prefix[pr + 1] - J.prefix[pr];
   for (int i = (blockIdx.x - J.prefix[pr]) * kVecBlock + threadIdx.x; i < a.n; i += nb * kVecBlock)
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void pcg_alpha_batch_kernel(const VecJobs J) {
   __shared__ double sred[4];
   const int pr = blockIdx.x;
   const VecJob& v = J.jobs[pr];
-  if (!v.state[ST_ACTIVE]) return;
+  if (!ld_coherent(v.state + ST_ACTIVE)) return;
   double a = 0.0;
   for (int i = threadIdx.x; i < v.n_pq; i += 256) a += v.red_pq[i];
   const double pq = block_sum<256>(a, sred);
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void pcg_alpha_batch_kernel(const VecJobs J) {
     double* sc = v.sc;
     sc[SC_PQ] = pq;
     if (pq > 0.0 && isfinite(pq)) {
-      sc[SC_ALPHA] = sc[SC_RZ] / pq;
+      sc[SC_ALPHA] = ld_coherent(sc + SC_RZ) / pq;
     } else {
       sc[SC_ALPHA] = 0.0;
       v.state[ST_FLAG] = 2;
@@ -197,9 +197,9 @@ __global__ __launch_bounds__(kVecBlock) void pcg_update_batch_kernel(const VecJo
   __shared__ double sred[kVecBlock / 64];
   const int pr = find_job(J.prefix, J.n, blockIdx.x);
   const VecJob& v = J.jobs[pr];
-  if (!v.state[ST_ACTIVE]) return;
+  if (!ld_coherent(v.state + ST_ACTIVE)) return;
   const int lb = blockIdx.x - J.prefix[pr], nb = J.prefix[pr + 1] - J.prefix[pr];
-  const float alpha = (float)v.sc[SC_ALPHA];
+  const float alpha = (float)ld_coherent(v.sc + SC_ALPHA);
   double rr = 0.0, rz = 0.0;
   for (int i = lb * kVecBlock + threadIdx.x; i < v.n3; i += nb * kVecBlock) {
     const float ri = fmaf(-alpha, v.q[i], v.r[i]);
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void pcg_beta_batch_kernel(const VecJobs J) {
   __shared__ double sred[4];
   const int pr = blockIdx.x;
   const VecJob& v = J.jobs[pr];
-  if (!v.state[ST_ACTIVE]) return;
+  if (!ld_coherent(v.state + ST_ACTIVE)) return;
   const int nb = J.prefix[pr + 1] - J.prefix[pr];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) {
@@ -240,21 +240,23 @@ __global__ __launch_bounds__(256) void pcg_beta_batch_kernel(const VecJobs J) {
   if (threadIdx.x == 0) {
     double* sc = v.sc;
     int* st = v.state;
+    const double rz_old = ld_coherent(sc + SC_RZ), bb = ld_coherent(sc + SC_BB), rtol = ld_coherent(sc + SC_RTOL);
+    const int iters = ld_coherent(st + ST_ITERS) + 1, maxit = ld_coherent(st + ST_MAXIT);
     sc[SC_RR] = rr;
     sc[SC_RZNEW] = rz;
-    sc[SC_BETA] = rz / sc[SC_RZ];
+    sc[SC_BETA] = rz / rz_old;
     sc[SC_RZ] = rz;
-    st[ST_ITERS] += 1;
-    const double rel = sqrt(rr) / sqrt(sc[SC_BB]);
+    st[ST_ITERS] = iters;
+    const double rel = sqrt(rr) / sqrt(bb);
     sc[SC_RELRES] = rel;
-    if (rel <= sc[SC_RTOL]) {
+    if (rel <= rtol) {
       st[ST_FLAG] = 0;
       st[ST_ACTIVE] = 0;
-    } else if (st[ST_ITERS] >= st[ST_MAXIT]) {
+    } else if (iters >= maxit) {
       st[ST_FLAG] = 1;
       st[ST_ACTIVE] = 0;
     }
-    J.active_out[pr] = st[ST_ACTIVE];
+    J.active_out[pr] = (rel <= rtol || iters >= maxit) ? 0 : 1;
   }
 }
 
@@ -266,9 +268,9 @@ hipError_t launch_pcg_beta_batch(const VecJobs& j, hipStream_t st) {
 __global__ __launch_bounds__(kVecBlock) void pcg_direction_batch_kernel(const VecJobs J) {
   const int pr = find_job(J.prefix, J.n, blockIdx.x);
   const VecJob& v = J.jobs[pr];
-  if (!v.state[ST_ACTIVE]) return;
+  if (!ld_coherent(v.state + ST_ACTIVE)) return;
   const int lb = blockIdx.x - J.prefix[pr], nb = J.prefix[pr + 1] - J.prefix[pr];
-  const float beta = (float)v.sc[SC_BETA];
+  const float beta = (float)ld_coherent(v.sc + SC_BETA);
   for (int i = lb * kVecBlock + threadIdx.x; i < v.n3; i += nb * kVecBlock) v.p[i] = fmaf(beta, v.p[i], v.z[i]);
 }
 

@@ -24,6 +24,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 constexpr int kTaps = 27;
 constexpr int kCh = 16;
 constexpr int kSteps = 14;   // ceil(27 / 2)
+constexpr int kTx = 16, kTy = 4, kTz = 4;   // output tile of the convolution kernel
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -41,6 +42,12 @@ __device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
   dx = t % 3 - 1;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ bf16x8 zero8() {
   uint4 z = make_uint4(0u, 0u, 0u, 0u);
   return __builtin_bit_cast(bf16x8, z);
@@ -52,9 +59,6 @@ __device__ __forceinline__ bf16x8 zero8() {
 __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, quad = lane >> 4;
-  const int nwaves = gridDim.x * 4;
-  const int gxn = (a.nx + 15) >> 4;
-  const int groups = gxn * a.ny * a.nz;
   const size_t nn = (size_t)a.nx * a.ny * a.nz;
 
   // A operand (weights): row = output channel col, k = 8 quad + e within the step:
@@ -69,6 +73,10 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
     } else if (a.transpose) {
       // W'[t][c][o] = W[26 - t][o][c]: contiguous in c
       const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((size_t)(kTaps - 1 - t) * kCh + col) * kCh + c0);
+      wa[j] = __builtin_bit_cast(bf16x8, v);
+    } else if (a.w_out_major) {
+      // weights given as [t][out][in]: contiguous in the input channel
+      const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((size_t)t * kCh + col) * kCh + c0);
       wa[j] = __builtin_bit_cast(bf16x8, v);
     } else {
       uint16_t e[8];
@@ -87,68 +95,112 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) bias[i] = a.bias[4 * quad + i];
   }
-  const float scale = a.z ? (float)*a.scale : 0.f;
+  const float scale = a.z ? (float)ld_coherent(a.scale) : 0.f;
+  double zr = 0.0, zrp = 0.0;
 
-  for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < groups; g += nwaves) {
-    const int gx = g % gxn;
-    const int rest = g / gxn;
-    const int y = rest % a.ny, z = rest / a.ny;
-    const int x = gx * 16 + col;   // node of this lane's B column
-    bf16x8 xb[kSteps];
+  // Output tiles of 16 (x) x 4 (y) x 4 (z) nodes: the block stages the input
+  // tile with a one-node halo (18 x 6 x 6 nodes, zero outside the grid) in LDS;
+  // wave w computes the x-rows (y, z) = rows w, w + 4, w + 8, w + 12 of the tile
+  // with four independent accumulators.
+  __shared__ __align__(16) uint16_t xs[kTz + 2][kTy + 2][kTx + 2][kCh];
+  const int wave = threadIdx.x >> 6;
+  const int tnx = (a.nx + kTx - 1) / kTx, tny = (a.ny + kTy - 1) / kTy, tnz = (a.nz + kTz - 1) / kTz;
+  const int tiles = tnx * tny * tnz;
+  constexpr int kChunks = (kTz + 2) * (kTy + 2) * (kTx + 2) * 2;   // 16-byte halves
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int x0 = (tile % tnx) * kTx, y0 = ((tile / tnx) % tny) * kTy, z0 = (tile / (tnx * tny)) * kTz;
+    for (int q = threadIdx.x; q < kChunks; q += 256) {
+      const int half = q & 1, rest = q >> 1;
+      const int lx = rest % (kTx + 2), ly = (rest / (kTx + 2)) % (kTy + 2), lz = rest / ((kTx + 2) * (kTy + 2));
+      const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz)
+        v = *reinterpret_cast<const uint4*>(a.x + (((size_t)zz * a.ny + yy) * a.nx + xx) * kCh + 8 * half);
+      *reinterpret_cast<uint4*>(&xs[lz][ly][lx][8 * half]) = v;
+    }
+    __syncthreads();
+    f32x4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < kSteps; ++j) {
       const int t = 2 * j + (quad >> 1);
-      xb[j] = zero8();
-      if (t < kTaps) {
-        int dz, dy, dx;
-        tap_offset(t, dz, dy, dx);
-        const int xx = x + dx, yy = y + dy, zz = z + dz;
-        if (x < a.nx && xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz) {
-          const size_t node = ((size_t)zz * a.ny + yy) * a.nx + xx;
-          xb[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * (quad & 1)));
+      int dz, dy, dx;
+      tap_offset(t < kTaps ? t : 13, dz, dy, dx);   // padding half of the last step: zero operands
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wave + 4 * i, ly = row % kTy, lz = row / kTy;
+        uint4 v = *reinterpret_cast<const uint4*>(&xs[lz + 1 + dz][ly + 1 + dy][col + 1 + dx][8 * (quad & 1)]);
+        if (t >= kTaps) v = make_uint4(0u, 0u, 0u, 0u);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], __builtin_bit_cast(bf16x8, v), acc[i], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wave + 4 * i;
+      const int x = x0 + col, y = y0 + row % kTy, z = z0 + row / kTy;
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      // this lane holds output channels 4 quad + r of node (x, y, z)
+      const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = acc[i][r] + bias[r];
+        if (a.relu) v[r] = fmaxf(v[r], 0.f);
+      }
+      if (a.mask) {
+        const uint2 m = *reinterpret_cast<const uint2*>(a.mask + node * kCh + 4 * quad);
+        const uint16_t mh[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffff),
+                                (uint16_t)(m.y >> 16)};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (!(bf2f(mh[r]) > 0.f)) v[r] = 0.f;
+      }
+      if (a.y16) {
+        uint2 o;
+        o.x = f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+        o.y = f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        *reinterpret_cast<uint2*>(a.y16 + node * kCh + 4 * quad) = o;
+      }
+      if (a.y32) *reinterpret_cast<float4*>(a.y32 + node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
+      if (a.z && quad == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const size_t id = (size_t)d * nn + node;
+          const float zi = fmaf(scale, v[d], a.r[id] / a.diag[id]);
+          a.z[id] = zi;
+          if (a.zred) {
+            zr += (double)zi * a.r[id];
+            zrp += (double)zi * a.rprev[id];
+          }
         }
       }
     }
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < kSteps; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], xb[j], acc, 0, 0, 0);
-    if (x >= a.nx) continue;
-    // this lane holds output channels 4 quad + i of node x
-    const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
-    float v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v[i] = acc[i] + bias[i];
-      if (a.relu) v[i] = fmaxf(v[i], 0.f);
+    __syncthreads();   // the next tile overwrites the staged input
+  }
+  if (a.zred) {   // per-group partials of z.r and z.r_prev (flexible CG)
+    __shared__ double sred[2][4];
+    zr = wave_sum(zr);
+    zrp = wave_sum(zrp);
+    if (lane == 0) {
+      sred[0][wave] = zr;
+      sred[1][wave] = zrp;
     }
-    if (a.mask) {
-      const uint2 m = *reinterpret_cast<const uint2*>(a.mask + node * kCh + 4 * quad);
-      const uint16_t mh[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffff),
-                              (uint16_t)(m.y >> 16)};
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (!(bf2f(mh[i]) > 0.f)) v[i] = 0.f;
-    }
-    if (a.y16) {
-      uint2 o;
-      o.x = f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-      o.y = f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-      *reinterpret_cast<uint2*>(a.y16 + node * kCh + 4 * quad) = o;
-    }
-    if (a.y32) *reinterpret_cast<float4*>(a.y32 + node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
-    if (a.z && quad == 0) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const size_t i = (size_t)d * nn + node;
-        a.z[i] = fmaf(scale, v[d], a.r[i] / a.diag[i]);
-      }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.zred[2 * blockIdx.x] = (sred[0][0] + sred[0][1]) + (sred[0][2] + sred[0][3]);
+      a.zred[2 * blockIdx.x + 1] = (sred[1][0] + sred[1][1]) + (sred[1][2] + sred[1][3]);
     }
   }
 }
 
+int cnn_conv_blocks(int nx, int ny, int nz) {
+  const long tiles = (long)((nx + kTx - 1) / kTx) * ((ny + kTy - 1) / kTy) * ((nz + kTz - 1) / kTz);
+  return (int)std::min<long>(tiles, 1024);
+}
+
 hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st) {
-  const long groups = (long)((a.nx + 15) / 16) * a.ny * a.nz;
-  const int blocks = (int)std::min<long>((groups + 3) / 4, 4096);
+  const int blocks = cnn_conv_blocks(a.nx, a.ny, a.nz);
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(cnn_conv_kernel, dim3(blocks), dim3(256), 0, st, a);
   return hipGetLastError();
@@ -281,12 +333,20 @@ __device__ __forceinline__ bool frozen_param(int i) {
   return o >= 3;
 }
 
+// bf16 weights in both layouts: [layer][t][in][out] (backward-data operand), then
+// [layer][t][out][in] (forward operand), so either product loads 16 contiguous bytes.
+__device__ __forceinline__ void store_weight(uint16_t* w16, int layer, int j, uint16_t v) {
+  const int t = j / (kCh * kCh), c = (j / kCh) % kCh, o = j % kCh;
+  w16[(size_t)layer * kCnnWeights + j] = v;
+  w16[(size_t)(kCnnLayers + layer) * kCnnWeights + (t * kCh + o) * kCh + c] = v;
+}
+
 __global__ __launch_bounds__(256) void cnn_cast_kernel(float* __restrict__ p, uint16_t* __restrict__ w16) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= kCnnParams) return;
   if (frozen_param(i)) p[i] = 0.f;
   const int layer = i / kCnnLayerParams, j = i % kCnnLayerParams;
-  if (j < kCnnWeights) w16[(size_t)layer * kCnnWeights + j] = f2bf(p[i]);
+  if (j < kCnnWeights) store_weight(w16, layer, j, f2bf(p[i]));
 }
 
 hipError_t launch_cnn_cast(float* params, uint16_t* w16, hipStream_t st) {
@@ -312,7 +372,7 @@ __global__ __launch_bounds__(256) void cnn_adam_kernel(float* __restrict__ p, co
   }
   p[i] = pi;
   const int layer = i / kCnnLayerParams, j = i % kCnnLayerParams;
-  if (j < kCnnWeights) w16[(size_t)layer * kCnnWeights + j] = f2bf(pi);
+  if (j < kCnnWeights) store_weight(w16, layer, j, f2bf(pi));
 }
 
 hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, uint16_t* w16, const AdamArgs& h,

@@ -12,6 +12,16 @@ namespace mfr {
 constexpr int kVecBlock = 256;
 constexpr int kNodeBlock = 256;
 
+// Reads of values that an earlier kernel wrote (CG scalars, control flags, scales):
+// agent-scope atomic loads are served coherently, never from a stale scalar-cache
+// or L1 line (plain uniform loads may be scalar loads through the scalar cache).
+__device__ __forceinline__ double ld_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_coherent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Grid conversion along one axis (Sec. 4.3, eq. grid_conversion): voxel index
 // a lies between nodes n0 and n0 + 1 with weights (1 - f, f).
 struct Conv1 {
@@ -279,6 +289,7 @@ struct ConvArgs {
   const uint16_t* w;
   const float* bias;
   int transpose, relu;
+  int w_out_major;   // forward only: w laid out [27][16 out][16 in]
   const uint16_t* mask;
   uint16_t* y16;
   float* y32;
@@ -286,12 +297,15 @@ struct ConvArgs {
   const float* r;
   const float* diag;
   const double* scale;
+  const float* rprev;   // with zred: per-group partials of z.r and z.rprev (2 per group)
+  double* zred;
 };
 
 struct AdamArgs {
   float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
 };
 
+int cnn_conv_blocks(int nx, int ny, int nz);   // groups of one launch (<= 1024)
 hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st);
 
 // Scalars of the learned preconditioner (device doubles).
@@ -335,10 +349,19 @@ struct GmArgs {
 // tmp1: mz*my*nx floats, tmp2: mz*ny*nx floats, gR: nz*ny*nx floats
 hipError_t launch_pc_gradmag(const GmArgs& g, float* tmp1, float* tmp2, float* gR, hipStream_t st);
 hipError_t launch_fpcg_beta(double* sc, hipStream_t st);
+// Flexible-CG update: s += alpha p, rprev = r, r -= alpha q; partials of r.r and
+// (r/diag).(r/diag) per block (2 per block, `blocks` blocks).
+hipError_t launch_fpcg_update(int n3, const float* diag, const float* p, const float* q, float* s, float* r,
+                              float* rprev, const double* sc, double* red, int blocks, hipStream_t st);
+// sc[SC_RR] = r.r; pc_sc[PC_RMS_R], pc_sc[PC_RMS_Y] = RMS of r and r/diag over n3 entries
+hipError_t launch_fpcg_scales(const double* red, int blocks, int n3, double* sc, double* pc_sc, hipStream_t st);
+// beta from the final convolution's partials (z.r, z.rprev): beta = (zr - zrp) / sc[SC_RZ]; sc[SC_RZ] = zr
+hipError_t launch_fpcg_beta_sum(const double* zred, int blocks, double* sc, hipStream_t st);
 int cnn_wgrad_groups(int nx, int ny, int nz);
 // part: cnn_wgrad_groups(...) x kCnnLayerParams floats; out: kCnnLayerParams floats
 hipError_t launch_cnn_wgrad(int nx, int ny, int nz, const uint16_t* x, const uint16_t* g, float* part,
                             float* out, hipStream_t st);
+// w16: 2 x kCnnLayers x kCnnWeights bf16, layouts [t][in][out] then [t][out][in]
 hipError_t launch_cnn_cast(float* params, uint16_t* w16, hipStream_t st);
 hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, uint16_t* w16, const AdamArgs& h,
                            hipStream_t st);

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_batch_kernel(const BatchJobs 
     if (item >= J.total) break;
     int pr = 0;
     while (pr + 1 < J.n && J.prefix[pr + 1] <= item) ++pr;
-    if (J.active && !J.active[pr]) continue;
+    if (J.active && !ld_coherent(J.active + pr)) continue;
     const BatchJob& jb = J.jobs[pr];
     tile_body<BX, BY, MODE>(jb.t, item - J.prefix[pr], jb.u, jb.p, S);
   }

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_batch_kernel(const NodeJ
   __shared__ double sred[kNodeBlock / 64];
   int pr = 0;
   while (pr + 1 < J.n && J.prefix[pr + 1] <= (int)blockIdx.x) ++pr;
-  if (J.active && !J.active[pr]) return;
+  if (J.active && !ld_coherent(J.active + pr)) return;
   const NodeJob& jb = J.jobs[pr];
   node_pass_body<MODE>(jb.q, jb.f, jb.out, blockIdx.x - J.prefix[pr], sred);
 }
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void pcg_alpha_kernel(const double* __restrict
   const double pq = block_sum<256>(a, sred);
   if (threadIdx.x == 0) {
     sc[SC_PQ] = pq;
-    sc[SC_ALPHA] = (pq > 0.0 && isfinite(pq)) ? sc[SC_RZ] / pq : 0.0;
+    sc[SC_ALPHA] = (pq > 0.0 && isfinite(pq)) ? ld_coherent(sc + SC_RZ) / pq : 0.0;
   }
 }
 
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kVecBlock) void pcg_update_kernel(int n3, const flo
                                                                const double* __restrict__ sc,
                                                                double* __restrict__ red) {
   __shared__ double sred[kVecBlock / 64];
-  const float alpha = (float)sc[SC_ALPHA];
+  const float alpha = (float)ld_coherent(sc + SC_ALPHA);
   double rr = 0.0, rz = 0.0;
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock) {
     const float ri = fmaf(-alpha, q[i], r[i]);
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(256) void pcg_beta_kernel(const double* __restrict_
   if (threadIdx.x == 0) {
     sc[SC_RR] = rr;
     sc[SC_RZNEW] = rz;
-    sc[SC_BETA] = rz / sc[SC_RZ];
+    sc[SC_BETA] = rz / ld_coherent(sc + SC_RZ);
     sc[SC_RZ] = rz;
   }
 }
@@ -457,7 +457,7 @@ hipError_t launch_pcg_beta(const double* red, int nred, double* sc, hipStream_t 
 __global__ __launch_bounds__(kVecBlock) void pcg_direction_kernel(int n3, const float* __restrict__ z,
                                                                   float* __restrict__ p,
                                                                   const double* __restrict__ sc) {
-  const float beta = (float)sc[SC_BETA];
+  const float beta = (float)ld_coherent(sc + SC_BETA);
   for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock)
     p[i] = fmaf(beta, p[i], z[i]);
 }

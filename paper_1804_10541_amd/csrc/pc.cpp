@@ -4,6 +4,7 @@
 // Newton equation of Sec. 2.3.1 with plain CG.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -18,7 +19,7 @@ struct mfr_pc {
   bool train = false;
   int nx = 0, ny = 0, nz = 0, n = 0, n3 = 0;
   float* params = nullptr;    // fp32 master copy, kCnnParams
-  uint16_t* w16 = nullptr;    // bf16 weights, kCnnLayers x kCnnWeights
+  uint16_t* w16 = nullptr;    // bf16 weights, both layouts (2 x kCnnLayers x kCnnWeights)
   float* grad = nullptr;      // train: kCnnParams
   float* am = nullptr;        // train: Adam first / second moments
   float* av = nullptr;
@@ -41,6 +42,8 @@ struct mfr_pc {
   double* sc = nullptr;       // PC_COUNT scalars
   double* red = nullptr;      // 4 x pc_dots_blocks partials
   int adam_t = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
   const float* gR_src = nullptr;
   unsigned gR_version = ~0u;
 };
@@ -61,8 +64,12 @@ PcLayout pc_layout(const Geo& g, bool train) {
     o = align_up(o + bytes);
     return at;
   };
+  // parameter state first: its offsets do not depend on the grid (mfr_pc_bind)
   L.params = take(sizeof(float) * kCnnParams);
-  L.w16 = take(sizeof(uint16_t) * kCnnLayers * kCnnWeights);
+  L.w16 = take(sizeof(uint16_t) * 2 * kCnnLayers * kCnnWeights);
+  L.grad = take(sizeof(float) * kCnnParams);
+  L.am = take(sizeof(float) * kCnnParams);
+  L.av = take(sizeof(float) * kCnnParams);
   for (int l = 0; l < kCnnLayers; ++l) L.h[l] = take(sizeof(uint16_t) * 16 * n);
   L.gR = take(sizeof(float) * n);
   L.diag = take(sizeof(float) * n3);
@@ -76,11 +83,8 @@ PcLayout pc_layout(const Geo& g, bool train) {
   L.wsy = take(sizeof(float) * g.n[1]);
   L.wsz = take(sizeof(float) * g.n[2]);
   L.sc = take(sizeof(double) * PC_COUNT);
-  L.red = take(sizeof(double) * 4 * pc_dots_blocks(n3));
+  L.red = take(sizeof(double) * std::max(4 * pc_dots_blocks(n3), 2 * 1024));
   if (train) {
-    L.grad = take(sizeof(float) * kCnnParams);
-    L.am = take(sizeof(float) * kCnnParams);
-    L.av = take(sizeof(float) * kCnnParams);
     L.gA = take(sizeof(uint16_t) * 16 * n);
     L.gB = take(sizeof(uint16_t) * 16 * n);
     L.y = take(sizeof(float) * n3);
@@ -233,20 +237,25 @@ mfr_status pc_begin_solve(mfr_pc* pc, const float* diag) {
   return MFR_OK;
 }
 
-// z = r / diag + rms(r / diag) * CNN(features)[0..2]
-mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z) {
+// z = r / diag + rms(r / diag) * CNN(features)[0..2].  scales_ready: the RMS of
+// r and r/diag are already in the scalars (the flexible-CG update computes them).
+// zred: the final layer also leaves per-group partials of z.r and z.rprev there.
+mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, bool scales_ready,
+                      const float* rprev, double* zred) {
   hipStream_t st = st_of(pc);
-  DotsArgs d{};
-  DotsOut o{};
-  d.n = (size_t)pc->n3;
-  d.count = 2;
-  d.a[0] = r;
-  d.den[0] = diag;
-  d.a[1] = r;
-  o.out[0] = pc->sc + PC_RMS_Y;
-  o.out[1] = pc->sc + PC_RMS_R;
-  o.rms_scale[0] = o.rms_scale[1] = 1.0 / pc->n3;
-  HIP_TRY(launch_pc_dots(d, o, pc->red, st));
+  if (!scales_ready) {
+    DotsArgs d{};
+    DotsOut o{};
+    d.n = (size_t)pc->n3;
+    d.count = 2;
+    d.a[0] = r;
+    d.den[0] = diag;
+    d.a[1] = r;
+    o.out[0] = pc->sc + PC_RMS_Y;
+    o.out[1] = pc->sc + PC_RMS_R;
+    o.rms_scale[0] = o.rms_scale[1] = 1.0 / pc->n3;
+    HIP_TRY(launch_pc_dots(d, o, pc->red, st));
+  }
   HIP_TRY(launch_pc_features(pc->n, r, diag, pc->gR, pc->sc, pc->h[0], st));
   for (int l = 0; l < kCnnLayers; ++l) {
     ConvArgs a{};
@@ -254,7 +263,8 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z) {
     a.ny = pc->ny;
     a.nz = pc->nz;
     a.x = pc->h[l];
-    a.w = pc->w16 + (size_t)l * kCnnWeights;
+    a.w = pc->w16 + (size_t)(kCnnLayers + l) * kCnnWeights;
+    a.w_out_major = 1;
     a.bias = pc->params + (size_t)l * kCnnLayerParams + kCnnWeights;
     if (l < kCnnLayers - 1) {
       a.relu = 1;
@@ -264,6 +274,8 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z) {
       a.r = r;
       a.diag = diag;
       a.scale = pc->sc + PC_RMS_Y;
+      a.rprev = rprev;
+      a.zred = zred;
     }
     HIP_TRY(launch_cnn_conv(a, st));
   }
@@ -271,6 +283,8 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z) {
 }
 
 float* pc_scratch_vec(mfr_pc* pc) { return pc->vtmp; }
+double* pc_scalars(mfr_pc* pc) { return pc->sc; }
+int pc_conv_blocks(const mfr_pc* pc) { return cnn_conv_blocks(pc->nx, pc->ny, pc->nz); }
 double* pc_red(mfr_pc* pc) { return pc->red; }
 
 }  // namespace mfr
@@ -285,28 +299,26 @@ mfr_status mfr_pc_workspace_size(const mfr_grid* grid, int32_t train, size_t* by
   return MFR_OK;
 }
 
-mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_bytes, mfr_pc** out) {
-  if (!out) return fail(MFR_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!c) return fail(MFR_EINVAL, "context is NULL");
+}  // extern "C"
+
+namespace {
+
+// Points the grid-dependent buffers of pc at context c's grid and uploads the
+// per-axis tables; the parameter state (front of the workspace) is kept.
+mfr_status bind_pc(mfr_pc* pc, mfr_ctx* c) {
   if (!c->have_images) return fail(MFR_EINVAL, "the context has no images");
-  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-    return fail(MFR_EINVAL, "workspace must be non-NULL and 256-byte aligned");
   const Geo& g = c->geo;
-  const PcLayout L = pc_layout(g, train != 0);
-  if (ws_bytes < L.total) return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", ws_bytes, L.total);
-  mfr_pc* pc = new (std::nothrow) mfr_pc();
-  if (!pc) return fail(MFR_EINVAL, "host allocation failed");
-  char* ws = reinterpret_cast<char*>(workspace);
+  const PcLayout L = pc_layout(g, pc->train);
+  if (pc->ws_bytes < L.total)
+    return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", pc->ws_bytes, L.total);
+  if (pc->c && pc->c != c && pc->c->pc == pc) pc->c->pc = nullptr;
+  char* ws = pc->ws;
   pc->c = c;
-  pc->train = train != 0;
   pc->nx = g.n[0];
   pc->ny = g.n[1];
   pc->nz = g.n[2];
   pc->n = (int)g.nbar;
   pc->n3 = (int)(3 * g.nbar);
-  pc->params = at<float>(ws, L.params);
-  pc->w16 = at<uint16_t>(ws, L.w16);
   for (int l = 0; l < kCnnLayers; ++l) pc->h[l] = at<uint16_t>(ws, L.h[l]);
   pc->gR = at<float>(ws, L.gR);
   pc->diag = at<float>(ws, L.diag);
@@ -322,9 +334,6 @@ mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_b
   pc->sc = at<double>(ws, L.sc);
   pc->red = at<double>(ws, L.red);
   if (pc->train) {
-    pc->grad = at<float>(ws, L.grad);
-    pc->am = at<float>(ws, L.am);
-    pc->av = at<float>(ws, L.av);
     pc->gA = at<uint16_t>(ws, L.gA);
     pc->gB = at<uint16_t>(ws, L.gB);
     pc->y = at<float>(ws, L.y);
@@ -334,6 +343,7 @@ mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_b
     pc->s = at<float>(ws, L.s);
     pc->wpart = at<float>(ws, L.wpart);
   }
+  pc->gR_src = nullptr;   // |grad R| is recomputed for the new images
   // per-axis node ranges of the conversion and their weight sums (host tables)
   std::vector<Range1> rr[3];
   std::vector<float> wsum[3];
@@ -347,24 +357,44 @@ mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_b
     }
   }
   hipStream_t st = c->stream;
-  mfr_status s = MFR_OK;
-  auto up = [&](void* dst, const void* src, size_t bytes) {
-    if (s == MFR_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
-      s = fail(MFR_EHIP, "table upload failed");
-  };
-  up(pc->rx, rr[0].data(), sizeof(Range1) * g.n[0]);
-  up(pc->ry, rr[1].data(), sizeof(Range1) * g.n[1]);
-  up(pc->rz, rr[2].data(), sizeof(Range1) * g.n[2]);
-  up(pc->wsx, wsum[0].data(), sizeof(float) * g.n[0]);
-  up(pc->wsy, wsum[1].data(), sizeof(float) * g.n[1]);
-  up(pc->wsz, wsum[2].data(), sizeof(float) * g.n[2]);
-  if (s == MFR_OK && hipMemsetAsync(pc->params, 0, sizeof(float) * kCnnParams, st) != hipSuccess)
+  HIP_TRY(hipMemcpyAsync(pc->rx, rr[0].data(), sizeof(Range1) * g.n[0], hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(pc->ry, rr[1].data(), sizeof(Range1) * g.n[1], hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(pc->rz, rr[2].data(), sizeof(Range1) * g.n[2], hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(pc->wsx, wsum[0].data(), sizeof(float) * g.n[0], hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(pc->wsy, wsum[1].data(), sizeof(float) * g.n[1], hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(pc->wsz, wsum[2].data(), sizeof(float) * g.n[2], hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope
+  return MFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_bytes, mfr_pc** out) {
+  if (!out) return fail(MFR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!c) return fail(MFR_EINVAL, "context is NULL");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(MFR_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  mfr_pc* pc = new (std::nothrow) mfr_pc();
+  if (!pc) return fail(MFR_EINVAL, "host allocation failed");
+  char* ws = reinterpret_cast<char*>(workspace);
+  pc->train = train != 0;
+  pc->ws = ws;
+  pc->ws_bytes = ws_bytes;
+  const PcLayout L = pc_layout(c->geo, pc->train);
+  pc->params = at<float>(ws, L.params);
+  pc->w16 = at<uint16_t>(ws, L.w16);
+  pc->grad = at<float>(ws, L.grad);
+  pc->am = at<float>(ws, L.am);
+  pc->av = at<float>(ws, L.av);
+  mfr_status s = bind_pc(pc, c);
+  hipStream_t st = c->stream;
+  if (s == MFR_OK && (hipMemsetAsync(pc->params, 0, sizeof(float) * kCnnParams, st) != hipSuccess ||
+                      hipMemsetAsync(pc->am, 0, sizeof(float) * kCnnParams, st) != hipSuccess ||
+                      hipMemsetAsync(pc->av, 0, sizeof(float) * kCnnParams, st) != hipSuccess))
     s = fail(MFR_EHIP, "parameter initialisation failed");
-  if (s == MFR_OK && pc->train) {
-    if (hipMemsetAsync(pc->am, 0, sizeof(float) * kCnnParams, st) != hipSuccess ||
-        hipMemsetAsync(pc->av, 0, sizeof(float) * kCnnParams, st) != hipSuccess)
-      s = fail(MFR_EHIP, "optimiser initialisation failed");
-  }
   if (s == MFR_OK && launch_cnn_cast(pc->params, pc->w16, st) != hipSuccess) s = fail(MFR_EHIP, "cast failed");
   if (s == MFR_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(MFR_EHIP, "synchronisation failed");
   if (s != MFR_OK) {
@@ -373,6 +403,12 @@ mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_b
   }
   *out = pc;
   return MFR_OK;
+}
+
+mfr_status mfr_pc_bind(mfr_pc* pc, mfr_ctx* c) {
+  MFR_TRY(check_pc(pc));
+  if (!c) return fail(MFR_EINVAL, "context is NULL");
+  return bind_pc(pc, c);
 }
 
 void mfr_pc_destroy(mfr_pc* pc) {

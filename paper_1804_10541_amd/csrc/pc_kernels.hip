@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kPB) void pc_features_kernel(int n, const float* __
                                                           uint16_t* __restrict__ h0) {
   const int i = blockIdx.x * kPB + threadIdx.x;
   if (i >= n) return;
-  const double sy = sc[PC_RMS_Y], sr = sc[PC_RMS_R], sd = sc[PC_RMS_D], sg = sc[PC_RMS_G];
+  const double sy = ld_coherent(sc + PC_RMS_Y), sr = ld_coherent(sc + PC_RMS_R);
+  const double sd = ld_coherent(sc + PC_RMS_D), sg = ld_coherent(sc + PC_RMS_G);
   const float iy = sy > 0.0 ? (float)(1.0 / sy) : 0.f, ir = sr > 0.0 ? (float)(1.0 / sr) : 0.f;
   const float id = sd > 0.0 ? (float)(1.0 / sd) : 0.f, ig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
   float f[16];
@@ -146,7 +147,8 @@ hipError_t launch_pc_jacobi(int n3, const float* r, const float* diag, float* y,
 // L = -(z.r)^2 / z.Az / E_J with E_J = (y.r)^2 / y.Ay, and dL/dz = cA Az + cR r.
 __global__ void pc_loss_kernel(double* sc) {
   if (threadIdx.x != 0) return;
-  const double zr = sc[PC_ZR], zAz = sc[PC_ZAZ], yr = sc[PC_YR], yAy = sc[PC_YAY];
+  const double zr = ld_coherent(sc + PC_ZR), zAz = ld_coherent(sc + PC_ZAZ);
+  const double yr = ld_coherent(sc + PC_YR), yAy = ld_coherent(sc + PC_YAY);
   const double EJ = yr * yr / yAy;
   const double s = zr / zAz;
   sc[PC_LOSS] = -(zr * s) / EJ;
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(kPB) void pc_grad_out_kernel(int n, const float* __
                                                           uint16_t* __restrict__ g16) {
   const int i = blockIdx.x * kPB + threadIdx.x;
   if (i >= n) return;
-  const float cA = (float)(sc[PC_CA] * sc[PC_RMS_Y]), cR = (float)(sc[PC_CR] * sc[PC_RMS_Y]);
+  const double sy = ld_coherent(sc + PC_RMS_Y);
+  const float cA = (float)(ld_coherent(sc + PC_CA) * sy), cR = (float)(ld_coherent(sc + PC_CR) * sy);
   float v[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) v[d] = fmaf(cA, Az[(size_t)d * n + i], cR * r[(size_t)d * n + i]);
@@ -265,13 +268,90 @@ hipError_t launch_pc_gradmag(const GmArgs& g, float* tmp1, float* tmp2, float* g
 // beta = (z.r - z.r_prev) / rz_old from sc[SC_ZR], sc[SC_ZRP]; then rz = z.r.
 __global__ void fpcg_beta_kernel(double* sc) {
   if (threadIdx.x != 0) return;
-  const double zr = sc[SC_ZR];
-  sc[SC_BETA] = (zr - sc[SC_ZRP]) / sc[SC_RZ];
+  const double zr = ld_coherent(sc + SC_ZR);
+  sc[SC_BETA] = (zr - ld_coherent(sc + SC_ZRP)) / ld_coherent(sc + SC_RZ);
   sc[SC_RZ] = zr;
 }
 
 hipError_t launch_fpcg_beta(double* sc, hipStream_t st) {
   hipLaunchKernelGGL(fpcg_beta_kernel, dim3(1), dim3(64), 0, st, sc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kPB) void fpcg_update_kernel(int n3, const float* __restrict__ diag,
+                                                          const float* __restrict__ p, const float* __restrict__ q,
+                                                          float* __restrict__ s, float* __restrict__ r,
+                                                          float* __restrict__ rprev, const double* __restrict__ sc,
+                                                          double* __restrict__ red) {
+  __shared__ double sred[4];
+  const float alpha = (float)ld_coherent(sc + SC_ALPHA);
+  double rr = 0.0, yy = 0.0;
+  for (int i = blockIdx.x * kPB + threadIdx.x; i < n3; i += gridDim.x * kPB) {
+    const float r0 = r[i];
+    const float ri = fmaf(-alpha, q[i], r0);
+    s[i] = fmaf(alpha, p[i], s[i]);
+    rprev[i] = r0;
+    r[i] = ri;
+    const float yi = ri / diag[i];
+    rr += (double)ri * ri;
+    yy += (double)yi * yi;
+  }
+  const double a = block_sum256(rr, sred);
+  const double b = block_sum256(yy, sred);
+  if (threadIdx.x == 0) {
+    red[2 * blockIdx.x] = a;
+    red[2 * blockIdx.x + 1] = b;
+  }
+}
+
+hipError_t launch_fpcg_update(int n3, const float* diag, const float* p, const float* q, float* s, float* r,
+                              float* rprev, const double* sc, double* red, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(fpcg_update_kernel, dim3(blocks), dim3(kPB), 0, st, n3, diag, p, q, s, r, rprev, sc, red);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fpcg_scales_kernel(const double* __restrict__ red, int blocks, int n3,
+                                                          double* __restrict__ sc, double* __restrict__ pc_sc) {
+  __shared__ double sred[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < blocks; i += 256) {
+    a += red[2 * i];
+    b += red[2 * i + 1];
+  }
+  const double rr = block_sum256(a, sred);
+  const double yy = block_sum256(b, sred);
+  if (threadIdx.x == 0) {
+    sc[SC_RR] = rr;
+    pc_sc[PC_RMS_R] = sqrt(rr / n3);
+    pc_sc[PC_RMS_Y] = sqrt(yy / n3);
+  }
+}
+
+hipError_t launch_fpcg_scales(const double* red, int blocks, int n3, double* sc, double* pc_sc, hipStream_t st) {
+  hipLaunchKernelGGL(fpcg_scales_kernel, dim3(1), dim3(256), 0, st, red, blocks, n3, sc, pc_sc);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fpcg_beta_sum_kernel(const double* __restrict__ zred, int blocks,
+                                                            double* __restrict__ sc) {
+  __shared__ double sred[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < blocks; i += 256) {
+    a += zred[2 * i];
+    b += zred[2 * i + 1];
+  }
+  const double zr = block_sum256(a, sred);
+  const double zrp = block_sum256(b, sred);
+  if (threadIdx.x == 0) {
+    sc[SC_ZR] = zr;
+    sc[SC_ZRP] = zrp;
+    sc[SC_BETA] = (zr - zrp) / ld_coherent(sc + SC_RZ);
+    sc[SC_RZ] = zr;
+  }
+}
+
+hipError_t launch_fpcg_beta_sum(const double* zred, int blocks, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(fpcg_beta_sum_kernel, dim3(1), dim3(256), 0, st, zred, blocks, sc);
   return hipGetLastError();
 }
 

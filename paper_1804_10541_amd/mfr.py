@@ -128,6 +128,7 @@ SIGNATURES = {
     "mfr_pc_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_pc_create": (ctypes.c_int, [_VP, _I, _VP, _SZ, ctypes.POINTER(_VP)]),
     "mfr_pc_destroy": (None, [_VP]),
+    "mfr_pc_bind": (ctypes.c_int, [_VP, _VP]),
     "mfr_pc_set_params": (ctypes.c_int, [_VP, _VP]),
     "mfr_pc_get_params": (ctypes.c_int, [_VP, _VP]),
     "mfr_pc_apply": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
@@ -465,13 +466,18 @@ class Batch:
 class LearnedPC:
     """The learned preconditioner of one context (see include/mfr.h)."""
 
-    def __init__(self, ctx, train=False):
+    def __init__(self, ctx, train=False, capacity=()):
+        """capacity: further grid specs the preconditioner may later be bound to
+        (the workspace is sized for the largest)."""
         self.lib = load()
         self.ctx = ctx
         self.train = bool(train)
-        n = ctypes.c_size_t()
-        _check(self.lib.mfr_pc_workspace_size(ctypes.byref(ctx.grid), 1 if train else 0, ctypes.byref(n)))
-        self.ws_bytes = n.value
+        sizes = []
+        for g in [ctx.grid] + [make_grid(sp) for sp in capacity]:
+            n = ctypes.c_size_t()
+            _check(self.lib.mfr_pc_workspace_size(ctypes.byref(g), 1 if train else 0, ctypes.byref(n)))
+            sizes.append(n.value)
+        self.ws_bytes = max(sizes)
         self._ws, ptr = _alloc_workspace(self.ws_bytes, ctx.device)
         h = ctypes.c_void_p()
         _check(self.lib.mfr_pc_create(ctx._h, 1 if train else 0, ctypes.c_void_p(ptr), self.ws_bytes,
@@ -490,6 +496,13 @@ class LearnedPC:
             self.close()
         except Exception:
             pass
+
+    def bind(self, ctx):
+        """Move to another context (parameters and optimiser state are kept)."""
+        if getattr(self.ctx, "_pc", None) is self:
+            self.ctx.attach_pc(None)
+        _check(self.lib.mfr_pc_bind(self._h, ctx._h))
+        self.ctx = ctx
 
     def set_params(self, params):
         import numpy as np

@@ -2,7 +2,9 @@
 systems that the registration itself produces.
 
 Systems: for every seed, a CT-like pair of the 128 x 128 x 96 multilevel
-workload (65 x 65 x 49 deformation nodes, eps 50, alpha 0.1); a Gauss-Newton
+workload (65 x 65 x 49 deformation nodes, eps 50, alpha 0.1) for even seeds
+and of one of the ten batched sizes (256^2 / 512^2 x 94..136, quarter-resolution
+grids) for odd seeds; a Gauss-Newton
 trajectory from u = 0 with Jacobi-PCG; at every iterate u_k the system
 (H + alpha nabla^2 S) s = -grad J(u_k).  Training runs Jacobi-PCG on each
 system and takes an Adam step on residuals sampled along it (the library's
@@ -62,72 +64,141 @@ def parse_range(s):
     return list(range(a, b))
 
 
-class SystemSource:
-    """Gauss-Newton systems of one seed, one after another along the trajectory."""
+def c4_specs():
+    from synth import GridSpec, config_c4_sizes, quarter_nodes
 
-    def __init__(self, ctx, spec, device):
-        self.ctx = ctx
-        self.spec = spec
-        self.device = device
+    return [GridSpec(m=m, h=(1.0, 1.0, 1.0), my=quarter_nodes(m), tau=50.0, rho=50.0, alpha=0.1)
+            for m in config_c4_sizes()]
 
-    def systems(self, seed, gn_iters, pcg_max=50, pcg_rtol=1e-3):
+
+def seed_spec(seed, mix=True):
+    """Workload of a seed: even seeds the 128 x 128 x 96 multilevel workload,
+    odd seeds cycle through the ten batched sizes (mix=False: always the former)."""
+    if not mix or seed % 2 == 0:
+        return workload_spec()
+    return c4_specs()[(seed // 2) % 10]
+
+
+class Systems:
+    """Gauss-Newton systems along registration trajectories, one context per grid size."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.ctxs = {}
+
+    def ctx(self, spec):
+        key = (tuple(spec.m), tuple(spec.my))
+        if key not in self.ctxs:
+            self.ctxs[key] = mfr.Context(spec, self.device)
+        return self.ctxs[key]
+
+    def trajectory(self, seed, spec, gn_iters, pcg_max=50, pcg_rtol=1e-3):
         from synth import ct_pair
 
-        R, T, _, _ = ct_pair(seed, self.spec.m, device=self.device)
-        self.ctx.set_images(R, T)
+        ctx = self.ctx(spec)
+        R, T, _, _ = ct_pair(seed, spec.m, device=self.device)
+        ctx.set_images(R, T)
         self._images = (R, T)
-        u = torch.zeros(self.ctx.node_shape(), dtype=torch.float32, device=self.device)
+        u = torch.zeros(ctx.node_shape(), dtype=torch.float32, device=self.device)
         for k in range(gn_iters):
-            g, _ = self.ctx.gradient(u)
+            g, _ = ctx.gradient(u)
             b = torch.neg(g)
-            yield k, u, b
-            info = self.ctx.gn_step(u, pcg_max=pcg_max, pcg_rtol=pcg_rtol, precond=1)
+            yield ctx, k, u, b
+            info = ctx.gn_step(u, pcg_max=pcg_max, pcg_rtol=pcg_rtol, precond=1)
             if not info["accepted"]:
                 break
 
+    def close(self):
+        for c in self.ctxs.values():
+            c.close()
+        self.ctxs = {}
+
+
+def val_iterations(params, systems, device="cuda:0"):
+    """Mean flexible-CG iterations to relative residual 1e-3 on validation systems
+    [(ctx, u, b)] (no fallback)."""
+    its = []
+    for ctx, u, b in systems:
+        pc = mfr.LearnedPC(ctx)
+        pc.set_params(params)
+        ctx.attach_pc(pc)
+        _, info = ctx.pcg_solve(u, b, max_iter=300, rtol=1e-3, precond=2)
+        its.append(info["iters"])
+        ctx.attach_pc(None)
+        pc.close()
+    return float(np.mean(its))
+
 
 def train(seeds, epochs=2, gn_iters=10, lr=1e-3, pcg_iters=24, sample_every=3, params=None, device="cuda:0",
-          spec=None, log_every=10):
-    spec = spec or workload_spec()
-    dev = torch.device(device)
-    ctx = mfr.Context(spec, dev)
-    src = SystemSource(ctx, spec, dev)
-    first = True
+          mix=True, log_every=10, val_seeds=(), val_every=10):
+    """Adam on the relative-energy loss over the systems of `seeds`.  With
+    val_seeds, every val_every seeds the flexible-CG iteration count on the
+    validation systems is measured and the best parameters so far are kept
+    (the one-step loss alone does not track CG convergence)."""
+    src = Systems(device)
+    specs = [workload_spec()] + (c4_specs() if mix else [])
     pc = None
     history = []
+    val = []
+    if val_seeds:
+        vsrc = Systems(device)
+        for vs in val_seeds:
+            for ctx, k, u, b in vsrc.trajectory(vs, seed_spec(vs, mix), 3):
+                val.append((ctx, u.clone(), b.clone()))
+    best = (float("inf"), None)
+    if val:
+        p0 = init_params() if params is None else params
+        best = (val_iterations(p0, val, device), p0)
+        log(f"[train] validation at start: {best[0]:.2f} iterations")
+    count = 0
     for ep in range(epochs):
         for i, seed in enumerate(seeds):
-            for k, u, b in src.systems(seed, gn_iters):
-                if first:
-                    pc = mfr.LearnedPC(ctx, train=True)
+            for ctx, k, u, b in src.trajectory(seed, seed_spec(seed, mix), gn_iters):
+                if pc is None:
+                    pc = mfr.LearnedPC(ctx, train=True, capacity=specs)
                     pc.set_params(init_params() if params is None else params)
-                    first = False
+                elif pc.ctx is not ctx:
+                    pc.bind(ctx)
                 info = pc.train_system(u, b, lr=lr, pcg_iters=pcg_iters, sample_every=sample_every)
                 history.append(info["loss_mean"])
+            count += 1
+            if val and count % val_every == 0:
+                cur = pc.get_params()
+                it = val_iterations(cur, val, device)
+                if it < best[0]:
+                    best = (it, cur)
+                log(f"[train] epoch {ep} seed {seed}: validation {it:.2f} iterations (best {best[0]:.2f})")
             if (i + 1) % log_every == 0 or i + 1 == len(seeds):
                 recent = history[-gn_iters * log_every:]
                 log(f"[train] epoch {ep} seed {seed}: mean loss {np.mean(recent):.4f} over {len(recent)} systems")
     params = pc.get_params()
     pc.close()
-    ctx.close()
+    src.close()
+    if val:
+        it = val_iterations(params, val, device)
+        if it < best[0]:
+            best = (it, params)
+        params = best[1]
+        log(f"[train] kept parameters with {best[0]:.2f} validation iterations")
+        vsrc.close()
     return params, history
 
 
-def evaluate(params, seeds, gn_iters=10, rtol=1e-3, max_iter=500, device="cuda:0", spec=None, fallback=True):
+def evaluate(params, seeds, gn_iters=10, rtol=1e-3, max_iter=500, device="cuda:0", spec=None, mix=True,
+             fallback=True):
     """Per system: iterations and wall time of Jacobi-PCG and of flexible CG with
-    the network (Jacobi fallback after twice the Jacobi count), same systems."""
-    spec = spec or workload_spec()
-    dev = torch.device(device)
-    ctx = mfr.Context(spec, dev)
-    src = SystemSource(ctx, spec, dev)
+    the network (Jacobi fallback after twice the Jacobi count), and of plain CG,
+    on the same systems."""
+    src = Systems(device)
     rows = []
-    pc = None
+    pcs = {}
     for seed in seeds:
-        for k, u, b in src.systems(seed, gn_iters):
-            if pc is None:
-                pc = mfr.LearnedPC(ctx)
-                pc.set_params(params)
-                ctx.attach_pc(pc)
+        sp = spec or seed_spec(seed, mix)
+        for ctx, k, u, b in src.trajectory(seed, sp, gn_iters):
+            if id(ctx) not in pcs:
+                pcs[id(ctx)] = mfr.LearnedPC(ctx)
+                pcs[id(ctx)].set_params(params)
+            ctx.attach_pc(pcs[id(ctx)])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, ij = ctx.pcg_solve(u, b, max_iter=max_iter, rtol=rtol, precond=1)
@@ -142,12 +213,14 @@ def evaluate(params, seeds, gn_iters=10, rtol=1e-3, max_iter=500, device="cuda:0
             _, ic = ctx.pcg_solve(u, b, max_iter=max_iter, rtol=rtol, precond=0)
             torch.cuda.synchronize()
             tc = time.perf_counter() - t0
-            rows.append(dict(seed=seed, gn=k, jacobi_iters=ij["iters"], jacobi_s=tj, learned_iters=il["iters"],
-                             learned_s=tl, learned_flag=il["flag"], fallback=il["used_fallback"],
-                             cg_iters=ic["iters"], cg_s=tc))
-    ctx.attach_pc(None)
-    pc.close()
-    ctx.close()
+            rows.append(dict(seed=seed, m=list(sp.m), gn=k, jacobi_iters=ij["iters"], jacobi_s=tj,
+                             learned_iters=il["iters"], learned_s=tl, learned_flag=il["flag"],
+                             fallback=il["used_fallback"], cg_iters=ic["iters"], cg_s=tc))
+    for ctx in src.ctxs.values():
+        ctx.attach_pc(None)
+    for pc in pcs.values():
+        pc.close()
+    src.close()
     return rows
 
 
@@ -175,17 +248,21 @@ def main():
     ap.add_argument("--pcg-iters", type=int, default=24)
     ap.add_argument("--sample-every", type=int, default=3)
     ap.add_argument("--init", default=None, help="start from these parameters (.npy)")
+    ap.add_argument("--c2-only", action="store_true", help="train on the 128 x 128 x 96 workload only")
+    ap.add_argument("--val", default="150:152", help="validation seeds (early stopping on CG iterations)")
+    ap.add_argument("--val-every", type=int, default=10)
     ap.add_argument("--out", default=WEIGHTS)
     args = ap.parse_args()
     init = np.load(args.init) if args.init else None
     t0 = time.perf_counter()
     params, hist = train(parse_range(args.train), args.epochs, args.gn_iters, args.lr, args.pcg_iters,
-                         args.sample_every, init)
+                         args.sample_every, init, mix=not args.c2_only, val_seeds=parse_range(args.val),
+                         val_every=args.val_every)
     log(f"[train] {len(hist)} systems in {time.perf_counter() - t0:.1f} s; "
         f"loss {np.mean(hist[:10]):.4f} -> {np.mean(hist[-10:]):.4f}")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, params)
-    rows = evaluate(params, parse_range(args.eval), args.gn_iters)
+    rows = evaluate(params, parse_range(args.eval), args.gn_iters, mix=not args.c2_only)
     import json
 
     print(json.dumps(summarize(rows)), flush=True)

@@ -43,7 +43,8 @@ def test_batch_hess_vec_equals_single_and_matches_oracle():
         ctx = mfr.Context(spec, DEV)
         ctx.set_images(to_dev(R), to_dev(T))
         q1 = ctx.hess_vec(to_dev(u), to_dev(probes[0])).cpu().numpy()
-        assert np.array_equal(q1, qs[k]), f"pair {k}: batched and single-pair Hv differ"
+        same = bool(np.array_equal(q1, qs[k]))
+        assert same, f"pair {k}: batched and single-pair Hv differ"
         ref = oracle_eval(spec, R, T, u, probes, diag=False)
         e = rel_l2(qs[k], ref["hv"][0])
         assert e <= 1e-4, f"pair {k}: Hv rel-L2 {e:.3e}"
@@ -68,7 +69,8 @@ def test_batch_register_equals_single_pair_register(use_graph):
     for k, (spec, R, T, _, _) in enumerate(cases):
         u1, r1 = mfr.register_multilevel(spec, to_dev(R), to_dev(T), levels=2, **opts)
         torch.cuda.synchronize()
-        assert np.array_equal(u1.cpu().numpy(), ub[k].cpu().numpy()), f"pair {k}: displacements differ"
+        same = bool(np.array_equal(u1.cpu().numpy(), ub[k].cpu().numpy()))
+        assert same, f"pair {k}: displacements differ (J {r1['J_final']!r} vs {rep['J_final'][k]!r})"
         assert r1["J_final"] == rep["J_final"][k], (k, r1["J_final"], rep["J_final"][k])
         assert sum(r1["gn_done"]) == rep["gn_done"][k]
         assert sum(r1["pcg_total"]) == rep["pcg_total"][k]
@@ -93,5 +95,7 @@ def test_batch_graph_replay_equals_direct_launches_twice():
         b.close()
     for run in range(2):
         for k in range(len(cases)):
-            assert np.array_equal(res[False][run][k], res[True][run][k]), (run, k)
-            assert np.array_equal(res[True][0][k], res[True][run][k]), (run, k)
+            same = bool(np.array_equal(res[False][run][k], res[True][run][k]))
+            assert same, (run, k)
+            same = bool(np.array_equal(res[True][0][k], res[True][run][k]))
+            assert same, (run, k)
