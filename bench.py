@@ -39,6 +39,12 @@ HV_FLOP_PER_VOXEL = 217
 HV_BYTES_PER_VOXEL = 8
 HV_BYTES_PER_NODE = 36
 
+# HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload
+# (32x16 tiles), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy kernel
+# (profiles/ngf_tile_hv_512x512x900.md): 2 x 1,411,340 KiB + 71,275 KiB.  Only
+# valid for that kernel build and tile configuration; otherwise reported as null.
+HV_TRAFFIC_C3 = {"bytes": 2963409920, "tile": (32, 16)}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -257,6 +263,9 @@ def main():
     achieved_tflops = flops / (hv_avg_ms * 1e-3) / 1e12
     alg_bytes = HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar
     hv_hbm_gbs = alg_bytes / (hv_avg_ms * 1e-3) / 1e9
+    traffic = None
+    if args.workload == "c3" and tile_cfg and (tile_cfg["bx"], tile_cfg["by"]) == HV_TRAFFIC_C3["tile"]:
+        traffic = HV_TRAFFIC_C3["bytes"]
     out = {
         "metric": "GN Hessian-vector Gvoxel/s + % HBM peak; PCG solve time, learned vs Jacobi",
         "value": round(value, 3),
@@ -276,7 +285,7 @@ def main():
                    "voxels": mbar, "nodes": nbar, "hv_per_step": HV_PER_STEP},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": None,
+                     "traffic": traffic,
                      "kernel": "ngf_tile_kernel<HV>", "avg_ms": round(hv_avg_ms, 4), "launches": hv_launches,
                      "flop_per_voxel": HV_FLOP_PER_VOXEL},
         "hv": {"kernel_gvoxel_s": round(mbar / (hv_avg_ms * 1e-3) / 1e9, 2),
@@ -288,6 +297,9 @@ def main():
         "workspace_bytes": int(ctx.ws_bytes),
         "tile_config": tile_cfg,
     }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
+        out["cpu_baseline"] = cpu_baseline(R, T, u0, spec)
     del ctx, R, T
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
@@ -295,9 +307,6 @@ def main():
     if not args.no_pc and args.workload != "small":
         log("[bench] learned preconditioner vs Jacobi")
         out["pcg_learned_vs_jacobi"] = pc_leg(dev)
-    if not args.no_cpu_baseline:
-        log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
-        out["cpu_baseline"] = cpu_baseline(R, T, u0, spec)
     print(json.dumps(out), flush=True)
 
 
