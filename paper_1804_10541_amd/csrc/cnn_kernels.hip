@@ -53,6 +53,39 @@ __device__ __forceinline__ bf16x8 zero8() {
   return __builtin_bit_cast(bf16x8, z);
 }
 
+// Reciprocal RMS scales of the network input (see the feature kernel).
+struct FeatScales {
+  float iy, ir, id, ig;
+};
+
+// Eight input channels (half 0: y0..y2, r0..r2, d0, d1; half 1: d2, |grad R|, 0...)
+// of one node, computed exactly as the feature kernel does.
+__device__ __forceinline__ uint4 feature_half(const ConvArgs& a, const FeatScales& fs, size_t node, size_t nn,
+                                              int half) {
+  float f[8];
+  if (half == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float rv = a.fr[(size_t)d * nn + node], dv = a.fdiag[(size_t)d * nn + node];
+      f[d] = (rv / dv) * fs.iy;
+      f[3 + d] = rv * fs.ir;
+    }
+    f[6] = a.fdiag[node] * fs.id;
+    f[7] = a.fdiag[nn + node] * fs.id;
+  } else {
+    f[0] = a.fdiag[2 * nn + node] * fs.id;
+    f[1] = a.fgR[node] * fs.ig;
+#pragma unroll
+    for (int c = 2; c < 8; ++c) f[c] = 0.f;
+  }
+  uint4 o;
+  o.x = f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+  o.y = f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+  o.z = f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16);
+  o.w = f2bf(f[6]) | ((uint32_t)f2bf(f[7]) << 16);
+  return o;
+}
+
 }  // namespace
 
 // ---- forward and backward-data convolution --------------------------------------
@@ -96,6 +129,15 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
     for (int i = 0; i < 4; ++i) bias[i] = a.bias[4 * quad + i];
   }
   const float scale = a.z ? (float)ld_coherent(a.scale) : 0.f;
+  FeatScales fs{0.f, 0.f, 0.f, 0.f};
+  if (a.fr) {
+    const double sy = ld_coherent(a.fsc + PC_RMS_Y), sr = ld_coherent(a.fsc + PC_RMS_R);
+    const double sd = ld_coherent(a.fsc + PC_RMS_D), sg = ld_coherent(a.fsc + PC_RMS_G);
+    fs.iy = sy > 0.0 ? (float)(1.0 / sy) : 0.f;
+    fs.ir = sr > 0.0 ? (float)(1.0 / sr) : 0.f;
+    fs.id = sd > 0.0 ? (float)(1.0 / sd) : 0.f;
+    fs.ig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
+  }
   double zr = 0.0, zrp = 0.0;
 
   // Output tiles of 16 (x) x 4 (y) x 4 (z) nodes: the block stages the input
@@ -109,14 +151,32 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
   constexpr int kChunks = (kTz + 2) * (kTy + 2) * (kTx + 2) * 2;   // 16-byte halves
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int x0 = (tile % tnx) * kTx, y0 = ((tile / tnx) % tny) * kTy, z0 = (tile / (tnx * tny)) * kTz;
-    for (int q = threadIdx.x; q < kChunks; q += 256) {
-      const int half = q & 1, rest = q >> 1;
-      const int lx = rest % (kTx + 2), ly = (rest / (kTx + 2)) % (kTy + 2), lz = rest / ((kTx + 2) * (kTy + 2));
-      const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz)
-        v = *reinterpret_cast<const uint4*>(a.x + (((size_t)zz * a.ny + yy) * a.nx + xx) * kCh + 8 * half);
-      *reinterpret_cast<uint4*>(&xs[lz][ly][lx][8 * half]) = v;
+    // all loads of the tile first, then the LDS stores (one memory latency per tile)
+    constexpr int kPer = (kChunks + 255) / 256;
+    uint4 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int q = threadIdx.x + 256 * k;
+      v[k] = make_uint4(0u, 0u, 0u, 0u);
+      if (q < kChunks) {
+        const int half = q & 1, rest = q >> 1;
+        const int lx = rest % (kTx + 2), ly = (rest / (kTx + 2)) % (kTy + 2), lz = rest / ((kTx + 2) * (kTy + 2));
+        const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
+        if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz) {
+          const size_t node = ((size_t)zz * a.ny + yy) * a.nx + xx;
+          v[k] = a.fr ? feature_half(a, fs, node, nn, half)
+                      : *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int q = threadIdx.x + 256 * k;
+      if (q < kChunks) {
+        const int half = q & 1, rest = q >> 1;
+        const int lx = rest % (kTx + 2), ly = (rest / (kTx + 2)) % (kTy + 2), lz = rest / ((kTx + 2) * (kTy + 2));
+        *reinterpret_cast<uint4*>(&xs[lz][ly][lx][8 * half]) = v[k];
+      }
     }
     __syncthreads();
     f32x4 acc[4];

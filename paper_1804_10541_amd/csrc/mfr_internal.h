@@ -299,6 +299,12 @@ struct ConvArgs {
   const double* scale;
   const float* rprev;   // with zred: per-group partials of z.r and z.rprev (2 per group)
   double* zred;
+  // fr non-null: the input is the preconditioner's feature vector, computed on the fly
+  // from r (fr), diag (fdiag), |grad R| (fgR) and the RMS scales in fsc (x unused)
+  const float* fr;
+  const float* fdiag;
+  const float* fgR;
+  const double* fsc;
 };
 
 struct AdamArgs {
