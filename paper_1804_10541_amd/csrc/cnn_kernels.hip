@@ -89,38 +89,47 @@ __device__ __forceinline__ uint4 feature_half(const ConvArgs& a, const FeatScale
 }  // namespace
 
 // ---- forward and backward-data convolution --------------------------------------
+// One kernel body, specialised per use so that each instance keeps only the
+// registers and branches it needs: kGeneric takes every option at run time (the
+// public convolution entry points); the others are the preconditioner's own
+// layers with out-major weights: kFirst (network input computed from r, diag and
+// |grad R|; ReLU; bf16 output), kHidden (bf16 input; ReLU; bf16 output), kLast
+// (bf16 input; output z = r / diag + scale * y[0..2]) and kBwd (transposed
+// weights, ReLU mask, bf16 output: backward-data of the training pass).
+enum ConvMode : int { kGeneric = 0, kFirst = 1, kHidden = 2, kLast = 3, kBwd = 4 };
+
+template <int kMode>
 __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
-  const int lane = threadIdx.x & 63;
+  constexpr bool kFeat = kMode == kFirst;
+  constexpr bool kRelu = kMode == kFirst || kMode == kHidden;
+  constexpr bool kOutZ = kMode == kLast;
+  constexpr bool kOut16 = kMode == kFirst || kMode == kHidden || kMode == kBwd;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, quad = lane >> 4;
   const size_t nn = (size_t)a.nx * a.ny * a.nz;
+  const bool transpose = kMode == kBwd || (kMode == kGeneric && a.transpose);
+  const bool out_major = kMode == kFirst || kMode == kHidden || kMode == kLast || (kMode == kGeneric && a.w_out_major);
 
-  // A operand (weights): row = output channel col, k = 8 quad + e within the step:
-  // tap 2 j + (quad >> 1), input channel 8 (quad & 1) + e.
-  bf16x8 wa[kSteps];
-#pragma unroll
-  for (int j = 0; j < kSteps; ++j) {
-    const int t = 2 * j + (quad >> 1);
-    const int c0 = 8 * (quad & 1);
-    if (t >= kTaps) {
-      wa[j] = zero8();
-    } else if (a.transpose) {
-      // W'[t][c][o] = W[26 - t][o][c]: contiguous in c
-      const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((size_t)(kTaps - 1 - t) * kCh + col) * kCh + c0);
-      wa[j] = __builtin_bit_cast(bf16x8, v);
-    } else if (a.w_out_major) {
-      // weights given as [t][out][in]: contiguous in the input channel
-      const uint4 v = *reinterpret_cast<const uint4*>(a.w + ((size_t)t * kCh + col) * kCh + c0);
-      wa[j] = __builtin_bit_cast(bf16x8, v);
-    } else {
-      uint16_t e[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) e[i] = a.w[((size_t)t * kCh + c0 + i) * kCh + col];
-      uint4 v;
-      v.x = e[0] | ((uint32_t)e[1] << 16);
-      v.y = e[2] | ((uint32_t)e[3] << 16);
-      v.z = e[4] | ((uint32_t)e[5] << 16);
-      v.w = e[6] | ((uint32_t)e[7] << 16);
-      wa[j] = __builtin_bit_cast(bf16x8, v);
+  // LDS: the block's weights as the A operand wants them, [tap][row][k channel]
+  // (tap 27 zero: the padding half of the last step), and the input tile with a
+  // one-node halo.  A wave's A operand of step j is the 1 KB at taps 2j, 2j + 1.
+  __shared__ __align__(16) uint16_t wl[kTaps + 1][kCh][kCh];
+  __shared__ __align__(16) uint16_t xs[kTz + 2][kTy + 2][kTx + 2][kCh];
+  if (transpose || out_major) {
+    // 16-byte chunks: forward out-major weights are [t][out][in] already; the
+    // transposed operand of tap t is the in-major block of tap 26 - t
+    for (int q = tid; q < (kTaps + 1) * kCh * 2; q += 256) {
+      const int t = q >> 5, rest = q & 31;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (t < kTaps)
+        v = *reinterpret_cast<const uint4*>(a.w + (size_t)(transpose ? kTaps - 1 - t : t) * kCh * kCh + 8 * rest);
+      *reinterpret_cast<uint4*>(&wl[t][0][0] + 8 * rest) = v;
+    }
+  } else {
+    // in-major forward weights [t][in][out]: transpose each tap's block
+    for (int q = tid; q < (kTaps + 1) * kCh * kCh; q += 256) {
+      const int t = q >> 8, o = (q >> 4) & 15, c = q & 15;
+      wl[t][o][c] = t < kTaps ? a.w[((size_t)t * kCh + c) * kCh + o] : (uint16_t)0;
     }
   }
   float bias[4] = {0.f, 0.f, 0.f, 0.f};
@@ -128,9 +137,10 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) bias[i] = a.bias[4 * quad + i];
   }
-  const float scale = a.z ? (float)ld_coherent(a.scale) : 0.f;
+  float scale = 0.f;
+  if constexpr (kOutZ) scale = (float)ld_coherent(a.scale);
   FeatScales fs{0.f, 0.f, 0.f, 0.f};
-  if (a.fr) {
+  if constexpr (kFeat) {
     const double sy = ld_coherent(a.fsc + PC_RMS_Y), sr = ld_coherent(a.fsc + PC_RMS_R);
     const double sd = ld_coherent(a.fsc + PC_RMS_D), sg = ld_coherent(a.fsc + PC_RMS_G);
     fs.iy = sy > 0.0 ? (float)(1.0 / sy) : 0.f;
@@ -140,15 +150,15 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
   }
   double zr = 0.0, zrp = 0.0;
 
-  // Output tiles of 16 (x) x 4 (y) x 4 (z) nodes: the block stages the input
-  // tile with a one-node halo (18 x 6 x 6 nodes, zero outside the grid) in LDS;
-  // wave w computes the x-rows (y, z) = rows w, w + 4, w + 8, w + 12 of the tile
-  // with four independent accumulators.
-  __shared__ __align__(16) uint16_t xs[kTz + 2][kTy + 2][kTx + 2][kCh];
-  const int wave = threadIdx.x >> 6;
+  // Output tiles of 16 (x) x 4 (y) x 4 (z) nodes, one per work-group; wave w
+  // computes the x-rows (y, z) = rows w, w + 4, w + 8, w + 12 of the tile with
+  // four independent accumulators.
   const int tnx = (a.nx + kTx - 1) / kTx, tny = (a.ny + kTy - 1) / kTy, tnz = (a.nz + kTz - 1) / kTz;
   const int tiles = tnx * tny * tnz;
   constexpr int kChunks = (kTz + 2) * (kTy + 2) * (kTx + 2) * 2;   // 16-byte halves
+  // this lane's A operand: tap 2 j + (quad >> 1), row col, k channels 8 (quad & 1) ..
+  const uint16_t* arow = &wl[quad >> 1][col][8 * (quad & 1)];
+  const int tap_hi = quad >> 1;
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int x0 = (tile % tnx) * kTx, y0 = ((tile / tnx) % tny) * kTy, z0 = (tile / (tnx * tny)) * kTz;
     // all loads of the tile first, then the LDS stores (one memory latency per tile)
@@ -156,7 +166,7 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
     uint4 v[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int q = threadIdx.x + 256 * k;
+      const int q = tid + 256 * k;
       v[k] = make_uint4(0u, 0u, 0u, 0u);
       if (q < kChunks) {
         const int half = q & 1, rest = q >> 1;
@@ -164,81 +174,115 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
         const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
         if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz) {
           const size_t node = ((size_t)zz * a.ny + yy) * a.nx + xx;
-          v[k] = a.fr ? feature_half(a, fs, node, nn, half)
-                      : *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
+          if constexpr (kFeat)
+            v[k] = feature_half(a, fs, node, nn, half);
+          else
+            v[k] = *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int q = threadIdx.x + 256 * k;
-      if (q < kChunks) {
-        const int half = q & 1, rest = q >> 1;
-        const int lx = rest % (kTx + 2), ly = (rest / (kTx + 2)) % (kTy + 2), lz = rest / ((kTx + 2) * (kTy + 2));
-        *reinterpret_cast<uint4*>(&xs[lz][ly][lx][8 * half]) = v[k];
-      }
+      const int q = tid + 256 * k;
+      if (q < kChunks) *reinterpret_cast<uint4*>(&xs[0][0][0][0] + 8 * q) = v[k];
     }
     __syncthreads();
     f32x4 acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // B operand of (step j, row i): 16 bytes of node col + dx of the shifted row
+    auto load_b = [&](int j, int i) {
+      const int t = 2 * j + tap_hi;
+      int dz, dy, dx;
+      tap_offset(t < kTaps ? t : 13, dz, dy, dx);   // padding half of the last step: zero weights
+      const int row = wave + 4 * i, ly = row % kTy, lz = row / kTy;
+      return *reinterpret_cast<const uint4*>(&xs[lz + 1 + dz][ly + 1 + dy][col + 1 + dx][8 * (quad & 1)]);
+    };
+    uint4 bc[4], bn[4];
+    uint4 ac = *reinterpret_cast<const uint4*>(arow), an;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bc[i] = load_b(0, i);
 #pragma unroll
     for (int j = 0; j < kSteps; ++j) {
-      const int t = 2 * j + (quad >> 1);
-      int dz, dy, dx;
-      tap_offset(t < kTaps ? t : 13, dz, dy, dx);   // padding half of the last step: zero operands
+      if (j + 1 < kSteps) {   // operands of the next step in flight during this one
+        an = *reinterpret_cast<const uint4*>(arow + (size_t)(j + 1) * 2 * kCh * kCh);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = wave + 4 * i, ly = row % kTy, lz = row / kTy;
-        uint4 v = *reinterpret_cast<const uint4*>(&xs[lz + 1 + dz][ly + 1 + dy][col + 1 + dx][8 * (quad & 1)]);
-        if (t >= kTaps) v = make_uint4(0u, 0u, 0u, 0u);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], __builtin_bit_cast(bf16x8, v), acc[i], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) bn[i] = load_b(j + 1, i);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ac),
+                                                         __builtin_bit_cast(bf16x8, bc[i]), acc[i], 0, 0, 0);
+      if (j + 1 < kSteps) {
+        ac = an;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bc[i] = bn[i];
       }
     }
+    if constexpr (kOutZ) {
+      // z = r / diag + scale * y[0..2] over the whole tile: the three channels go
+      // through LDS (over the staged input) so that every lane takes one node
+      __syncthreads();
+      float* zs = reinterpret_cast<float*>(&xs[0][0][0][0]);   // [3][256]
+      if (quad == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wave + 4 * i;
-      const int x = x0 + col, y = y0 + row % kTy, z = z0 + row / kTy;
-      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-      // this lane holds output channels 4 quad + r of node (x, y, z)
-      const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
-      float v[4];
+        for (int i = 0; i < 4; ++i) {
+          const int nl = (wave + 4 * i) * kTx + col;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        v[r] = acc[i][r] + bias[r];
-        if (a.relu) v[r] = fmaxf(v[r], 0.f);
+          for (int r = 0; r < 3; ++r) zs[r * 256 + nl] = acc[i][r] + bias[r];
+        }
       }
-      if (a.mask) {
-        const uint2 m = *reinterpret_cast<const uint2*>(a.mask + node * kCh + 4 * quad);
-        const uint16_t mh[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffff),
-                                (uint16_t)(m.y >> 16)};
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (!(bf2f(mh[r]) > 0.f)) v[r] = 0.f;
-      }
-      if (a.y16) {
-        uint2 o;
-        o.x = f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-        o.y = f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-        *reinterpret_cast<uint2*>(a.y16 + node * kCh + 4 * quad) = o;
-      }
-      if (a.y32) *reinterpret_cast<float4*>(a.y32 + node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
-      if (a.z && quad == 0) {
+      __syncthreads();
+      const int x = x0 + (tid & 15), row = tid >> 4, y = y0 + row % kTy, z = z0 + row / kTy;
+      if (x < a.nx && y < a.ny && z < a.nz) {
+        const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           const size_t id = (size_t)d * nn + node;
-          const float zi = fmaf(scale, v[d], a.r[id] / a.diag[id]);
+          const float rv = a.r[id];
+          const float zi = fmaf(scale, zs[d * 256 + tid], rv / a.diag[id]);
           a.z[id] = zi;
           if (a.zred) {
-            zr += (double)zi * a.r[id];
+            zr += (double)zi * rv;
             zrp += (double)zi * a.rprev[id];
           }
         }
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wave + 4 * i;
+        const int x = x0 + col, y = y0 + row % kTy, z = z0 + row / kTy;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        // this lane holds output channels 4 quad + r of node (x, y, z)
+        const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = acc[i][r] + bias[r];
+          if (kRelu || (kMode == kGeneric && a.relu)) v[r] = fmaxf(v[r], 0.f);
+        }
+        if (kMode == kBwd || (kMode == kGeneric && a.mask)) {
+          const uint2 m = *reinterpret_cast<const uint2*>(a.mask + node * kCh + 4 * quad);
+          const uint16_t mh[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffff),
+                                  (uint16_t)(m.y >> 16)};
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (!(bf2f(mh[r]) > 0.f)) v[r] = 0.f;
+        }
+        if (kOut16 || (kMode == kGeneric && a.y16)) {
+          uint2 o;
+          o.x = f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+          o.y = f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+          *reinterpret_cast<uint2*>(a.y16 + node * kCh + 4 * quad) = o;
+        }
+        if (kMode == kGeneric && a.y32)
+          *reinterpret_cast<float4*>(a.y32 + node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
+      }
     }
     __syncthreads();   // the next tile overwrites the staged input
   }
-  if (a.zred) {   // per-group partials of z.r and z.r_prev (flexible CG)
+  if (kOutZ && a.zred) {   // per-group partials of z.r and z.r_prev (flexible CG)
     __shared__ double sred[2][4];
     zr = wave_sum(zr);
     zrp = wave_sum(zrp);
@@ -247,7 +291,7 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
       sred[1][wave] = zrp;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       a.zred[2 * blockIdx.x] = (sred[0][0] + sred[0][1]) + (sred[0][2] + sred[0][3]);
       a.zred[2 * blockIdx.x + 1] = (sred[1][0] + sred[1][1]) + (sred[1][2] + sred[1][3]);
     }
@@ -256,13 +300,30 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
 
 int cnn_conv_blocks(int nx, int ny, int nz) {
   const long tiles = (long)((nx + kTx - 1) / kTx) * ((ny + kTy - 1) / kTy) * ((nz + kTz - 1) / kTz);
-  return (int)std::min<long>(tiles, 1024);
+  return (int)std::min<long>(tiles, kCnnMaxConvGroups);
 }
 
 hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st) {
   const int blocks = cnn_conv_blocks(a.nx, a.ny, a.nz);
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cnn_conv_kernel, dim3(blocks), dim3(256), 0, st, a);
+  int mode = kGeneric;
+  if (!a.y32 && a.bias) {
+    if (!a.transpose && a.w_out_major && !a.mask) {
+      if (a.fr && a.relu && a.y16 && !a.z) mode = kFirst;
+      else if (!a.fr && a.x && a.relu && a.y16 && !a.z) mode = kHidden;
+      else if (!a.fr && a.x && !a.relu && !a.y16 && a.z) mode = kLast;
+    }
+  }
+  if (a.transpose && a.mask && a.y16 && !a.y32 && !a.relu && !a.bias && !a.z && !a.fr) mode = kBwd;
+  // the feature input and the z output exist only in their specialisations
+  if ((a.fr && mode != kFirst) || (a.z && mode != kLast)) return hipErrorInvalidValue;
+  switch (mode) {
+    case kFirst: hipLaunchKernelGGL(cnn_conv_kernel<kFirst>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kHidden: hipLaunchKernelGGL(cnn_conv_kernel<kHidden>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kLast: hipLaunchKernelGGL(cnn_conv_kernel<kLast>, dim3(blocks), dim3(256), 0, st, a); break;
+    case kBwd: hipLaunchKernelGGL(cnn_conv_kernel<kBwd>, dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL(cnn_conv_kernel<kGeneric>, dim3(blocks), dim3(256), 0, st, a); break;
+  }
   return hipGetLastError();
 }
 

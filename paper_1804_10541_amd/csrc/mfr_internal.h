@@ -311,7 +311,8 @@ struct AdamArgs {
   float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
 };
 
-int cnn_conv_blocks(int nx, int ny, int nz);   // groups of one launch (<= 1024)
+constexpr int kCnnMaxConvGroups = 1 << 16;
+int cnn_conv_blocks(int nx, int ny, int nz);   // groups of one launch (one per tile, <= kCnnMaxConvGroups)
 hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st);
 
 // Scalars of the learned preconditioner (device doubles).

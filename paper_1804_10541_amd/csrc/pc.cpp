@@ -40,7 +40,7 @@ struct mfr_pc {
   Range1 *rx = nullptr, *ry = nullptr, *rz = nullptr;
   float *wsx = nullptr, *wsy = nullptr, *wsz = nullptr;
   double* sc = nullptr;       // PC_COUNT scalars
-  double* red = nullptr;      // 4 x pc_dots_blocks partials
+  double* red = nullptr;      // 4 x pc_dots_blocks partials, or 2 per convolution group
   int adam_t = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -83,7 +83,7 @@ PcLayout pc_layout(const Geo& g, bool train) {
   L.wsy = take(sizeof(float) * g.n[1]);
   L.wsz = take(sizeof(float) * g.n[2]);
   L.sc = take(sizeof(double) * PC_COUNT);
-  L.red = take(sizeof(double) * std::max(4 * pc_dots_blocks(n3), 2 * 1024));
+  L.red = take(sizeof(double) * std::max(4 * pc_dots_blocks(n3), 2 * cnn_conv_blocks(g.n[0], g.n[1], g.n[2])));
   if (train) {
     L.gA = take(sizeof(uint16_t) * 16 * n);
     L.gB = take(sizeof(uint16_t) * 16 * n);
