@@ -64,12 +64,16 @@ def test_parity_ct_like():
 
 
 @pytest.mark.parametrize("tile", ["64x8", "32x32", "64x16"])
-def test_parity_other_tile_shapes_and_chunks(tile, monkeypatch):
+def test_parity_other_tile_shapes_and_chunks(tile):
     _announce(f"tile {tile}")
-    monkeypatch.setenv("MFR_TILE", tile)
-    monkeypatch.setenv("MFR_CHUNK", "7")
-    spec, R, T, u, probes = blob_case(4, (70, 45, 33), (24, 16, 12), (1.0, 1.0, 1.0), 0.15, 0.15, 0.8, 0.6)
-    assert_parity(gpu_eval(spec, R, T, u, probes), oracle_eval(spec, R, T, u, probes))
+    bx, by = (int(k) for k in tile.split("x"))
+    prev = mfr.get_tile_config()
+    mfr.set_tile_config(bx, by, chunk_len=7)
+    try:
+        spec, R, T, u, probes = blob_case(4, (70, 45, 33), (24, 16, 12), (1.0, 1.0, 1.0), 0.15, 0.15, 0.8, 0.6)
+        assert_parity(gpu_eval(spec, R, T, u, probes), oracle_eval(spec, R, T, u, probes))
+    finally:
+        mfr.set_tile_config(**prev)
 
 
 def test_hessian_symmetric_psd_and_deterministic():
