@@ -24,16 +24,24 @@ template <int AX, int AY>
 __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, const float* __restrict__ u,
                                                              float* __restrict__ diag) {
   constexpr int NT = AX * AY;
+  // Voxel-column arrays use a padded row stride SP: the gather's lanes read rows
+  // of one node column (ten or so x-positions on consecutive y-rows), which an
+  // unpadded stride of 32 floats maps onto the same LDS banks.
+  constexpr int SP = AX + 10, NP = AY * SP;
   const TileParams& P = J.t;
-  __shared__ float sTw[2][NT];
-  __shared__ float sR[2][NT];
-  __shared__ float sG[3][3][NT];   // template derivative, 3 plane slots
-  __shared__ float sRho[7][NT];    // rho-hat rows: k = 0, -x, +x, -y, +y, -z, +z
+  __shared__ float sTw[2][NP];
+  __shared__ float sR[2][NP];
+  __shared__ float sG[3][3][NP];   // template derivative, 3 plane slots
+  __shared__ float sRho[7][NP];    // rho-hat rows: k = 0, -x, +x, -y, +y, -z, +z
   __shared__ float sPart[3][NT];
   __shared__ Conv1 sCx[AX], sCy[AY];
+  // conversion weight of local voxel column la (row lb) for the block's node
+  // column jc (row jr); 0 for columns outside the image (no stencil term there)
+  __shared__ float sWx[AX][AX], sWy[AY][AY];
 
   const int tid = threadIdx.x;
   const int tx = tid % AX, ty = tid / AX;
+  const int lid = ty * SP + tx;   // this thread's voxel column in the padded arrays
   const int bid = xcd_block_id();
   const int ib = bid % J.nbx;
   const int rest = bid / J.nbx;
@@ -58,12 +66,25 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
   // node column of this thread for the gather
   const int ncx = BX.hi - BX.lo + 1, ncy = BY.hi - BY.lo + 1, NC = ncx * ncy;
   const int G = NT / NC;
-  const int jcol = tid % NC, kgrp = tid / NC;
-  const bool gathers = kgrp < G;
+  // consecutive threads take consecutive rows of one node column
+  const int jcol = min(tid / G, NC - 1), kgrp = tid % G;
+  const bool gathers = tid < NC * G;
+  const int pslot = kgrp * NC + jcol;   // partial-sum slot (flush reads node column jc at jc + k NC)
   const int nxn = BX.lo + jcol % ncx, nyn = BY.lo + jcol / ncx;
   const Range1 rxr = J.rx[nxn], ryr = J.ry[nyn];
   const int rw = rxr.hi - rxr.lo + 1;
   const int nrows = rw * (ryr.hi - ryr.lo + 1);
+  __syncthreads();   // sCx, sCy
+  for (int q = tid; q < ncx * AX; q += NT) {
+    const int jc = q / AX, la = q % AX, a = BX.a0 + la;
+    sWx[jc][la] = (a >= 0 && a < P.mx) ? conv_weight(sCx[la], BX.lo + jc) : 0.0f;
+  }
+  for (int q = tid; q < ncy * AY; q += NT) {
+    const int jr = q / AY, lb = q % AY, b = BY.a0 + lb;
+    sWy[jr][lb] = (b >= 0 && b < P.my) ? conv_weight(sCy[lb], BY.lo + jr) : 0.0f;
+  }
+  const float* wxr = sWx[jcol % ncx];
+  const float* wyr = sWy[jcol / ncx];
 
   // acc[q] accumulates node plane kflush + q (kflush: lowest plane not yet written)
   float acc[4][3];
@@ -74,7 +95,7 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
   auto flush = [&](int K) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      sPart[d][tid] = gathers ? acc[0][d] : 0.0f;
+      if (gathers) sPart[d][pslot] = acc[0][d];
       acc[0][d] = acc[1][d];
       acc[1][d] = acc[2][d];
       acc[2][d] = acc[3][d];
@@ -152,11 +173,11 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
         Rv = nx_R;
       }
       const int sl = t & 1, s3 = (t + 3) % 3;
-      sTw[sl][tid] = Tv;
-      sR[sl][tid] = Rv;
-      sG[s3][0][tid] = g0;
-      sG[s3][1][tid] = g1;
-      sG[s3][2][tid] = g2;
+      sTw[sl][lid] = Tv;
+      sR[sl][lid] = Rv;
+      sG[s3][0][lid] = g0;
+      sG[s3][1][lid] = g1;
+      sG[s3][2][lid] = g2;
       Tw_n = Tv;
       R_n = Rv;
     }
@@ -174,11 +195,11 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
         const float Tc = Tw_c, Rc = R_c;
         const bool hxm = gx > 0, hxp = gx < P.mx - 1, hym = gy > 0, hyp = gy < P.my - 1;
         const bool hzm = c > 0, hzp = c < P.mz - 1;
-        const float dT[6] = {(hxm ? sTw[s1][tid - 1] : Tc) - Tc, (hxp ? sTw[s1][tid + 1] : Tc) - Tc,
-                             (hym ? sTw[s1][tid - AX] : Tc) - Tc, (hyp ? sTw[s1][tid + AX] : Tc) - Tc,
+        const float dT[6] = {(hxm ? sTw[s1][lid - 1] : Tc) - Tc, (hxp ? sTw[s1][lid + 1] : Tc) - Tc,
+                             (hym ? sTw[s1][lid - SP] : Tc) - Tc, (hyp ? sTw[s1][lid + SP] : Tc) - Tc,
                              (hzm ? Tw_p : Tc) - Tc, (hzp ? Tw_n : Tc) - Tc};
-        const float dR[6] = {(hxm ? sR[s1][tid - 1] : Rc) - Rc, (hxp ? sR[s1][tid + 1] : Rc) - Rc,
-                             (hym ? sR[s1][tid - AX] : Rc) - Rc, (hyp ? sR[s1][tid + AX] : Rc) - Rc,
+        const float dR[6] = {(hxm ? sR[s1][lid - 1] : Rc) - Rc, (hxp ? sR[s1][lid + 1] : Rc) - Rc,
+                             (hym ? sR[s1][lid - SP] : Rc) - Rc, (hyp ? sR[s1][lid + SP] : Rc) - Rc,
                              (hzm ? R_p : Rc) - Rc, (hzp ? R_n : Rc) - Rc};
         const float ih2[3] = {P.ih2x, P.ih2y, P.ih2z};
         float sTT = 0.f, sRR = 0.f, sTR = 0.f;
@@ -199,7 +220,7 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
         }
       }
 #pragma unroll
-      for (int k = 0; k < 7; ++k) sRho[k][tid] = rh[k];
+      for (int k = 0; k < 7; ++k) sRho[k][lid] = rh[k];
     }
     __syncthreads();
 
@@ -208,6 +229,7 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
       const bool hzm = c > 0, hzp = c < P.mz - 1;
       const Conv1 czm = P.cz[max(c - 1, 0)], cz0 = P.cz[c], czp = P.cz[min(c + 1, P.mz - 1)];
       float wz0[4], wzp[4], wzm[4];
+      int qmask = 0;   // node planes this row plane reaches (the others add exactly 0)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int nz = kflush + q;
@@ -215,19 +237,17 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
         wz0[q] = ok ? conv_weight(cz0, nz) : 0.0f;
         wzp[q] = (ok && hzp) ? conv_weight(czp, nz) : 0.0f;
         wzm[q] = (ok && hzm) ? conv_weight(czm, nz) : 0.0f;
+        if (wz0[q] != 0.0f || wzp[q] != 0.0f || wzm[q] != 0.0f) qmask |= 1 << q;
       }
+      qmask = __builtin_amdgcn_readfirstlane(qmask);   // uniform: c and kflush are
       const int sc = (c + 3) % 3, sp = (c + 4) % 3, sm = (c + 2) % 3;
       if (gathers) {
         for (int r = kgrp; r < nrows; r += G) {
           const int a = rxr.lo + r % rw, b = ryr.lo + r / rw;
           const int la = a - BX.a0, lb = b - BY.a0;
-          const int li = lb * AX + la;
-          const float vx0 = conv_weight(sCx[la], nxn);
-          const float vxm = a > 0 ? conv_weight(sCx[la - 1], nxn) : 0.0f;
-          const float vxp = a < P.mx - 1 ? conv_weight(sCx[la + 1], nxn) : 0.0f;
-          const float vy0 = conv_weight(sCy[lb], nyn);
-          const float vym = b > 0 ? conv_weight(sCy[lb - 1], nyn) : 0.0f;
-          const float vyp = b < P.my - 1 ? conv_weight(sCy[lb + 1], nyn) : 0.0f;
+          const int li = lb * SP + la;
+          const float vx0 = wxr[la], vxm = wxr[la - 1], vxp = wxr[la + 1];
+          const float vy0 = wyr[lb], vym = wyr[lb - 1], vyp = wyr[lb + 1];
           const float w00 = vx0 * vy0;
           const float al0 = sRho[0][li] * w00;
           const float alxm = sRho[1][li] * vxm * vy0, alxp = sRho[2][li] * vxp * vy0;
@@ -239,14 +259,16 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
             float pxy = al0 * gc[li];
             pxy = fmaf(alxm, gc[li - 1], pxy);
             pxy = fmaf(alxp, gc[li + 1], pxy);
-            pxy = fmaf(alym, gc[li - AX], pxy);
-            pxy = fmaf(alyp, gc[li + AX], pxy);
+            pxy = fmaf(alym, gc[li - SP], pxy);
+            pxy = fmaf(alyp, gc[li + SP], pxy);
             const float zp = alzp * sG[sp][d][li];
             const float zm = alzm * sG[sm][d][li];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
-              acc[q][d] = fmaf(zz, zz, acc[q][d]);
+              if (qmask & (1 << q)) {
+                const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
+                acc[q][d] = fmaf(zz, zz, acc[q][d]);
+              }
             }
           }
         }

@@ -14,6 +14,8 @@ iterations and wall time of both.
 
     python -m paper_1804_10541_amd.pc_train --train 0:40 --eval 200:205 \\
         --out paper_1804_10541_amd/weights/pc_ct128.npy
+    python -m paper_1804_10541_amd.pc_train --c2-only --eval 210:212 --gn-iters 8 \\
+        --eval-only paper_1804_10541_amd/weights/pc_ct128.npy
 """
 from __future__ import annotations
 
@@ -252,7 +254,18 @@ def main():
     ap.add_argument("--val", default="150:152", help="validation seeds (early stopping on CG iterations)")
     ap.add_argument("--val-every", type=int, default=10)
     ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--eval-only", metavar="PARAMS", default=None,
+                    help="skip training: evaluate these parameters (.npy) on the --eval seeds")
     args = ap.parse_args()
+    import json
+
+    if args.eval_only:
+        rows = evaluate(np.load(args.eval_only), parse_range(args.eval), args.gn_iters, mix=not args.c2_only)
+        for r in rows:
+            log(f"[eval] seed {r['seed']} GN {r['gn']}: Jacobi {r['jacobi_iters']} ({1e3 * r['jacobi_s']:.2f} ms), "
+                f"learned {r['learned_iters']} ({1e3 * r['learned_s']:.2f} ms), CG {r['cg_iters']}")
+        print(json.dumps(summarize(rows)), flush=True)
+        return
     init = np.load(args.init) if args.init else None
     t0 = time.perf_counter()
     params, hist = train(parse_range(args.train), args.epochs, args.gn_iters, args.lr, args.pcg_iters,
@@ -263,8 +276,6 @@ def main():
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, params)
     rows = evaluate(params, parse_range(args.eval), args.gn_iters, mix=not args.c2_only)
-    import json
-
     print(json.dumps(summarize(rows)), flush=True)
 
 
