@@ -242,6 +242,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.red_node = take(sizeof(double) * L.n_red_node);
   L.sc = take(sizeof(double) * SC_COUNT);
   L.vec = take(sizeof(float) * 3 * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
+  L.lap = take(sizeof(float) * 3 * g.nbar);       // curvature Laplacian (node pass, first half)
   L.total = o;
   return L;
 }
@@ -395,6 +396,7 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   q.orgy = at<int>(c->ws, L.orgy);
   q.orgz = at<int>(c->ws, L.orgz);
   q.red = at<double>(c->ws, L.red_node);
+  q.lap = at<float>(c->ws, L.lap);
 
   DiagParams& d = c->dp;
   d.t = p;

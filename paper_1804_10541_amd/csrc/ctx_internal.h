@@ -61,7 +61,7 @@ void set_tile_config(const mfr_tile_config& c);
 
 struct Layout {
   size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
-  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz;
+  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz, lap;
   size_t n_red_node;
   size_t total;
 };

@@ -97,6 +97,7 @@ struct NodeParams {
   const int* orgy;
   const int* orgz;
   double* red;
+  float* lap;                 // 3 nbar scratch: the curvature Laplacian of the input (first pass)
 };
 
 // Parameters of the Jacobi-diagonal kernel.

@@ -48,6 +48,35 @@ __device__ __forceinline__ float lap7(const float* __restrict__ f, int i, int j,
 
 }  // namespace
 
+// The curvature part runs in two passes over the nodes: the first stores the
+// 7-point Laplacian L f_d of every node (eq. laplace_discretized) in Q.lap and,
+// for the regulariser value, sums (L f_d)^2; the second reads the Laplacians of
+// the node and its six neighbours (clamped, so a missing neighbour contributes
+// its own value) for L L f_d and adds the gathered tile partials.  Each
+// Laplacian is evaluated once instead of seven times; the floats are the same
+// as evaluating them in place.
+template <int MODE>
+__device__ __forceinline__ void lap_body(const NodeParams& Q, const float* __restrict__ f, const int blk,
+                                         double* sred) {
+  const int n = blk * kNodeBlock + threadIdx.x;
+  double local = 0.0;
+  if (n < Q.nbar) {
+    const int i = n % Q.nx;
+    const int j = (n / Q.nx) % Q.ny;
+    const int k = n / (Q.nx * Q.ny);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float L0 = lap7(f + (size_t)d * Q.nbar, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z);
+      Q.lap[(size_t)d * Q.nbar + n] = L0;
+      if (MODE == NP_S) local += (double)L0 * (double)L0;
+    }
+  }
+  if (MODE == NP_S) {
+    const double s = block_sum<kNodeBlock>(local, sred);
+    if (threadIdx.x == 0) Q.red[blk] = s;
+  }
+}
+
 // One thread per node: q_d = s_ngf * (sum of the tile partials) + s_curv * (L L f_d).
 template <int MODE>
 __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float* __restrict__ f,
@@ -58,20 +87,18 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     const int i = n % Q.nx;
     const int j = (n / Q.nx) % Q.ny;
     const int k = n / (Q.nx * Q.ny);
+    const int nxy = Q.nx * Q.ny;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float* fd = f + (size_t)d * Q.nbar;
-      const float L0 = lap7(fd, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z);
-      if (MODE == NP_S) {
-        local += (double)L0 * (double)L0;
-        continue;
-      }
-      const float Lxm = i > 0 ? lap7(fd, i - 1, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
-      const float Lxp = i < Q.nx - 1 ? lap7(fd, i + 1, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
-      const float Lym = j > 0 ? lap7(fd, i, j - 1, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
-      const float Lyp = j < Q.ny - 1 ? lap7(fd, i, j + 1, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
-      const float Lzm = k > 0 ? lap7(fd, i, j, k - 1, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
-      const float Lzp = k < Q.nz - 1 ? lap7(fd, i, j, k + 1, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : L0;
+      const float* Ld = Q.lap + (size_t)d * Q.nbar;
+      const float L0 = Ld[n];
+      const float Lxm = i > 0 ? Ld[n - 1] : L0;
+      const float Lxp = i < Q.nx - 1 ? Ld[n + 1] : L0;
+      const float Lym = j > 0 ? Ld[n - Q.nx] : L0;
+      const float Lyp = j < Q.ny - 1 ? Ld[n + Q.nx] : L0;
+      const float Lzm = k > 0 ? Ld[n - nxy] : L0;
+      const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
       const float m2 = -2.0f * L0;
       const float LL = fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
       // gather of the transposed conversion: every tile slot overlapping node n
@@ -99,6 +126,22 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
 }
 
 template <int MODE>
+__global__ __launch_bounds__(kNodeBlock) void lap_kernel(const NodeParams Q, const float* __restrict__ f) {
+  __shared__ double sred[kNodeBlock / 64];
+  lap_body<MODE>(Q, f, blockIdx.x, sred);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kNodeBlock) void lap_batch_kernel(const NodeJobs J) {
+  __shared__ double sred[kNodeBlock / 64];
+  int pr = 0;
+  while (pr + 1 < J.n && J.prefix[pr + 1] <= (int)blockIdx.x) ++pr;
+  if (J.active && !ld_coherent(J.active + pr)) return;
+  const NodeJob& jb = J.jobs[pr];
+  lap_body<MODE>(jb.q, jb.f, blockIdx.x - J.prefix[pr], sred);
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams Q,
                                                                const float* __restrict__ f,
                                                                float* __restrict__ out) {
@@ -119,9 +162,14 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_batch_kernel(const NodeJ
 
 hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
   const int blocks = j.prefix[j.n];
-  if (mode == NP_S)
-    hipLaunchKernelGGL(node_pass_batch_kernel<NP_S>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
-  else if (mode == NP_GRAD)
+  if (mode == NP_S) {
+    hipLaunchKernelGGL(lap_batch_kernel<NP_S>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(lap_batch_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (mode == NP_GRAD)
     hipLaunchKernelGGL(node_pass_batch_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
   else
     hipLaunchKernelGGL(node_pass_batch_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
@@ -131,9 +179,14 @@ hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
 
 hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float* out, int blocks,
                             hipStream_t st) {
-  if (mode == NP_S)
-    hipLaunchKernelGGL(node_pass_kernel<NP_S>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
-  else if (mode == NP_GRAD)
+  if (mode == NP_S) {
+    hipLaunchKernelGGL(lap_kernel<NP_S>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(lap_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (mode == NP_GRAD)
     hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
   else
     hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
