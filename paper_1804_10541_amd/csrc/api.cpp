@@ -243,6 +243,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.sc = take(sizeof(double) * SC_COUNT);
   L.vec = take(sizeof(float) * 3 * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
   L.lap = take(sizeof(float) * 3 * g.nbar);       // curvature Laplacian (node pass, first half)
+  L.ctrl = take(sizeof(int) * (1 + ST_COUNT));    // device-steered CG: active flag, state
   L.total = o;
   return L;
 }
@@ -330,6 +331,7 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   HIP_TRY(hipStreamSynchronize(c->stream));
 
   TileParams& p = c->tp;
+  p.live = nullptr;
   p.mx = g.m[0];
   p.my = g.m[1];
   p.mz = g.m[2];
@@ -397,6 +399,8 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   q.orgz = at<int>(c->ws, L.orgz);
   q.red = at<double>(c->ws, L.red_node);
   q.lap = at<float>(c->ws, L.lap);
+  q.live = nullptr;
+  c->ctrl = at<int>(c->ws, L.ctrl);
 
   DiagParams& d = c->dp;
   d.t = p;
@@ -541,12 +545,87 @@ static mfr_status ctx_dots(mfr_ctx* c, double* red, int count, const float* cons
   return MFR_OK;
 }
 
+// CG iterations enqueued between two host checks of a device-steered solve.
+constexpr int kSteerIters = 8;
+
+// Plain or Jacobi-preconditioned CG steered on the device: alpha, beta, the
+// convergence test and the iteration limit are evaluated by the CG kernels
+// (the batched path's, with a table of one problem), which clear an active
+// flag that turns every later kernel of the solve into a no-op.  The host
+// enqueues kSteerIters iterations at a time and reads the flag once per
+// batch of iterations instead of reading the scalars after every iteration;
+// the iterates, the stopping iteration and the reported state are those of
+// the per-iteration loop (on a breakdown, p.q <= 0, the last update is not
+// applied).
+mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
+                           mfr_pcg_info* info) {
+  float* diag = nullptr;
+  if (o->precond >= 1) {
+    diag = c->vec[4];
+    HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
+  }
+  VecJobs V{};
+  V.n = 1;
+  V.prefix[0] = 0;
+  V.prefix[1] = c->vec_blocks;
+  VecJob& v = V.jobs[0];
+  v.r = c->vec[0];
+  v.z = c->vec[1];
+  v.p = c->vec[2];
+  v.q = c->vec[3];
+  v.s = s_out;
+  v.b = b;
+  v.diag = diag;
+  v.sc = c->sc;
+  v.state = c->ctrl + 1;
+  v.red = c->red_node;
+  v.red_pq = c->red_node;
+  v.n_pq = node_blocks(c);
+  v.n3 = (int)(3 * c->geo.nbar);
+  v.max_iter = o->max_iter;
+  v.rtol = o->rtol;
+  V.active_out = c->ctrl;
+  HIP_TRY(launch_pcg_init_batch(V, c->stream));
+  TileParams tp = c->tp;
+  tp.live = c->ctrl;
+  NodeParams np = c->np;
+  np.s_ngf = (float)(2.0 * c->geo.hbar());
+  np.live = c->ctrl;
+  const Tiling& t = c->tiling;
+  int done = 0, active = 1;
+  while (done < o->max_iter && active) {
+    const int k = std::min(kSteerIters, o->max_iter - done);
+    for (int i = 0; i < k; ++i) {
+      HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, tp, u, v.p, t.grid(), c->stream); }));
+      HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, v.p, v.q, node_blocks(c), c->stream); }));
+      HIP_TRY(launch_pcg_alpha_batch(V, c->stream));
+      HIP_TRY(launch_pcg_update_batch(V, c->stream));
+      HIP_TRY(launch_pcg_beta_batch(V, c->stream));
+      HIP_TRY(launch_pcg_direction_batch(V, c->stream));
+    }
+    done += k;
+    HIP_TRY(hipMemcpyAsync(&active, c->ctrl, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  double h[SC_COUNT];
+  int st[ST_COUNT];
+  HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(st, c->ctrl + 1, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!std::isfinite(h[SC_BB])) return fail(MFR_ENONFINITE, "right-hand side is not finite");
+  mfr_pcg_info inf{st[ST_ITERS], h[SC_RELRES], st[ST_FLAG], 0};
+  if (info) *info = inf;
+  return MFR_OK;
+}
+
 // Preconditioned CG (Sec. 2.3.1; CG from s = 0, relative recursive residual).
-// precond 1: Jacobi.  precond 2: the attached learned preconditioner with the
-// flexible direction update beta = z_{k+1}.(r_{k+1} - r_k) / z_k.r_k, optionally
-// switching to Jacobi after fallback_iters iterations.
+// precond 0 / 1: none / Jacobi, steered on the device (pcg_run_steered).
+// precond 2: the attached learned preconditioner with the flexible direction
+// update beta = z_{k+1}.(r_{k+1} - r_k) / z_k.r_k, optionally switching to
+// Jacobi after fallback_iters iterations; host loop.
 mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
                    mfr_pcg_info* info) {
+  if (o->precond != 2) return pcg_run_steered(c, u, b, s_out, o, info);
   const int n3 = (int)(3 * c->geo.nbar);
   float* s = s_out;
   float* r = c->vec[0];

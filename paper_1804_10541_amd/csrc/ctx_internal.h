@@ -61,7 +61,7 @@ void set_tile_config(const mfr_tile_config& c);
 
 struct Layout {
   size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
-  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz, lap;
+  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz, lap, ctrl;
   size_t n_red_node;
   size_t total;
 };
@@ -102,6 +102,7 @@ struct mfr_ctx {
   double* red_node;
   float* vec[8];
   int vec_blocks;
+  int* ctrl;                     // device-steered CG: [0] active flag, [1..] PcgState
   mfr_pc* pc = nullptr;          // learned preconditioner used by precond = 2
   unsigned image_version = 0;    // bumped by mfr_set_images
   // kernel timing (mfr_profile_*)

@@ -79,6 +79,7 @@ struct TileParams {
   int nxt, nyt, nzt;      // node extents of one tile's partial block
   float* part;            // transposed-conversion partial blocks
   double* red;            // one float64 partial per work-group
+  const int* live;        // single-problem launches: skip all work while *live == 0 (nullable)
 };
 
 // Parameters of the node pass.
@@ -98,6 +99,7 @@ struct NodeParams {
   const int* orgz;
   double* red;
   float* lap;                 // 3 nbar scratch: the curvature Laplacian of the input (first pass)
+  const int* live;            // single-problem launches: skip all work while *live == 0 (nullable)
 };
 
 // Parameters of the Jacobi-diagonal kernel.

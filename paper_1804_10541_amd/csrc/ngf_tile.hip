@@ -400,6 +400,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
 template <int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P, const float* __restrict__ u,
                                                           const float* __restrict__ pv) {
+  if (P.live && !ld_coherent(P.live)) return;   // a device-steered solve has stopped
   __shared__ TileSmem<BX, BY, MODE> S;
   tile_body<BX, BY, MODE>(P, xcd_block_id(), u, pv, S);
 }

@@ -127,6 +127,7 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
 
 template <int MODE>
 __global__ __launch_bounds__(kNodeBlock) void lap_kernel(const NodeParams Q, const float* __restrict__ f) {
+  if (Q.live && !ld_coherent(Q.live)) return;   // a device-steered solve has stopped
   __shared__ double sred[kNodeBlock / 64];
   lap_body<MODE>(Q, f, blockIdx.x, sred);
 }
@@ -145,6 +146,7 @@ template <int MODE>
 __global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams Q,
                                                                const float* __restrict__ f,
                                                                float* __restrict__ out) {
+  if (Q.live && !ld_coherent(Q.live)) return;   // a device-steered solve has stopped
   __shared__ double sred[kNodeBlock / 64];
   node_pass_body<MODE>(Q, f, out, blockIdx.x, sred);
 }
