@@ -65,3 +65,48 @@ def hessian_diag(grid, L=None):
     L = laplacian(grid) if L is None else L
     d = 2.0 * grid.hybar * np.asarray(L.multiply(L).sum(axis=0)).ravel()
     return np.stack([d, d, d]).reshape(3, grid.my[2], grid.my[1], grid.my[0])
+
+
+def _row_entries(grid, m):
+    """Column -> coefficient of row ``m`` of L (coinciding clamped columns summed)."""
+    abc = [int(x) for x in grid.node_abc(m)]
+    out = {}
+    for k in range(3):
+        w = 1.0 / grid.hy[k] ** 2
+        lo, hi = list(abc), list(abc)
+        lo[k] = max(abc[k] - 1, 0)
+        hi[k] = min(abc[k] + 1, grid.my[k] - 1)
+        for idx, c in ((lo, w), (abc, -2.0 * w), (hi, w)):
+            col = int(grid.node_id(*idx))
+            out[col] = out.get(col, 0.0) + c
+    return out
+
+
+def node_outputs(grid, u, p, node):
+    """Exact (grad S, (nabla^2 S) p, diag nabla^2 S) at one node (all three
+    components) of a grid of any size: (L^T L f)_n = sum over the rows m of L
+    with a non-zero in column n (the node and its neighbours) of
+    L[m, n] (L f)_m, every row evaluated from its own stencil."""
+    abc = [int(x) for x in grid.node_abc(node)]
+    rows = {int(node)}
+    for k in range(3):
+        for s in (-1, 1):
+            q = list(abc)
+            q[k] += s
+            if 0 <= q[k] < grid.my[k]:
+                rows.add(int(grid.node_id(*q)))
+    uc = _comps(grid, u)
+    pc = _comps(grid, p) if p is not None else None
+    grad, hv, dg = np.zeros(3), np.zeros(3), 0.0
+    for m in sorted(rows):
+        e = _row_entries(grid, m)
+        lmn = e.get(int(node), 0.0)
+        if lmn == 0.0:
+            continue
+        dg += lmn * lmn
+        for d in range(3):
+            grad[d] += lmn * sum(c * uc[d][col] for col, c in e.items())
+            if pc is not None:
+                hv[d] += lmn * sum(c * pc[d][col] for col, c in e.items())
+    s = 2.0 * grid.hybar
+    return s * grad, (s * hv if pc is not None else None), np.full(3, s * dg)

@@ -387,6 +387,20 @@ def test_node_outputs_match_full_evaluation():
         np.testing.assert_allclose(dn, diag[:, c, b, a], rtol=1e-12, atol=1e-13)
 
 
+def test_curvature_node_outputs_match_full_evaluation():
+    g, R, T, u, rng = tiny_problem(9, m=(10, 9, 8), my=(5, 4, 6))
+    p = rng.standard_normal(u.shape)
+    grad = curvature.gradient(g, u)
+    hv = curvature.hess_vec(g, p)
+    diag = curvature.hessian_diag(g)
+    for node in [0, g.nbar - 1, g.node_id(2, 1, 2), g.node_id(4, 3, 0), g.node_id(1, 2, 5), g.node_id(4, 0, 3)]:
+        gn, hn, dn = curvature.node_outputs(g, u, p, node)
+        a, b, c = g.node_abc(node)
+        np.testing.assert_allclose(gn, grad[:, c, b, a], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(hn, hv[:, c, b, a], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dn, diag[:, c, b, a], rtol=1e-12, atol=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Solvers (Sec. 2.3)
 # ---------------------------------------------------------------------------
