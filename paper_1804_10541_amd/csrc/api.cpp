@@ -174,7 +174,7 @@ Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector
   Tiling t;
   const mfr_tile_config cfg = current_tile_config();
   t.shape = TileShape{cfg.bx, cfg.by};
-  const int TX = t.shape.bx - 4, TY = t.shape.by - 4;
+  const int TX = t.shape.bx - 2, TY = t.shape.by - 2;   // own columns; one-column ring
   t.tiles_x = (g.m[0] + TX - 1) / TX;
   t.tiles_y = (g.m[1] + TY - 1) / TY;
   const int xy = t.tiles_x * t.tiles_y;
@@ -186,12 +186,13 @@ Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector
   t.chunk_len = std::min(clen, g.m[2]);
   t.chunks = (g.m[2] + t.chunk_len - 1) / t.chunk_len;
   t.nxt = t.nyt = t.nzt = 0;
+  // node extent of a group's columns inside the image (own columns and ring)
   for (int i = 0; i < t.tiles_x; ++i) {
-    const int a0 = i * TX, a1 = std::min(a0 + TX, g.m[0]) - 1;
+    const int a0 = std::max(i * TX - 1, 0), a1 = std::min(i * TX + TX, g.m[0] - 1);
     t.nxt = std::max(t.nxt, cx[a1].n0 + 2 - cx[a0].n0);
   }
   for (int i = 0; i < t.tiles_y; ++i) {
-    const int a0 = i * TY, a1 = std::min(a0 + TY, g.m[1]) - 1;
+    const int a0 = std::max(i * TY - 1, 0), a1 = std::min(i * TY + TY, g.m[1] - 1);
     t.nyt = std::max(t.nyt, cy[a1].n0 + 2 - cy[a0].n0);
   }
   for (int i = 0; i < t.chunks; ++i) {
@@ -272,7 +273,12 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   c->R = nullptr;
   c->have_images = false;
   const Tiling& t = c->tiling;
-  const int TX = t.shape.bx - 4, TY = t.shape.by - 4;
+  const int TX = t.shape.bx - 2, TY = t.shape.by - 2;
+  // groups whose columns [i TX - 1, i TX + TX] meet the columns [lo, hi] of a node's support
+  auto groups_touching = [](const Range1& cols, int T, int tiles) {
+    const int lo = cols.lo < T ? 0 : (cols.lo - 1) / T;
+    return Range1{lo, std::min(tiles - 1, (cols.hi + 1) / T)};
+  };
 
   auto sx = samp_table(g.m[0], g.h[0], g.hT[0]);
   auto sy = samp_table(g.m[1], g.h[1], g.hT[1]);
@@ -280,11 +286,11 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   auto colx = node_cols(cx, g.n[0]), coly = node_cols(cy, g.n[1]), colz = node_cols(cz, g.n[2]);
   std::vector<Range1> ntx(g.n[0]), nty(g.n[1]), ntz(g.n[2]), rx(g.n[0]), ry(g.n[1]), rz(g.n[2]);
   for (int i = 0; i < g.n[0]; ++i) {
-    ntx[i] = Range1{colx[i].lo / TX, colx[i].hi / TX};
+    ntx[i] = groups_touching(colx[i], TX, t.tiles_x);
     rx[i] = Range1{std::max(colx[i].lo - 1, 0), std::min(colx[i].hi + 1, g.m[0] - 1)};
   }
   for (int i = 0; i < g.n[1]; ++i) {
-    nty[i] = Range1{coly[i].lo / TY, coly[i].hi / TY};
+    nty[i] = groups_touching(coly[i], TY, t.tiles_y);
     ry[i] = Range1{std::max(coly[i].lo - 1, 0), std::min(coly[i].hi + 1, g.m[1] - 1)};
   }
   for (int i = 0; i < g.n[2]; ++i) {
@@ -300,8 +306,8 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
     jbz = node_blocks_z(rz, (g.n[2] + nbz - 1) / nbz);
   }
   std::vector<int> orgx(t.tiles_x), orgy(t.tiles_y), orgz(t.chunks);
-  for (int i = 0; i < t.tiles_x; ++i) orgx[i] = cx[i * TX].n0;
-  for (int i = 0; i < t.tiles_y; ++i) orgy[i] = cy[i * TY].n0;
+  for (int i = 0; i < t.tiles_x; ++i) orgx[i] = cx[std::max(i * TX - 1, 0)].n0;
+  for (int i = 0; i < t.tiles_y; ++i) orgy[i] = cy[std::max(i * TY - 1, 0)].n0;
   for (int i = 0; i < t.chunks; ++i) orgz[i] = cz[i * t.chunk_len].n0;
 
   const Layout& L = c->lay;

@@ -133,8 +133,8 @@ struct JacParams {
   float ihy2x, ihy2y, ihy2z;
 };
 
-// Tile shape of the voxel kernel: the work-group covers BX x BY columns; the
-// inner (BX-4) x (BY-4) are its output voxels, the rest a two-voxel halo.
+// Tile shape of the voxel kernel: the work-group covers BX x BY columns; it
+// owns the rows of the inner (BX-2) x (BY-2), the rest is a one-column ring.
 struct TileShape {
   int bx, by;
 };

@@ -1,11 +1,12 @@
 // Fused matrix-free NGF kernel on voxel tiles (CDNA4 / gfx950).
 //
-// One work-group owns a column block of BX x BY voxel columns: the inner
-// (BX-4) x (BY-4) columns are its output voxels, the outer ring a two-voxel
-// halo that is recomputed rather than exchanged.  The group marches through a
-// chunk of z planes; each thread owns one column and keeps the values of its
-// own column in registers across planes, while the x/y neighbours of the
-// current plane are exchanged through LDS.  Per step t three stages run:
+// One work-group covers a column block of BX x BY voxel columns: it owns the
+// rows of dr at the inner (BX-2) x (BY-2) columns and samples the template on
+// a one-column ring around them as well, which the differences of its rows
+// need.  The group marches through a chunk of z planes; each thread owns one
+// column and keeps the values of its own column in registers across planes,
+// while the x/y neighbours of the current plane are exchanged through LDS.
+// Per step t three stages run:
 //
 //  A(t)   conversion P of u (and of p) at plane t (Sec. 4.3,
 //         eq. grid_conversion), trilinear template sample T(hat-y) and its
@@ -20,6 +21,11 @@
 //         sum_k e_{i+k}(-k) over neighbours inside the image (eq. gradNGF and
 //         eq. drTdr / eq. hessMult as a gather over the rows of dr), v = g w,
 //         accumulated into the node planes of the transposed conversion P^T.
+//         A group gathers only its own rows, at every column it covers (own
+//         columns and ring): a ring column is an own column of the
+//         neighbouring group, which adds the contributions of its rows there,
+//         and P^T is linear, so the two partial node blocks sum to the whole.
+//         Each row's contributions are formed exactly once.
 //
 // Columns and planes outside the image sample the template at the clamped
 // position, so every neighbour read in stage B already holds the clamped
@@ -42,16 +48,16 @@ namespace mfr {
 // LDS of one work-group of the voxel-tile kernel.
 template <int BX, int BY, int MODE>
 struct TileSmem {
-  static constexpr int NT = BX * BY, TX = BX - 4, TY = BY - 4, MAXNX = TX + 1, MAXNY = TY + 1;
+  static constexpr int NT = BX * BY, MAXNX = BX + 1, MAXNY = BY + 1;
   static constexpr bool HV = (MODE == MODE_HV), NEED_C = (MODE != MODE_OBJ);
   float sTw[2][NT];
   float sR[2][NT];
   float sA[HV ? 2 : 1][HV ? NT : 1];
   float sE[NEED_C ? 2 : 1][4][NEED_C ? NT : 1];
-  float sV[3][TX * TY];
-  float sW[3][TY * MAXNX];
+  float sV[NEED_C ? 3 : 1][NEED_C ? NT : 1];
+  float sW[NEED_C ? 3 : 1][NEED_C ? BY * MAXNX : 1];
   int sColLo[MAXNX], sColHi[MAXNX], sRowLo[MAXNY], sRowHi[MAXNY];
-  Conv1 sCx[TX], sCy[TY];
+  Conv1 sCx[BX], sCy[BY];
   double sRed[NT / 64];
 };
 
@@ -60,12 +66,10 @@ template <int BX, int BY, int MODE>
 __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, const float* __restrict__ u,
                                           const float* __restrict__ pv, TileSmem<BX, BY, MODE>& S) {
   constexpr int NT = BX * BY;
-  constexpr int TX = BX - 4, TY = BY - 4;
-  constexpr int MAXNX = TX + 1, MAXNY = TY + 1;
+  constexpr int TX = BX - 2, TY = BY - 2;   // own columns per tile
+  constexpr int MAXNX = BX + 1;
   constexpr bool HV = (MODE == MODE_HV);
   constexpr bool NEED_C = (MODE != MODE_OBJ);
-  static_assert(MAXNX * TY <= NT && MAXNX * MAXNY <= NT, "flush mapping needs more threads");
-  static_assert(NT >= 64 + MAXNY, "node-range setup needs more threads");
   auto& sTw = S.sTw;
   auto& sR = S.sR;
   auto& sA = S.sA;
@@ -91,11 +95,17 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   const int zb = chunk * P.chunk_len;
   const int ze = min(P.mz, zb + P.chunk_len);
 
-  const int gx = x0 - 2 + tx, gy = y0 - 2 + ty;
+  // Columns: the own columns tx in [1, BX-2] plus a one-column ring.  Stage B
+  // forms the rows of dr at own columns only; stage C gathers, at every column
+  // of the group inside the image, the contributions of the group's own rows
+  // (the ring's other contributions come from the neighbouring group, whose
+  // own columns they are) and the transposed conversion sums both groups'
+  // partial node blocks.
+  const int gx = x0 - 1 + tx, gy = y0 - 1 + ty;
   const bool in_img = (gx >= 0) && (gx < P.mx) && (gy >= 0) && (gy < P.my);
-  const bool inB = (tx >= 1) && (tx < BX - 1) && (ty >= 1) && (ty < BY - 1);
-  const bool inner = (tx >= 2) && (tx < BX - 2) && (ty >= 2) && (ty < BY - 2);
-  const bool inC = inner && in_img;
+  const bool own = (tx >= 1) && (tx < BX - 1) && (ty >= 1) && (ty < BY - 1);
+  const bool inB = own && in_img;
+  const bool inC = in_img;
 
   // own column, clamped into the image
   const int cxi = min(max(gx, 0), P.mx - 1), cyi = min(max(gy, 0), P.my - 1);
@@ -108,40 +118,37 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   const unsigned colxy = (unsigned)(cyi * P.mx + cxi);
   const unsigned nb = (unsigned)P.nbar, nxu = (unsigned)P.nx;
 
-  // Tile node origins and the column / row ranges of each local node.
-  const int TXv = min(TX, P.mx - x0), TYv = min(TY, P.my - y0);
-  const int nox = P.cx[x0].n0, noy = P.cy[y0].n0, noz = P.cz[zb].n0;
-  const int nxl = P.cx[x0 + TXv - 1].n0 + 2 - nox;
-  const int nyl = P.cy[y0 + TYv - 1].n0 + 2 - noy;
+  // Local columns [lxa, lxb] and rows [lya, lyb] of the group inside the image,
+  // the first node they touch and the number of node columns / rows touched.
+  const int lxa = x0 == 0 ? 1 : 0, lya = y0 == 0 ? 1 : 0;
+  const int lxb = min(BX - 1, P.mx - x0), lyb = min(BY - 1, P.my - y0);
+  const int nox = P.cx[x0 - 1 + lxa].n0, noy = P.cy[y0 - 1 + lya].n0, noz = P.cz[zb].n0;
+  const int nxl = P.cx[x0 - 1 + lxb].n0 + 2 - nox;
+  const int nyl = P.cy[y0 - 1 + lyb].n0 + 2 - noy;
   if constexpr (NEED_C) {
-    if (tid < TX) sCx[tid] = P.cx[min(x0 + tid, P.mx - 1)];
-    if (tid < TY) sCy[tid] = P.cy[min(y0 + tid, P.my - 1)];
+    if (tid < BX) sCx[tid] = P.cx[min(max(x0 - 1 + tid, 0), P.mx - 1)];
+    if (tid < BY) sCy[tid] = P.cy[min(max(y0 - 1 + tid, 0), P.my - 1)];
     __syncthreads();
-    if (tid < nxl) {
-      const int jg = nox + tid;
-      int lo = TXv, hi = -1;
-      for (int l = 0; l < TXv; ++l) {
-        const int n0 = sCx[l].n0;
-        if (n0 == jg || n0 + 1 == jg) {
+    for (int w = tid; w < nxl + nyl; w += NT) {
+      const bool isx = w < nxl;
+      const int i = isx ? w : w - nxl;
+      const int ng = (isx ? nox : noy) + i;
+      const int la = isx ? lxa : lya, lb = isx ? lxb : lyb;
+      int lo = lb + 1, hi = -1;
+      for (int l = la; l <= lb; ++l) {
+        const int n0 = isx ? sCx[l].n0 : sCy[l].n0;
+        if (n0 == ng || n0 + 1 == ng) {
           lo = min(lo, l);
           hi = max(hi, l);
         }
       }
-      sColLo[tid] = lo;
-      sColHi[tid] = hi;
-    }
-    if (tid >= 64 && tid - 64 < nyl) {
-      const int i = tid - 64, ig = noy + i;
-      int lo = TYv, hi = -1;
-      for (int l = 0; l < TYv; ++l) {
-        const int n0 = sCy[l].n0;
-        if (n0 == ig || n0 + 1 == ig) {
-          lo = min(lo, l);
-          hi = max(hi, l);
-        }
+      if (isx) {
+        sColLo[i] = lo;
+        sColHi[i] = hi;
+      } else {
+        sRowLo[i] = lo;
+        sRowHi[i] = hi;
       }
-      sRowLo[i] = lo;
-      sRowHi[i] = hi;
     }
   }
 
@@ -150,41 +157,42 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
 
   // Writes one node plane (local index kloc) of the transposed conversion:
   // reduce the per-column sums acc over x, then y, into the slot's node block.
-  const int fj = tid % MAXNX, fr = tid / MAXNX;   // flush roles (compile-time divisor)
+  const int nrow = lyb - lya + 1;
   auto flush = [&](const float (&acc)[3], int kloc) {
-    if (inner) {
-      const int l = (ty - 2) * TX + (tx - 2);
-      sV[0][l] = acc[0];
-      sV[1][l] = acc[1];
-      sV[2][l] = acc[2];
+    if (inC) {
+      sV[0][tid] = acc[0];
+      sV[1][tid] = acc[1];
+      sV[2][tid] = acc[2];
     }
     __syncthreads();
-    if (fj < nxl && fr < TYv) {   // x reduction: node column fj, voxel row fr
+    for (int w = tid; w < nxl * nrow; w += NT) {   // x reduction: node column fj, local row ly
+      const int fj = w % nxl, ly = lya + w / nxl;
       const int jg = nox + fj;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
       for (int l = sColLo[fj]; l <= sColHi[fj]; ++l) {
         const Conv1 c = sCx[l];
-        const float w = (c.n0 == jg) ? 1.0f - c.f : c.f;
-        const int q = fr * TX + l;
-        s0 = fmaf(w, sV[0][q], s0);
-        s1 = fmaf(w, sV[1][q], s1);
-        s2 = fmaf(w, sV[2][q], s2);
+        const float wt = (c.n0 == jg) ? 1.0f - c.f : c.f;
+        const int q = ly * BX + l;
+        s0 = fmaf(wt, sV[0][q], s0);
+        s1 = fmaf(wt, sV[1][q], s1);
+        s2 = fmaf(wt, sV[2][q], s2);
       }
-      sW[0][fr * MAXNX + fj] = s0;
-      sW[1][fr * MAXNX + fj] = s1;
-      sW[2][fr * MAXNX + fj] = s2;
+      sW[0][ly * MAXNX + fj] = s0;
+      sW[1][ly * MAXNX + fj] = s1;
+      sW[2][ly * MAXNX + fj] = s2;
     }
     __syncthreads();
-    if (fj < nxl && fr < nyl) {   // y reduction: node (fj, fr)
+    for (int w = tid; w < nxl * nyl; w += NT) {   // y reduction: node (fj, fr)
+      const int fj = w % nxl, fr = w / nxl;
       const int ig = noy + fr;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
       for (int l = sRowLo[fr]; l <= sRowHi[fr]; ++l) {
         const Conv1 c = sCy[l];
-        const float w = (c.n0 == ig) ? 1.0f - c.f : c.f;
+        const float wt = (c.n0 == ig) ? 1.0f - c.f : c.f;
         const int q = l * MAXNX + fj;
-        s0 = fmaf(w, sW[0][q], s0);
-        s1 = fmaf(w, sW[1][q], s1);
-        s2 = fmaf(w, sW[2][q], s2);
+        s0 = fmaf(wt, sW[0][q], s0);
+        s1 = fmaf(wt, sW[1][q], s1);
+        s2 = fmaf(wt, sW[2][q], s2);
       }
       const size_t o = ((size_t)kloc * P.nyt + fr) * P.nxt + fj;
       const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
@@ -286,7 +294,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     if (zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
       const int s1 = zc & 1;
       float ex_p = 0.f, ex_m = 0.f, ey_p = 0.f, ey_m = 0.f;
-      if (inB && in_img) {
+      if (inB) {
         const float Tc = Tw[K1], Rc = Rv[K1];
         const float dTxm = sTw[s1][tid - 1] - Tc, dTxp = sTw[s1][tid + 1] - Tc;
         const float dTym = sTw[s1][tid - BX] - Tc, dTyp = sTw[s1][tid + BX] - Tc;
@@ -309,7 +317,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         const float rnT = rsqrtf(nT2), rnR = rsqrtf(nR2);
         const float c1 = rnT * rnR;
         const float r = r1 * c1;
-        if (MODE != MODE_HV && inner && zc >= zb && zc < ze) obj += (double)fmaf(-r, r, 1.0f);
+        if (MODE != MODE_HV && zc >= zb && zc < ze) obj += (double)fmaf(-r, r, 1.0f);
         if constexpr (NEED_C) {
           const float c2 = r1 * rnT * rnT;
           const float kx = P.hhx * c1, ky = P.hhy * c1, kz = P.hhz * c1;
@@ -362,11 +370,12 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         }
         if (inC) {
           const int s2 = c & 1;
+          // rows of the neighbours within the group (none beyond its edge)
           float w = e0[K2];
-          w += sE[s2][1][tid + 1];
-          w += sE[s2][0][tid - 1];
-          w += sE[s2][3][tid + BX];
-          w += sE[s2][2][tid - BX];
+          w += tx < BX - 1 ? sE[s2][1][tid + 1] : 0.f;
+          w += tx > 0 ? sE[s2][0][tid - 1] : 0.f;
+          w += ty < BY - 1 ? sE[s2][3][tid + BX] : 0.f;
+          w += ty > 0 ? sE[s2][2][tid - BX] : 0.f;
           w += ezm;
           w += ezp[K];
           const float wz1 = cvz.f, wz0 = 1.0f - cvz.f;
