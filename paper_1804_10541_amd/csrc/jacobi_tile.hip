@@ -209,7 +209,7 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
           sRR = fmaf(fmaf(dR[2 * a], dR[2 * a], dR[2 * a + 1] * dR[2 * a + 1]), ih2[a], sRR);
           sTR = fmaf(fmaf(dT[2 * a], dR[2 * a], dT[2 * a + 1] * dR[2 * a + 1]), ih2[a], sTR);
         }
-        const float rnT = rsqrtf(fmaf(0.5f, sTT, P.tau2)), rnR = rsqrtf(fmaf(0.5f, sRR, P.rho2));
+        const float rnT = rsq_norm(fmaf(0.5f, sTT, P.tau2)), rnR = rsq_norm(fmaf(0.5f, sRR, P.rho2));
         const float r1 = fmaf(0.5f, sTR, P.taurho);
         const float c1 = rnT * rnR, c2 = r1 * rnT * rnT;
         const float hh[3] = {P.hhx, P.hhy, P.hhz};

@@ -314,7 +314,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         const float nT2 = fmaf(0.5f, sTT, P.tau2);
         const float nR2 = fmaf(0.5f, sRR, P.rho2);
         const float r1 = fmaf(0.5f, sTR, P.taurho);
-        const float rnT = rsqrtf(nT2), rnR = rsqrtf(nR2);
+        const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
         const float c1 = rnT * rnR;
         const float r = r1 * c1;
         if (MODE != MODE_HV && zc >= zb && zc < ze) obj += (double)fmaf(-r, r, 1.0f);

@@ -113,6 +113,11 @@ __device__ __forceinline__ int template_cell(const Samp1 s, float d, float ihT, 
   return s.base + (int)fl;
 }
 
+// 1/sqrt(x) by the hardware reciprocal square root; the argument is clamped to
+// the smallest normal float, which leaves the NGF norms (>= tau^2, rho^2 > 0)
+// untouched and spares the range scaling that rsqrtf applies for denormals.
+__device__ __forceinline__ float rsq_norm(float x) { return __builtin_amdgcn_rsqf(fmaxf(x, 1.17549435e-38f)); }
+
 // Weight of node index n for a voxel with conversion entry c (0 outside its pair).
 __device__ __forceinline__ float conv_weight(const Conv1 c, int n) {
   return (c.n0 == n) ? 1.0f - c.f : ((c.n0 + 1 == n) ? c.f : 0.0f);
