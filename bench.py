@@ -40,10 +40,11 @@ HV_BYTES_PER_VOXEL = 8
 HV_BYTES_PER_NODE = 36
 
 # HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload
-# (32x16 tiles), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy kernel
-# (profiles/ngf_tile_hv_512x512x900.md): 2 x 1,411,340 KiB + 71,275 KiB.  Only
-# valid for that kernel build and tile configuration; otherwise reported as null.
-HV_TRAFFIC_C3 = {"bytes": 2963409920, "tile": (32, 16)}
+# (32x16 tiles, split target 4096), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
+# plain copy kernel (profiles/ngf_tile_hv_512x512x900.md): 2 x 1,248,390 KiB +
+# 117,524 KiB.  Only valid for that kernel build and tile configuration; otherwise
+# reported as null.
+HV_TRAFFIC_C3 = {"bytes": 2677046651, "tile": (32, 16, 4096)}
 
 
 def log(msg):
@@ -264,7 +265,8 @@ def main():
     alg_bytes = HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar
     hv_hbm_gbs = alg_bytes / (hv_avg_ms * 1e-3) / 1e9
     traffic = None
-    if args.workload == "c3" and tile_cfg and (tile_cfg["bx"], tile_cfg["by"]) == HV_TRAFFIC_C3["tile"]:
+    if args.workload == "c3" and tile_cfg and \
+            (tile_cfg["bx"], tile_cfg["by"], tile_cfg["target_groups"]) == HV_TRAFFIC_C3["tile"]:
         traffic = HV_TRAFFIC_C3["bytes"]
     out = {
         "metric": "GN Hessian-vector Gvoxel/s + % HBM peak; PCG solve time, learned vs Jacobi",
