@@ -535,22 +535,6 @@ mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q
   return MFR_OK;
 }
 
-// float64 dot products into context scalars: out[k] = a[k] . b[k] (b null: a . a).
-static mfr_status ctx_dots(mfr_ctx* c, double* red, int count, const float* const* a, const float* const* b,
-                           const int* slots) {
-  DotsArgs d{};
-  DotsOut o{};
-  d.n = 3 * c->geo.nbar;
-  d.count = count;
-  for (int k = 0; k < count; ++k) {
-    d.a[k] = a[k];
-    d.b[k] = b ? b[k] : nullptr;
-    o.out[k] = c->sc + slots[k];
-  }
-  HIP_TRY(launch_pc_dots(d, o, red, c->stream));
-  return MFR_OK;
-}
-
 // CG iterations enqueued between two host checks of a device-steered solve.
 constexpr int kSteerIters = 8;
 
@@ -624,100 +608,125 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   return MFR_OK;
 }
 
-// Preconditioned CG (Sec. 2.3.1; CG from s = 0, relative recursive residual).
-// precond 0 / 1: none / Jacobi, steered on the device (pcg_run_steered).
-// precond 2: the attached learned preconditioner with the flexible direction
-// update beta = z_{k+1}.(r_{k+1} - r_k) / z_k.r_k, optionally switching to
-// Jacobi after fallback_iters iterations; host loop.
-mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
-                   mfr_pcg_info* info) {
-  if (o->precond != 2) return pcg_run_steered(c, u, b, s_out, o, info);
+// Flexible CG with the attached learned preconditioner, steered on the device
+// like pcg_run_steered: beta = z_{k+1}.(r_{k+1} - r_k) / z_k.r_k, the
+// convergence test in the kernel that forms |r|, and every kernel of the solve
+// (the network's included) a no-op once the solve has stopped.  After
+// fallback_iters iterations (if > 0 and the solve is still running) it continues
+// as Jacobi-PCG from the current iterate with a fresh direction; the host knows
+// that iteration number, so the switch is a fixed point of the launch sequence.
+mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
+                            mfr_pcg_info* info) {
+  if (!c->pc) return fail(MFR_EINVAL, "precond 2 needs a preconditioner attached with mfr_attach_pc");
   const int n3 = (int)(3 * c->geo.nbar);
-  float* s = s_out;
   float* r = c->vec[0];
   float* z = c->vec[1];
   float* p = c->vec[2];
   float* q = c->vec[3];
-  float* diag = nullptr;
-  bool flexible = o->precond == 2;
-  if (flexible && !c->pc) return fail(MFR_EINVAL, "precond 2 needs a preconditioner attached with mfr_attach_pc");
-  if (o->precond >= 1) {
-    diag = c->vec[4];
-    HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
-  }
+  float* diag = c->vec[4];
+  int* active = c->ctrl;
+  int* state = c->ctrl + 1;
+  HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
+  VecJobs V{};
+  V.n = 1;
+  V.prefix[0] = 0;
+  V.prefix[1] = c->vec_blocks;
+  VecJob& v = V.jobs[0];
+  v.r = r;
+  v.z = z;
+  v.p = p;
+  v.q = q;
+  v.s = s_out;
+  v.b = b;
+  v.diag = nullptr;   // start: z = r, replaced by the network below
+  v.sc = c->sc;
+  v.state = state;
+  v.red = c->red_node;
+  v.red_pq = c->red_node;
+  v.n_pq = node_blocks(c);
+  v.n3 = n3;
+  v.max_iter = o->max_iter;
+  v.rtol = o->rtol;
+  V.active_out = active;
+  HIP_TRY(launch_pcg_init_batch(V, c->stream));
+  VecJobs VJ = V;   // the Jacobi phase after a fallback
+  VJ.jobs[0].diag = diag;
+  double* fred = pc_red(c->pc);
+  float* r_prev = pc_scratch_vec(c->pc);
   const int vb = c->vec_blocks;
-  HIP_TRY(launch_pcg_init(n3, b, flexible ? nullptr : diag, s, r, z, p, c->red_node, vb, c->stream));
-  HIP_TRY(launch_pcg_init_finish(c->red_node, vb, c->sc, c->stream));
-  double* fred = flexible ? pc_red(c->pc) : nullptr;
-  float* r_prev = flexible ? pc_scratch_vec(c->pc) : nullptr;
-  if (flexible) {
-    MFR_TRY(pc_begin_solve(c->pc, diag));
-    MFR_TRY(pc_forward(c->pc, r, diag, z));
-    HIP_TRY(hipMemcpyAsync(p, z, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
-    const float* a[1] = {z};
-    const float* bb[1] = {r};
-    const int sl[1] = {SC_RZ};
-    MFR_TRY(ctx_dots(c, fred, 1, a, bb, sl));
+  auto rz_dot = [&]() -> mfr_status {   // sc[SC_RZ] = z.r
+    DotsArgs d{};
+    DotsOut dout{};
+    d.n = (size_t)n3;
+    d.count = 1;
+    d.a[0] = z;
+    d.b[0] = r;
+    d.live = active;
+    dout.out[0] = c->sc + SC_RZ;
+    HIP_TRY(launch_pc_dots(d, dout, fred, c->stream));
+    return MFR_OK;
+  };
+  MFR_TRY(pc_begin_solve(c->pc, diag));
+  MFR_TRY(pc_forward(c->pc, r, diag, z, false, nullptr, nullptr, false, active));
+  HIP_TRY(hipMemcpyAsync(p, z, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
+  MFR_TRY(rz_dot());
+  TileParams tp = c->tp;
+  tp.live = active;
+  NodeParams np = c->np;
+  np.s_ngf = (float)(2.0 * c->geo.hbar());
+  np.live = active;
+  const Tiling& t = c->tiling;
+  bool jacobi = false;
+  int done = 0, act = 1;
+  while (done < o->max_iter && act) {
+    const int k = std::min(kSteerIters, o->max_iter - done);
+    for (int i = 0; i < k; ++i) {
+      const int it = done + i + 1;
+      HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, tp, u, p, t.grid(), c->stream); }));
+      HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream); }));
+      HIP_TRY(launch_pcg_alpha_batch(V, c->stream));
+      if (jacobi) {
+        HIP_TRY(launch_pcg_update_batch(VJ, c->stream));
+        HIP_TRY(launch_pcg_beta_batch(VJ, c->stream));
+        HIP_TRY(launch_pcg_direction_batch(VJ, c->stream));
+        continue;
+      }
+      // s += alpha p, r_prev = r, r -= alpha q; |r|, the convergence test, the RMS scales
+      HIP_TRY(launch_fpcg_update(n3, diag, p, q, s_out, r, r_prev, c->sc, c->red_node, vb, c->stream, active));
+      HIP_TRY(launch_fpcg_scales(c->red_node, vb, n3, c->sc, pc_scalars(c->pc), c->stream, state, active));
+      if (o->fallback_iters > 0 && it >= o->fallback_iters) {
+        HIP_TRY(launch_pc_fallback(n3, r, diag, z, p, active, state, c->stream));
+        MFR_TRY(rz_dot());
+        jacobi = true;
+        continue;
+      }
+      // z = M(r); the last layer leaves the partials of z.r and z.r_prev for beta
+      MFR_TRY(pc_forward(c->pc, r, diag, z, true, r_prev, fred, false, active));
+      HIP_TRY(launch_fpcg_beta_sum(fred, pc_conv_blocks(c->pc), c->sc, c->stream, active));
+      HIP_TRY(launch_pcg_direction_batch(V, c->stream));
+    }
+    done += k;
+    HIP_TRY(hipMemcpyAsync(&act, active, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
   }
   double h[SC_COUNT];
+  int st[ST_COUNT];
   HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(st, state, sizeof(st), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  const double bn = std::sqrt(h[SC_BB]);
-  mfr_pcg_info inf{0, 0.0, 1, 0};
-  if (!std::isfinite(bn)) return fail(MFR_ENONFINITE, "right-hand side is not finite");
-  if (bn == 0.0) {
-    inf.flag = 0;
-    if (info) *info = inf;
-    return MFR_OK;
-  }
-  inf.relres = 1.0;
-  for (int it = 1; it <= o->max_iter; ++it) {
-    MFR_TRY(enqueue_hess_vec(c, u, p, q));
-    HIP_TRY(launch_pcg_alpha(c->red_node, node_blocks(c), c->sc, c->stream));
-    if (flexible) {
-      // s += alpha p, r_prev = r, r -= alpha q, and the RMS scales of the next network input
-      HIP_TRY(launch_fpcg_update(n3, diag, p, q, s, r, r_prev, c->sc, c->red_node, vb, c->stream));
-      HIP_TRY(launch_fpcg_scales(c->red_node, vb, n3, c->sc, pc_scalars(c->pc), c->stream));
-    } else {
-      HIP_TRY(launch_pcg_update(n3, diag, p, q, s, r, z, c->sc, c->red_node, vb, c->stream));
-      HIP_TRY(launch_pcg_beta(c->red_node, vb, c->sc, c->stream));
-    }
-    HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    const double pq = h[SC_PQ];
-    if (!(pq > 0.0) || !std::isfinite(pq)) {
-      inf.flag = 2;
-      inf.iters = it - 1;
-      break;
-    }
-    inf.iters = it;
-    inf.relres = std::sqrt(h[SC_RR]) / bn;
-    if (inf.relres <= o->rtol) {
-      inf.flag = 0;
-      break;
-    }
-    if (it == o->max_iter) break;
-    if (flexible && o->fallback_iters > 0 && it >= o->fallback_iters) {
-      // continue as Jacobi-PCG from the current iterate: z = D^-1 r, p = z
-      flexible = false;
-      inf.used_fallback = 1;
-      HIP_TRY(launch_pc_jacobi(n3, r, diag, z, c->stream));
-      HIP_TRY(hipMemcpyAsync(p, z, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
-      const float* a[1] = {z};
-      const float* bb[1] = {r};
-      const int sl[1] = {SC_RZ};
-      MFR_TRY(ctx_dots(c, fred, 1, a, bb, sl));
-      continue;
-    }
-    if (flexible) {
-      // z = M(r); the last layer leaves the partials of z.r and z.r_prev for beta
-      MFR_TRY(pc_forward(c->pc, r, diag, z, true, r_prev, fred));
-      HIP_TRY(launch_fpcg_beta_sum(fred, pc_conv_blocks(c->pc), c->sc, c->stream));
-    }
-    HIP_TRY(launch_pcg_direction(n3, z, p, c->sc, vb, c->stream));
-  }
+  if (!std::isfinite(h[SC_BB])) return fail(MFR_ENONFINITE, "right-hand side is not finite");
+  mfr_pcg_info inf{st[ST_ITERS], h[SC_RELRES], st[ST_FLAG], st[ST_FALLBACK]};
   if (info) *info = inf;
   return MFR_OK;
+}
+
+// Preconditioned CG (Sec. 2.3.1; CG from s = 0, relative recursive residual).
+// precond 0 / 1: none / Jacobi (pcg_run_steered); precond 2: the attached
+// learned preconditioner in flexible CG (pcg_run_flexible).
+mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
+                   mfr_pcg_info* info) {
+  if (o->precond == 2) return pcg_run_flexible(c, u, b, s_out, o, info);
+  return pcg_run_steered(c, u, b, s_out, o, info);
 }
 
 // One Gauss-Newton step (Sec. 2.3.1).  Vectors: vec[5] right-hand side -grad J,

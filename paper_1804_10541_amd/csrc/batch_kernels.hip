@@ -150,6 +150,7 @@ __global__ __launch_bounds__(256) void pcg_init_finish_batch_kernel(const VecJob
     const bool live = bb > 0.0 && isfinite(bb) && v.max_iter > 0;
     st[ST_ITERS] = 0;
     st[ST_MAXIT] = v.max_iter;
+    st[ST_FALLBACK] = 0;
     sc[SC_RTOL] = v.rtol;
     st[ST_FLAG] = (bb == 0.0) ? 0 : 1;
     st[ST_ACTIVE] = live ? 1 : 0;

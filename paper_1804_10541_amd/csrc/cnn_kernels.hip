@@ -104,6 +104,7 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
   constexpr bool kRelu = kMode == kFirst || kMode == kHidden;
   constexpr bool kOutZ = kMode == kLast;
   constexpr bool kOut16 = kMode == kFirst || kMode == kHidden || kMode == kBwd;
+  if (a.live && !ld_coherent(a.live)) return;   // a device-steered solve has stopped
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, quad = lane >> 4;
   const size_t nn = (size_t)a.nx * a.ny * a.nz;

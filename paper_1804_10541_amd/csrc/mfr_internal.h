@@ -203,7 +203,7 @@ struct AxpyJobs {
 // Conjugate-gradient vectors and device-side control of one problem.
 // ST_MAXIT and SC_RTOL are copied from the job table by the start kernel, so
 // launches captured once stay valid for later solves with other limits.
-enum PcgState : int { ST_ACTIVE = 0, ST_ITERS = 1, ST_FLAG = 2, ST_MAXIT = 3, ST_COUNT = 4 };
+enum PcgState : int { ST_ACTIVE = 0, ST_ITERS = 1, ST_FLAG = 2, ST_MAXIT = 3, ST_FALLBACK = 4, ST_COUNT = 5 };
 struct VecJob {
   float *r, *z, *p, *q, *s;
   const float* b;
@@ -308,6 +308,7 @@ struct ConvArgs {
   const float* fdiag;
   const float* fgR;
   const double* fsc;
+  const int* live;   // nullable: skip while *live == 0 (device-steered solve)
 };
 
 struct AdamArgs {
@@ -333,6 +334,7 @@ struct DotsArgs {
   const float* a[4];
   const float* b[4];
   const float* den[4];
+  const int* live;   // nullable: skip while *live == 0 (device-steered solve)
 };
 struct DotsOut {
   double* out[4];
@@ -343,6 +345,10 @@ hipError_t launch_pc_dots(const DotsArgs& d, const DotsOut& o, double* red, hipS
 hipError_t launch_pc_features(int n, const float* r, const float* diag, const float* gR, const double* sc,
                               uint16_t* h0, hipStream_t st);
 hipError_t launch_pc_jacobi(int n3, const float* r, const float* diag, float* y, hipStream_t st);
+// Switch of a device-steered flexible solve to Jacobi-PCG: z = r / diag, p = z,
+// state[ST_FALLBACK] = 1; nothing while *live == 0.
+hipError_t launch_pc_fallback(int n3, const float* r, const float* diag, float* z, float* p, const int* live,
+                              int* state, hipStream_t st);
 hipError_t launch_pc_loss(double* sc, hipStream_t st);
 hipError_t launch_pc_grad_out(int n, const float* Az, const float* r, const double* sc, uint16_t* g16,
                               hipStream_t st);
@@ -361,12 +367,19 @@ hipError_t launch_pc_gradmag(const GmArgs& g, float* tmp1, float* tmp2, float* g
 hipError_t launch_fpcg_beta(double* sc, hipStream_t st);
 // Flexible-CG update: s += alpha p, rprev = r, r -= alpha q; partials of r.r and
 // (r/diag).(r/diag) per block (2 per block, `blocks` blocks).
+// live (nullable): every flexible-CG kernel does nothing while *live == 0.
 hipError_t launch_fpcg_update(int n3, const float* diag, const float* p, const float* q, float* s, float* r,
-                              float* rprev, const double* sc, double* red, int blocks, hipStream_t st);
-// sc[SC_RR] = r.r; pc_sc[PC_RMS_R], pc_sc[PC_RMS_Y] = RMS of r and r/diag over n3 entries
-hipError_t launch_fpcg_scales(const double* red, int blocks, int n3, double* sc, double* pc_sc, hipStream_t st);
+                              float* rprev, const double* sc, double* red, int blocks, hipStream_t st,
+                              const int* live = nullptr);
+// sc[SC_RR] = r.r; pc_sc[PC_RMS_R], pc_sc[PC_RMS_Y] = RMS of r and r/diag over n3 entries.
+// With state (device-steered solve, state = PcgState, active = the solve's live
+// flag): the iteration count, sc[SC_RELRES] and the convergence / iteration-limit
+// test, which clears state[ST_ACTIVE] and *active.
+hipError_t launch_fpcg_scales(const double* red, int blocks, int n3, double* sc, double* pc_sc, hipStream_t st,
+                              int* state = nullptr, int* active = nullptr);
 // beta from the final convolution's partials (z.r, z.rprev): beta = (zr - zrp) / sc[SC_RZ]; sc[SC_RZ] = zr
-hipError_t launch_fpcg_beta_sum(const double* zred, int blocks, double* sc, hipStream_t st);
+hipError_t launch_fpcg_beta_sum(const double* zred, int blocks, double* sc, hipStream_t st,
+                                const int* live = nullptr);
 int cnn_wgrad_groups(int nx, int ny, int nz);
 // part: cnn_wgrad_groups(...) x kCnnLayerParams floats; out: kCnnLayerParams floats
 hipError_t launch_cnn_wgrad(int nx, int ny, int nz, const uint16_t* x, const uint16_t* g, float* part,

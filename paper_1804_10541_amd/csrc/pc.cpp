@@ -241,7 +241,7 @@ mfr_status pc_begin_solve(mfr_pc* pc, const float* diag) {
 // r and r/diag are already in the scalars (the flexible-CG update computes them).
 // zred: the final layer also leaves per-group partials of z.r and z.rprev there.
 mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, bool scales_ready,
-                      const float* rprev, double* zred, bool keep_input) {
+                      const float* rprev, double* zred, bool keep_input, const int* live) {
   hipStream_t st = st_of(pc);
   if (!scales_ready) {
     DotsArgs d{};
@@ -251,6 +251,7 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, b
     d.a[0] = r;
     d.den[0] = diag;
     d.a[1] = r;
+    d.live = live;
     o.out[0] = pc->sc + PC_RMS_Y;
     o.out[1] = pc->sc + PC_RMS_R;
     o.rms_scale[0] = o.rms_scale[1] = 1.0 / pc->n3;
@@ -265,6 +266,7 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, b
     a.ny = pc->ny;
     a.nz = pc->nz;
     a.x = pc->h[l];
+    a.live = live;
     if (l == 0 && !keep_input) {
       a.x = nullptr;
       a.fr = r;

@@ -46,6 +46,7 @@ int vec_blocks_for(size_t n) { return (int)std::max<size_t>(1, std::min<size_t>(
 // red[k * blocks + b] = partial of sum_i a_k[i] * b_k[i]; b_k null means a_k . a_k;
 // den_k (nullable) divides a_k elementwise first (Jacobi-scaled vectors).
 __global__ __launch_bounds__(kPB) void pc_dots_kernel(const DotsArgs d, double* __restrict__ red) {
+  if (d.live && !ld_coherent(d.live)) return;
   __shared__ double sred[4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * kPB + threadIdx.x; i < d.n; i += (size_t)gridDim.x * kPB) {
@@ -71,7 +72,8 @@ __global__ __launch_bounds__(kPB) void pc_dots_kernel(const DotsArgs d, double* 
 // out[k] = sum_b red[k * blocks + b] (fixed order); sqrt_scale[k] > 0 stores
 // sqrt(sum * sqrt_scale[k]) instead (an RMS).
 __global__ __launch_bounds__(256) void pc_dots_finish_kernel(const double* __restrict__ red, int blocks, int count,
-                                                             DotsOut o) {
+                                                             DotsOut o, const int* live) {
+  if (live && !ld_coherent(live)) return;
   __shared__ double sred[4];
   for (int k = 0; k < count; ++k) {
     double a = 0.0;
@@ -88,7 +90,7 @@ hipError_t launch_pc_dots(const DotsArgs& d, const DotsOut& o, double* red, hipS
   hipLaunchKernelGGL(pc_dots_kernel, dim3(blocks), dim3(kPB), 0, st, d, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pc_dots_finish_kernel, dim3(1), dim3(256), 0, st, red, blocks, d.count, o);
+  hipLaunchKernelGGL(pc_dots_finish_kernel, dim3(1), dim3(256), 0, st, red, blocks, d.count, o, d.live);
   return hipGetLastError();
 }
 
@@ -139,6 +141,25 @@ __global__ __launch_bounds__(kPB) void pc_jacobi_kernel(int n3, const float* __r
 hipError_t launch_pc_jacobi(int n3, const float* r, const float* diag, float* y, hipStream_t st) {
   const int blocks = std::min((n3 + kPB - 1) / kPB, 4096);
   hipLaunchKernelGGL(pc_jacobi_kernel, dim3(blocks), dim3(kPB), 0, st, n3, r, diag, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kPB) void pc_fallback_kernel(int n3, const float* __restrict__ r,
+                                                          const float* __restrict__ diag, float* __restrict__ z,
+                                                          float* __restrict__ p, const int* live, int* state) {
+  if (!ld_coherent(live)) return;
+  for (int i = blockIdx.x * kPB + threadIdx.x; i < n3; i += gridDim.x * kPB) {
+    const float zi = r[i] / diag[i];
+    z[i] = zi;
+    p[i] = zi;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) state[ST_FALLBACK] = 1;
+}
+
+hipError_t launch_pc_fallback(int n3, const float* r, const float* diag, float* z, float* p, const int* live,
+                              int* state, hipStream_t st) {
+  const int blocks = std::min((n3 + kPB - 1) / kPB, 4096);
+  hipLaunchKernelGGL(pc_fallback_kernel, dim3(blocks), dim3(kPB), 0, st, n3, r, diag, z, p, live, state);
   return hipGetLastError();
 }
 
@@ -282,7 +303,8 @@ __global__ __launch_bounds__(kPB) void fpcg_update_kernel(int n3, const float* _
                                                           const float* __restrict__ p, const float* __restrict__ q,
                                                           float* __restrict__ s, float* __restrict__ r,
                                                           float* __restrict__ rprev, const double* __restrict__ sc,
-                                                          double* __restrict__ red) {
+                                                          double* __restrict__ red, const int* live) {
+  if (live && !ld_coherent(live)) return;
   __shared__ double sred[4];
   const float alpha = (float)ld_coherent(sc + SC_ALPHA);
   double rr = 0.0, yy = 0.0;
@@ -305,13 +327,16 @@ __global__ __launch_bounds__(kPB) void fpcg_update_kernel(int n3, const float* _
 }
 
 hipError_t launch_fpcg_update(int n3, const float* diag, const float* p, const float* q, float* s, float* r,
-                              float* rprev, const double* sc, double* red, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(fpcg_update_kernel, dim3(blocks), dim3(kPB), 0, st, n3, diag, p, q, s, r, rprev, sc, red);
+                              float* rprev, const double* sc, double* red, int blocks, hipStream_t st,
+                              const int* live) {
+  hipLaunchKernelGGL(fpcg_update_kernel, dim3(blocks), dim3(kPB), 0, st, n3, diag, p, q, s, r, rprev, sc, red, live);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void fpcg_scales_kernel(const double* __restrict__ red, int blocks, int n3,
-                                                          double* __restrict__ sc, double* __restrict__ pc_sc) {
+                                                          double* __restrict__ sc, double* __restrict__ pc_sc,
+                                                          int* state, int* active) {
+  if (active && !ld_coherent(active)) return;
   __shared__ double sred[4];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < blocks; i += 256) {
@@ -324,16 +349,33 @@ __global__ __launch_bounds__(256) void fpcg_scales_kernel(const double* __restri
     sc[SC_RR] = rr;
     pc_sc[PC_RMS_R] = sqrt(rr / n3);
     pc_sc[PC_RMS_Y] = sqrt(yy / n3);
+    if (state) {   // the convergence test of a device-steered solve
+      const int iters = ld_coherent(state + ST_ITERS) + 1;
+      const double rel = sqrt(rr) / sqrt(ld_coherent(sc + SC_BB));
+      state[ST_ITERS] = iters;
+      sc[SC_RELRES] = rel;
+      if (rel <= ld_coherent(sc + SC_RTOL)) {
+        state[ST_FLAG] = 0;
+        state[ST_ACTIVE] = 0;
+        *active = 0;
+      } else if (iters >= ld_coherent(state + ST_MAXIT)) {
+        state[ST_FLAG] = 1;
+        state[ST_ACTIVE] = 0;
+        *active = 0;
+      }
+    }
   }
 }
 
-hipError_t launch_fpcg_scales(const double* red, int blocks, int n3, double* sc, double* pc_sc, hipStream_t st) {
-  hipLaunchKernelGGL(fpcg_scales_kernel, dim3(1), dim3(256), 0, st, red, blocks, n3, sc, pc_sc);
+hipError_t launch_fpcg_scales(const double* red, int blocks, int n3, double* sc, double* pc_sc, hipStream_t st,
+                              int* state, int* active) {
+  hipLaunchKernelGGL(fpcg_scales_kernel, dim3(1), dim3(256), 0, st, red, blocks, n3, sc, pc_sc, state, active);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void fpcg_beta_sum_kernel(const double* __restrict__ zred, int blocks,
-                                                            double* __restrict__ sc) {
+                                                            double* __restrict__ sc, const int* live) {
+  if (live && !ld_coherent(live)) return;
   __shared__ double sred[4];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < blocks; i += 256) {
@@ -350,8 +392,8 @@ __global__ __launch_bounds__(256) void fpcg_beta_sum_kernel(const double* __rest
   }
 }
 
-hipError_t launch_fpcg_beta_sum(const double* zred, int blocks, double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(fpcg_beta_sum_kernel, dim3(1), dim3(256), 0, st, zred, blocks, sc);
+hipError_t launch_fpcg_beta_sum(const double* zred, int blocks, double* sc, hipStream_t st, const int* live) {
+  hipLaunchKernelGGL(fpcg_beta_sum_kernel, dim3(1), dim3(256), 0, st, zred, blocks, sc, live);
   return hipGetLastError();
 }
 
