@@ -22,6 +22,9 @@ from . import mfr
 
 SHAPES = ((32, 16), (64, 8), (32, 32), (64, 16))
 GROUP_TARGETS = (1024, 2048, 4096)
+# explicit z-chunk lengths (planes per work-group), tried besides the derived
+# splits: small volumes run fastest with chunks shorter than the derived minimum
+CHUNK_LENS = (6, 12, 24)
 KERNEL = "tile_hv"
 
 
@@ -75,7 +78,8 @@ def lookup(spec, device="cuda:0", path=None):
 
 
 def candidates():
-    return [dict(bx=bx, by=by, chunk_len=0, target_groups=g) for (bx, by) in SHAPES for g in GROUP_TARGETS]
+    return ([dict(bx=bx, by=by, chunk_len=0, target_groups=g) for (bx, by) in SHAPES for g in GROUP_TARGETS]
+            + [dict(bx=bx, by=by, chunk_len=c, target_groups=0) for (bx, by) in SHAPES for c in CHUNK_LENS])
 
 
 def time_config(cfg, spec, R, T, u, p, device, reps):

@@ -88,17 +88,24 @@ class Systems:
         self.device = torch.device(device)
         self.ctxs = {}
 
-    def ctx(self, spec):
+    def ctx(self, spec, R=None, T=None):
+        """Context of this grid size, created with the tile configuration the
+        autotuner picks for it (timed on R, T when given)."""
         key = (tuple(spec.m), tuple(spec.my))
         if key not in self.ctxs:
+            if R is not None:
+                from . import autotune
+
+                u0 = torch.zeros((3, spec.my[2], spec.my[1], spec.my[0]), dtype=torch.float32, device=self.device)
+                autotune.apply(spec, R, T, u0, device=self.device)
             self.ctxs[key] = mfr.Context(spec, self.device)
         return self.ctxs[key]
 
     def trajectory(self, seed, spec, gn_iters, pcg_max=50, pcg_rtol=1e-3):
         from synth import ct_pair
 
-        ctx = self.ctx(spec)
         R, T, _, _ = ct_pair(seed, spec.m, device=self.device)
+        ctx = self.ctx(spec, R, T)
         ctx.set_images(R, T)
         self._images = (R, T)
         u = torch.zeros(ctx.node_shape(), dtype=torch.float32, device=self.device)

@@ -8,9 +8,10 @@ from synth import GridSpec
 
 def test_candidates_cover_every_shape_and_split():
     c = autotune.candidates()
-    assert len(c) == len(autotune.SHAPES) * len(autotune.GROUP_TARGETS)
+    assert len(c) == len(autotune.SHAPES) * (len(autotune.GROUP_TARGETS) + len(autotune.CHUNK_LENS))
+    assert {d["chunk_len"] for d in c} == {0, *autotune.CHUNK_LENS}
     assert {(d["bx"], d["by"]) for d in c} == set(autotune.SHAPES)
-    assert all(d["chunk_len"] == 0 and d["target_groups"] > 0 for d in c)
+    assert all((d["chunk_len"] == 0) != (d["target_groups"] == 0) for d in c)
 
 
 def test_cache_round_trip(tmp_path, monkeypatch):
