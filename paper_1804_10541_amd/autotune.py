@@ -24,7 +24,7 @@ SHAPES = ((32, 16), (64, 8), (32, 32), (64, 16))
 GROUP_TARGETS = (1024, 2048, 4096)
 # explicit z-chunk lengths (planes per work-group), tried besides the derived
 # splits: small volumes run fastest with chunks shorter than the derived minimum
-CHUNK_LENS = (6, 12, 24)
+CHUNK_LENS = (4, 6, 12, 24)
 KERNEL = "tile_hv"
 
 
