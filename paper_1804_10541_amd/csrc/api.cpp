@@ -239,7 +239,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.part = take(sizeof(float) * (size_t)t.grid() * 3 * t.nzt * t.nyt * t.nxt);
   L.red_tile = take(sizeof(double) * (size_t)t.grid());
   const size_t node_blocks = (g.nbar + kNodeBlock - 1) / kNodeBlock;
-  L.n_red_node = std::max<size_t>(node_blocks, 2 * 1024);
+  L.n_red_node = std::max<size_t>(3 * node_blocks, 2 * 1024);   // the node pass: one partial per block and component
   L.red_node = take(sizeof(double) * L.n_red_node);
   L.sc = take(sizeof(double) * SC_COUNT);
   L.vec = take(sizeof(float) * 3 * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
@@ -476,6 +476,7 @@ hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
 }
 
 int node_blocks(const mfr_ctx* c) { return (int)((c->geo.nbar + kNodeBlock - 1) / kNodeBlock); }
+int node_parts(const mfr_ctx* c) { return 3 * node_blocks(c); }
 
 mfr_status check_ptr(const void* p, const char* name) {
   if (!p) return fail(MFR_EINVAL, "%s is NULL", name);
@@ -521,7 +522,7 @@ mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
   NodeParams q = c->np;
   q.s_ngf = (float)(-2.0 * c->geo.hbar());
   HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_GRAD, q, u, g, node_blocks(c), c->stream); }));
-  HIP_TRY(launch_sum(c->red_node, node_blocks(c), c->sc + SC_S, c->stream));
+  HIP_TRY(launch_sum(c->red_node, node_parts(c), c->sc + SC_S, c->stream));
   return MFR_OK;
 }
 
@@ -570,7 +571,7 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   v.state = c->ctrl + 1;
   v.red = c->red_node;
   v.red_pq = c->red_node;
-  v.n_pq = node_blocks(c);
+  v.n_pq = node_parts(c);
   v.n3 = (int)(3 * c->geo.nbar);
   v.max_iter = o->max_iter;
   v.rtol = o->rtol;
@@ -643,7 +644,7 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
   v.state = state;
   v.red = c->red_node;
   v.red_pq = c->red_node;
-  v.n_pq = node_blocks(c);
+  v.n_pq = node_parts(c);
   v.n3 = n3;
   v.max_iter = o->max_iter;
   v.rtol = o->rtol;

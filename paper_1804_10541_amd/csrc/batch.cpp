@@ -165,13 +165,17 @@ mfr_status sum_tile_parts(mfr_batch* b, const int* mask) {
   return MFR_OK;
 }
 
-// Sums the node-pass partials of every masked pair into its slot SC_S.
-mfr_status sum_node_parts(mfr_batch* b, const int* mask) {
+// Sums the node-pass partials of every masked pair into its slot SC_S: one per
+// node group after the regulariser pass (objective), one per group and
+// component after the gradient pass.
+mfr_status sum_node_parts(mfr_batch* b, const int* mask, bool per_component) {
   SumJobs S{};
   S.n = b->n;
   S.active = mask;
-  for (int k = 0; k < b->n; ++k)
-    S.jobs[k] = SumJob{b->ctx[k]->red_node, node_blocks(b->ctx[k]), 1, b->ctx[k]->sc + SC_S};
+  for (int k = 0; k < b->n; ++k) {
+    mfr_ctx* c = b->ctx[k];
+    S.jobs[k] = SumJob{c->red_node, per_component ? node_parts(c) : node_blocks(c), 1, c->sc + SC_S};
+  }
   HIP_TRY(launch_sum_batch(S, b->st));
   return MFR_OK;
 }
@@ -201,7 +205,7 @@ mfr_status batch_objective(mfr_batch* b, const float* const* u, const int* mask)
   MFR_TRY(sum_tile_parts(b, mask));
   NodeJobs N = node_jobs(b, 0.0f, u, nullptr, mask);
   HIP_TRY(launch_node_pass_batch(NP_S, N, b->st));
-  return sum_node_parts(b, mask);
+  return sum_node_parts(b, mask, false);
 }
 
 // Gradient of every masked pair into out[k]; the objective parts in the scalars.
@@ -211,7 +215,7 @@ mfr_status batch_gradient(mfr_batch* b, const float* const* u, float* const* out
   MFR_TRY(sum_tile_parts(b, mask));
   NodeJobs N = node_jobs(b, -2.0f, u, out, mask);
   HIP_TRY(launch_node_pass_batch(NP_GRAD, N, b->st));
-  return sum_node_parts(b, mask);
+  return sum_node_parts(b, mask, true);
 }
 
 // q_k = A_k p_k for CG-active pairs; p.q partials in each context's red_node.
@@ -241,7 +245,7 @@ VecJobs vec_jobs(mfr_batch* b, const int* max_iter, double rtol, bool precond) {
     v.state = b->state + ST_COUNT * k;
     v.red = c->red_node;
     v.red_pq = c->red_node;
-    v.n_pq = node_blocks(c);
+    v.n_pq = node_parts(c);
     v.n3 = (int)(3 * c->geo.nbar);
     v.max_iter = max_iter[k];
     v.rtol = rtol;

@@ -77,10 +77,12 @@ __device__ __forceinline__ void lap_body(const NodeParams& Q, const float* __res
   }
 }
 
-// One thread per node: q_d = s_ngf * (sum of the tile partials) + s_curv * (L L f_d).
+// One thread per node and component d (work-group row d): q_d = s_ngf * (sum of
+// the tile partials) + s_curv * (L L f_d).  Partials: red[d * nb + blk].
 template <int MODE>
 __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float* __restrict__ f,
-                                               float* __restrict__ out, const int blk, double* sred) {
+                                               float* __restrict__ out, const int blk, const int nb, const int d,
+                                               double* sred) {
   const int n = blk * kNodeBlock + threadIdx.x;
   double local = 0.0;
   if (n < Q.nbar) {
@@ -88,41 +90,38 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     const int j = (n / Q.nx) % Q.ny;
     const int k = n / (Q.nx * Q.ny);
     const int nxy = Q.nx * Q.ny;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float* fd = f + (size_t)d * Q.nbar;
-      const float* Ld = Q.lap + (size_t)d * Q.nbar;
-      const float L0 = Ld[n];
-      const float Lxm = i > 0 ? Ld[n - 1] : L0;
-      const float Lxp = i < Q.nx - 1 ? Ld[n + 1] : L0;
-      const float Lym = j > 0 ? Ld[n - Q.nx] : L0;
-      const float Lyp = j < Q.ny - 1 ? Ld[n + Q.nx] : L0;
-      const float Lzm = k > 0 ? Ld[n - nxy] : L0;
-      const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
-      const float m2 = -2.0f * L0;
-      const float LL = fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
-      // gather of the transposed conversion: every tile slot overlapping node n
-      const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
-      float s = 0.0f;
-      for (int cz = rz.lo; cz <= rz.hi; ++cz) {
-        const int kz = k - Q.orgz[cz];
-        for (int cy = ry.lo; cy <= ry.hi; ++cy) {
-          const int iy = j - Q.orgy[cy];
-          for (int cx = rx.lo; cx <= rx.hi; ++cx) {
-            const int jx = i - Q.orgx[cx];
-            const size_t slot = (size_t)cx + (size_t)Q.tiles_x * ((size_t)cy + (size_t)Q.tiles_y * cz);
-            s += Q.part[(((slot * 3 + d) * Q.nzt + kz) * Q.nyt + iy) * Q.nxt + jx];
-          }
+    const float* fd = f + (size_t)d * Q.nbar;
+    const float* Ld = Q.lap + (size_t)d * Q.nbar;
+    const float L0 = Ld[n];
+    const float Lxm = i > 0 ? Ld[n - 1] : L0;
+    const float Lxp = i < Q.nx - 1 ? Ld[n + 1] : L0;
+    const float Lym = j > 0 ? Ld[n - Q.nx] : L0;
+    const float Lyp = j < Q.ny - 1 ? Ld[n + Q.nx] : L0;
+    const float Lzm = k > 0 ? Ld[n - nxy] : L0;
+    const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
+    const float m2 = -2.0f * L0;
+    const float LL = fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
+    // gather of the transposed conversion: every tile slot overlapping node n
+    const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
+    float s = 0.0f;
+    for (int cz = rz.lo; cz <= rz.hi; ++cz) {
+      const int kz = k - Q.orgz[cz];
+      for (int cy = ry.lo; cy <= ry.hi; ++cy) {
+        const int iy = j - Q.orgy[cy];
+        for (int cx = rx.lo; cx <= rx.hi; ++cx) {
+          const int jx = i - Q.orgx[cx];
+          const size_t slot = (size_t)cx + (size_t)Q.tiles_x * ((size_t)cy + (size_t)Q.tiles_y * cz);
+          s += Q.part[(((slot * 3 + d) * Q.nzt + kz) * Q.nyt + iy) * Q.nxt + jx];
         }
       }
-      const float q = fmaf(Q.s_ngf, s, Q.s_curv * LL);
-      out[(size_t)d * Q.nbar + n] = q;
-      if (MODE == NP_GRAD) local += (double)L0 * (double)L0;
-      if (MODE == NP_HV) local += (double)fd[n] * (double)q;
     }
+    const float q = fmaf(Q.s_ngf, s, Q.s_curv * LL);
+    out[(size_t)d * Q.nbar + n] = q;
+    if (MODE == NP_GRAD) local = (double)L0 * (double)L0;
+    if (MODE == NP_HV) local = (double)fd[n] * (double)q;
   }
   const double s = block_sum<kNodeBlock>(local, sred);
-  if (threadIdx.x == 0) Q.red[blk] = s;
+  if (threadIdx.x == 0) Q.red[(size_t)d * nb + blk] = s;
 }
 
 template <int MODE>
@@ -148,7 +147,7 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams 
                                                                float* __restrict__ out) {
   if (Q.live && !ld_coherent(Q.live)) return;   // a device-steered solve has stopped
   __shared__ double sred[kNodeBlock / 64];
-  node_pass_body<MODE>(Q, f, out, blockIdx.x, sred);
+  node_pass_body<MODE>(Q, f, out, blockIdx.x, gridDim.x, blockIdx.y, sred);
 }
 
 // The same per-node arithmetic for a table of problems (batched path).
@@ -159,7 +158,8 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_batch_kernel(const NodeJ
   while (pr + 1 < J.n && J.prefix[pr + 1] <= (int)blockIdx.x) ++pr;
   if (J.active && !ld_coherent(J.active + pr)) return;
   const NodeJob& jb = J.jobs[pr];
-  node_pass_body<MODE>(jb.q, jb.f, jb.out, blockIdx.x - J.prefix[pr], sred);
+  node_pass_body<MODE>(jb.q, jb.f, jb.out, blockIdx.x - J.prefix[pr], J.prefix[pr + 1] - J.prefix[pr], blockIdx.y,
+                       sred);
 }
 
 hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
@@ -172,9 +172,9 @@ hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == NP_GRAD)
-    hipLaunchKernelGGL(node_pass_batch_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_GRAD>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, j);
   else
-    hipLaunchKernelGGL(node_pass_batch_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_HV>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, j);
   return hipGetLastError();
 }
 
@@ -189,9 +189,9 @@ hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == NP_GRAD)
-    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
+    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, q, f, out);
   else
-    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
+    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, q, f, out);
   return hipGetLastError();
 }
 

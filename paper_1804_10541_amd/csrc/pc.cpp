@@ -506,7 +506,7 @@ mfr_status mfr_pc_train_system(mfr_pc* pc, const float* u, const float* b, const
     if (it == o->pcg_iters) break;
     // one Jacobi-PCG iteration to move to the next residual
     MFR_TRY(enqueue_hess_vec(c, u, p, q));
-    HIP_TRY(launch_pcg_alpha(c->red_node, node_blocks(c), c->sc, st));
+    HIP_TRY(launch_pcg_alpha(c->red_node, node_parts(c), c->sc, st));
     HIP_TRY(launch_pcg_update(n3, pc->diag, p, q, pc->s, r, z, c->sc, c->red_node, vb, st));
     HIP_TRY(launch_pcg_beta(c->red_node, vb, c->sc, st));
     HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, st));
