@@ -364,7 +364,6 @@ struct GmArgs {
 };
 // tmp1: mz*my*nx floats, tmp2: mz*ny*nx floats, gR: nz*ny*nx floats
 hipError_t launch_pc_gradmag(const GmArgs& g, float* tmp1, float* tmp2, float* gR, hipStream_t st);
-hipError_t launch_fpcg_beta(double* sc, hipStream_t st);
 // Flexible-CG update: s += alpha p, rprev = r, r -= alpha q; partials of r.r and
 // (r/diag).(r/diag) per block (2 per block, `blocks` blocks).
 // live (nullable): every flexible-CG kernel does nothing while *live == 0.

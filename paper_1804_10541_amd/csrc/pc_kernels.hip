@@ -286,19 +286,6 @@ hipError_t launch_pc_gradmag(const GmArgs& g, float* tmp1, float* tmp2, float* g
 }
 
 // ---- flexible CG (Polak-Ribiere) --------------------------------------------------
-// beta = (z.r - z.r_prev) / rz_old from sc[SC_ZR], sc[SC_ZRP]; then rz = z.r.
-__global__ void fpcg_beta_kernel(double* sc) {
-  if (threadIdx.x != 0) return;
-  const double zr = ld_coherent(sc + SC_ZR);
-  sc[SC_BETA] = (zr - ld_coherent(sc + SC_ZRP)) / ld_coherent(sc + SC_RZ);
-  sc[SC_RZ] = zr;
-}
-
-hipError_t launch_fpcg_beta(double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(fpcg_beta_kernel, dim3(1), dim3(64), 0, st, sc);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(kPB) void fpcg_update_kernel(int n3, const float* __restrict__ diag,
                                                           const float* __restrict__ p, const float* __restrict__ q,
                                                           float* __restrict__ s, float* __restrict__ r,
