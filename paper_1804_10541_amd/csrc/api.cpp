@@ -668,7 +668,7 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
     return MFR_OK;
   };
   MFR_TRY(pc_begin_solve(c->pc, diag));
-  MFR_TRY(pc_forward(c->pc, r, diag, z, false, nullptr, nullptr, false, active));
+  MFR_TRY(pc_forward(c->pc, r, diag, z, false, nullptr, nullptr, active));
   HIP_TRY(hipMemcpyAsync(p, z, sizeof(float) * n3, hipMemcpyDeviceToDevice, c->stream));
   MFR_TRY(rz_dot());
   TileParams tp = c->tp;
@@ -702,7 +702,7 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
         continue;
       }
       // z = M(r); the last layer leaves the partials of z.r and z.r_prev for beta
-      MFR_TRY(pc_forward(c->pc, r, diag, z, true, r_prev, fred, false, active));
+      MFR_TRY(pc_forward(c->pc, r, diag, z, true, r_prev, fred, active));
       HIP_TRY(launch_fpcg_beta_sum(fred, pc_conv_blocks(c->pc), c->sc, c->stream, active));
       HIP_TRY(launch_pcg_direction_batch(V, c->stream));
     }

@@ -53,63 +53,28 @@ __device__ __forceinline__ bf16x8 zero8() {
   return __builtin_bit_cast(bf16x8, z);
 }
 
-// Reciprocal RMS scales of the network input (see the feature kernel).
-struct FeatScales {
-  float iy, ir, id, ig;
-};
-
-// Eight input channels (half 0: y0..y2, r0..r2, d0, d1; half 1: d2, |grad R|, 0...)
-// of one node, computed exactly as the feature kernel does.
-__device__ __forceinline__ uint4 feature_half(const ConvArgs& a, const FeatScales& fs, size_t node, size_t nn,
-                                              int half) {
-  float f[8];
-  if (half == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float rv = a.fr[(size_t)d * nn + node], dv = a.fdiag[(size_t)d * nn + node];
-      f[d] = (rv / dv) * fs.iy;
-      f[3 + d] = rv * fs.ir;
-    }
-    f[6] = a.fdiag[node] * fs.id;
-    f[7] = a.fdiag[nn + node] * fs.id;
-  } else {
-    f[0] = a.fdiag[2 * nn + node] * fs.id;
-    f[1] = a.fgR[node] * fs.ig;
-#pragma unroll
-    for (int c = 2; c < 8; ++c) f[c] = 0.f;
-  }
-  uint4 o;
-  o.x = f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
-  o.y = f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
-  o.z = f2bf(f[4]) | ((uint32_t)f2bf(f[5]) << 16);
-  o.w = f2bf(f[6]) | ((uint32_t)f2bf(f[7]) << 16);
-  return o;
-}
-
 }  // namespace
 
 // ---- forward and backward-data convolution --------------------------------------
 // One kernel body, specialised per use so that each instance keeps only the
 // registers and branches it needs: kGeneric takes every option at run time (the
 // public convolution entry points); the others are the preconditioner's own
-// layers with out-major weights: kFirst (network input computed from r, diag and
-// |grad R|; ReLU; bf16 output), kHidden (bf16 input; ReLU; bf16 output), kLast
+// layers with out-major weights: kHidden (bf16 input; ReLU; bf16 output), kLast
 // (bf16 input; output z = r / diag + scale * y[0..2]) and kBwd (transposed
 // weights, ReLU mask, bf16 output: backward-data of the training pass).
-enum ConvMode : int { kGeneric = 0, kFirst = 1, kHidden = 2, kLast = 3, kBwd = 4 };
+enum ConvMode : int { kGeneric = 0, kHidden = 2, kLast = 3, kBwd = 4 };
 
 template <int kMode>
 __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
-  constexpr bool kFeat = kMode == kFirst;
-  constexpr bool kRelu = kMode == kFirst || kMode == kHidden;
+  constexpr bool kRelu = kMode == kHidden;
   constexpr bool kOutZ = kMode == kLast;
-  constexpr bool kOut16 = kMode == kFirst || kMode == kHidden || kMode == kBwd;
+  constexpr bool kOut16 = kMode == kHidden || kMode == kBwd;
   if (a.live && !ld_coherent(a.live)) return;   // a device-steered solve has stopped
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, quad = lane >> 4;
   const size_t nn = (size_t)a.nx * a.ny * a.nz;
   const bool transpose = kMode == kBwd || (kMode == kGeneric && a.transpose);
-  const bool out_major = kMode == kFirst || kMode == kHidden || kMode == kLast || (kMode == kGeneric && a.w_out_major);
+  const bool out_major = kMode == kHidden || kMode == kLast || (kMode == kGeneric && a.w_out_major);
 
   // LDS: the block's weights as the A operand wants them, [tap][row][k channel]
   // (tap 27 zero: the padding half of the last step), and the input tile with a
@@ -140,15 +105,6 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
   }
   float scale = 0.f;
   if constexpr (kOutZ) scale = (float)ld_coherent(a.scale);
-  FeatScales fs{0.f, 0.f, 0.f, 0.f};
-  if constexpr (kFeat) {
-    const double sy = ld_coherent(a.fsc + PC_RMS_Y), sr = ld_coherent(a.fsc + PC_RMS_R);
-    const double sd = ld_coherent(a.fsc + PC_RMS_D), sg = ld_coherent(a.fsc + PC_RMS_G);
-    fs.iy = sy > 0.0 ? (float)(1.0 / sy) : 0.f;
-    fs.ir = sr > 0.0 ? (float)(1.0 / sr) : 0.f;
-    fs.id = sd > 0.0 ? (float)(1.0 / sd) : 0.f;
-    fs.ig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
-  }
   double zr = 0.0, zrp = 0.0;
 
   // Output tiles of 16 (x) x 4 (y) x 4 (z) nodes, one per work-group; wave w
@@ -175,10 +131,7 @@ __global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
         const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
         if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz) {
           const size_t node = ((size_t)zz * a.ny + yy) * a.nx + xx;
-          if constexpr (kFeat)
-            v[k] = feature_half(a, fs, node, nn, half);
-          else
-            v[k] = *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
+          v[k] = *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
         }
       }
     }
@@ -310,16 +263,14 @@ hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st) {
   int mode = kGeneric;
   if (!a.y32 && a.bias) {
     if (!a.transpose && a.w_out_major && !a.mask) {
-      if (a.fr && a.relu && a.y16 && !a.z) mode = kFirst;
-      else if (!a.fr && a.x && a.relu && a.y16 && !a.z) mode = kHidden;
-      else if (!a.fr && a.x && !a.relu && !a.y16 && a.z) mode = kLast;
+      if (a.x && a.relu && a.y16 && !a.z) mode = kHidden;
+      else if (a.x && !a.relu && !a.y16 && a.z) mode = kLast;
     }
   }
-  if (a.transpose && a.mask && a.y16 && !a.y32 && !a.relu && !a.bias && !a.z && !a.fr) mode = kBwd;
-  // the feature input and the z output exist only in their specialisations
-  if ((a.fr && mode != kFirst) || (a.z && mode != kLast)) return hipErrorInvalidValue;
+  if (a.transpose && a.mask && a.y16 && !a.y32 && !a.relu && !a.bias && !a.z) mode = kBwd;
+  // the z output exists only in its specialisation
+  if (a.z && mode != kLast) return hipErrorInvalidValue;
   switch (mode) {
-    case kFirst: hipLaunchKernelGGL(cnn_conv_kernel<kFirst>, dim3(blocks), dim3(256), 0, st, a); break;
     case kHidden: hipLaunchKernelGGL(cnn_conv_kernel<kHidden>, dim3(blocks), dim3(256), 0, st, a); break;
     case kLast: hipLaunchKernelGGL(cnn_conv_kernel<kLast>, dim3(blocks), dim3(256), 0, st, a); break;
     case kBwd: hipLaunchKernelGGL(cnn_conv_kernel<kBwd>, dim3(blocks), dim3(256), 0, st, a); break;

@@ -139,8 +139,7 @@ mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out)
 mfr_status pc_begin_solve(mfr_pc* pc, const float* diag);
 // live (nullable): every kernel of the application does nothing while *live == 0.
 mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, bool scales_ready = false,
-                      const float* rprev = nullptr, double* zred = nullptr, bool keep_input = false,
-                      const int* live = nullptr);
+                      const float* rprev = nullptr, double* zred = nullptr, const int* live = nullptr);
 float* pc_scratch_vec(mfr_pc* pc);
 double* pc_red(mfr_pc* pc);
 double* pc_scalars(mfr_pc* pc);

@@ -302,12 +302,6 @@ struct ConvArgs {
   const double* scale;
   const float* rprev;   // with zred: per-group partials of z.r and z.rprev (2 per group)
   double* zred;
-  // fr non-null: the input is the preconditioner's feature vector, computed on the fly
-  // from r (fr), diag (fdiag), |grad R| (fgR) and the RMS scales in fsc (x unused)
-  const float* fr;
-  const float* fdiag;
-  const float* fgR;
-  const double* fsc;
   const int* live;   // nullable: skip while *live == 0 (device-steered solve)
 };
 
@@ -343,7 +337,7 @@ struct DotsOut {
 int pc_dots_blocks(size_t n);   // partials per product (red needs 4 x this many doubles)
 hipError_t launch_pc_dots(const DotsArgs& d, const DotsOut& o, double* red, hipStream_t st);
 hipError_t launch_pc_features(int n, const float* r, const float* diag, const float* gR, const double* sc,
-                              uint16_t* h0, hipStream_t st);
+                              uint16_t* h0, hipStream_t st, const int* live = nullptr);
 hipError_t launch_pc_jacobi(int n3, const float* r, const float* diag, float* y, hipStream_t st);
 // Switch of a device-steered flexible solve to Jacobi-PCG: z = r / diag, p = z,
 // state[ST_FALLBACK] = 1; nothing while *live == 0.

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(kPB) void pc_features_kernel(int n, const float* __
                                                           const float* __restrict__ diag,
                                                           const float* __restrict__ gR,
                                                           const double* __restrict__ sc,
-                                                          uint16_t* __restrict__ h0) {
+                                                          uint16_t* __restrict__ h0, const int* live) {
+  if (live && !ld_coherent(live)) return;
   const int i = blockIdx.x * kPB + threadIdx.x;
   if (i >= n) return;
   const double sy = ld_coherent(sc + PC_RMS_Y), sr = ld_coherent(sc + PC_RMS_R);
@@ -127,8 +128,9 @@ __global__ __launch_bounds__(kPB) void pc_features_kernel(int n, const float* __
 }
 
 hipError_t launch_pc_features(int n, const float* r, const float* diag, const float* gR, const double* sc,
-                              uint16_t* h0, hipStream_t st) {
-  hipLaunchKernelGGL(pc_features_kernel, dim3((n + kPB - 1) / kPB), dim3(kPB), 0, st, n, r, diag, gR, sc, h0);
+                              uint16_t* h0, hipStream_t st, const int* live) {
+  hipLaunchKernelGGL(pc_features_kernel, dim3((n + kPB - 1) / kPB), dim3(kPB), 0, st, n, r, diag, gR, sc, h0,
+                     live);
   return hipGetLastError();
 }
 
