@@ -48,12 +48,16 @@ def template_sample(grid, T, pos):
 
 def deformed_points(grid, u, vox):
     """hat-y_i = (P y)_i at the voxels ``vox`` for the deformation
-    y = x^y + u (Sec. 2.2: u is the displacement on the nodal grid).
+    y = x^y + u (Sec. 2.2: u is the displacement on the nodal grid), evaluated
+    as x_i + (P u)_i: P reproduces the node positions exactly (P x^y = x, the
+    node-count reading of m^y), and forming x_i directly keeps voxel centres
+    that coincide with template samples exactly on them, where the derivative
+    takes the floor cell (no rounding of P x^y to either side).
     u: (3, nz, ny, nx).  Returns (N, 3)."""
     vox = np.asarray(vox, dtype=np.int64)
     Pr = grid.P_rows(vox)
-    y = (grid.node_positions() + np.asarray(u, dtype=np.float64)).reshape(3, grid.nbar)
-    return np.stack([Pr @ y[d] for d in range(3)], axis=-1)
+    uc = np.asarray(u, dtype=np.float64).reshape(3, grid.nbar)
+    return grid.voxel_centres(vox) + np.stack([Pr @ uc[d] for d in range(3)], axis=-1)
 
 
 def warped_template(grid, T, u, vox):

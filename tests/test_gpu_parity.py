@@ -40,6 +40,8 @@ CASES = [
     ("tiny-2x2x2", (2, 2, 2), (2, 2, 2), (1.0, 1.0, 1.0), 0.1, 0.1, 1.0, 0.3),
     ("tiny-3x5x2", (3, 5, 2), (2, 3, 3), (0.7, 1.0, 1.4), 0.3, 0.2, 1.0, 0.3),
     ("large-displacement", (20, 20, 20), (6, 6, 6), (1.0, 1.0, 1.0), 0.1, 0.1, 0.1, 8.0),
+    # u = 0: every voxel centre on a template sample, where the derivative takes the floor cell
+    ("zero-displacement", (24, 20, 16), (9, 8, 7), (1.0, 1.0, 1.0), 0.1, 0.1, 1.0, 0.0),
 ]
 
 
@@ -120,3 +122,38 @@ def test_pcg_first_iterates_match_oracle():
     assert info["flag"] == 0 and info["relres"] <= 1e-3
     r = tb - ctx.hess_vec(tu, s)
     assert float(torch.linalg.norm(r.double()) / torch.linalg.norm(tb.double())) <= 2e-3
+
+
+def test_pcg_without_regulariser_zero_diagonal_entries():
+    # alpha = 0 and a template that is zero (flat) in most of the domain: nodes that
+    # no row of dr reaches with a non-zero template derivative get a zero diagonal
+    _announce("pcg, alpha 0, zero Jacobi entries")
+    m = (24, 20, 16)
+    spec, R, T, u, probes = blob_case(9, m, (9, 8, 7), (1.0, 1.0, 1.0), 0.1, 0.1, 0.0, 0.0)
+    T = np.zeros_like(T)
+    T[4:10, 5:11, 6:12] = 1.0
+    ora = oracle_eval(spec, R, T, u, probes[:0])
+    prob, Jac = ora["prob"], ora["Jac"]
+    u64 = u.astype(np.float64)
+    diag = prob.jacobi_diag(u64, Jac)
+    assert np.any(diag == 0.0) and np.any(diag > 0.0)
+    b32 = (-ora["grad"]).astype(np.float32)
+    ctx = mfr.Context(spec, DEV)
+    ctx.set_images(to_dev(R), to_dev(T))
+    tu, tb = to_dev(u), to_dev(b32)
+    dg = ctx.jacobi_diag(tu).cpu().numpy()
+    z_o, z_g = diag == 0.0, dg == 0.0
+    print(f"[gpu-case] zero diagonal entries: oracle {int(z_o.sum())}, GPU {int(z_g.sum())}, GPU max where "
+          f"oracle is 0: {float(np.abs(dg[z_o]).max()):.3e}, oracle max where GPU is 0: "
+          f"{float(np.abs(diag[z_g]).max()) if z_g.any() else 0.0:.3e}", flush=True)
+    assert z_g.any() and np.all(np.abs(dg[z_o]) <= 1e-6 * float(diag.max()))
+    assert rel_l2(dg, diag) <= 1e-4
+    for k in (1, 2, 4):
+        s_gpu, info = ctx.pcg_solve(tu, tb, max_iter=k, rtol=0.0, precond=1)
+        s_ora, info_o = solver.pcg(lambda p: prob.hess_vec(u64, p, Jac), b32.astype(np.float64), diag, k, 0.0)
+        assert info["iters"] == k == info_o["iters"]
+        s_gpu = s_gpu.cpu().numpy()
+        assert np.all(np.isfinite(s_gpu))
+        e = rel_l2(s_gpu, s_ora)
+        assert e <= 1e-4, f"iterate {k}: rel-L2 {e:.3e}"
+    ctx.close()

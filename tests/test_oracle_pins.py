@@ -119,6 +119,21 @@ def test_template_exact_at_centres_and_zero_outside():
     np.testing.assert_array_equal(gr, 0.0)
 
 
+def test_zero_displacement_puts_voxels_exactly_on_template_samples():
+    # with the template on the reference grid, u = 0 samples the template exactly at
+    # its own samples, where the derivative is the forward difference (floor cell)
+    g = Grid(m=(7, 6, 5), h=(1.0, 1.0, 1.0), my=(4, 3, 4), tau=0.1, rho=0.1, alpha=0.1)
+    vox = np.arange(g.mbar)
+    pts = interp.deformed_points(g, np.zeros((3, 4, 3, 4)), vox)
+    assert np.array_equal(pts, g.voxel_centres(vox))
+    T = np.zeros((5, 6, 7))
+    T[:, :, 3:] = 1.0                                    # a step in x between samples 2 and 3
+    _, grad = interp.template_sample(g, T, pts)
+    a = g.voxel_abc(vox)[0]
+    expect = np.where(a == 2, 1.0, np.where(a == 6, -1.0, 0.0))   # forward differences (zero outside)
+    np.testing.assert_array_equal(grad[:, 0], expect)
+
+
 def test_template_linear_inside_and_derivative_fd():
     g = Grid((6, 5, 4), (1.0, 1.5, 0.7), (3, 3, 3), 1, 1, 1)
     cen = g.voxel_centres(np.arange(g.mbar))
@@ -431,6 +446,24 @@ def test_pcg_breakdown_flag():
     A = np.diag([1.0, -1.0])
     _, info = solver.pcg(lambda p: A @ p, np.array([0.0, 1.0]), None, 10, 1e-10)
     assert info["flag"] == 2
+
+
+def test_pcg_zero_diagonal_entries_left_unscaled():
+    # a block-diagonal system with a zero block: Jacobi with zero entries acts as 1
+    # there, so the iterates equal those of the solve on the non-zero block alone
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((6, 6))
+    A1 = B @ B.T + 0.5 * np.eye(6)
+    A = np.zeros((9, 9))
+    A[:6, :6] = A1
+    b = np.concatenate([rng.standard_normal(6), np.zeros(3)])
+    d = np.concatenate([np.diag(A1), np.zeros(3)])
+    for k in (1, 3, 6):
+        s, info = solver.pcg(lambda p: A @ p, b, d, k, 0.0)
+        s1, info1 = solver.pcg(lambda p: A1 @ p, b[:6], np.diag(A1), k, 0.0)
+        assert np.all(np.isfinite(s)) and np.all(s[6:] == 0.0)
+        np.testing.assert_allclose(s[:6], s1, rtol=1e-12, atol=1e-14)
+        assert info["iters"] == info1["iters"]
 
 
 def test_gauss_newton_monotone_on_tiny_problem():
