@@ -59,7 +59,7 @@ class Problem:
 def pcg(apply_A, b, diag=None, max_iter=50, rtol=1e-3):
     """Preconditioned conjugate gradients for A s = b from s = 0.
 
-    ``diag``: Jacobi preconditioner (None = plain CG).  Returns
+    ``diag``: Jacobi preconditioner (None = plain CG; zero entries act as 1).  Returns
     (s, info) with info = dict(iters, relres, flag): flag 0 converged,
     1 reached max_iter, 2 breakdown (p^T A p <= 0 or not finite)."""
     b = np.asarray(b, dtype=np.float64)
@@ -69,7 +69,12 @@ def pcg(apply_A, b, diag=None, max_iter=50, rtol=1e-3):
     bn = np.linalg.norm(b)
     if bn == 0.0:
         return s.reshape(shape), dict(iters=0, relres=0.0, flag=0)
-    Minv = (lambda r: r) if diag is None else (lambda r, d=np.asarray(diag, dtype=np.float64).ravel(): r / d)
+    if diag is not None:
+        # a zero diagonal entry (no regulariser, no template derivative reaching the
+        # node) is left unscaled
+        diag = np.asarray(diag, dtype=np.float64).ravel()
+        diag = np.where(diag == 0.0, 1.0, diag)
+    Minv = (lambda r: r) if diag is None else (lambda r, d=diag: r / d)
     r = b.copy()
     z = Minv(r)
     p = z.copy()

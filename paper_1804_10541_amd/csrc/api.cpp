@@ -475,6 +475,14 @@ hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
   return launch_jacobi_diag(c->dp, u, diag, c->stream);
 }
 
+// The Jacobi preconditioner of a CG solve: the exact diagonal with zero entries
+// replaced by 1.
+hipError_t enqueue_pcg_diag(mfr_ctx* c, const float* u, float* diag) {
+  hipError_t e = enqueue_diag(c, u, diag);
+  if (e != hipSuccess) return e;
+  return launch_safe_diag((int)(3 * c->geo.nbar), diag, c->stream);
+}
+
 int node_blocks(const mfr_ctx* c) { return (int)((c->geo.nbar + kNodeBlock - 1) / kNodeBlock); }
 int node_parts(const mfr_ctx* c) { return 3 * node_blocks(c); }
 
@@ -553,7 +561,7 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   float* diag = nullptr;
   if (o->precond >= 1) {
     diag = c->vec[4];
-    HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
+    HIP_TRY(timed(c, 3, [&] { return enqueue_pcg_diag(c, u, diag); }));
   }
   VecJobs V{};
   V.n = 1;
@@ -627,7 +635,7 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
   float* diag = c->vec[4];
   int* active = c->ctrl;
   int* state = c->ctrl + 1;
-  HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
+  HIP_TRY(timed(c, 3, [&] { return enqueue_pcg_diag(c, u, diag); }));
   VecJobs V{};
   V.n = 1;
   V.prefix[0] = 0;
@@ -861,7 +869,7 @@ mfr_status mfr_jacobi_diag(mfr_ctx* c, const float* u, float* diag) {
   MFR_TRY(need_images(c));
   MFR_TRY(check_ptr(u, "u"));
   MFR_TRY(check_ptr(diag, "diag"));
-  HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));
+  HIP_TRY(timed(c, 3, [&] { return enqueue_diag(c, u, diag); }));   // the exact diagonal
   return MFR_OK;
 }
 

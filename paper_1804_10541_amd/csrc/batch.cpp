@@ -280,7 +280,7 @@ mfr_status batch_pcg(mfr_batch* b, const float* const* u, const mfr_ml_opts* o, 
   const bool pre = o->precond == 1;
   if (pre)
     for (int k = 0; k < b->n; ++k)
-      if (live[k]) HIP_TRY(enqueue_diag(b->ctx[k], u[k], b->ctx[k]->vec[4]));
+      if (live[k]) HIP_TRY(enqueue_pcg_diag(b->ctx[k], u[k], b->ctx[k]->vec[4]));
   VecJobs V = vec_jobs(b, maxit, o->pcg_rtol, pre);
   HIP_TRY(launch_pcg_init_batch(V, b->st));
   if (use_graph && (!b->graph || b->graph_level != b->cur || b->graph_precond != (int)pre)) {

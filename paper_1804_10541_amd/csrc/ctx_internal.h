@@ -124,6 +124,7 @@ namespace mfr {
 
 mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes);
 hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag);
+hipError_t enqueue_pcg_diag(mfr_ctx* c, const float* u, float* diag);   // zero entries -> 1
 int node_blocks(const mfr_ctx* c);   // work-groups (per component) of a node pass
 int node_parts(const mfr_ctx* c);    // float64 partials of a gradient / Hv node pass (3 per group)
 mfr_status check_ptr(const void* p, const char* name);

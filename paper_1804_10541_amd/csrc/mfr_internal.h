@@ -241,6 +241,8 @@ enum PcgSlot : int {
   SC_D = 8, SC_S = 9, SC_J = 10, SC_DOT = 11, SC_RELRES = 12, SC_RTOL = 13, SC_ZR = 14, SC_ZRP = 15,
   SC_COUNT = 16
 };
+// zero entries of a Jacobi diagonal -> 1 (the preconditioner leaves them unscaled)
+hipError_t launch_safe_diag(int n3, float* d, hipStream_t st);
 hipError_t launch_pcg_init(int n3, const float* b, const float* diag, float* s, float* r, float* z,
                            float* p, double* red, int blocks, hipStream_t st);
 hipError_t launch_pcg_alpha(const double* red_pq, int nred, double* sc, hipStream_t st);

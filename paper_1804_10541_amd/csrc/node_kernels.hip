@@ -374,6 +374,20 @@ hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, 
 // ---------------------------------------------------------------------------
 // PCG vector kernels (float32 vectors, float64 dots and step lengths)
 // ---------------------------------------------------------------------------
+// Jacobi preconditioner of the CG solves: a zero diagonal entry (possible only
+// without the regulariser, at a node that no row of dr reaches with a non-zero
+// template derivative) is replaced by 1, i.e. that entry is left unscaled.
+__global__ __launch_bounds__(kVecBlock) void safe_diag_kernel(int n3, float* __restrict__ d) {
+  for (int i = blockIdx.x * kVecBlock + threadIdx.x; i < n3; i += gridDim.x * kVecBlock)
+    if (d[i] == 0.0f) d[i] = 1.0f;
+}
+
+hipError_t launch_safe_diag(int n3, float* d, hipStream_t st) {
+  const int blocks = std::min((n3 + kVecBlock - 1) / kVecBlock, 4096);
+  hipLaunchKernelGGL(safe_diag_kernel, dim3(blocks), dim3(kVecBlock), 0, st, n3, d);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kVecBlock) void pcg_init_kernel(int n3, const float* __restrict__ b,
                                                              const float* __restrict__ diag,
                                                              float* __restrict__ s, float* __restrict__ r,
