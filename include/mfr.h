@@ -110,7 +110,7 @@ mfr_status mfr_hess_vec(mfr_ctx* ctx, const float* u, const float* p, float* q);
 
 /* diag = diag(H + alpha nabla^2 S) at u, exactly (the Jacobi preconditioner
  * of the conjugate-gradient solve; the paper leaves CG unpreconditioned).
- * Asynchronous. */
+ * Entries may be 0 when alpha = 0.  Asynchronous. */
 mfr_status mfr_jacobi_diag(mfr_ctx* ctx, const float* u, float* diag);
 
 typedef struct {
@@ -134,8 +134,11 @@ typedef struct {
  * (Sec. 2.3.1: the Newton equation solved with CG).  Vectors in float32, dot
  * products and step lengths in float64.  s: device [3][n].  With precond 2 the
  * direction update is the flexible (Polak-Ribiere) one, since the learned
- * preconditioner is nonlinear.  Synchronises once per iteration (convergence
- * test on the host). */
+ * preconditioner is nonlinear.  The Jacobi preconditioner is the exact
+ * diagonal with zero entries (possible only for alpha = 0) taken as 1.  The
+ * convergence test runs on the device; the call synchronises once per eight
+ * iterations and at the end.  On a breakdown (flag 2) the iterate is the one
+ * before the failing step. */
 mfr_status mfr_pcg_solve(mfr_ctx* ctx, const float* u, const float* b, float* s,
                          const mfr_pcg_opts* opts, mfr_pcg_info* info);
 

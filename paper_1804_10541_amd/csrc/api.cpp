@@ -553,9 +553,9 @@ constexpr int kSteerIters = 8;
 // flag that turns every later kernel of the solve into a no-op.  The host
 // enqueues kSteerIters iterations at a time and reads the flag once per
 // batch of iterations instead of reading the scalars after every iteration;
-// the iterates, the stopping iteration and the reported state are those of
-// the per-iteration loop (on a breakdown, p.q <= 0, the last update is not
-// applied).
+// the solve stops at the iteration a check after every iteration would stop
+// at, with the same iterate (on a breakdown, p.q <= 0, the update of that
+// iteration is not applied).
 mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
                            mfr_pcg_info* info) {
   float* diag = nullptr;
