@@ -14,9 +14,11 @@ dT, the residual Jacobian dr and the Laplacian L are built entry by entry from
 their definitions and multiplied with scipy.sparse.  It shares no code with
 the HIP path: no kernels, no tables, no per-voxel recipe (the rho-hat
 formulation of Sec. 4 is what the GPU computes; the oracle never uses it).
+``ssd`` holds the same derivatives for the sum-of-squared-differences
+distance (Sec. 4.4: the residual Jacobian becomes the identity).
 ``cnn`` defines the learned preconditioner, an extension of the method
 (convolutions, network, features, loss), and ``solver.fpcg`` the flexible CG
 that uses it.
 """
 from .grid import Grid  # noqa: F401
-from . import interp, ngf, curvature, solver, multilevel, cnn  # noqa: F401
+from . import interp, ngf, ssd, curvature, solver, multilevel, cnn  # noqa: F401

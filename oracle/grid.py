@@ -21,16 +21,20 @@ import scipy.sparse as sp
 
 class Grid:
     """Image grid (``m`` cells, spacing ``h``), deformation grid (``my`` nodes),
-    template grid (``mT`` cells, spacing ``hT``; default = image grid) and the
-    model parameters tau, rho (NGF) and alpha (curvature weight)."""
+    template grid (``mT`` cells, spacing ``hT``; default = image grid), the
+    model parameters tau, rho (NGF) and alpha (curvature weight), and the
+    distance measure: "ngf" (the paper's) or "ssd" (Sec. 4.4)."""
 
-    def __init__(self, m, h, my, tau, rho, alpha, mT=None, hT=None):
+    def __init__(self, m, h, my, tau, rho, alpha, mT=None, hT=None, distance="ngf"):
         self.m = tuple(int(k) for k in m)
         self.h = tuple(float(k) for k in h)
         self.my = tuple(int(k) for k in my)
         self.mT = tuple(int(k) for k in (mT if mT is not None else m))
         self.hT = tuple(float(k) for k in (hT if hT is not None else h))
         self.tau, self.rho, self.alpha = float(tau), float(rho), float(alpha)
+        if distance not in ("ngf", "ssd"):
+            raise ValueError("distance must be 'ngf' or 'ssd'")
+        self.distance = distance
         for k in range(3):
             if not (2 <= self.my[k] and self.my[k] - 1 <= self.m[k]):
                 raise ValueError("need 2 <= my <= m + 1 in every dimension")
@@ -38,7 +42,8 @@ class Grid:
     @classmethod
     def from_spec(cls, spec):
         return cls(spec.m, spec.h, spec.my, spec.tau, spec.rho, spec.alpha,
-                   getattr(spec, "mT", None), getattr(spec, "hT", None))
+                   getattr(spec, "mT", None), getattr(spec, "hT", None),
+                   getattr(spec, "distance", "ngf"))
 
     # sizes -----------------------------------------------------------------
     @property

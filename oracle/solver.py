@@ -18,41 +18,43 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import curvature, ngf
+from . import curvature, ngf, ssd
 
 
 class Problem:
-    """One registration level: grid, reference R, template T (float64 copies)."""
+    """One registration level: grid, reference R, template T (float64 copies).
+    The distance term is NGF or SSD as the grid says."""
 
     def __init__(self, grid, R, T):
         self.grid = grid
         self.R = np.asarray(R, dtype=np.float64)
         self.T = np.asarray(T, dtype=np.float64)
         self.L = curvature.laplacian(grid)
+        self.dist = ssd if grid.distance == "ssd" else ngf
 
     def objective(self, u):
         """(J, D, S)."""
-        D = ngf.distance(self.grid, self.R, self.T, u)
+        D = self.dist.distance(self.grid, self.R, self.T, u)
         S = curvature.energy(self.grid, u, self.L)
         return D + self.grid.alpha * S, D, S
 
     def gradient(self, u):
         """(J, grad J)."""
         Jv, _, _ = self.objective(u)
-        g = ngf.gradient_D(self.grid, self.R, self.T, u) + self.grid.alpha * curvature.gradient(self.grid, u, self.L)
+        g = self.dist.gradient_D(self.grid, self.R, self.T, u) + self.grid.alpha * curvature.gradient(self.grid, u, self.L)
         return Jv, g
 
     def jacobian(self, u):
-        return ngf.jacobian(self.grid, self.R, self.T, u)[0]
+        return self.dist.jacobian(self.grid, self.R, self.T, u)[0]
 
     def hess_vec(self, u, p, Jac=None):
         """(H + alpha nabla^2 S) p."""
-        return (ngf.hess_vec_D(self.grid, self.R, self.T, u, p, Jac)
+        return (self.dist.hess_vec_D(self.grid, self.R, self.T, u, p, Jac)
                 + self.grid.alpha * curvature.hess_vec(self.grid, p, self.L))
 
     def jacobi_diag(self, u, Jac=None):
         """diag(H + alpha nabla^2 S)."""
-        return (ngf.hessian_diag_D(self.grid, self.R, self.T, u, Jac)
+        return (self.dist.hessian_diag_D(self.grid, self.R, self.T, u, Jac)
                 + self.grid.alpha * curvature.hessian_diag(self.grid, self.L))
 
 

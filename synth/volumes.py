@@ -36,6 +36,7 @@ class GridSpec:
     alpha: float        # curvature weight
     mT: tuple = None    # template cells (default: m)
     hT: tuple = None    # template spacing (default: h)
+    distance: str = "ngf"   # distance measure: "ngf" or "ssd"
 
     def template_cells(self):
         return tuple(self.mT) if self.mT is not None else tuple(self.m)

@@ -1,6 +1,7 @@
 """Pure-Python loop evaluation of the discretised objective on tiny grids.
 
-Written directly from eq. NGF_discretized, eq. gradient_discretized,
+Written directly from eq. NGF_discretized (and the sum-of-squared-differences
+distance hbar/2 sum (T(P y) - R)^2 for the SSD variant), eq. gradient_discretized,
 eq. boundary_conditions (0-based clamping), eq. grid_conversion and the
 trilinear template with zero extension (Sec. 2.2), scalar by scalar, with no
 numpy vectorisation and no code shared with ``oracle/``.  Used to pin the
@@ -32,15 +33,13 @@ def _tri(T, mT, hT, p):
     return tot
 
 
-def objective_D(m, h, my, tau, rho, R, T, u, mT=None, hT=None):
-    """D(y) for y = x^y + u.  R, T nested lists/arrays [z][y][x];
-    u: [3][nz][ny][nx] displacement."""
+def warped_template(m, h, my, T, u, mT=None, hT=None):
+    """T(P y) on the image grid [z][y][x] for y = x^y + u, u: [3][nz][ny][nx]."""
     mT = mT or m
     hT = hT or h
     mx, my_, mz = m
     nx, ny, nz = my
     hy = [m[d] * h[d] / (my[d] - 1) for d in range(3)]
-    # deformed template on the image grid
     Tw = [[[0.0] * mx for _ in range(my_)] for _ in range(mz)]
     for c in range(mz):
         for b in range(my_):
@@ -54,6 +53,27 @@ def objective_D(m, h, my, tau, rho, R, T, u, mT=None, hT=None):
                             for d in range(3):
                                 yhat[d] += w * (node[d] + u[d][k][j][i])
                 Tw[c][b][a] = _tri(T, mT, hT, yhat)
+    return Tw
+
+
+def objective_ssd(m, h, my, R, T, u, mT=None, hT=None):
+    """Sum-of-squared-differences distance hbar/2 sum_i (T(P y)_i - R_i)^2."""
+    Tw = warped_template(m, h, my, T, u, mT, hT)
+    hbar = h[0] * h[1] * h[2]
+    D = 0.0
+    for c in range(m[2]):
+        for b in range(m[1]):
+            for a in range(m[0]):
+                r = Tw[c][b][a] - R[c][b][a]
+                D += 0.5 * hbar * r * r
+    return D
+
+
+def objective_D(m, h, my, tau, rho, R, T, u, mT=None, hT=None):
+    """D(y) for y = x^y + u.  R, T nested lists/arrays [z][y][x];
+    u: [3][nz][ny][nx] displacement."""
+    mx, my_, mz = m
+    Tw = warped_template(m, h, my, T, u, mT, hT)
 
     def grad6(I, a, b, c):
         out = []

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import bruteforce
-from oracle import Grid, curvature, interp, multilevel, ngf, solver
+from oracle import Grid, curvature, interp, multilevel, ngf, solver, ssd
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -489,3 +489,109 @@ def test_prolongation_exact_for_linear_fields_and_restriction_of_constants():
     Ic = multilevel.restrict_image(I)
     assert Ic.shape == (4, 3, 5)
     np.testing.assert_allclose(Ic, 2.5)
+
+
+# ---------------------------------------------------------------------------
+# Sum-of-squared-differences distance (Sec. 4.4: dr/dT = identity)
+# ---------------------------------------------------------------------------
+
+def ssd_problem(seed=0, m=(6, 5, 4), my=(4, 3, 3), h=(1.0, 1.2, 0.9), alpha=0.7, amp=0.4):
+    rng = np.random.default_rng(seed)
+    g = Grid(m, h, my, 1.0, 1.0, alpha, distance="ssd")
+    R = rng.standard_normal((m[2], m[1], m[0]))
+    T = rng.standard_normal((m[2], m[1], m[0]))
+    u = amp * rng.standard_normal((3, my[2], my[1], my[0]))
+    return g, R, T, u, rng
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ssd_distance_matches_bruteforce_loops(seed):
+    g, R, T, u, _ = ssd_problem(seed)
+    ref = bruteforce.objective_ssd(g.m, g.h, g.my, R.tolist(), T.tolist(), u.tolist())
+    assert abs(ssd.distance(g, R, T, u) - ref) <= 1e-12 * abs(ref)
+
+
+def test_ssd_closed_forms_at_zero_displacement():
+    # u = 0 puts every voxel on its template sample (up to the rounding of
+    # (a + 1/2) h / h - 1/2 for spacings such as 0.9): T = R + c gives
+    # D = hbar/2 mbar c^2; T = R gives D = 0 and a zero gradient
+    g, R, _, _, _ = ssd_problem(3)
+    u0 = np.zeros((3, g.my[2], g.my[1], g.my[0]))
+    c = 0.37
+    assert abs(ssd.distance(g, R, R + c, u0) - 0.5 * g.hbar * g.mbar * c * c) <= 1e-12
+    assert ssd.distance(g, R, R, u0) <= 1e-24
+    assert np.abs(ssd.gradient_D(g, R, R, u0)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ssd_gradient_against_fd_of_bruteforce(seed):
+    g, R, T, u, rng = ssd_problem(seed)
+    grad = ssd.gradient_D(g, R, T, u)
+
+    def Db(uu):
+        return bruteforce.objective_ssd(g.m, g.h, g.my, R.tolist(), T.tolist(), uu.tolist())
+
+    for _ in range(3):
+        d = rng.standard_normal(u.shape)
+        fd = _fd_dir(Db, u, d)
+        assert abs(fd - np.sum(grad * d)) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_ssd_gradient_each_component_fd_including_boundary_nodes():
+    g, R, T, u, _ = ssd_problem(4, m=(5, 4, 3), my=(3, 3, 2))
+    grad = ssd.gradient_D(g, R, T, u).ravel()
+    f = lambda uu: ssd.distance(g, R, T, uu)
+    for j in range(grad.size):
+        d = np.zeros(grad.size)
+        d[j] = 1.0
+        fd = _fd_dir(f, u, d.reshape(u.shape))
+        assert abs(fd - grad[j]) <= 1e-6 * max(1.0, abs(fd)), j
+
+
+def test_ssd_hessian_is_the_true_hessian_where_the_residual_vanishes():
+    # With R = T(P y) (from the brute-force loops) the residual is 0 at u, so the
+    # dropped second-derivative term vanishes and the Gauss-Newton product equals
+    # the derivative of the gradient (centred differences along p).
+    g, _, T, u, rng = ssd_problem(5)
+    R = np.array(bruteforce.warped_template(g.m, g.h, g.my, T.tolist(), u.tolist()))
+    assert np.abs(ssd.residual(g, R, T, u)).max() <= 1e-13
+    J, _ = ssd.jacobian(g, R, T, u)
+    for _ in range(3):
+        p = rng.standard_normal(u.shape)
+        fd = _fd_dir(lambda uu: ssd.gradient_D(g, R, T, uu), u, p)
+        hp = ssd.hess_vec_D(g, R, T, u, p, J)
+        np.testing.assert_allclose(hp, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def test_ssd_hessian_symmetric_psd_diagonal_and_node_outputs():
+    g, R, T, u, rng = ssd_problem(6, m=(7, 6, 5), my=(4, 4, 3))
+    J, _ = ssd.jacobian(g, R, T, u)
+    n = 3 * g.nbar
+    H = np.stack([ssd.hess_vec_D(g, R, T, u, e.reshape(u.shape), J).ravel() for e in np.eye(n)], axis=1)
+    np.testing.assert_allclose(H, H.T, atol=1e-12 * np.abs(H).max())
+    assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() > -1e-10 * np.abs(H).max()
+    # <p, H p> = hbar ||J p||^2 with J p from differences of the residual vector
+    p = rng.standard_normal(u.shape)
+    jp = _fd_dir(lambda uu: ssd.residual(g, R, T, uu).ravel(), u, p)
+    php = float(np.sum(p * ssd.hess_vec_D(g, R, T, u, p, J)))
+    assert abs(php - g.hbar * float(jp @ jp)) <= 1e-6 * php
+    np.testing.assert_allclose(ssd.hessian_diag_D(g, R, T, u, J).ravel(), np.diag(H), rtol=1e-12, atol=1e-14)
+    grad = ssd.gradient_D(g, R, T, u)
+    hv = ssd.hess_vec_D(g, R, T, u, p, J)
+    diag = ssd.hessian_diag_D(g, R, T, u, J)
+    for node in [0, g.nbar - 1, g.node_id(2, 1, 2), g.node_id(3, 3, 0), g.node_id(1, 2, 1)]:
+        gn, hn, dn = ssd.node_outputs(g, R, T, u, p, node)
+        a, b, c = g.node_abc(node)
+        np.testing.assert_allclose(gn, grad[:, c, b, a], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(hn, hv[:, c, b, a], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(dn, diag[:, c, b, a], rtol=1e-12, atol=1e-13)
+
+
+def test_ssd_gauss_newton_reduces_objective_and_multilevel_keeps_distance():
+    g, R, T, u, _ = ssd_problem(7, m=(8, 7, 6), my=(5, 4, 4), amp=0.0)
+    prob = solver.Problem(g, R, T)
+    J0 = prob.objective(u)[0]
+    u1, hist = solver.gauss_newton(prob, u, iters=3)
+    assert prob.objective(u1)[0] < J0
+    assert all(h["J_new"] <= h["J"] for h in hist if "J_new" in h)
+    assert multilevel.coarse_grid(g).distance == "ssd"
