@@ -38,6 +38,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz)
 HV_FLOP_PER_VOXEL = 217
 HV_BYTES_PER_VOXEL = 8
 HV_BYTES_PER_NODE = 36
+# The same product for the sum-of-squared-differences distance (dr/dT = identity):
+# the NGF-only arithmetic (differences of T and R, the three weighted sums, norms and
+# residual, the rho-hat row, dr a, the dr^T gather: 119 flop) drops out; the bytes stay.
+SSD_HV_FLOP_PER_VOXEL = 98
 
 # HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload
 # (32x16 tiles, split target 4096), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
@@ -120,6 +124,59 @@ def batch_leg(dev, tune):
             "identical_to_sequential": bool(same), "tile_config": cfg}
 
 
+def ssd_leg(dev, spec, R, T, u0, reps=20):
+    """Hessian-vector products and the Jacobi diagonal with the sum-of-squared-
+    differences distance on the same pair, displacement and tile configuration
+    as the headline step (HIP-event kernel timings on the context's stream)."""
+    import dataclasses
+
+    import torch
+
+    from paper_1804_10541_amd import mfr
+
+    s = dataclasses.replace(spec, distance="ssd")
+    ctx = mfr.Context(s, dev)
+    ctx.set_images(R, T)
+    gen = torch.Generator(device=dev).manual_seed(5)
+    p = torch.randn(u0.shape, generator=gen, device=dev, dtype=torch.float32)
+    q = torch.empty_like(p)
+    diag = torch.empty_like(p)
+    for _ in range(3):
+        ctx.hess_vec(u0, p, out=q)
+    ctx.jacobi_diag(u0, out=diag)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.hess_vec(u0, p, out=q)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.jacobi_diag(u0, out=diag)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    ctx.close()
+    mbar, nbar = s.voxels, s.nodes
+    hv_n, hv_ms = prof["tile_hv"]
+    np_n, np_ms = prof["node_pass"]
+    hv_avg = hv_ms / max(hv_n, 1)
+    np_avg = np_ms / max(np_n, 1)
+    tflops = SSD_HV_FLOP_PER_VOXEL * mbar / (hv_avg * 1e-3) / 1e12
+    gbs = (HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar) / (hv_avg * 1e-3) / 1e9
+    out = {"workload": "the headline pair and displacement with the sum-of-squared-differences distance",
+           "kernel": "ngf_tile_kernel<HV, SSD>", "avg_ms": round(hv_avg, 4), "launches": hv_n,
+           "kernel_gvoxel_s": round(mbar / (hv_avg * 1e-3) / 1e9, 2),
+           "with_node_pass_gvoxel_s": round(mbar / ((hv_avg + np_avg) * 1e-3) / 1e9, 2),
+           "wall_gvoxel_s": round(mbar * reps / dt / 1e9, 2),
+           "alu_tflops": round(tflops, 3), "alu_frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+           "flop_per_voxel": SSD_HV_FLOP_PER_VOXEL,
+           "hbm_algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "jacobi_diag_ms": round(prof["jacobi_diag"][1] / max(prof["jacobi_diag"][0], 1), 3)}
+    log(f"[bench] ssd: {out}")
+    return out
+
+
 def pc_leg(dev):
     """PCG solve time to relative residual 1e-3, flexible CG with the learned
     preconditioner (Jacobi fallback after twice the Jacobi count) against
@@ -193,6 +250,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the ten-pair batched registration leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile configuration")
     ap.add_argument("--no-pc", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--no-ssd", action="store_true", help="skip the sum-of-squared-differences leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -302,7 +360,11 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(R, T, u0, spec)
-    del ctx, R, T
+    del ctx
+    if not args.no_ssd:
+        log("[bench] sum-of-squared-differences distance")
+        out["ssd"] = ssd_leg(dev, spec, R, T, u0)
+    del R, T
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
         out["batch"] = batch_leg(dev, not args.no_autotune)

@@ -45,7 +45,12 @@
 extern "C" {
 #endif
 
-#define MFR_ABI_VERSION 1
+#define MFR_ABI_VERSION 2
+
+/* Distance measures (mfr_grid.distance). */
+#define MFR_DIST_NGF 0   /* normalized gradient fields, eq. NGF_discretized (the paper's) */
+#define MFR_DIST_SSD 1   /* sum of squared differences hbar/2 sum_i (T(P y)_i - R_i)^2
+                            (Sec. 4.4: the residual Jacobian dr/dT is the identity)    */
 
 typedef enum {
   MFR_OK = 0,
@@ -65,9 +70,10 @@ typedef struct {
   int32_t my[3];    /* deformation grid NODES; 2 <= my and my - 1 <= m (Sec. 2.2)             */
   int32_t mT[3];    /* template grid cells (all 0: same as m)                                 */
   double hT[3];     /* template grid spacing (all 0: same as h)                               */
-  double tau;       /* NGF edge parameter of the template, > 0 (eq. ngf)                     */
-  double rho;       /* NGF edge parameter of the reference, > 0 (eq. ngf)                    */
+  double tau;       /* NGF edge parameter of the template, > 0 (eq. ngf; ignored for SSD)    */
+  double rho;       /* NGF edge parameter of the reference, > 0 (eq. ngf; ignored for SSD)   */
   double alpha;     /* curvature weight, >= 0 (eq. optimizationProblem)                       */
+  int32_t distance; /* MFR_DIST_NGF (0) or MFR_DIST_SSD (1)                                   */
 } mfr_grid;
 
 typedef struct mfr_ctx mfr_ctx;   /* opaque host-side context; owns no device memory */
@@ -93,18 +99,21 @@ void mfr_destroy(mfr_ctx* ctx);
 mfr_status mfr_set_images(mfr_ctx* ctx, const float* R, const float* T);
 
 /* J = D + alpha S at displacement u (eq. discreteenergy).  D follows
- * eq. NGF_discretized_ri, S eq. CURV_discretized.  Any of J, D, S may be
- * NULL.  Sums are accumulated in float64.  Synchronises the stream. */
+ * eq. NGF_discretized_ri (SSD: hbar/2 sum_i r_i^2 with r = T(P y) - R),
+ * S eq. CURV_discretized.  Any of J, D, S may be NULL.  Sums are accumulated
+ * in float64.  Synchronises the stream. */
 mfr_status mfr_objective(mfr_ctx* ctx, const float* u, double* J, double* D, double* S);
 
 /* g = grad D + alpha grad S at u (eq. gradNGF with the transposed grid
- * conversion of Sec. 4.3, and eq. curvatureMF).  g: device [3][n].  If J is
- * not NULL it receives J(u) (and the stream is synchronised). */
+ * conversion of Sec. 4.3, and eq. curvatureMF; SSD: hbar P^T (g_T r) with
+ * g_T the template derivative, Sec. 4.4).  g: device [3][n].  If J is not
+ * NULL it receives J(u) (and the stream is synchronised). */
 mfr_status mfr_gradient(mfr_ctx* ctx, const float* u, float* g, double* J);
 
 /* q = (H + alpha nabla^2 S) p with H the Gauss-Newton matrix of D at u
  * (eq. NGF_discretized_hessian, evaluated matrix-free as in eq. hessMult /
- * eq. drTdr) and nabla^2 S = 2 hbar^y L^T L (eq. curv_hessMult).
+ * eq. drTdr; SSD: hbar P^T dT^T dT P, Sec. 4.4) and
+ * nabla^2 S = 2 hbar^y L^T L (eq. curv_hessMult).
  * q must not alias u or p.  Asynchronous. */
 mfr_status mfr_hess_vec(mfr_ctx* ctx, const float* u, const float* p, float* q);
 
@@ -226,7 +235,9 @@ typedef struct {
 } mfr_batch_report;
 
 /* Device workspace for `n` pairs (grids[i]: finest grid of pair i) with
- * `levels` pyramid levels each. */
+ * `levels` pyramid levels each.  The batched path evaluates NGF only: a grid
+ * with distance MFR_DIST_SSD is rejected (MFR_EINVAL) here and in
+ * mfr_batch_create. */
 mfr_status mfr_batch_workspace_size(int32_t n, const mfr_grid* grids, int32_t levels, size_t* bytes);
 
 /* Create a batch bound to `hip_stream` and a caller-owned workspace. */

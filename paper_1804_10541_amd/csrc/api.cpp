@@ -53,7 +53,11 @@ mfr_status make_geo(const mfr_grid* g, Geo* o) {
     if (!(o->hT[k] > 0) || !std::isfinite(o->hT[k])) return fail(MFR_EINVAL, "hT[%d] must be > 0", k);
     o->hy[k] = o->m[k] * o->h[k] / (o->n[k] - 1);
   }
-  if (!(g->tau > 0) || !(g->rho > 0) || !std::isfinite(g->tau) || !std::isfinite(g->rho))
+  if (g->distance != MFR_DIST_NGF && g->distance != MFR_DIST_SSD)
+    return fail(MFR_EINVAL, "distance = %d: need MFR_DIST_NGF (0) or MFR_DIST_SSD (1)", (int)g->distance);
+  o->dist = g->distance;
+  if (o->dist == MFR_DIST_NGF &&
+      (!(g->tau > 0) || !(g->rho > 0) || !std::isfinite(g->tau) || !std::isfinite(g->rho)))
     return fail(MFR_EINVAL, "tau and rho must be > 0");
   if (!(g->alpha >= 0) || !std::isfinite(g->alpha)) return fail(MFR_EINVAL, "alpha must be >= 0");
   o->tau = g->tau;
@@ -360,9 +364,11 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   p.ihTx = (float)(1.0 / g.hT[0]);
   p.ihTy = (float)(1.0 / g.hT[1]);
   p.ihTz = (float)(1.0 / g.hT[2]);
-  p.tau2 = (float)(g.tau * g.tau);
-  p.rho2 = (float)(g.rho * g.rho);
-  p.taurho = (float)(g.tau * g.rho);
+  const bool ssd = g.dist == MFR_DIST_SSD;   // tau, rho unused (and unchecked) for SSD
+  p.ssd = ssd ? 1 : 0;
+  p.tau2 = ssd ? 1.0f : (float)(g.tau * g.tau);
+  p.rho2 = ssd ? 1.0f : (float)(g.rho * g.rho);
+  p.taurho = ssd ? 1.0f : (float)(g.tau * g.rho);
   p.R = nullptr;
   p.Tp = at<float>(c->ws, L.Tp);
   p.cx = at<Conv1>(c->ws, L.cx);
@@ -413,7 +419,7 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   d.rx = at<Range1>(c->ws, L.rx);
   d.ry = at<Range1>(c->ws, L.ry);
   d.rz = at<Range1>(c->ws, L.rz);
-  d.s_ngf = (float)(2.0 * g.hbar());
+  d.s_ngf = (float)g.hess_scale();
   d.s_curv = q.s_curv;
   d.ihy2x = q.ihy2x;
   d.ihy2y = q.ihy2y;
@@ -528,7 +534,7 @@ mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
   HIP_TRY(timed(c, 1, [&] { return launch_tile(t.shape, MODE_GRAD, c->tp, u, nullptr, t.grid(), c->stream); }));
   HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
   NodeParams q = c->np;
-  q.s_ngf = (float)(-2.0 * c->geo.hbar());
+  q.s_ngf = (float)c->geo.grad_scale();
   HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_GRAD, q, u, g, node_blocks(c), c->stream); }));
   HIP_TRY(launch_sum(c->red_node, node_parts(c), c->sc + SC_S, c->stream));
   return MFR_OK;
@@ -539,7 +545,7 @@ mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q
   const Tiling& t = c->tiling;
   HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, c->tp, u, p, t.grid(), c->stream); }));
   NodeParams np = c->np;
-  np.s_ngf = (float)(2.0 * c->geo.hbar());
+  np.s_ngf = (float)c->geo.hess_scale();
   HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream); }));
   return MFR_OK;
 }
@@ -588,7 +594,7 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   TileParams tp = c->tp;
   tp.live = c->ctrl;
   NodeParams np = c->np;
-  np.s_ngf = (float)(2.0 * c->geo.hbar());
+  np.s_ngf = (float)c->geo.hess_scale();
   np.live = c->ctrl;
   const Tiling& t = c->tiling;
   int done = 0, active = 1;
@@ -682,7 +688,7 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
   TileParams tp = c->tp;
   tp.live = active;
   NodeParams np = c->np;
-  np.s_ngf = (float)(2.0 * c->geo.hbar());
+  np.s_ngf = (float)c->geo.hess_scale();
   np.live = active;
   const Tiling& t = c->tiling;
   bool jacobi = false;
@@ -968,6 +974,7 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
     g.tau = f.tau;
     g.rho = f.rho;
     g.alpha = f.alpha;
+    g.distance = f.dist;
     L[l].grid = g;
     MFR_TRY(make_geo(&g, &L[l].geo));
   }

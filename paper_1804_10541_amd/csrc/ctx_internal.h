@@ -35,9 +35,16 @@ struct Geo {
   int m[3], n[3], mT[3];
   double h[3], hT[3], hy[3];
   double tau, rho, alpha;
+  int dist;   // MFR_DIST_NGF or MFR_DIST_SSD
   size_t mbar, nbar;
   double hbar() const { return h[0] * h[1] * h[2]; }
   double hybar() const { return hy[0] * hy[1] * hy[2]; }
+  // Scales of the gathered voxel contributions P^T(...) in the gradient and in
+  // the Gauss-Newton product.  NGF, psi = hbar sum (1 - r^2): grad = -2 hbar J^T r,
+  // H = 2 hbar J^T J (eq. dPsi, eq. NGF_discretized_hessian).  SSD,
+  // psi = hbar/2 r^T r: grad = hbar J^T r, H = hbar J^T J.
+  double grad_scale() const { return dist == MFR_DIST_SSD ? hbar() : -2.0 * hbar(); }
+  double hess_scale() const { return dist == MFR_DIST_SSD ? hbar() : 2.0 * hbar(); }
 };
 
 mfr_status make_geo(const mfr_grid* g, Geo* o);

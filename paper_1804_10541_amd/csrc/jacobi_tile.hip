@@ -16,11 +16,15 @@
 // rows' squared stencil sums from LDS into per-node-plane accumulators, and a
 // node plane is reduced (fixed order) and written once no later voxel plane
 // can touch it.
+//
+// For the sum-of-squared-differences distance (Sec. 4.4) dr is the identity:
+// each row has the single coefficient 1 at its own voxel, so
+//   diag_{(d,n)} = hbar sum_l (g_{l,d} W_n(l))^2.
 #include "tile_common.h"
 
 namespace mfr {
 
-template <int AX, int AY>
+template <int AX, int AY, bool SSD>
 __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, const float* __restrict__ u,
                                                              float* __restrict__ diag) {
   constexpr int NT = AX * AY;
@@ -190,7 +194,9 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
     // ---- B: rho-hat rows at plane c ----
     if (row_plane) {
       float rh[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (inB && in_img) {
+      if (SSD) {
+        rh[0] = (inB && in_img) ? 1.0f : 0.0f;
+      } else if (inB && in_img) {
         const int s1 = c & 1;
         const float Tc = Tw_c, Rc = R_c;
         const bool hxm = gx > 0, hxp = gx < P.mx - 1, hym = gy > 0, hyp = gy < P.my - 1;
@@ -235,8 +241,8 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
         const int nz = kflush + q;
         const bool ok = nz <= BZ.hi;
         wz0[q] = ok ? conv_weight(cz0, nz) : 0.0f;
-        wzp[q] = (ok && hzp) ? conv_weight(czp, nz) : 0.0f;
-        wzm[q] = (ok && hzm) ? conv_weight(czm, nz) : 0.0f;
+        wzp[q] = (ok && hzp && !SSD) ? conv_weight(czp, nz) : 0.0f;
+        wzm[q] = (ok && hzm && !SSD) ? conv_weight(czm, nz) : 0.0f;
         if (wz0[q] != 0.0f || wzp[q] != 0.0f || wzm[q] != 0.0f) qmask |= 1 << q;
       }
       qmask = __builtin_amdgcn_readfirstlane(qmask);   // uniform: c and kflush are
@@ -250,6 +256,20 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
           const float vy0 = wyr[lb], vym = wyr[lb - 1], vyp = wyr[lb + 1];
           const float w00 = vx0 * vy0;
           const float al0 = sRho[0][li] * w00;
+          if constexpr (SSD) {   // the row's only coefficient sits at its own voxel
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const float pxy = al0 * sG[sc][d][li];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                if (qmask & (1 << q)) {
+                  const float zz = wz0[q] * pxy;
+                  acc[q][d] = fmaf(zz, zz, acc[q][d]);
+                }
+              }
+            }
+            continue;
+          }
           const float alxm = sRho[1][li] * vxm * vy0, alxp = sRho[2][li] * vxp * vy0;
           const float alym = sRho[3][li] * vx0 * vym, alyp = sRho[4][li] * vx0 * vyp;
           const float alzm = sRho[5][li] * w00, alzp = sRho[6][li] * w00;
@@ -288,7 +308,10 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
 
 hipError_t launch_jacobi_tile(const JacParams& j, const float* u, float* diag, hipStream_t st) {
   const int blocks = j.nbx * j.nby * j.nbz;
-  hipLaunchKernelGGL((jacobi_tile_kernel<32, 32>), dim3(blocks), dim3(1024), 0, st, j, u, diag);
+  if (j.t.ssd)
+    hipLaunchKernelGGL((jacobi_tile_kernel<32, 32, true>), dim3(blocks), dim3(1024), 0, st, j, u, diag);
+  else
+    hipLaunchKernelGGL((jacobi_tile_kernel<32, 32, false>), dim3(blocks), dim3(1024), 0, st, j, u, diag);
   return hipGetLastError();
 }
 

@@ -80,6 +80,7 @@ struct TileParams {
   float* part;            // transposed-conversion partial blocks
   double* red;            // one float64 partial per work-group
   const int* live;        // single-problem launches: skip all work while *live == 0 (nullable)
+  int ssd;                // distance: 0 NGF, 1 sum of squared differences (dr/dT = identity)
 };
 
 // Parameters of the node pass.

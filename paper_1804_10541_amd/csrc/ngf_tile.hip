@@ -39,6 +39,11 @@
 // writes the node block to its own slot of a partial buffer.  A node pass sums
 // the slots that overlap each node in a fixed order, so results are
 // deterministic and no atomics are used.  Nothing per voxel reaches HBM.
+//
+// The same march evaluates the sum-of-squared-differences distance (SSD,
+// Sec. 4.4), whose residual Jacobian dr/dT is the identity: stage B forms
+// r = T(P y) - R and z_l = a_l (Hessian) or r_l (gradient) at the own columns,
+// stage C takes w_i = z_i, and no plane data is exchanged through LDS.
 #include <type_traits>
 
 #include "tile_common.h"
@@ -46,14 +51,15 @@
 namespace mfr {
 
 // LDS of one work-group of the voxel-tile kernel.
-template <int BX, int BY, int MODE>
+template <int BX, int BY, int MODE, bool SSD>
 struct TileSmem {
   static constexpr int NT = BX * BY, MAXNX = BX + 1, MAXNY = BY + 1;
   static constexpr bool HV = (MODE == MODE_HV), NEED_C = (MODE != MODE_OBJ);
-  float sTw[2][NT];
-  float sR[2][NT];
-  float sA[HV ? 2 : 1][HV ? NT : 1];
-  float sE[NEED_C ? 2 : 1][4][NEED_C ? NT : 1];
+  static constexpr int NX = SSD ? 1 : NT;   // plane exchange (NGF differences only)
+  float sTw[2][NX];
+  float sR[2][NX];
+  float sA[HV ? 2 : 1][HV ? NX : 1];
+  float sE[NEED_C ? 2 : 1][4][NEED_C ? NX : 1];
   float sV[NEED_C ? 3 : 1][NEED_C ? NT : 1];
   float sW[NEED_C ? 3 : 1][NEED_C ? BY * MAXNX : 1];
   int sColLo[MAXNX], sColHi[MAXNX], sRowLo[MAXNY], sRowHi[MAXNY];
@@ -62,9 +68,9 @@ struct TileSmem {
 };
 
 // One tile (work-group id `bid` of the problem P) of the fused kernel.
-template <int BX, int BY, int MODE>
+template <int BX, int BY, int MODE, bool SSD>
 __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, const float* __restrict__ u,
-                                          const float* __restrict__ pv, TileSmem<BX, BY, MODE>& S) {
+                                          const float* __restrict__ pv, TileSmem<BX, BY, MODE, SSD>& S) {
   constexpr int NT = BX * BY;
   constexpr int TX = BX - 2, TY = BY - 2;   // own columns per tile
   constexpr int MAXNX = BX + 1;
@@ -276,10 +282,12 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
       g[K][2] = s.gz;
       Rv[K] = nx_R;
       if (HV) av[K] = fmaf(s.gx, nx_pp[0], fmaf(s.gy, nx_pp[1], s.gz * nx_pp[2]));
-      const int sl = t & 1;
-      sTw[sl][tid] = Tw[K];
-      sR[sl][tid] = Rv[K];
-      if (HV) sA[sl][tid] = av[K];
+      if constexpr (!SSD) {
+        const int sl = t & 1;
+        sTw[sl][tid] = Tw[K];
+        sR[sl][tid] = Rv[K];
+        if (HV) sA[sl][tid] = av[K];
+      }
     }
     if (t < tlast) issue(t + 1);
     // No barrier here: stage B reads only LDS slots of plane t-1 (written in the
@@ -291,7 +299,16 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     float ezm = 0.f;
     e0[K1] = 0.f;
     ezp[K1] = 0.f;
-    if (zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
+    if (SSD && zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
+      if (inB) {
+        const float r = Tw[K1] - Rv[K1];
+        if (MODE != MODE_HV && zc >= zb && zc < ze) {
+          const double rd = r;
+          obj += 0.5 * rd * rd;
+        }
+        if constexpr (NEED_C) e0[K1] = HV ? av[K1] : r;
+      }
+    } else if (!SSD && zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
       const int s1 = zc & 1;
       float ex_p = 0.f, ex_m = 0.f, ey_p = 0.f, ey_m = 0.f;
       if (inB) {
@@ -369,15 +386,17 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
           KL = cvz.n0;
         }
         if (inC) {
-          const int s2 = c & 1;
-          // rows of the neighbours within the group (none beyond its edge)
           float w = e0[K2];
-          w += tx < BX - 1 ? sE[s2][1][tid + 1] : 0.f;
-          w += tx > 0 ? sE[s2][0][tid - 1] : 0.f;
-          w += ty < BY - 1 ? sE[s2][3][tid + BX] : 0.f;
-          w += ty > 0 ? sE[s2][2][tid - BX] : 0.f;
-          w += ezm;
-          w += ezp[K];
+          if constexpr (!SSD) {
+            // rows of the neighbours within the group (none beyond its edge)
+            const int s2 = c & 1;
+            w += tx < BX - 1 ? sE[s2][1][tid + 1] : 0.f;
+            w += tx > 0 ? sE[s2][0][tid - 1] : 0.f;
+            w += ty < BY - 1 ? sE[s2][3][tid + BX] : 0.f;
+            w += ty > 0 ? sE[s2][2][tid - BX] : 0.f;
+            w += ezm;
+            w += ezp[K];
+          }
           const float wz1 = cvz.f, wz0 = 1.0f - cvz.f;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
@@ -388,7 +407,8 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         }
       }
     }
-    __syncthreads();
+    // SSD exchanges nothing between columns within a step (flush has its own barriers)
+    if constexpr (!SSD) __syncthreads();
   };
 
   issue(tfirst);
@@ -406,12 +426,12 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   __syncthreads();   // LDS may be reused by the next tile of a persistent group
 }
 
-template <int BX, int BY, int MODE>
+template <int BX, int BY, int MODE, bool SSD>
 __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P, const float* __restrict__ u,
                                                           const float* __restrict__ pv) {
   if (P.live && !ld_coherent(P.live)) return;   // a device-steered solve has stopped
-  __shared__ TileSmem<BX, BY, MODE> S;
-  tile_body<BX, BY, MODE>(P, xcd_block_id(), u, pv, S);
+  __shared__ TileSmem<BX, BY, MODE, SSD> S;
+  tile_body<BX, BY, MODE, SSD>(P, xcd_block_id(), u, pv, S);
 }
 
 // Persistent form over a batch of problems: every group takes tiles from a
@@ -420,7 +440,7 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P, co
 // one launch per problem bit for bit.
 template <int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void ngf_tile_batch_kernel(const BatchJobs J) {
-  __shared__ TileSmem<BX, BY, MODE> S;
+  __shared__ TileSmem<BX, BY, MODE, false> S;
   __shared__ int sItem;
   for (;;) {
     if (threadIdx.x == 0) sItem = atomicAdd(J.counter, 1);
@@ -432,25 +452,34 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_batch_kernel(const BatchJobs 
     while (pr + 1 < J.n && J.prefix[pr + 1] <= item) ++pr;
     if (J.active && !ld_coherent(J.active + pr)) continue;
     const BatchJob& jb = J.jobs[pr];
-    tile_body<BX, BY, MODE>(jb.t, item - J.prefix[pr], jb.u, jb.p, S);
+    tile_body<BX, BY, MODE, false>(jb.t, item - J.prefix[pr], jb.u, jb.p, S);
+  }
+}
+
+template <int BX, int BY, bool SSD>
+static void launch_tile_dist(int mode, const TileParams& p, const float* u, const float* pv, int grid,
+                             hipStream_t st) {
+  dim3 blk(BX * BY), grd(grid);
+  switch (mode) {
+    case MODE_OBJ:
+      hipLaunchKernelGGL((ngf_tile_kernel<BX, BY, MODE_OBJ, SSD>), grd, blk, 0, st, p, u, pv);
+      break;
+    case MODE_GRAD:
+      hipLaunchKernelGGL((ngf_tile_kernel<BX, BY, MODE_GRAD, SSD>), grd, blk, 0, st, p, u, pv);
+      break;
+    default:
+      hipLaunchKernelGGL((ngf_tile_kernel<BX, BY, MODE_HV, SSD>), grd, blk, 0, st, p, u, pv);
+      break;
   }
 }
 
 template <int BX, int BY>
 static hipError_t launch_tile_shape(int mode, const TileParams& p, const float* u, const float* pv,
                                     int grid, hipStream_t st) {
-  dim3 blk(BX * BY), grd(grid);
-  switch (mode) {
-    case MODE_OBJ:
-      hipLaunchKernelGGL((ngf_tile_kernel<BX, BY, MODE_OBJ>), grd, blk, 0, st, p, u, pv);
-      break;
-    case MODE_GRAD:
-      hipLaunchKernelGGL((ngf_tile_kernel<BX, BY, MODE_GRAD>), grd, blk, 0, st, p, u, pv);
-      break;
-    default:
-      hipLaunchKernelGGL((ngf_tile_kernel<BX, BY, MODE_HV>), grd, blk, 0, st, p, u, pv);
-      break;
-  }
+  if (p.ssd)
+    launch_tile_dist<BX, BY, true>(mode, p, u, pv, grid, st);
+  else
+    launch_tile_dist<BX, BY, false>(mode, p, u, pv, grid, st);
   return hipGetLastError();
 }
 

@@ -237,6 +237,7 @@ hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz
 // Exact Jacobi diagonal: diag_{(d,n)} = 2 hbar sum_l (sum_k drow_l(k) g_{l+k,d}
 // W_n(l+k))^2 + 2 alpha hbar^y (L^T L)_{nn}; one thread per node, rows l of
 // dr whose 7-point stencil meets the node's support, everything recomputed.
+// SSD: drow_l is the unit row at l and the scale is hbar.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -342,6 +343,11 @@ __global__ __launch_bounds__(kNodeBlock) void jacobi_diag_kernel(const DiagParam
         for (int k = 1; k < 7; ++k) {
           rh[k] = hh[k] * c1 * fmaf(-c2, dT[k], dR[k]);
           rh[0] -= rh[k];
+        }
+        if (P.ssd) {   // sum of squared differences: dr/dT is the identity
+          rh[0] = 1.0f;
+#pragma unroll
+          for (int k = 1; k < 7; ++k) rh[k] = 0.0f;
         }
         float zd[3] = {0.f, 0.f, 0.f};
 #pragma unroll

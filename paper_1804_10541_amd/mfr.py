@@ -30,7 +30,8 @@ class MfrError(RuntimeError):
 class CGrid(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("my", ctypes.c_int32 * 3),
                 ("mT", ctypes.c_int32 * 3), ("hT", ctypes.c_double * 3),
-                ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("alpha", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("distance", ctypes.c_int32)]
 
 
 class CPcgOpts(ctypes.Structure):
@@ -166,8 +167,12 @@ def _check(status):
         raise MfrError(status, _lib.mfr_last_error().decode())
 
 
+DISTANCES = {"ngf": 0, "ssd": 1}   # mfr_grid.distance
+
+
 def make_grid(spec):
-    """CGrid from any object with m, h, my, tau, rho, alpha (optional mT, hT)."""
+    """CGrid from any object with m, h, my, tau, rho, alpha (optional mT, hT,
+    distance "ngf" or "ssd")."""
     g = CGrid()
     for k in range(3):
         g.m[k] = int(spec.m[k])
@@ -178,6 +183,10 @@ def make_grid(spec):
         g.mT[k] = int(mT[k]) if mT is not None else 0
         g.hT[k] = float(hT[k]) if hT is not None else 0.0
     g.tau, g.rho, g.alpha = float(spec.tau), float(spec.rho), float(spec.alpha)
+    dist = getattr(spec, "distance", "ngf")
+    if dist not in DISTANCES:
+        raise ValueError(f"distance must be one of {sorted(DISTANCES)}, got {dist!r}")
+    g.distance = DISTANCES[dist]
     return g
 
 

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.mfr_abi_version() == 1
+    assert lib.mfr_abi_version() == 2
 
 
 def _ws(spec):
@@ -79,3 +79,23 @@ def test_null_arguments_rejected(lib):
     assert lib.mfr_workspace_size(None, None) == -1
     assert lib.mfr_objective(None, None, None, None, None) == -1
     assert lib.mfr_hess_vec(None, None, None, None) == -1
+
+
+def test_distance_field_validation(lib):
+    # SSD ignores tau and rho; an unknown distance code and SSD in the batched
+    # path are rejected with MFR_EINVAL
+    ssd = GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=0.0, rho=-1.0, alpha=1.0, distance="ssd")
+    assert _ws(ssd) > 0
+    with pytest.raises(mfr.MfrError):
+        _ws(GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=0.0, rho=1.0, alpha=1.0))
+    g = mfr.make_grid(GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1, alpha=1))
+    g.distance = 2
+    n = ctypes.c_size_t()
+    assert lib.mfr_workspace_size(ctypes.byref(g), ctypes.byref(n)) == -1
+    assert b"distance" in lib.mfr_last_error()
+    with pytest.raises(ValueError):
+        mfr.make_grid(GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1, alpha=1, distance="mi"))
+    grids = (mfr.CGrid * 2)(mfr.make_grid(GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1,
+                                                    alpha=1)), mfr.make_grid(ssd))
+    assert lib.mfr_batch_workspace_size(2, grids, 1, ctypes.byref(n)) == -1
+    assert b"NGF" in lib.mfr_last_error()

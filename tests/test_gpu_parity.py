@@ -42,6 +42,8 @@ CASES = [
     ("large-displacement", (20, 20, 20), (6, 6, 6), (1.0, 1.0, 1.0), 0.1, 0.1, 0.1, 8.0),
     # u = 0: every voxel centre on a template sample, where the derivative takes the floor cell
     ("zero-displacement", (24, 20, 16), (9, 8, 7), (1.0, 1.0, 1.0), 0.1, 0.1, 1.0, 0.0),
+    # node supports wider than the diagonal kernel's 32-column blocks: the one-thread-per-node diagonal
+    ("coarse-nodes", (70, 40, 20), (3, 2, 3), (1.0, 1.0, 1.0), 0.1, 0.1, 0.5, 0.8),
 ]
 
 
