@@ -16,9 +16,11 @@ the HIP path: no kernels, no tables, no per-voxel recipe (the rho-hat
 formulation of Sec. 4 is what the GPU computes; the oracle never uses it).
 ``ssd`` holds the same derivatives for the sum-of-squared-differences
 distance (Sec. 4.4: the residual Jacobian becomes the identity).
+``lbfgs`` is the limited-memory BFGS alternative of Sec. 2.3.2 with the
+regulariser's Hessian in the initial matrix.
 ``cnn`` defines the learned preconditioner, an extension of the method
 (convolutions, network, features, loss), and ``solver.fpcg`` the flexible CG
 that uses it.
 """
 from .grid import Grid  # noqa: F401
-from . import interp, ngf, ssd, curvature, solver, multilevel, cnn  # noqa: F401
+from . import interp, ngf, ssd, curvature, solver, multilevel, lbfgs, cnn  # noqa: F401

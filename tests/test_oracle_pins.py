@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import bruteforce
-from oracle import Grid, curvature, interp, multilevel, ngf, solver, ssd
+from oracle import Grid, curvature, interp, lbfgs, multilevel, ngf, solver, ssd
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -595,3 +595,83 @@ def test_ssd_gauss_newton_reduces_objective_and_multilevel_keeps_distance():
     assert prob.objective(u1)[0] < J0
     assert all(h["J_new"] <= h["J"] for h in hist if "J_new" in h)
     assert multilevel.coarse_grid(g).distance == "ssd"
+
+
+# ---------------------------------------------------------------------------
+# L-BFGS with H_0 = alpha nabla^2 S + gamma I (Sec. 2.3.2)
+# ---------------------------------------------------------------------------
+
+def test_lbfgs_two_loop_equals_dense_bfgs_inverse_update():
+    # the recursion against the textbook product form of the inverse update,
+    # H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T from H = H_0^{-1}
+    rng = np.random.default_rng(11)
+    n = 12
+    B = rng.standard_normal((n, n))
+    H0 = B @ B.T + n * np.eye(n)
+    H0inv = np.linalg.inv(H0)
+    A = rng.standard_normal((n, n))
+    A = A @ A.T + np.eye(n)
+    pairs = []
+    H = H0inv.copy()
+    for _ in range(4):
+        s = rng.standard_normal(n)
+        y = A @ s
+        rho = 1.0 / float(s @ y)
+        V = np.eye(n) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+        pairs.append((s, y))
+    g = rng.standard_normal(n)
+    d = lbfgs.two_loop(g, pairs, lambda v: H0inv @ v)
+    np.testing.assert_allclose(d, -H @ g, rtol=1e-10, atol=1e-12)
+    # secant condition of the newest pair
+    s, y = pairs[-1]
+    np.testing.assert_allclose(-lbfgs.two_loop(y, pairs, lambda v: H0inv @ v), s, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("my,gamma", [((5, 4, 3), 0.3), ((6, 2, 4), 2.0)])
+def test_h0_solver_on_cosine_eigenvectors(my, gamma):
+    # the Neumann Laplacian's eigenvectors are the DCT-II cosines
+    # cos(pi k (i + 1/2) / n) with eigenvalue -4 sin^2(pi k / 2n) / hy^2 per axis
+    g = Grid((12, 9, 8), (1.0, 1.3, 0.8), my, 1.0, 1.0, 0.7)
+    h0 = lbfgs.H0Solver(g, gamma)
+    for ks in [(0, 0, 0), (1, 0, 2), (my[0] - 1, my[1] - 1, my[2] - 1), (2, 1, 1)]:
+        ks = tuple(min(k, n - 1) for k, n in zip(ks, my))
+        axes = [np.cos(np.pi * ks[d] * (np.arange(my[d]) + 0.5) / my[d]) for d in range(3)]
+        v = np.einsum("k,j,i->kji", axes[2], axes[1], axes[0])
+        lam = -sum(4.0 * np.sin(np.pi * ks[d] / (2 * my[d])) ** 2 / g.hy[d] ** 2 for d in range(3))
+        mu = 2.0 * g.alpha * g.hybar * lam * lam + gamma
+        V = np.stack([v, 2.0 * v, -v])
+        np.testing.assert_allclose(h0.apply(V), V / mu, rtol=1e-9, atol=1e-12)
+
+
+def test_lbfgs_first_step_is_the_regularised_newton_step():
+    # zero images (SSD): D = 0 and J = alpha S is quadratic with Hessian A = alpha nabla^2 S,
+    # so the first step is -(A + gamma I)^{-1} A u0 and eta = 1 passes the Armijo test
+    g = Grid((10, 8, 7), (1.0, 1.0, 1.0), (5, 4, 4), 1.0, 1.0, 0.6, distance="ssd")
+    rng = np.random.default_rng(4)
+    Z = np.zeros((7, 8, 10))
+    prob = solver.Problem(g, Z, Z)
+    u0 = rng.standard_normal((3, 4, 4, 5))
+    gamma = 0.05
+    u1, hist = lbfgs.lbfgs(prob, u0, iters=1, gamma=gamma)
+    L = curvature.laplacian(g)
+    A = 2.0 * g.alpha * g.hybar * (L.T @ L).toarray()
+    M = A + gamma * np.eye(g.nbar)
+    want = np.stack([u0[d].ravel() - np.linalg.solve(M, A @ u0[d].ravel()) for d in range(3)]).reshape(u0.shape)
+    assert hist[0]["eta"] == 1.0
+    np.testing.assert_allclose(u1, want, rtol=1e-9, atol=1e-11)
+
+
+def test_lbfgs_monotone_armijo_and_curvature_pairs_on_tiny_problem():
+    g, R, T, u, rng = tiny_problem(12, m=(9, 8, 7), my=(5, 4, 4), amp=0.0)
+    T = R + 0.2 * rng.standard_normal(R.shape)
+    prob = solver.Problem(g, R, T)
+    recs = []
+    u1, hist = lbfgs.lbfgs(prob, u, iters=6, mem=3, gamma=0.5, callback=lambda rec, uu, d: recs.append(
+        (rec["J"], float(np.sum(prob.gradient(uu)[1] * d)))))
+    assert len(hist) >= 3
+    for h, (J0, slope) in zip(hist, recs):
+        assert slope < 0
+        if "J_new" in h:
+            assert h["J_new"] <= h["J"] + 1e-4 * h["eta"] * slope + 1e-14
+    assert prob.objective(u1)[0] < prob.objective(u)[0]
