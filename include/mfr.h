@@ -211,6 +211,50 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* op
                                    void* workspace, size_t ws_bytes, const float* R, const float* T,
                                    float* u, mfr_ml_report* report);
 
+/* ---- L-BFGS (Sec. 2.3.2) ------------------------------------------------
+ * Limited-memory BFGS on J = D + alpha S from the objective and gradient, with
+ * the regulariser's Hessian in the initial matrix:
+ *   H_0 = alpha nabla^2 S + gamma I = 2 alpha hbar^y L^T L + gamma I, gamma > 0.
+ * H_0 is inverted exactly in the cosine (DCT-II) basis that diagonalises the
+ * Neumann Laplacian L.  The direction comes from the two-loop recursion over
+ * the last `mem` pairs (s, y) with float64 dot products; a pair is kept only
+ * if s^T y > 1e-12 |s| |y|; a non-descent direction clears the memory and
+ * restarts from -H_0^{-1} grad J.  Step length: Armijo backtracking from 1.
+ * The caller provides a device work buffer (256-byte aligned) of at least
+ * mfr_lbfgs_workspace_size bytes for the cosine tables and 8 + 2 mem node
+ * vectors; at most 4096 nodes per axis. */
+#define MFR_LBFGS_MAX_MEM 64
+
+typedef struct {
+  int32_t iters;       /* iterations, >= 0                                       */
+  int32_t mem;         /* stored pairs, 1..MFR_LBFGS_MAX_MEM                     */
+  double gamma;        /* > 0                                                    */
+  double armijo_c1;    /* in [0, 1)                                              */
+  int32_t armijo_max;  /* step halvings before the line search fails, >= 1       */
+} mfr_lbfgs_opts;
+
+typedef struct {
+  int32_t iters;          /* accepted iterations                                 */
+  int32_t status;         /* 0, or MFR_ELINESEARCH if a line search failed       */
+  int32_t restarts;       /* memory cleared after a non-descent direction        */
+  int32_t pairs_skipped;  /* pairs that failed the curvature test                */
+  int32_t evals;          /* objective evaluations (gradients included)          */
+  double J_initial, J_final;
+  double seconds;         /* wall time of the call                               */
+} mfr_lbfgs_report;
+
+mfr_status mfr_lbfgs_workspace_size(const mfr_grid* grid, int32_t mem, size_t* bytes);
+
+/* x = H_0^{-1} v (all three components).  x may alias v.  work: at least
+ * mfr_lbfgs_workspace_size(grid, 1) bytes.  Asynchronous apart from the upload
+ * of the cosine tables. */
+mfr_status mfr_h0_solve(mfr_ctx* ctx, double gamma, const float* v, float* x, void* work, size_t work_bytes);
+
+/* Runs opts->iters L-BFGS iterations from u (updated in place).  Synchronises
+ * the stream. */
+mfr_status mfr_lbfgs(mfr_ctx* ctx, float* u, const mfr_lbfgs_opts* opts, void* work, size_t work_bytes,
+                     mfr_lbfgs_report* report);
+
 /* ---- Batched registration of independent pairs ------------------------------
  * Up to MFR_MAX_BATCH image pairs of different sizes advance together: every
  * phase (voxel-tile kernels, node passes, sums, CG vector updates) is one

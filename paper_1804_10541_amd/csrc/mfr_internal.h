@@ -236,6 +236,20 @@ hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, 
 hipError_t launch_jacobi_tile(const JacParams& j, const float* u, float* diag, hipStream_t st);
 constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi work-group
 
+// L-BFGS initial-matrix solve (lbfgs_kernels.hip): orthonormal DCT-II matrices
+// C[d] (n_d x n_d, row k = cosine k), their transposes Ct[d], and the per-axis
+// eigenvalues of the Neumann second difference (lam: x, then y, then z).
+struct H0Tables {
+  int n[3];
+  const float* C[3];
+  const float* Ct[3];
+  const float* lam;
+};
+// x = (s (L^T L) + gamma I)^{-1} v per component; ta, tb: scratch node vectors
+// (x may alias v, not ta or tb).
+hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* ta, float* tb, float s, float gamma,
+                           hipStream_t st);
+
 // PCG vector kernels.  sc: device scalars (see PcgSlot).
 enum PcgSlot : int {
   SC_BB = 0, SC_RZ = 1, SC_PQ = 2, SC_RR = 3, SC_RZNEW = 4, SC_ALPHA = 5, SC_BETA = 6,

@@ -97,6 +97,17 @@ class CPcTrainInfo(ctypes.Structure):
                 ("loss_mean", ctypes.c_double)]
 
 
+class CLbfgsOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("mem", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32)]
+
+
+class CLbfgsReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("pairs_skipped", ctypes.c_int32), ("evals", ctypes.c_int32), ("J_initial", ctypes.c_double),
+                ("J_final", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 PROFILE_KERNELS = ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass")
 
 _lib = None
@@ -143,6 +154,9 @@ SIGNATURES = {
     "mfr_get_tile_config": (ctypes.c_int, [ctypes.POINTER(CTileConfig)]),
     "mfr_profile_enable": (ctypes.c_int, [_VP, _I]),
     "mfr_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(CProfile), _I]),
+    "mfr_lbfgs_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
+    "mfr_h0_solve": (ctypes.c_int, [_VP, _D, _VP, _VP, _VP, _SZ]),
+    "mfr_lbfgs": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(CLbfgsOpts), _VP, _SZ, ctypes.POINTER(CLbfgsReport)]),
 }
 
 
@@ -290,6 +304,33 @@ class Context:
         _check(self.lib.mfr_jacobi_diag(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
                                         _dev_tensor(out, 3 * self.nbar, "diag", self.device)))
         return out
+
+    def _lbfgs_work(self, mem):
+        n = ctypes.c_size_t()
+        _check(self.lib.mfr_lbfgs_workspace_size(ctypes.byref(self.grid), int(mem), ctypes.byref(n)))
+        cache = getattr(self, "_lb_work", None)
+        if cache is None or cache[2] < n.value:
+            buf, ptr = _alloc_workspace(n.value, self.device)
+            self._lb_work = (buf, ptr, n.value)
+        return self._lb_work[1], self._lb_work[2]
+
+    def h0_solve(self, v, gamma, out=None):
+        """x = (alpha nabla^2 S + gamma I)^{-1} v, the L-BFGS initial matrix solve."""
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        ptr, nbytes = self._lbfgs_work(1)
+        _check(self.lib.mfr_h0_solve(self._h, float(gamma), _dev_tensor(v, 3 * self.nbar, "v", self.device),
+                                     _dev_tensor(out, 3 * self.nbar, "x", self.device), ctypes.c_void_p(ptr),
+                                     nbytes))
+        return out
+
+    def lbfgs(self, u, iters=10, mem=5, gamma=1.0, armijo_c1=1e-4, armijo_max=10):
+        """L-BFGS iterations; u (device, float32) is updated in place.  Returns the report."""
+        ptr, nbytes = self._lbfgs_work(mem)
+        opts = CLbfgsOpts(int(iters), int(mem), float(gamma), float(armijo_c1), int(armijo_max))
+        rep = CLbfgsReport()
+        _check(self.lib.mfr_lbfgs(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device), ctypes.byref(opts),
+                                  ctypes.c_void_p(ptr), nbytes, ctypes.byref(rep)))
+        return {f[0]: getattr(rep, f[0]) for f in CLbfgsReport._fields_}
 
     def gn_step(self, u, pcg_max=50, pcg_rtol=1e-3, precond=1, armijo_c1=1e-4, armijo_max=10, fallback_iters=0):
         """One Gauss-Newton step; u (device, float32) is updated in place."""

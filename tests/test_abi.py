@@ -99,3 +99,17 @@ def test_distance_field_validation(lib):
                                                     alpha=1)), mfr.make_grid(ssd))
     assert lib.mfr_batch_workspace_size(2, grids, 1, ctypes.byref(n)) == -1
     assert b"NGF" in lib.mfr_last_error()
+
+
+def test_lbfgs_workspace_validation(lib):
+    g = mfr.make_grid(GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1, alpha=1))
+    n1, n5 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 1, ctypes.byref(n1)) == 0
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 5, ctypes.byref(n5)) == 0
+    vec = 3 * 9 ** 3 * 4
+    assert n5.value - n1.value >= 8 * vec   # two node vectors per extra pair
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 0, ctypes.byref(n1)) == -1
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 65, ctypes.byref(n1)) == -1
+    big = mfr.make_grid(GridSpec(m=(8192, 4, 4), h=(1, 1, 1), my=(5000, 3, 3), tau=1, rho=1, alpha=1))
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(big), 1, ctypes.byref(n1)) == -1
+    assert b"4096" in lib.mfr_last_error()
