@@ -40,8 +40,10 @@ HV_BYTES_PER_VOXEL = 8
 HV_BYTES_PER_NODE = 36
 # The same product for the sum-of-squared-differences distance (dr/dT = identity):
 # the NGF-only arithmetic (differences of T and R, the three weighted sums, norms and
-# residual, the rho-hat row, dr a, the dr^T gather: 119 flop) drops out; the bytes stay.
+# residual, the rho-hat row, dr a, the dr^T gather: 119 flop) drops out, and so does
+# the reference image (its Gauss-Newton matrix does not depend on R): T once per voxel.
 SSD_HV_FLOP_PER_VOXEL = 98
+SSD_HV_BYTES_PER_VOXEL = 4
 
 # HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload
 # (32x16 tiles, split target 4096), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
@@ -163,7 +165,7 @@ def ssd_leg(dev, spec, R, T, u0, reps=20):
     hv_avg = hv_ms / max(hv_n, 1)
     np_avg = np_ms / max(np_n, 1)
     tflops = SSD_HV_FLOP_PER_VOXEL * mbar / (hv_avg * 1e-3) / 1e12
-    gbs = (HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar) / (hv_avg * 1e-3) / 1e9
+    gbs = (SSD_HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar) / (hv_avg * 1e-3) / 1e9
     out = {"workload": "the headline pair and displacement with the sum-of-squared-differences distance",
            "kernel": "ngf_tile_kernel<HV, SSD>", "avg_ms": round(hv_avg, 4), "launches": hv_n,
            "kernel_gvoxel_s": round(mbar / (hv_avg * 1e-3) / 1e9, 2),
@@ -174,6 +176,45 @@ def ssd_leg(dev, spec, R, T, u0, reps=20):
            "hbm_algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "jacobi_diag_ms": round(prof["jacobi_diag"][1] / max(prof["jacobi_diag"][0], 1), 3)}
     log(f"[bench] ssd: {out}")
+    return out
+
+
+def lbfgs_leg(dev, spec, R, T, u0, iters=3, gamma=100.0):
+    """L-BFGS iterations (two-loop recursion, H_0 = alpha nabla^2 S + gamma I
+    solved in the cosine basis, Armijo steps) on the headline pair from the same
+    start, and the time of one H_0 solve (events on the context's stream)."""
+    import torch
+
+    from paper_1804_10541_amd import mfr
+
+    ctx = mfr.Context(spec, dev)
+    ctx.set_images(R, T)
+    v = torch.randn(u0.shape, generator=torch.Generator(device=dev).manual_seed(9), device=dev)
+    x = torch.empty_like(v)
+    for _ in range(2):
+        ctx.h0_solve(v, gamma, out=x)
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.h0_solve(v, gamma, out=x)
+    e1.record()
+    torch.cuda.synchronize()
+    h0_ms = e0.elapsed_time(e1) / reps
+    u = u0.clone()
+    ctx.lbfgs(u.clone(), iters=1, mem=5, gamma=gamma)   # warm-up
+    torch.cuda.synchronize()
+    rep = ctx.lbfgs(u, iters=iters, mem=5, gamma=gamma)
+    ctx.close()
+    nb = spec.nodes
+    h0_flop = 4.0 * 3 * nb * sum(spec.my)   # forward and inverse cosine transforms along x, y, z
+    out = {"workload": f"the headline pair and start, {iters} L-BFGS iterations, memory 5, gamma {gamma:g}",
+           "iters": rep["iters"], "status": rep["status"], "evals": rep["evals"],
+           "J_initial": rep["J_initial"], "J_final": rep["J_final"],
+           "s_per_iter": round(rep["seconds"] / max(rep["iters"], 1), 4),
+           "h0_solve_ms": round(h0_ms, 3), "h0_solve_tflops": round(h0_flop / (h0_ms * 1e-3) / 1e12, 2)}
+    log(f"[bench] lbfgs: {out}")
     return out
 
 
@@ -251,6 +292,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile configuration")
     ap.add_argument("--no-pc", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--no-ssd", action="store_true", help="skip the sum-of-squared-differences leg")
+    ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -364,6 +406,9 @@ def main():
     if not args.no_ssd:
         log("[bench] sum-of-squared-differences distance")
         out["ssd"] = ssd_leg(dev, spec, R, T, u0)
+    if not args.no_lbfgs:
+        log("[bench] L-BFGS")
+        out["lbfgs"] = lbfgs_leg(dev, spec, R, T, u0)
     del R, T
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")

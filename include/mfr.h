@@ -246,8 +246,8 @@ typedef struct {
 mfr_status mfr_lbfgs_workspace_size(const mfr_grid* grid, int32_t mem, size_t* bytes);
 
 /* x = H_0^{-1} v (all three components).  x may alias v.  work: at least
- * mfr_lbfgs_workspace_size(grid, 1) bytes.  Asynchronous apart from the upload
- * of the cosine tables. */
+ * mfr_lbfgs_workspace_size(grid, 1) bytes; every call copies the cosine tables
+ * into it (from host copies the context keeps).  Asynchronous. */
 mfr_status mfr_h0_solve(mfr_ctx* ctx, double gamma, const float* v, float* x, void* work, size_t work_bytes);
 
 /* Runs opts->iters L-BFGS iterations from u (updated in place).  Synchronises

@@ -828,7 +828,11 @@ mfr_status mfr_create(const mfr_grid* grid, void* hip_stream, void* workspace, s
   return MFR_OK;
 }
 
-void mfr_destroy(mfr_ctx* ctx) { delete ctx; }
+void mfr_destroy(mfr_ctx* ctx) {
+  // pending copies may still read host memory the context owns
+  if (ctx) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
 
 mfr_status mfr_set_images(mfr_ctx* c, const float* R, const float* T) {
   if (!c) return fail(MFR_EINVAL, "context is NULL");

@@ -112,6 +112,9 @@ struct mfr_ctx {
   int* ctrl;                     // device-steered CG: [0] active flag, [1..] PcgState
   mfr_pc* pc = nullptr;          // learned preconditioner used by precond = 2
   unsigned image_version = 0;    // bumped by mfr_set_images
+  // host copies of the L-BFGS initial-matrix tables (cosine matrices, their
+  // transposes, eigenvalues); kept here so uploads need no synchronisation
+  std::vector<float> h0_C[3], h0_Ct[3], h0_lam;
   // kernel timing (mfr_profile_*)
   bool prof_on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;

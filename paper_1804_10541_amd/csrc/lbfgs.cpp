@@ -58,32 +58,41 @@ mfr_status check_geo(const Geo& g) {
 }
 
 // Orthonormal DCT-II matrices, their transposes and the eigenvalues
-// -4 sin^2(pi k / 2n) / hy^2 of the Neumann second difference, uploaded to work.
+// -4 sin^2(pi k / 2n) / hy^2 of the Neumann second difference, built once per
+// context on the host and copied into work (the work buffer is the caller's,
+// so every call copies them again; the host copies outlive the copies).
 mfr_status upload_tables(mfr_ctx* c, const LbLayout& L, char* work, H0Tables* t) {
   const Geo& g = c->geo;
-  std::vector<float> lam;
-  for (int d = 0; d < 3; ++d) {
-    const int n = g.n[d];
-    std::vector<float> C((size_t)n * n), Ct((size_t)n * n);
-    for (int k = 0; k < n; ++k) {
-      const double w = std::sqrt((k == 0 ? 1.0 : 2.0) / n);
-      for (int i = 0; i < n; ++i) {
-        const float v = (float)(w * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n)));
-        C[(size_t)k * n + i] = v;
-        Ct[(size_t)i * n + k] = v;
+  if (c->h0_lam.empty()) {
+    for (int d = 0; d < 3; ++d) {
+      const int n = g.n[d];
+      std::vector<float>& C = c->h0_C[d];
+      std::vector<float>& Ct = c->h0_Ct[d];
+      C.assign((size_t)n * n, 0.0f);
+      Ct.assign((size_t)n * n, 0.0f);
+      for (int k = 0; k < n; ++k) {
+        const double w = std::sqrt((k == 0 ? 1.0 : 2.0) / n);
+        for (int i = 0; i < n; ++i) {
+          const float v = (float)(w * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n)));
+          C[(size_t)k * n + i] = v;
+          Ct[(size_t)i * n + k] = v;
+        }
+        const double sn = std::sin(M_PI * k / (2.0 * n));
+        c->h0_lam.push_back((float)(-4.0 * sn * sn / (g.hy[d] * g.hy[d])));
       }
-      const double sn = std::sin(M_PI * k / (2.0 * n));
-      lam.push_back((float)(-4.0 * sn * sn / (g.hy[d] * g.hy[d])));
     }
-    HIP_TRY(hipMemcpyAsync(work + L.C[d], C.data(), sizeof(float) * C.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(work + L.Ct[d], Ct.data(), sizeof(float) * Ct.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));   // the host vectors go out of scope
-    t->n[d] = n;
+  }
+  for (int d = 0; d < 3; ++d) {
+    HIP_TRY(hipMemcpyAsync(work + L.C[d], c->h0_C[d].data(), sizeof(float) * c->h0_C[d].size(),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(work + L.Ct[d], c->h0_Ct[d].data(), sizeof(float) * c->h0_Ct[d].size(),
+                           hipMemcpyHostToDevice, c->stream));
+    t->n[d] = g.n[d];
     t->C[d] = reinterpret_cast<const float*>(work + L.C[d]);
     t->Ct[d] = reinterpret_cast<const float*>(work + L.Ct[d]);
   }
-  HIP_TRY(hipMemcpyAsync(work + L.lam, lam.data(), sizeof(float) * lam.size(), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpyAsync(work + L.lam, c->h0_lam.data(), sizeof(float) * c->h0_lam.size(), hipMemcpyHostToDevice,
+                         c->stream));
   t->lam = reinterpret_cast<const float*>(work + L.lam);
   return MFR_OK;
 }
