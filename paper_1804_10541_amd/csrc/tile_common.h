@@ -36,6 +36,12 @@ struct Tri {
   float v, gx, gy, gz;
 };
 
+// Two consecutive floats loaded together (one 8-byte load; 4-byte alignment
+// suffices on this GPU).
+struct __attribute__((aligned(4))) FPair {
+  float a, b;
+};
+
 // Loads the 8 corner samples of the zero-bordered template for the cell with
 // lower corner (kx, ky, kz) (template cells).  Indices are clamped to [-2, mT],
 // which only ever maps fully outside samples onto the zero border, so value
@@ -46,14 +52,17 @@ __device__ __forceinline__ void template_corners(const TileParams& P, int kx, in
   kz = min(max(kz, -2), P.mTz);
   const float* b0 = P.Tp + (size_t)(kz + 2) * (size_t)P.PXY + (size_t)((ky + 2) * P.PX + (kx + 2));
   const float* b1 = b0 + P.PXY;
-  t[0] = b0[0];
-  t[1] = b0[1];
-  t[2] = b0[P.PX];
-  t[3] = b0[P.PX + 1];
-  t[4] = b1[0];
-  t[5] = b1[1];
-  t[6] = b1[P.PX];
-  t[7] = b1[P.PX + 1];
+  // x-pairs of corners with one 8-byte load each (4-byte alignment suffices)
+  const FPair a = *reinterpret_cast<const FPair*>(b0), b = *reinterpret_cast<const FPair*>(b0 + P.PX);
+  const FPair c = *reinterpret_cast<const FPair*>(b1), d = *reinterpret_cast<const FPair*>(b1 + P.PX);
+  t[0] = a.a;
+  t[1] = a.b;
+  t[2] = b.a;
+  t[3] = b.b;
+  t[4] = c.a;
+  t[5] = c.b;
+  t[6] = d.a;
+  t[7] = d.b;
 }
 
 // Trilinear value and exact derivative from the 8 corners (x fastest) and
@@ -79,7 +88,14 @@ __device__ __forceinline__ float ld32(const float* __restrict__ base, unsigned i
   return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (idx << 2));
 }
 
-// template_corners with 32-bit offsets.
+// Two consecutive floats at a 32-bit element offset: one 8-byte load (4-byte
+// alignment suffices on this GPU), which halves the address work of a gather
+// in the texture addresser (the voxel-tile kernel's vector-memory bottleneck).
+__device__ __forceinline__ FPair ld32x2(const float* __restrict__ base, unsigned idx) {
+  return *reinterpret_cast<const FPair*>(reinterpret_cast<const char*>(base) + (idx << 2));
+}
+
+// template_corners with 32-bit offsets; the x-pairs of corners are loaded together.
 __device__ __forceinline__ void template_corners32(const TileParams& P, int kx, int ky, int kz, float (&t)[8]) {
   kx = min(max(kx, -2), P.mTx);
   ky = min(max(ky, -2), P.mTy);
@@ -87,14 +103,15 @@ __device__ __forceinline__ void template_corners32(const TileParams& P, int kx, 
   const unsigned PX = (unsigned)P.PX, PXY = (unsigned)P.PXY;
   const unsigned i0 = (unsigned)(kz + 2) * PXY + (unsigned)__mul24(ky + 2, (int)PX) + (unsigned)(kx + 2);
   const unsigned i1 = i0 + PXY;
-  t[0] = ld32(P.Tp, i0);
-  t[1] = ld32(P.Tp, i0 + 1);
-  t[2] = ld32(P.Tp, i0 + PX);
-  t[3] = ld32(P.Tp, i0 + PX + 1);
-  t[4] = ld32(P.Tp, i1);
-  t[5] = ld32(P.Tp, i1 + 1);
-  t[6] = ld32(P.Tp, i1 + PX);
-  t[7] = ld32(P.Tp, i1 + PX + 1);
+  const FPair a = ld32x2(P.Tp, i0), b = ld32x2(P.Tp, i0 + PX), c = ld32x2(P.Tp, i1), d = ld32x2(P.Tp, i1 + PX);
+  t[0] = a.a;
+  t[1] = a.b;
+  t[2] = b.a;
+  t[3] = b.b;
+  t[4] = c.a;
+  t[5] = c.b;
+  t[6] = d.a;
+  t[7] = d.b;
 }
 
 __device__ __forceinline__ Tri sample_template(const TileParams& P, int kx, int ky, int kz, float fx, float fy,
