@@ -187,7 +187,7 @@ Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector
   chunks = std::min(chunks, std::max(1, g.m[2] / 16));
   int clen = (g.m[2] + chunks - 1) / chunks;
   if (cfg.chunk_len > 0) clen = cfg.chunk_len;
-  t.chunk_len = std::min(clen, g.m[2]);
+  t.chunk_len = std::min(std::min(clen, g.m[2]), kMaxChunk);
   t.chunks = (g.m[2] + t.chunk_len - 1) / t.chunk_len;
   t.nxt = t.nyt = t.nzt = 0;
   // node extent of a group's columns inside the image (own columns and ring)

@@ -11,6 +11,9 @@ namespace mfr {
 
 constexpr int kVecBlock = 256;
 constexpr int kNodeBlock = 256;
+// Longest z chunk of the voxel-tile kernel: a group keeps the per-plane tables of
+// its chunk (plus two planes either side) in LDS.
+constexpr int kMaxChunk = 252;
 
 // Reads of values that an earlier kernel wrote (CG scalars, control flags, scales):
 // agent-scope atomic loads are served coherently, never from a stale scalar-cache

@@ -64,6 +64,11 @@ struct TileSmem {
   float sW[NEED_C ? 3 : 1][NEED_C ? BY * MAXNX : 1];
   int sColLo[MAXNX], sColHi[MAXNX], sRowLo[MAXNY], sRowHi[MAXNY];
   Conv1 sCx[BX], sCy[BY];
+  // z conversion and template-coordinate entries of planes zb-2 .. ze+1 (clamped
+  // into the image): read at a uniform index every plane, from LDS rather than
+  // through a vector load whose latency would sit on every step's address path
+  Conv1 sCz[kMaxChunk + 4];
+  Samp1 sSz[kMaxChunk + 4];
   double sRed[NT / 64];
 };
 
@@ -88,6 +93,8 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   auto& sRowHi = S.sRowHi;
   auto& sCx = S.sCx;
   auto& sCy = S.sCy;
+  auto& sCz = S.sCz;
+  auto& sSz = S.sSz;
   auto& sRed = S.sRed;
 
   const int tid = threadIdx.x;
@@ -129,6 +136,12 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   const int lxa = x0 == 0 ? 1 : 0, lya = y0 == 0 ? 1 : 0;
   const int lxb = min(BX - 1, P.mx - x0), lyb = min(BY - 1, P.my - y0);
   const int nox = P.cx[x0 - 1 + lxa].n0, noy = P.cy[y0 - 1 + lya].n0, noz = P.cz[zb].n0;
+  for (int j = tid; j < ze - zb + 4; j += NT) {
+    const int q = min(max(zb - 2 + j, 0), P.mz - 1);
+    sCz[j] = P.cz[q];
+    sSz[j] = P.sz[q];
+  }
+  if constexpr (!NEED_C) __syncthreads();   // (with NEED_C the barrier after sCx / sCy covers it)
   const int nxl = P.cx[x0 - 1 + lxb].n0 + 2 - nox;
   const int nyl = P.cy[y0 - 1 + lyb].n0 + 2 - noy;
   if constexpr (NEED_C) {
@@ -238,7 +251,9 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   float nx_pp[3] = {0.f, 0.f, 0.f};
   auto issue = [&](int tt) {
     const int tc = min(max(tt, 0), P.mz - 1);
-    const Conv1 cvz = P.cz[tc];
+    const int jz = tt - zb + 2;   // LDS slot of plane tt (entries are clamped into the image)
+    Conv1 cvz = sCz[jz];
+    cvz.n0 = __builtin_amdgcn_readfirstlane(cvz.n0);   // uniform: keeps the plane logic scalar
     if (cvz.n0 != Kp) {
       if (cvz.n0 == Kp + 1) {
 #pragma unroll
@@ -257,7 +272,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     const float fz = cvz.f;
     const int kx = template_cell(spx, fmaf(fz, uhi[0] - ulo[0], ulo[0]), P.ihTx, nx_fx);
     const int ky = template_cell(spy, fmaf(fz, uhi[1] - ulo[1], ulo[1]), P.ihTy, nx_fy);
-    const int kz = template_cell(P.sz[tc], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, nx_fz);
+    const int kz = template_cell(sSz[jz], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, nx_fz);
     template_corners32(P, kx, ky, kz, nx_t);
     nx_R = ld32(P.R, (unsigned)tc * plane + colxy);
     if (HV) {
@@ -375,7 +390,8 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     if constexpr (NEED_C) {
       const int c = t - 2;
       if (c >= zb && c < ze) {
-        const Conv1 cvz = P.cz[c];
+        Conv1 cvz = sCz[c - zb + 2];
+        cvz.n0 = __builtin_amdgcn_readfirstlane(cvz.n0);
         if (cvz.n0 != KL) {  // node plane KL is complete
           flush(acc_lo, KL - noz);
 #pragma unroll
