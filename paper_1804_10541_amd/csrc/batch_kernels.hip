@@ -167,14 +167,21 @@ hipError_t launch_pcg_init_batch(const VecJobs& j, hipStream_t st) {
 }
 
 // alpha = r.z / p.q from the node-pass partials; breakdown ends the problem.
-__global__ __launch_bounds__(256) void pcg_alpha_batch_kernel(const VecJobs J) {
-  __shared__ double sred[4];
+// One 1024-thread group per problem with two independent running sums per thread
+// (a fixed order, so the result does not depend on timing).
+__global__ __launch_bounds__(1024) void pcg_alpha_batch_kernel(const VecJobs J) {
+  __shared__ double sred[16];
   const int pr = blockIdx.x;
   const VecJob& v = J.jobs[pr];
   if (!ld_coherent(v.state + ST_ACTIVE)) return;
-  double a = 0.0;
-  for (int i = threadIdx.x; i < v.n_pq; i += 256) a += v.red_pq[i];
-  const double pq = block_sum<256>(a, sred);
+  double a = 0.0, b = 0.0;
+  int i = threadIdx.x;
+  for (; i + 1024 < v.n_pq; i += 2048) {
+    a += v.red_pq[i];
+    b += v.red_pq[i + 1024];
+  }
+  if (i < v.n_pq) a += v.red_pq[i];
+  const double pq = block_sum<1024>(a + b, sred);
   if (threadIdx.x == 0) {
     double* sc = v.sc;
     sc[SC_PQ] = pq;
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(256) void pcg_alpha_batch_kernel(const VecJobs J) {
 }
 
 hipError_t launch_pcg_alpha_batch(const VecJobs& j, hipStream_t st) {
-  hipLaunchKernelGGL(pcg_alpha_batch_kernel, dim3(j.n), dim3(256), 0, st, j);
+  hipLaunchKernelGGL(pcg_alpha_batch_kernel, dim3(j.n), dim3(1024), 0, st, j);
   return hipGetLastError();
 }
 

@@ -80,6 +80,21 @@ def test_parity_other_tile_shapes_and_chunks(tile):
         mfr.set_tile_config(**prev)
 
 
+@pytest.mark.parametrize("distance", ["ngf", "ssd"])
+def test_parity_chunk_longer_than_the_lds_tables(distance):
+    # a requested z chunk of 400 planes is capped at the 252 planes whose tables a group
+    # keeps in LDS: 300 planes become chunks of 252 and 48
+    _announce(f"{distance} chunk cap, 300 planes")
+    prev = mfr.get_tile_config()
+    mfr.set_tile_config(32, 16, chunk_len=400)
+    try:
+        spec, R, T, u, probes = blob_case(7, (20, 18, 300), (6, 5, 76), (1.0, 1.0, 1.0), 0.1, 0.1, 0.5, 0.6,
+                                          n_probes=2, distance=distance)
+        assert_parity(gpu_eval(spec, R, T, u, probes), oracle_eval(spec, R, T, u, probes))
+    finally:
+        mfr.set_tile_config(**prev)
+
+
 def test_hessian_symmetric_psd_and_deterministic():
     _announce("symmetry / determinism")
     spec, R, T, u, probes = blob_case(6, (40, 36, 30), (14, 13, 11), (1.0, 1.0, 1.0), 0.1, 0.1, 0.5, 0.5)
