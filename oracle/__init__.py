@@ -16,6 +16,7 @@ the HIP path: no kernels, no tables, no per-voxel recipe (the rho-hat
 formulation of Sec. 4 is what the GPU computes; the oracle never uses it).
 ``ssd`` holds the same derivatives for the sum-of-squared-differences
 distance (Sec. 4.4: the residual Jacobian becomes the identity).
+``diffusive`` is the diffusive regulariser (Sec. 4.4), an alternative to curvature.
 ``lbfgs`` is the limited-memory BFGS alternative of Sec. 2.3.2 with the
 regulariser's Hessian in the initial matrix.
 ``cnn`` defines the learned preconditioner, an extension of the method
@@ -23,4 +24,4 @@ regulariser's Hessian in the initial matrix.
 that uses it.
 """
 from .grid import Grid  # noqa: F401
-from . import interp, ngf, ssd, curvature, solver, multilevel, lbfgs, cnn  # noqa: F401
+from . import interp, ngf, ssd, curvature, diffusive, solver, multilevel, lbfgs, cnn  # noqa: F401

@@ -67,6 +67,12 @@ def hessian_diag(grid, L=None):
     return np.stack([d, d, d]).reshape(3, grid.my[2], grid.my[1], grid.my[0])
 
 
+def hessian_matrix(grid, L=None):
+    """The per-component Hessian 2 hbar^y L^T L."""
+    L = laplacian(grid) if L is None else L
+    return 2.0 * grid.hybar * (L.T @ L)
+
+
 def _row_entries(grid, m):
     """Column -> coefficient of row ``m`` of L (coinciding clamped columns summed)."""
     abc = [int(x) for x in grid.node_abc(m)]

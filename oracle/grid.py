@@ -23,9 +23,10 @@ class Grid:
     """Image grid (``m`` cells, spacing ``h``), deformation grid (``my`` nodes),
     template grid (``mT`` cells, spacing ``hT``; default = image grid), the
     model parameters tau, rho (NGF) and alpha (curvature weight), and the
-    distance measure: "ngf" (the paper's) or "ssd" (Sec. 4.4)."""
+    distance measure: "ngf" (the paper's) or "ssd" (Sec. 4.4), and the
+    regulariser: "curvature" (the paper's) or "diffusive" (Sec. 4.4)."""
 
-    def __init__(self, m, h, my, tau, rho, alpha, mT=None, hT=None, distance="ngf"):
+    def __init__(self, m, h, my, tau, rho, alpha, mT=None, hT=None, distance="ngf", regulariser="curvature"):
         self.m = tuple(int(k) for k in m)
         self.h = tuple(float(k) for k in h)
         self.my = tuple(int(k) for k in my)
@@ -35,6 +36,9 @@ class Grid:
         if distance not in ("ngf", "ssd"):
             raise ValueError("distance must be 'ngf' or 'ssd'")
         self.distance = distance
+        if regulariser not in ("curvature", "diffusive"):
+            raise ValueError("regulariser must be 'curvature' or 'diffusive'")
+        self.regulariser = regulariser
         for k in range(3):
             if not (2 <= self.my[k] and self.my[k] - 1 <= self.m[k]):
                 raise ValueError("need 2 <= my <= m + 1 in every dimension")
@@ -43,7 +47,7 @@ class Grid:
     def from_spec(cls, spec):
         return cls(spec.m, spec.h, spec.my, spec.tau, spec.rho, spec.alpha,
                    getattr(spec, "mT", None), getattr(spec, "hT", None),
-                   getattr(spec, "distance", "ngf"))
+                   getattr(spec, "distance", "ngf"), getattr(spec, "regulariser", "curvature"))
 
     # sizes -----------------------------------------------------------------
     @property

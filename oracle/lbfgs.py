@@ -25,18 +25,23 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import curvature
+from . import curvature, diffusive
 
 
 class H0Solver:
-    """x = H_0^{-1} v for H_0 = 2 alpha hbar^y L^T L + gamma I (per component)."""
+    """x = H_0^{-1} v for H_0 = alpha nabla^2 S + gamma I (per component):
+    2 alpha hbar^y L^T L + gamma I for curvature, alpha hbar^y sum_k D_k^T D_k / hy_k^2
+    + gamma I for the diffusive regulariser."""
 
     def __init__(self, grid, gamma, L=None):
         if not gamma > 0:
             raise ValueError("gamma must be > 0")
-        L = curvature.laplacian(grid) if L is None else L
         self.grid = grid
-        self.A = (2.0 * grid.alpha * grid.hybar * (L.T @ L) + gamma * sp.identity(grid.nbar)).tocsc()
+        if getattr(grid, "regulariser", "curvature") == "diffusive":
+            H = diffusive.hessian_matrix(grid)
+        else:
+            H = curvature.hessian_matrix(grid, curvature.laplacian(grid) if L is None else L)
+        self.A = (grid.alpha * H + gamma * sp.identity(grid.nbar)).tocsc()
         self._solve = spla.factorized(self.A)
 
     def apply(self, v):
@@ -70,7 +75,7 @@ def two_loop(g, pairs, h0_inv):
 def lbfgs(problem, u0, iters=10, mem=5, gamma=1.0, c1=1e-4, max_ls=10, callback=None):
     """L-BFGS iterations from u0.  Returns (u, history) with one dict per
     iteration (J before, gradient norm, step length, whether the pair was kept)."""
-    h0 = H0Solver(problem.grid, gamma, problem.L)
+    h0 = H0Solver(problem.grid, gamma, problem.L if problem.reg is curvature else None)
     u = np.array(u0, dtype=np.float64, copy=True)
     Jv, g = problem.gradient(u)
     pairs = []

@@ -18,30 +18,32 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import curvature, ngf, ssd
+from . import curvature, diffusive, ngf, ssd
 
 
 class Problem:
     """One registration level: grid, reference R, template T (float64 copies).
-    The distance term is NGF or SSD as the grid says."""
+    The distance term (NGF or SSD) and the regulariser (curvature or
+    diffusive) are the grid's."""
 
     def __init__(self, grid, R, T):
         self.grid = grid
         self.R = np.asarray(R, dtype=np.float64)
         self.T = np.asarray(T, dtype=np.float64)
-        self.L = curvature.laplacian(grid)
+        self.reg = diffusive if grid.regulariser == "diffusive" else curvature
+        self.L = curvature.laplacian(grid) if self.reg is curvature else diffusive.operator(grid)
         self.dist = ssd if grid.distance == "ssd" else ngf
 
     def objective(self, u):
         """(J, D, S)."""
         D = self.dist.distance(self.grid, self.R, self.T, u)
-        S = curvature.energy(self.grid, u, self.L)
+        S = self.reg.energy(self.grid, u, self.L)
         return D + self.grid.alpha * S, D, S
 
     def gradient(self, u):
         """(J, grad J)."""
         Jv, _, _ = self.objective(u)
-        g = self.dist.gradient_D(self.grid, self.R, self.T, u) + self.grid.alpha * curvature.gradient(self.grid, u, self.L)
+        g = self.dist.gradient_D(self.grid, self.R, self.T, u) + self.grid.alpha * self.reg.gradient(self.grid, u, self.L)
         return Jv, g
 
     def jacobian(self, u):
@@ -50,12 +52,12 @@ class Problem:
     def hess_vec(self, u, p, Jac=None):
         """(H + alpha nabla^2 S) p."""
         return (self.dist.hess_vec_D(self.grid, self.R, self.T, u, p, Jac)
-                + self.grid.alpha * curvature.hess_vec(self.grid, p, self.L))
+                + self.grid.alpha * self.reg.hess_vec(self.grid, p, self.L))
 
     def jacobi_diag(self, u, Jac=None):
         """diag(H + alpha nabla^2 S)."""
         return (self.dist.hessian_diag_D(self.grid, self.R, self.T, u, Jac)
-                + self.grid.alpha * curvature.hessian_diag(self.grid, self.L))
+                + self.grid.alpha * self.reg.hessian_diag(self.grid, self.L))
 
 
 def pcg(apply_A, b, diag=None, max_iter=50, rtol=1e-3):

@@ -37,6 +37,7 @@ class GridSpec:
     mT: tuple = None    # template cells (default: m)
     hT: tuple = None    # template spacing (default: h)
     distance: str = "ngf"   # distance measure: "ngf" or "ssd"
+    regulariser: str = "curvature"   # "curvature" or "diffusive"
 
     def template_cells(self):
         return tuple(self.mT) if self.mT is not None else tuple(self.m)

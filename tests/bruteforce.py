@@ -115,3 +115,20 @@ def curvature_S(my, hy, u):
                            + (u[d][max(k - 1, 0)][j][i] - 2 * c0 + u[d][min(k + 1, nz - 1)][j][i]) / hy[2] ** 2)
                     S += hyb * lap * lap
     return S
+
+
+def diffusive_S(my, hy, u):
+    """hbar^y / 2 sum_d sum over node edges ((u_{n+e_k} - u_n) / hy_k)^2, loop by loop."""
+    nx, ny, nz = my
+    hyb = hy[0] * hy[1] * hy[2]
+    S = 0.0
+    for d in range(3):
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    for (di, dj, dk, h) in ((1, 0, 0, hy[0]), (0, 1, 0, hy[1]), (0, 0, 1, hy[2])):
+                        a, b, c = i + di, j + dj, k + dk
+                        if a < nx and b < ny and c < nz:
+                            diff = (u[d][c][b][a] - u[d][k][j][i]) / h
+                            S += 0.5 * hyb * diff * diff
+    return S

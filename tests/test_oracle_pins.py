@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import bruteforce
-from oracle import Grid, curvature, interp, lbfgs, multilevel, ngf, solver, ssd
+from oracle import Grid, curvature, diffusive, interp, lbfgs, multilevel, ngf, solver, ssd
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -675,3 +675,70 @@ def test_lbfgs_monotone_armijo_and_curvature_pairs_on_tiny_problem():
         if "J_new" in h:
             assert h["J_new"] <= h["J"] + 1e-4 * h["eta"] * slope + 1e-14
     assert prob.objective(u1)[0] < prob.objective(u)[0]
+
+
+# ---------------------------------------------------------------------------
+# Diffusive regulariser (Sec. 4.4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("my,h", [((4, 3, 5), (1.0, 1.2, 0.9)), ((2, 6, 3), (0.5, 1.0, 2.0))])
+def test_diffusive_energy_bruteforce_closed_forms_and_laplacian(my, h):
+    rng = np.random.default_rng(21)
+    m = tuple(2 * (n - 1) for n in my)
+    g = Grid(m, h, my, 1.0, 1.0, 0.7, regulariser="diffusive")
+    u = rng.standard_normal((3, my[2], my[1], my[0]))
+    ref = bruteforce.diffusive_S(g.my, g.hy, u.tolist())
+    assert abs(diffusive.energy(g, u) - ref) <= 1e-12 * abs(ref)
+    # constants cost nothing; a linear field a.x in component d costs
+    # hbar^y/2 sum_k a_k^2 (edges along k)
+    X = g.node_positions()
+    assert diffusive.energy(g, np.ones_like(u) * 3.0) == 0.0
+    a = (0.3, -0.2, 0.5)
+    lin = np.zeros_like(u)
+    lin[1] = a[0] * X[0] + a[1] * X[1] + a[2] * X[2]
+    edges = [(my[0] - 1) * my[1] * my[2], my[0] * (my[1] - 1) * my[2], my[0] * my[1] * (my[2] - 1)]
+    want = 0.5 * g.hybar * sum(a[k] ** 2 * edges[k] for k in range(3))
+    assert abs(diffusive.energy(g, lin) - want) <= 1e-12 * want
+    # the operator is minus the clamped 7-point Laplacian of the curvature term
+    np.testing.assert_allclose(diffusive.operator(g).toarray(), -curvature.laplacian(g).toarray(), atol=1e-12)
+
+
+def test_diffusive_gradient_fd_hessian_diag_and_node_outputs():
+    rng = np.random.default_rng(22)
+    my = (5, 4, 3)
+    g = Grid((8, 6, 4), (1.0, 1.3, 0.8), my, 1.0, 1.0, 0.5, regulariser="diffusive")
+    u = rng.standard_normal((3, my[2], my[1], my[0]))
+    grad = diffusive.gradient(g, u).ravel()
+    f = lambda uu: diffusive.energy(g, uu)
+    for j in range(grad.size):
+        d = np.zeros(grad.size)
+        d[j] = 1.0
+        fd = _fd_dir(f, u, d.reshape(u.shape))
+        assert abs(fd - grad[j]) <= 1e-6 * max(1.0, abs(fd)), j
+    p = rng.standard_normal(u.shape)
+    # quadratic: the Hessian product equals the gradient's directional derivative exactly
+    np.testing.assert_allclose(diffusive.hess_vec(g, p).ravel(), _fd_dir(lambda uu: diffusive.gradient(g, uu), u, p).ravel(),
+                               rtol=1e-7, atol=1e-9)
+    H = diffusive.hessian_matrix(g).toarray()
+    np.testing.assert_allclose(diffusive.hessian_diag(g)[0].ravel(), np.diag(H), rtol=1e-12)
+    gr, hv, dg = diffusive.gradient(g, u), diffusive.hess_vec(g, p), diffusive.hessian_diag(g)
+    for node in [0, g.nbar - 1, g.node_id(2, 1, 1), g.node_id(4, 0, 2)]:
+        gn, hn, dn = diffusive.node_outputs(g, u, p, node)
+        a, b, c = g.node_abc(node)
+        np.testing.assert_allclose(gn, gr[:, c, b, a], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(hn, hv[:, c, b, a], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dn, dg[:, c, b, a], rtol=1e-12, atol=1e-12)
+
+
+def test_problem_and_h0_use_the_diffusive_regulariser():
+    g, R, T, u, rng = tiny_problem(23, m=(8, 7, 6), my=(5, 4, 4))
+    gd = Grid(g.m, g.h, g.my, g.tau, g.rho, g.alpha, regulariser="diffusive")
+    prob = solver.Problem(gd, R, T)
+    Jv, D, S = prob.objective(u)
+    assert abs(S - diffusive.energy(gd, u)) <= 1e-12 * S and abs(Jv - (D + gd.alpha * S)) <= 1e-12 * abs(Jv)
+    h0 = lbfgs.H0Solver(gd, 0.3)
+    v = rng.standard_normal(u.shape)
+    np.testing.assert_allclose(h0.matvec(h0.apply(v)), v, rtol=1e-9, atol=1e-11)
+    A = gd.alpha * diffusive.hessian_matrix(gd).toarray() + 0.3 * np.eye(gd.nbar)
+    np.testing.assert_allclose(h0.apply(v)[0].ravel(), np.linalg.solve(A, v[0].ravel()), rtol=1e-9, atol=1e-11)
+    assert multilevel.coarse_grid(gd).regulariser == "diffusive"
