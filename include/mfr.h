@@ -47,6 +47,11 @@ extern "C" {
 
 #define MFR_ABI_VERSION 2
 
+/* Regularisers (mfr_grid.regulariser). */
+#define MFR_REG_CURVATURE 0   /* curvature, eq. CURV_discretized (the paper's)                  */
+#define MFR_REG_DIFFUSIVE 1   /* diffusive hbar^y/2 sum_d sum_edges ((u_m - u_n)/hy_k)^2 over
+                                 neighbouring nodes (Sec. 4.4); Hessian -hbar^y L               */
+
 /* Distance measures (mfr_grid.distance). */
 #define MFR_DIST_NGF 0   /* normalized gradient fields, eq. NGF_discretized (the paper's) */
 #define MFR_DIST_SSD 1   /* sum of squared differences hbar/2 sum_i (T(P y)_i - R_i)^2
@@ -74,6 +79,7 @@ typedef struct {
   double rho;       /* NGF edge parameter of the reference, > 0 (eq. ngf; ignored for SSD)   */
   double alpha;     /* curvature weight, >= 0 (eq. optimizationProblem)                       */
   int32_t distance; /* MFR_DIST_NGF (0) or MFR_DIST_SSD (1)                                   */
+  int32_t regulariser; /* MFR_REG_CURVATURE (0) or MFR_REG_DIFFUSIVE (1)                     */
 } mfr_grid;
 
 typedef struct mfr_ctx mfr_ctx;   /* opaque host-side context; owns no device memory */
@@ -100,7 +106,7 @@ mfr_status mfr_set_images(mfr_ctx* ctx, const float* R, const float* T);
 
 /* J = D + alpha S at displacement u (eq. discreteenergy).  D follows
  * eq. NGF_discretized_ri (SSD: hbar/2 sum_i r_i^2 with r = T(P y) - R),
- * S eq. CURV_discretized.  Any of J, D, S may be NULL.  Sums are accumulated
+ * S eq. CURV_discretized (diffusive: see MFR_REG_DIFFUSIVE).  Any of J, D, S may be NULL.  Sums are accumulated
  * in float64.  Synchronises the stream. */
 mfr_status mfr_objective(mfr_ctx* ctx, const float* u, double* J, double* D, double* S);
 
@@ -283,6 +289,7 @@ typedef struct {
  * with distance MFR_DIST_SSD is rejected (MFR_EINVAL) here and in
  * mfr_batch_create. */
 mfr_status mfr_batch_workspace_size(int32_t n, const mfr_grid* grids, int32_t levels, size_t* bytes);
+/* (The batched path also takes the curvature regulariser only.) */
 
 /* Create a batch bound to `hip_stream` and a caller-owned workspace. */
 mfr_status mfr_batch_create(int32_t n, const mfr_grid* grids, int32_t levels, void* hip_stream,

@@ -56,6 +56,10 @@ mfr_status make_geo(const mfr_grid* g, Geo* o) {
   if (g->distance != MFR_DIST_NGF && g->distance != MFR_DIST_SSD)
     return fail(MFR_EINVAL, "distance = %d: need MFR_DIST_NGF (0) or MFR_DIST_SSD (1)", (int)g->distance);
   o->dist = g->distance;
+  if (g->regulariser != MFR_REG_CURVATURE && g->regulariser != MFR_REG_DIFFUSIVE)
+    return fail(MFR_EINVAL, "regulariser = %d: need MFR_REG_CURVATURE (0) or MFR_REG_DIFFUSIVE (1)",
+                (int)g->regulariser);
+  o->reg = g->regulariser;
   if (o->dist == MFR_DIST_NGF &&
       (!(g->tau > 0) || !(g->rho > 0) || !std::isfinite(g->tau) || !std::isfinite(g->rho)))
     return fail(MFR_EINVAL, "tau and rho must be > 0");
@@ -366,6 +370,7 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   p.ihTz = (float)(1.0 / g.hT[2]);
   const bool ssd = g.dist == MFR_DIST_SSD;   // tau, rho unused (and unchecked) for SSD
   p.ssd = ssd ? 1 : 0;
+  p.reg = g.reg;
   p.tau2 = ssd ? 1.0f : (float)(g.tau * g.tau);
   p.rho2 = ssd ? 1.0f : (float)(g.rho * g.rho);
   p.taurho = ssd ? 1.0f : (float)(g.tau * g.rho);
@@ -396,7 +401,8 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   q.ihy2y = (float)(1.0 / (g.hy[1] * g.hy[1]));
   q.ihy2z = (float)(1.0 / (g.hy[2] * g.hy[2]));
   q.s_ngf = 0.0f;
-  q.s_curv = (float)(2.0 * g.alpha * g.hybar());
+  q.s_curv = (float)g.reg_scale();
+  q.reg = g.reg;
   q.tiles_x = t.tiles_x;
   q.tiles_y = t.tiles_y;
   q.nxt = t.nxt;
@@ -520,7 +526,7 @@ mfr_status read_objective(mfr_ctx* c, double* J, double* D, double* S) {
   HIP_TRY(hipMemcpyAsync(h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const double Dv = c->geo.hbar() * h[SC_D];
-  const double Sv = c->geo.hybar() * h[SC_S];
+  const double Sv = c->geo.s_value(h[SC_S]);
   const double Jv = Dv + c->geo.alpha * Sv;
   if (J) *J = Jv;
   if (D) *D = Dv;
@@ -979,6 +985,7 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
     g.rho = f.rho;
     g.alpha = f.alpha;
     g.distance = f.dist;
+    g.regulariser = f.reg;
     L[l].grid = g;
     MFR_TRY(make_geo(&g, &L[l].geo));
   }

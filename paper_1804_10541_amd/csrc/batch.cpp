@@ -58,6 +58,8 @@ mfr_status batch_layout(int n, const mfr_grid* grids, int levels, mfr_batch* b, 
   for (int k = 0; k < n; ++k) {
     if (grids[k].distance != MFR_DIST_NGF)
       return fail(MFR_EINVAL, "pair %d: the batched path evaluates the NGF distance only", k);
+    if (grids[k].regulariser != MFR_REG_CURVATURE)
+      return fail(MFR_EINVAL, "pair %d: the batched path evaluates the curvature regulariser only", k);
     size_t per = 0;
     MFR_TRY(ml_levels(&grids[k], levels, &b->lv[k], &per));
     size_t cb = 0;

@@ -36,6 +36,7 @@ struct Geo {
   double h[3], hT[3], hy[3];
   double tau, rho, alpha;
   int dist;   // MFR_DIST_NGF or MFR_DIST_SSD
+  int reg;    // MFR_REG_CURVATURE or MFR_REG_DIFFUSIVE
   size_t mbar, nbar;
   double hbar() const { return h[0] * h[1] * h[2]; }
   double hybar() const { return hy[0] * hy[1] * hy[2]; }
@@ -45,6 +46,12 @@ struct Geo {
   // psi = hbar/2 r^T r: grad = hbar J^T r, H = hbar J^T J.
   double grad_scale() const { return dist == MFR_DIST_SSD ? hbar() : -2.0 * hbar(); }
   double hess_scale() const { return dist == MFR_DIST_SSD ? hbar() : 2.0 * hbar(); }
+  // Regulariser: curvature S = hbar^y sum (L u)^2, grad = 2 alpha hbar^y L^T L u;
+  // diffusive S = hbar^y/2 sum of squared edge differences (= -hbar^y/2 u.L u),
+  // grad = -alpha hbar^y L u.  reg_scale() is the factor of the node pass's
+  // stencil term, s_value() the one of its sum.
+  double reg_scale() const { return reg == MFR_REG_DIFFUSIVE ? alpha * hybar() : 2.0 * alpha * hybar(); }
+  double s_value(double sum) const { return (reg == MFR_REG_DIFFUSIVE ? 0.5 : 1.0) * hybar() * sum; }
 };
 
 mfr_status make_geo(const mfr_grid* g, Geo* o);

@@ -110,7 +110,9 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
       const int i = BX.lo + tid % ncx, j = BY.lo + tid / ncx;
       const int cxn = (i > 0) + (i < P.nx - 1), cyn = (j > 0) + (j < P.ny - 1), czn = (K > 0) + (K < P.nz - 1);
       const float Lnn = -(cxn * J.ihy2x + cyn * J.ihy2y + czn * J.ihy2z);
-      const float LL = Lnn * Lnn + cxn * J.ihy2x * J.ihy2x + cyn * J.ihy2y * J.ihy2y + czn * J.ihy2z * J.ihy2z;
+      // curvature: (L^T L)_nn; diffusive: -L_nn
+      const float LL =
+          P.reg ? -Lnn : Lnn * Lnn + cxn * J.ihy2x * J.ihy2x + cyn * J.ihy2y * J.ihy2y + czn * J.ihy2z * J.ihy2z;
       const size_t n = (size_t)K * nxy + (size_t)j * P.nx + i;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {

@@ -1,6 +1,6 @@
 // L-BFGS on J = D + alpha S (Sec. 2.3.2) with the regulariser's Hessian in
-// the initial matrix, H_0 = alpha nabla^2 S + gamma I = 2 alpha hbar^y L^T L +
-// gamma I, solved exactly in the cosine basis of the Neumann Laplacian
+// the initial matrix, H_0 = alpha nabla^2 S + gamma I (2 alpha hbar^y L^T L +
+// gamma I for curvature, -alpha hbar^y L + gamma I for the diffusive one), solved exactly in the cosine basis of the Neumann Laplacian
 // (lbfgs_kernels.hip).  The host runs the two-loop recursion over device
 // vectors with float64 dot products, an Armijo line search from eta = 1, and
 // keeps a pair (s, y) only when s^T y > 1e-12 |s| |y|.  A direction that is
@@ -115,7 +115,11 @@ mfr_status dot(mfr_ctx* c, const float* a, const float* b, double* out) {
   return MFR_OK;
 }
 
-float h0_scale(const Geo& g) { return (float)(2.0 * g.alpha * g.hybar()); }
+// H_0 = c2 L^T L + c1 L + gamma I: (2 alpha hbar^y, 0) for curvature, (0, -alpha hbar^y) diffusive
+void h0_coeffs(const Geo& g, float* c2, float* c1) {
+  *c2 = g.reg == MFR_REG_DIFFUSIVE ? 0.0f : (float)(2.0 * g.alpha * g.hybar());
+  *c1 = g.reg == MFR_REG_DIFFUSIVE ? (float)(-g.alpha * g.hybar()) : 0.0f;
+}
 
 mfr_status lbfgs_run(mfr_ctx* c, float* u, const mfr_lbfgs_opts* o, char* work, const LbLayout& L,
                      mfr_lbfgs_report* rep) {
@@ -138,7 +142,9 @@ mfr_status lbfgs_run(mfr_ctx* c, float* u, const mfr_lbfgs_opts* o, char* work, 
   }
   std::vector<double> rho(slots, 0.0), a(slots, 0.0);
   std::vector<int> hist;   // slots of the stored pairs, oldest first
-  const float s_h0 = h0_scale(c->geo), gam = (float)o->gamma;
+  float c2 = 0.0f, c1 = 0.0f;
+  h0_coeffs(c->geo, &c2, &c1);
+  const float gam = (float)o->gamma;
 
   mfr_lbfgs_report R{};
   double J = 0.0;
@@ -156,7 +162,7 @@ mfr_status lbfgs_run(mfr_ctx* c, float* u, const mfr_lbfgs_opts* o, char* work, 
       a[k] = rho[k] * sq;
       HIP_TRY(launch_axpy(n3, d, (float)-a[k], Y[k], d, c->stream));
     }
-    HIP_TRY(launch_h0_solve(tab, d, d, ta, tb, s_h0, gam, c->stream));
+    HIP_TRY(launch_h0_solve(tab, d, d, ta, tb, c2, c1, gam, c->stream));
     for (int k : hist) {
       double yr = 0.0;
       MFR_TRY(dot(c, Y[k], d, &yr));
@@ -169,7 +175,7 @@ mfr_status lbfgs_run(mfr_ctx* c, float* u, const mfr_lbfgs_opts* o, char* work, 
       hist.clear();
       ++R.restarts;
       HIP_TRY(launch_axpy(n3, g, -2.0f, g, d, c->stream));
-      HIP_TRY(launch_h0_solve(tab, d, d, ta, tb, s_h0, gam, c->stream));
+      HIP_TRY(launch_h0_solve(tab, d, d, ta, tb, c2, c1, gam, c->stream));
       MFR_TRY(dot(c, g, d, &slope));
       if (!(slope < 0.0)) break;   // zero (or non-finite) gradient: nothing to do
     }
@@ -251,7 +257,9 @@ mfr_status mfr_h0_solve(mfr_ctx* c, double gamma, const float* v, float* x, void
   MFR_TRY(upload_tables(c, L, w, &tab));
   float* ta = reinterpret_cast<float*>(w + L.vec);
   float* tb = reinterpret_cast<float*>(w + L.vec + L.vbytes);
-  HIP_TRY(launch_h0_solve(tab, v, x, ta, tb, h0_scale(c->geo), (float)gamma, c->stream));
+  float c2 = 0.0f, c1 = 0.0f;
+  h0_coeffs(c->geo, &c2, &c1);
+  HIP_TRY(launch_h0_solve(tab, v, x, ta, tb, c2, c1, (float)gamma, c->stream));
   return MFR_OK;
 }
 

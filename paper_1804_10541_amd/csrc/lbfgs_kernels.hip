@@ -1,11 +1,13 @@
 // Kernels of the L-BFGS initial-matrix solve (Sec. 2.3.2):
-// x = H_0^{-1} v with H_0 = 2 alpha hbar^y L^T L + gamma I.
+// x = H_0^{-1} v with H_0 = 2 alpha hbar^y L^T L + gamma I (curvature) or
+// -alpha hbar^y L + gamma I (diffusive regulariser).
 //
 // The 7-point Laplacian with clamped (Neumann) neighbours is the Kronecker sum
 // of one-dimensional second-difference matrices whose eigenvectors are the
 // DCT-II cosines, so H_0 is diagonal in the separable cosine basis: the solve
 // is a forward transform along z, y and x, a division by the eigenvalues
-// 2 alpha hbar^y (lx + ly + lz)^2 + gamma, and the inverse transform.  Each
+// 2 alpha hbar^y (lx + ly + lz)^2 + gamma (curvature) or
+// -alpha hbar^y (lx + ly + lz) + gamma (diffusive), and the inverse transform.  Each
 // axis transform is a small dense product (the n x n cosine matrix against
 // all lines of that axis), done here as an LDS-tiled float32 product.
 #include "mfr_internal.h"
@@ -75,9 +77,9 @@ __global__ __launch_bounds__(256) void axis_transform_kernel(const float* __rest
   }
 }
 
-// x = v / (s (lx[i] + ly[j] + lz[k])^2 + gamma) in the cosine basis.
+// x = v / (c2 l^2 + c1 l + gamma), l = lx[i] + ly[j] + lz[k], in the cosine basis.
 __global__ __launch_bounds__(256) void h0_scale_kernel(float* __restrict__ x, const float* __restrict__ lam, int nx,
-                                                       int ny, int nz, float s, float gamma) {
+                                                       int ny, int nz, float c2, float c1, float gamma) {
   const size_t nb = (size_t)nx * ny * nz, total = 3 * nb;
   const float* lx = lam;
   const float* ly = lam + nx;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(256) void h0_scale_kernel(float* __restrict__ x, co
     const size_t n = idx % nb;
     const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / ((size_t)nx * ny));
     const float l = lx[i] + ly[j] + lz[k];
-    x[idx] = x[idx] / fmaf(s * l, l, gamma);
+    x[idx] = x[idx] / fmaf(fmaf(c2, l, c1), l, gamma);
   }
 }
 
@@ -105,8 +107,8 @@ hipError_t transform(const float* M, int n, const float* in, float* out, long lo
 // x = H_0^{-1} v.  tab: the cosine matrices and their transposes (x, y, z)
 // followed by the per-axis Laplacian eigenvalues; ta, tb: scratch node vectors.
 // x may alias v.
-hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* ta, float* tb, float s, float gamma,
-                           hipStream_t st) {
+hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* ta, float* tb, float c2, float c1,
+                           float gamma, hipStream_t st) {
   const int nx = t.n[0], ny = t.n[1], nz = t.n[2];
   const long long nxy = (long long)nx * ny, nb = nxy * nz;
   hipError_t e;
@@ -115,7 +117,7 @@ hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* t
   if ((e = transform(t.C[1], ny, ta, tb, nxy, nx, 1, nx, 3 * nz, false, st)) != hipSuccess) return e;
   if ((e = transform(t.C[0], nx, tb, ta, 0, 1, nx, (int)(3 * nz * ny), 1, true, st)) != hipSuccess) return e;
   const int blocks = (int)std::min<long long>((3 * nb + 255) / 256, 8192);
-  hipLaunchKernelGGL(h0_scale_kernel, dim3(blocks), dim3(256), 0, st, ta, t.lam, nx, ny, nz, s, gamma);
+  hipLaunchKernelGGL(h0_scale_kernel, dim3(blocks), dim3(256), 0, st, ta, t.lam, nx, ny, nz, c2, c1, gamma);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // inverse: the transposed matrices in reverse order
   if ((e = transform(t.Ct[0], nx, ta, tb, 0, 1, nx, (int)(3 * nz * ny), 1, true, st)) != hipSuccess) return e;

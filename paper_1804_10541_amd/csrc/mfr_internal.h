@@ -84,6 +84,7 @@ struct TileParams {
   double* red;            // one float64 partial per work-group
   const int* live;        // single-problem launches: skip all work while *live == 0 (nullable)
   int ssd;                // distance: 0 NGF, 1 sum of squared differences (dr/dT = identity)
+  int reg;                // regulariser: 0 curvature, 1 diffusive (for the diagonal kernels)
 };
 
 // Parameters of the node pass.
@@ -91,7 +92,8 @@ struct NodeParams {
   int nx, ny, nz, nbar;
   float ihy2x, ihy2y, ihy2z;  // 1 / hy^2
   float s_ngf;                // scale of the gathered voxel contributions (+-2 hbar)
-  float s_curv;               // 2 alpha hbar^y
+  float s_curv;               // 2 alpha hbar^y (curvature) or alpha hbar^y (diffusive)
+  int reg;                    // 0 curvature (L L f), 1 diffusive (-L f)
   int tiles_x, tiles_y;
   int nxt, nyt, nzt;
   const float* part;
@@ -113,7 +115,7 @@ struct DiagParams {
   const Range1* ry;
   const Range1* rz;
   float s_ngf;        // 2 hbar
-  float s_curv;       // 2 alpha hbar^y
+  float s_curv;       // regulariser scale (2 alpha hbar^y curvature, alpha hbar^y diffusive)
   float ihy2x, ihy2y, ihy2z;
 };
 
@@ -133,7 +135,7 @@ struct JacParams {
   const Range1* rx;   // per node index: voxel rows whose dr row touches the node's support
   const Range1* ry;
   float s_ngf;        // 2 hbar
-  float s_curv;       // 2 alpha hbar^y
+  float s_curv;       // regulariser scale (2 alpha hbar^y curvature, alpha hbar^y diffusive)
   float ihy2x, ihy2y, ihy2z;
 };
 
@@ -248,10 +250,11 @@ struct H0Tables {
   const float* Ct[3];
   const float* lam;
 };
-// x = (s (L^T L) + gamma I)^{-1} v per component; ta, tb: scratch node vectors
-// (x may alias v, not ta or tb).
-hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* ta, float* tb, float s, float gamma,
-                           hipStream_t st);
+// x = (c2 L^T L + c1 L + gamma I)^{-1} v per component (L diagonal in the cosine
+// basis with eigenvalue lx + ly + lz); ta, tb: scratch node vectors (x may
+// alias v, not ta or tb).
+hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* ta, float* tb, float c2, float c1,
+                           float gamma, hipStream_t st);
 
 // PCG vector kernels.  sc: device scalars (see PcgSlot).
 enum PcgSlot : int {

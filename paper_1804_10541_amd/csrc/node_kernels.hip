@@ -46,6 +46,19 @@ __device__ __forceinline__ float lap7(const float* __restrict__ f, int i, int j,
   return fmaf(fxm + fxp + m2, ix2, fmaf(fym + fyp + m2, iy2, (fzm + fzp + m2) * iz2));
 }
 
+// Squared forward differences at node (i, j, k), sum_k ((f_{n+e_k} - f_n)/hy_k)^2
+// (none past the last node: the clamped neighbour gives 0).  The diffusive
+// regulariser's value is the sum of these over the nodes; summing f . (-L f)
+// instead would cancel large terms whenever f has a large mean.
+__device__ __forceinline__ float fwd_sq(const float* __restrict__ f, int i, int j, int k, int nx, int ny, int nz,
+                                        float ix2, float iy2, float iz2) {
+  const int nxy = nx * ny;
+  const int c = i + nx * j + nxy * k;
+  const float f0 = f[c];
+  const float dx = f[c + (i < nx - 1)] - f0, dy = f[c + nx * (j < ny - 1)] - f0, dz = f[c + nxy * (k < nz - 1)] - f0;
+  return fmaf(dx * dx, ix2, fmaf(dy * dy, iy2, dz * dz * iz2));
+}
+
 }  // namespace
 
 // The curvature part runs in two passes over the nodes: the first stores the
@@ -68,7 +81,10 @@ __device__ __forceinline__ void lap_body(const NodeParams& Q, const float* __res
     for (int d = 0; d < 3; ++d) {
       const float L0 = lap7(f + (size_t)d * Q.nbar, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z);
       Q.lap[(size_t)d * Q.nbar + n] = L0;
-      if (MODE == NP_S) local += (double)L0 * (double)L0;
+      // curvature: sum (L f)^2; diffusive: the squared edge differences
+      if (MODE == NP_S)
+        local += Q.reg ? (double)fwd_sq(f + (size_t)d * Q.nbar, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z)
+                       : (double)L0 * (double)L0;
     }
   }
   if (MODE == NP_S) {
@@ -100,7 +116,8 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     const float Lzm = k > 0 ? Ld[n - nxy] : L0;
     const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
     const float m2 = -2.0f * L0;
-    const float LL = fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
+    // curvature: L L f; diffusive: -L f (its Hessian is -hbar^y L)
+    const float LL = Q.reg ? -L0 : fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
     // gather of the transposed conversion: every tile slot overlapping node n
     const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
     float s = 0.0f;
@@ -117,7 +134,8 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     }
     const float q = fmaf(Q.s_ngf, s, Q.s_curv * LL);
     out[(size_t)d * Q.nbar + n] = q;
-    if (MODE == NP_GRAD) local = (double)L0 * (double)L0;
+    if (MODE == NP_GRAD)
+      local = Q.reg ? (double)fwd_sq(fd, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : (double)L0 * (double)L0;
     if (MODE == NP_HV) local = (double)fd[n] * (double)q;
   }
   const double s = block_sum<kNodeBlock>(local, sred);
@@ -366,7 +384,8 @@ __global__ __launch_bounds__(kNodeBlock) void jacobi_diag_kernel(const DiagParam
   // curvature part: (L^T L)_{nn} = (L_nn)^2 + sum over in-range neighbours 1/hy_k^4
   const int cxn = (ni > 0) + (ni < P.nx - 1), cyn = (nj > 0) + (nj < P.ny - 1), czn = (nk > 0) + (nk < P.nz - 1);
   const float Lnn = -(cxn * D.ihy2x + cyn * D.ihy2y + czn * D.ihy2z);
-  const float LL = Lnn * Lnn + cxn * D.ihy2x * D.ihy2x + cyn * D.ihy2y * D.ihy2y + czn * D.ihy2z * D.ihy2z;
+  // curvature: (L^T L)_nn; diffusive: -L_nn
+  const float LL = P.reg ? -Lnn : Lnn * Lnn + cxn * D.ihy2x * D.ihy2x + cyn * D.ihy2y * D.ihy2y + czn * D.ihy2z * D.ihy2z;
 #pragma unroll
   for (int d = 0; d < 3; ++d) diag[(size_t)d * P.nbar + n] = fmaf(D.s_ngf, acc[d], D.s_curv * LL);
 }

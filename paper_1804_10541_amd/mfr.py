@@ -31,7 +31,7 @@ class CGrid(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("my", ctypes.c_int32 * 3),
                 ("mT", ctypes.c_int32 * 3), ("hT", ctypes.c_double * 3),
                 ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("distance", ctypes.c_int32)]
+                ("distance", ctypes.c_int32), ("regulariser", ctypes.c_int32)]
 
 
 class CPcgOpts(ctypes.Structure):
@@ -182,11 +182,12 @@ def _check(status):
 
 
 DISTANCES = {"ngf": 0, "ssd": 1}   # mfr_grid.distance
+REGULARISERS = {"curvature": 0, "diffusive": 1}   # mfr_grid.regulariser
 
 
 def make_grid(spec):
     """CGrid from any object with m, h, my, tau, rho, alpha (optional mT, hT,
-    distance "ngf" or "ssd")."""
+    distance "ngf" or "ssd", regulariser "curvature" or "diffusive")."""
     g = CGrid()
     for k in range(3):
         g.m[k] = int(spec.m[k])
@@ -201,6 +202,10 @@ def make_grid(spec):
     if dist not in DISTANCES:
         raise ValueError(f"distance must be one of {sorted(DISTANCES)}, got {dist!r}")
     g.distance = DISTANCES[dist]
+    reg = getattr(spec, "regulariser", "curvature")
+    if reg not in REGULARISERS:
+        raise ValueError(f"regulariser must be one of {sorted(REGULARISERS)}, got {reg!r}")
+    g.regulariser = REGULARISERS[reg]
     return g
 
 

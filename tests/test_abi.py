@@ -99,6 +99,16 @@ def test_distance_field_validation(lib):
                                                     alpha=1)), mfr.make_grid(ssd))
     assert lib.mfr_batch_workspace_size(2, grids, 1, ctypes.byref(n)) == -1
     assert b"NGF" in lib.mfr_last_error()
+    # regulariser codes: diffusive accepted, unknown rejected, diffusive not batched
+    dif = GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1, alpha=1.0, regulariser="diffusive")
+    assert _ws(dif) > 0
+    g2 = mfr.make_grid(dif)
+    g2.regulariser = 5
+    assert lib.mfr_workspace_size(ctypes.byref(g2), ctypes.byref(n)) == -1
+    assert b"regulariser" in lib.mfr_last_error()
+    grids = (mfr.CGrid * 1)(mfr.make_grid(dif))
+    assert lib.mfr_batch_workspace_size(1, grids, 1, ctypes.byref(n)) == -1
+    assert b"curvature" in lib.mfr_last_error()
 
 
 def test_lbfgs_workspace_validation(lib):

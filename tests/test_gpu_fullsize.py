@@ -4,14 +4,15 @@
 product and the Jacobi diagonal computed on the GPU over the whole grid are
 compared at sampled nodes (corners, faces, tile and z-chunk borders, random
 interior nodes) with the oracle's exact single-node evaluation, which builds
-only the Jacobian rows and curvature rows that touch each node.  Both
-distance measures: NGF (the bench's) and the sum of squared differences."""
+only the Jacobian rows and regulariser rows that touch each node.  Cases: NGF with
+curvature (the bench's), the sum of squared differences with curvature, and NGF with
+the diffusive regulariser."""
 import numpy as np
 import pytest
 import torch
 
 from gpu_cases import rel_l2
-from oracle import Grid, curvature, ngf, ssd
+from oracle import Grid, curvature, diffusive, ngf, ssd
 from paper_1804_10541_amd import mfr
 from synth import GridSpec, ct_pair, smooth_field
 
@@ -29,12 +30,14 @@ def sample_nodes(grid, rng, n_random=12):
     return [int(grid.node_id(a, b, c)) for a, b, c in picks]
 
 
-@pytest.mark.parametrize("distance", ["ngf", "ssd"])
-def test_bench_workload_sampled_nodes(distance):
-    print(f"[gpu-case] {distance} 512x512x900 / 129x129x225, tile 32x16 target 4096, seed 0", flush=True)
+@pytest.mark.parametrize("distance,regulariser", [("ngf", "curvature"), ("ssd", "curvature"), ("ngf", "diffusive")])
+def test_bench_workload_sampled_nodes(distance, regulariser):
+    print(f"[gpu-case] {distance} {regulariser} 512x512x900 / 129x129x225, tile 32x16 target 4096, seed 0", flush=True)
     m, my = (512, 512, 900), (129, 129, 225)
-    spec = GridSpec(m=m, h=(1.0, 1.0, 1.0), my=my, tau=50.0, rho=50.0, alpha=0.1, distance=distance)
+    spec = GridSpec(m=m, h=(1.0, 1.0, 1.0), my=my, tau=50.0, rho=50.0, alpha=0.1, distance=distance,
+                    regulariser=regulariser)
     dist = ssd if distance == "ssd" else ngf
+    reg = diffusive if regulariser == "diffusive" else curvature
     R, T, _, rng = ct_pair(0, m, device=DEV)
     u = torch.from_numpy(smooth_field(rng, my, 0.5).astype("float32")).to(DEV)
     gen = torch.Generator(device=DEV).manual_seed(11)
@@ -63,7 +66,7 @@ def test_bench_workload_sampled_nodes(distance):
     og, oh, od = [], [], []
     for node in nodes:
         gD, hD, dD = dist.node_outputs(grid, R64, T64, u64, p64, node)
-        gS, hS, dS = curvature.node_outputs(grid, u64, p64, node)
+        gS, hS, dS = reg.node_outputs(grid, u64, p64, node)
         og.append(gD + grid.alpha * gS)
         oh.append(hD + grid.alpha * hS)
         od.append(dD + grid.alpha * dS)
