@@ -179,6 +179,42 @@ def ssd_leg(dev, spec, R, T, u0, reps=20):
     return out
 
 
+def diffusive_leg(dev, spec, R, T, u0, steps=2):
+    """Gauss-Newton steps with the diffusive regulariser on the headline pair and
+    start (same step as the headline: 20 Jacobi-PCG iterations, rtol 0), with the
+    node-pass and Jacobi-diagonal kernel times (events on the context's stream)."""
+    import dataclasses
+
+    import torch
+
+    from paper_1804_10541_amd import mfr
+
+    s = dataclasses.replace(spec, regulariser="diffusive")
+    ctx = mfr.Context(s, dev)
+    ctx.set_images(R, T)
+    u = u0.clone()
+    gn = dict(pcg_max=HV_PER_STEP, pcg_rtol=0.0, precond=1, armijo_c1=1e-4, armijo_max=10)
+    ctx.gn_step(u, **gn)   # warm-up
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    infos = [ctx.gn_step(u, **gn) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    ctx.close()
+    avg = lambda k: round(prof[k][1] / max(prof[k][0], 1), 4)
+    n_hv = sum(i["pcg_iters"] for i in infos)
+    out = {"workload": "the headline Gauss-Newton step with the diffusive regulariser",
+           "ms_per_step": round(dt * 1e3 / steps, 3), "gvoxel_s": round(s.voxels * n_hv / dt / 1e9, 3),
+           "J": [round(i["J_after"], 1) for i in infos],
+           "tile_hv_ms": avg("tile_hv"), "node_pass_ms": avg("node_pass"), "jacobi_diag_ms": avg("jacobi_diag")}
+    log(f"[bench] diffusive: {out}")
+    return out
+
+
 def lbfgs_leg(dev, spec, R, T, u0, iters=3, gamma=100.0):
     """L-BFGS iterations (two-loop recursion, H_0 = alpha nabla^2 S + gamma I
     solved in the cosine basis, Armijo steps) on the headline pair from the same
@@ -293,6 +329,7 @@ def main():
     ap.add_argument("--no-pc", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--no-ssd", action="store_true", help="skip the sum-of-squared-differences leg")
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS leg")
+    ap.add_argument("--no-diffusive", action="store_true", help="skip the diffusive-regulariser leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -409,6 +446,9 @@ def main():
     if not args.no_lbfgs:
         log("[bench] L-BFGS")
         out["lbfgs"] = lbfgs_leg(dev, spec, R, T, u0)
+    if not args.no_diffusive:
+        log("[bench] diffusive regulariser")
+        out["diffusive"] = diffusive_leg(dev, spec, R, T, u0)
     del R, T
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
