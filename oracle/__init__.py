@@ -16,7 +16,8 @@ the HIP path: no kernels, no tables, no per-voxel recipe (the rho-hat
 formulation of Sec. 4 is what the GPU computes; the oracle never uses it).
 ``ssd`` holds the same derivatives for the sum-of-squared-differences
 distance (Sec. 4.4: the residual Jacobian becomes the identity).
-``diffusive`` is the diffusive regulariser (Sec. 4.4), an alternative to curvature.
+``diffusive`` and ``elastic`` are the diffusive and linear-elastic regularisers (Sec. 4.4),
+alternatives to curvature.
 ``lbfgs`` is the limited-memory BFGS alternative of Sec. 2.3.2 with the
 regulariser's Hessian in the initial matrix.
 ``cnn`` defines the learned preconditioner, an extension of the method
@@ -24,4 +25,4 @@ regulariser's Hessian in the initial matrix.
 that uses it.
 """
 from .grid import Grid  # noqa: F401
-from . import interp, ngf, ssd, curvature, diffusive, solver, multilevel, lbfgs, cnn  # noqa: F401
+from . import interp, ngf, ssd, curvature, diffusive, elastic, solver, multilevel, lbfgs, cnn  # noqa: F401

@@ -24,9 +24,11 @@ class Grid:
     template grid (``mT`` cells, spacing ``hT``; default = image grid), the
     model parameters tau, rho (NGF) and alpha (curvature weight), and the
     distance measure: "ngf" (the paper's) or "ssd" (Sec. 4.4), and the
-    regulariser: "curvature" (the paper's) or "diffusive" (Sec. 4.4)."""
+    regulariser: "curvature" (the paper's), "diffusive" or "elastic" (Sec. 4.4;
+    elastic with the Lame parameters lame_mu, lame_lambda)."""
 
-    def __init__(self, m, h, my, tau, rho, alpha, mT=None, hT=None, distance="ngf", regulariser="curvature"):
+    def __init__(self, m, h, my, tau, rho, alpha, mT=None, hT=None, distance="ngf", regulariser="curvature",
+                 lame_mu=1.0, lame_lambda=0.0):
         self.m = tuple(int(k) for k in m)
         self.h = tuple(float(k) for k in h)
         self.my = tuple(int(k) for k in my)
@@ -36,9 +38,10 @@ class Grid:
         if distance not in ("ngf", "ssd"):
             raise ValueError("distance must be 'ngf' or 'ssd'")
         self.distance = distance
-        if regulariser not in ("curvature", "diffusive"):
-            raise ValueError("regulariser must be 'curvature' or 'diffusive'")
+        if regulariser not in ("curvature", "diffusive", "elastic"):
+            raise ValueError("regulariser must be 'curvature', 'diffusive' or 'elastic'")
         self.regulariser = regulariser
+        self.lame_mu, self.lame_lambda = float(lame_mu), float(lame_lambda)
         for k in range(3):
             if not (2 <= self.my[k] and self.my[k] - 1 <= self.m[k]):
                 raise ValueError("need 2 <= my <= m + 1 in every dimension")
@@ -47,7 +50,8 @@ class Grid:
     def from_spec(cls, spec):
         return cls(spec.m, spec.h, spec.my, spec.tau, spec.rho, spec.alpha,
                    getattr(spec, "mT", None), getattr(spec, "hT", None),
-                   getattr(spec, "distance", "ngf"), getattr(spec, "regulariser", "curvature"))
+                   getattr(spec, "distance", "ngf"), getattr(spec, "regulariser", "curvature"),
+                   getattr(spec, "lame_mu", 1.0), getattr(spec, "lame_lambda", 0.0))
 
     # sizes -----------------------------------------------------------------
     @property

@@ -37,6 +37,8 @@ class H0Solver:
         if not gamma > 0:
             raise ValueError("gamma must be > 0")
         self.grid = grid
+        if getattr(grid, "regulariser", "curvature") == "elastic":
+            raise ValueError("the elastic regulariser's Hessian couples the components; no H_0 solve here")
         if getattr(grid, "regulariser", "curvature") == "diffusive":
             H = diffusive.hessian_matrix(grid)
         else:

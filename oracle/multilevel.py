@@ -39,7 +39,7 @@ def coarse_grid(g):
     my = tuple(int(math.ceil((k - 1) / 2)) + 1 for k in g.my)
     mT = tuple((k + 1) // 2 for k in g.mT)
     hT = tuple(2.0 * k for k in g.hT)
-    return Grid(m, h, my, g.tau, g.rho, g.alpha, mT, hT, g.distance, g.regulariser)
+    return Grid(m, h, my, g.tau, g.rho, g.alpha, mT, hT, g.distance, g.regulariser, g.lame_mu, g.lame_lambda)
 
 
 def _interp_matrix_1d(n_f, hy_f, n_c, hy_c):

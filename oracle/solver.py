@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import curvature, diffusive, ngf, ssd
+from . import curvature, diffusive, elastic, ngf, ssd
 
 
 class Problem:
@@ -30,8 +30,13 @@ class Problem:
         self.grid = grid
         self.R = np.asarray(R, dtype=np.float64)
         self.T = np.asarray(T, dtype=np.float64)
-        self.reg = diffusive if grid.regulariser == "diffusive" else curvature
-        self.L = curvature.laplacian(grid) if self.reg is curvature else diffusive.operator(grid)
+        self.reg = {"diffusive": diffusive, "elastic": elastic}.get(grid.regulariser, curvature)
+        if self.reg is curvature:
+            self.L = curvature.laplacian(grid)
+        elif self.reg is diffusive:
+            self.L = diffusive.operator(grid)
+        else:
+            self.L = elastic.hessian_matrix(grid)
         self.dist = ssd if grid.distance == "ssd" else ngf
 
     def objective(self, u):

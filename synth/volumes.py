@@ -37,7 +37,9 @@ class GridSpec:
     mT: tuple = None    # template cells (default: m)
     hT: tuple = None    # template spacing (default: h)
     distance: str = "ngf"   # distance measure: "ngf" or "ssd"
-    regulariser: str = "curvature"   # "curvature" or "diffusive"
+    regulariser: str = "curvature"   # "curvature", "diffusive" or "elastic"
+    lame_mu: float = 1.0            # elastic regulariser: Lame parameters
+    lame_lambda: float = 0.0
 
     def template_cells(self):
         return tuple(self.mT) if self.mT is not None else tuple(self.m)

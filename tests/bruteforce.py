@@ -132,3 +132,26 @@ def diffusive_S(my, hy, u):
                             diff = (u[d][c][b][a] - u[d][k][j][i]) / h
                             S += 0.5 * hyb * diff * diff
     return S
+
+
+def elastic_S(my, hy, u, mu, lam):
+    """mu * diffusive_S + hbar^y/2 (lam + mu) sum over cells of the divergence squared, the
+    divergence per cell being sum_d (mean of its four edge differences along d) / hy_d."""
+    nx, ny, nz = my
+    hyb = hy[0] * hy[1] * hy[2]
+    S = mu * diffusive_S(my, hy, u)
+    for k in range(nz - 1):
+        for j in range(ny - 1):
+            for i in range(nx - 1):
+                div = 0.0
+                for d in range(3):
+                    tot = 0.0
+                    for oz in (0, 1):
+                        for oy in (0, 1):
+                            for ox in (0, 1):
+                                off = (ox, oy, oz)
+                                sgn = 1.0 if off[d] else -1.0
+                                tot += sgn * u[d][k + oz][j + oy][i + ox]
+                    div += tot / (4.0 * hy[d])
+                S += 0.5 * hyb * (lam + mu) * div * div
+    return S

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import bruteforce
-from oracle import Grid, curvature, diffusive, interp, lbfgs, multilevel, ngf, solver, ssd
+from oracle import Grid, curvature, diffusive, elastic, interp, lbfgs, multilevel, ngf, solver, ssd
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -742,3 +742,45 @@ def test_problem_and_h0_use_the_diffusive_regulariser():
     A = gd.alpha * diffusive.hessian_matrix(gd).toarray() + 0.3 * np.eye(gd.nbar)
     np.testing.assert_allclose(h0.apply(v)[0].ravel(), np.linalg.solve(A, v[0].ravel()), rtol=1e-9, atol=1e-11)
     assert multilevel.coarse_grid(gd).regulariser == "diffusive"
+
+
+# ---------------------------------------------------------------------------
+# Linear-elastic regulariser (Sec. 4.4)
+# ---------------------------------------------------------------------------
+
+def test_elastic_energy_bruteforce_divergence_of_linear_fields_and_limits():
+    rng = np.random.default_rng(31)
+    my, h = (4, 3, 5), (1.0, 1.2, 0.9)
+    g = Grid(tuple(2 * (n - 1) for n in my), h, my, 1.0, 1.0, 0.7, regulariser="elastic", lame_mu=0.8,
+             lame_lambda=1.7)
+    u = rng.standard_normal((3, my[2], my[1], my[0]))
+    ref = bruteforce.elastic_S(g.my, g.hy, u.tolist(), 0.8, 1.7)
+    assert abs(elastic.energy(g, u) - ref) <= 1e-12 * abs(ref)
+    # the cell divergence of a linear field A x is trace(A) in every cell
+    A = rng.standard_normal((3, 3))
+    X = g.node_positions()
+    lin = np.stack([sum(A[d, k] * X[k] for k in range(3)) for d in range(3)])
+    div = elastic.divergence(g) @ lin.ravel()
+    np.testing.assert_allclose(div, np.trace(A), rtol=1e-12, atol=1e-12)
+    # lambda = -mu leaves mu times the diffusive energy; constants cost nothing
+    g2 = Grid(g.m, g.h, g.my, 1.0, 1.0, 0.7, regulariser="elastic", lame_mu=0.8, lame_lambda=-0.8)
+    assert abs(elastic.energy(g2, u) - 0.8 * diffusive.energy(g2, u)) <= 1e-12 * elastic.energy(g2, u)
+    assert elastic.energy(g, np.full_like(u, 2.0)) == 0.0
+
+
+def test_elastic_gradient_fd_hessian_symmetric_psd_and_diagonal():
+    rng = np.random.default_rng(32)
+    my = (4, 4, 3)
+    g = Grid((6, 6, 4), (1.0, 1.3, 0.8), my, 1.0, 1.0, 0.5, regulariser="elastic", lame_mu=1.3, lame_lambda=0.6)
+    u = rng.standard_normal((3, my[2], my[1], my[0]))
+    grad = elastic.gradient(g, u)
+    for _ in range(4):
+        d = rng.standard_normal(u.shape)
+        fd = _fd_dir(lambda uu: elastic.energy(g, uu), u, d)
+        assert abs(fd - float(np.sum(grad * d))) <= 1e-6 * max(1.0, abs(fd))
+    H = elastic.hessian_matrix(g).toarray()
+    np.testing.assert_allclose(H, H.T, atol=1e-12 * np.abs(H).max())
+    assert np.linalg.eigvalsh(H).min() > -1e-10 * np.abs(H).max()
+    np.testing.assert_allclose(elastic.hessian_diag(g).ravel(), np.diag(H), rtol=1e-12)
+    prob = solver.Problem(g, np.zeros((4, 6, 6)), np.zeros((4, 6, 6)))
+    assert abs(prob.objective(u)[2] - elastic.energy(g, u)) <= 1e-12 * elastic.energy(g, u)
