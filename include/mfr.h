@@ -51,6 +51,10 @@ extern "C" {
 #define MFR_REG_CURVATURE 0   /* curvature, eq. CURV_discretized (the paper's)                  */
 #define MFR_REG_DIFFUSIVE 1   /* diffusive hbar^y/2 sum_d sum_edges ((u_m - u_n)/hy_k)^2 over
                                  neighbouring nodes (Sec. 4.4); Hessian -hbar^y L               */
+#define MFR_REG_ELASTIC 2     /* linear elastic (Sec. 4.4): lame_mu times the diffusive term plus
+                                 hbar^y/2 (lame_lambda + lame_mu) sum_cells (div u)^2, the
+                                 divergence per cell of the nodal grid being sum_d of the mean
+                                 of its four edge differences along d over hy_d                 */
 
 /* Distance measures (mfr_grid.distance). */
 #define MFR_DIST_NGF 0   /* normalized gradient fields, eq. NGF_discretized (the paper's) */
@@ -79,7 +83,9 @@ typedef struct {
   double rho;       /* NGF edge parameter of the reference, > 0 (eq. ngf; ignored for SSD)   */
   double alpha;     /* curvature weight, >= 0 (eq. optimizationProblem)                       */
   int32_t distance; /* MFR_DIST_NGF (0) or MFR_DIST_SSD (1)                                   */
-  int32_t regulariser; /* MFR_REG_CURVATURE (0) or MFR_REG_DIFFUSIVE (1)                     */
+  int32_t regulariser; /* MFR_REG_CURVATURE (0), MFR_REG_DIFFUSIVE (1) or MFR_REG_ELASTIC (2)  */
+  double lame_mu;      /* elastic only: > 0                                                  */
+  double lame_lambda;  /* elastic only: lame_lambda + lame_mu >= 0                           */
 } mfr_grid;
 
 typedef struct mfr_ctx mfr_ctx;   /* opaque host-side context; owns no device memory */

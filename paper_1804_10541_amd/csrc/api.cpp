@@ -56,10 +56,16 @@ mfr_status make_geo(const mfr_grid* g, Geo* o) {
   if (g->distance != MFR_DIST_NGF && g->distance != MFR_DIST_SSD)
     return fail(MFR_EINVAL, "distance = %d: need MFR_DIST_NGF (0) or MFR_DIST_SSD (1)", (int)g->distance);
   o->dist = g->distance;
-  if (g->regulariser != MFR_REG_CURVATURE && g->regulariser != MFR_REG_DIFFUSIVE)
-    return fail(MFR_EINVAL, "regulariser = %d: need MFR_REG_CURVATURE (0) or MFR_REG_DIFFUSIVE (1)",
+  if (g->regulariser != MFR_REG_CURVATURE && g->regulariser != MFR_REG_DIFFUSIVE && g->regulariser != MFR_REG_ELASTIC)
+    return fail(MFR_EINVAL, "regulariser = %d: need MFR_REG_CURVATURE (0), MFR_REG_DIFFUSIVE (1) or MFR_REG_ELASTIC (2)",
                 (int)g->regulariser);
   o->reg = g->regulariser;
+  o->lame_mu = g->lame_mu;
+  o->lame_lambda = g->lame_lambda;
+  if (o->reg == MFR_REG_ELASTIC &&
+      (!(g->lame_mu > 0) || !std::isfinite(g->lame_mu) || !std::isfinite(g->lame_lambda) ||
+       !(g->lame_lambda + g->lame_mu >= 0)))
+    return fail(MFR_EINVAL, "elastic regulariser: need lame_mu > 0 and lame_lambda + lame_mu >= 0");
   if (o->dist == MFR_DIST_NGF &&
       (!(g->tau > 0) || !(g->rho > 0) || !std::isfinite(g->tau) || !std::isfinite(g->rho)))
     return fail(MFR_EINVAL, "tau and rho must be > 0");
@@ -252,6 +258,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.sc = take(sizeof(double) * SC_COUNT);
   L.vec = take(sizeof(float) * 3 * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
   L.lap = take(sizeof(float) * 3 * g.nbar);       // curvature Laplacian (node pass, first half)
+  L.div = take(sizeof(float) * g.nbar);           // elastic: divergence per cell of the nodal grid
   L.ctrl = take(sizeof(int) * (1 + ST_COUNT));    // device-steered CG: active flag, state
   L.total = o;
   return L;
@@ -371,6 +378,7 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   const bool ssd = g.dist == MFR_DIST_SSD;   // tau, rho unused (and unchecked) for SSD
   p.ssd = ssd ? 1 : 0;
   p.reg = g.reg;
+  p.kappa = (float)g.kappa();
   p.tau2 = ssd ? 1.0f : (float)(g.tau * g.tau);
   p.rho2 = ssd ? 1.0f : (float)(g.rho * g.rho);
   p.taurho = ssd ? 1.0f : (float)(g.tau * g.rho);
@@ -403,6 +411,8 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   q.s_ngf = 0.0f;
   q.s_curv = (float)g.reg_scale();
   q.reg = g.reg;
+  q.kappa = (float)g.kappa();
+  q.div = at<float>(c->ws, L.div);
   q.tiles_x = t.tiles_x;
   q.tiles_y = t.tiles_y;
   q.nxt = t.nxt;
@@ -986,6 +996,8 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
     g.alpha = f.alpha;
     g.distance = f.dist;
     g.regulariser = f.reg;
+    g.lame_mu = f.lame_mu;
+    g.lame_lambda = f.lame_lambda;
     L[l].grid = g;
     MFR_TRY(make_geo(&g, &L[l].geo));
   }

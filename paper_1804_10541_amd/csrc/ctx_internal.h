@@ -36,7 +36,8 @@ struct Geo {
   double h[3], hT[3], hy[3];
   double tau, rho, alpha;
   int dist;   // MFR_DIST_NGF or MFR_DIST_SSD
-  int reg;    // MFR_REG_CURVATURE or MFR_REG_DIFFUSIVE
+  int reg;    // MFR_REG_CURVATURE, MFR_REG_DIFFUSIVE or MFR_REG_ELASTIC
+  double lame_mu, lame_lambda;   // elastic only
   size_t mbar, nbar;
   double hbar() const { return h[0] * h[1] * h[2]; }
   double hybar() const { return hy[0] * hy[1] * hy[2]; }
@@ -50,8 +51,14 @@ struct Geo {
   // diffusive S = hbar^y/2 sum of squared edge differences (= -hbar^y/2 u.L u),
   // grad = -alpha hbar^y L u.  reg_scale() is the factor of the node pass's
   // stencil term, s_value() the one of its sum.
-  double reg_scale() const { return reg == MFR_REG_DIFFUSIVE ? alpha * hybar() : 2.0 * alpha * hybar(); }
-  double s_value(double sum) const { return (reg == MFR_REG_DIFFUSIVE ? 0.5 : 1.0) * hybar() * sum; }
+  // Elastic: both scaled by lame_mu, the divergence part carries kappa() inside the kernels.
+  double reg_scale() const {
+    return reg == MFR_REG_CURVATURE ? 2.0 * alpha * hybar() : alpha * hybar() * (reg == MFR_REG_ELASTIC ? lame_mu : 1.0);
+  }
+  double s_value(double sum) const {
+    return reg == MFR_REG_CURVATURE ? hybar() * sum : 0.5 * hybar() * sum * (reg == MFR_REG_ELASTIC ? lame_mu : 1.0);
+  }
+  double kappa() const { return reg == MFR_REG_ELASTIC ? (lame_lambda + lame_mu) / lame_mu : 0.0; }
 };
 
 mfr_status make_geo(const mfr_grid* g, Geo* o);
@@ -75,7 +82,7 @@ void set_tile_config(const mfr_tile_config& c);
 
 struct Layout {
   size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
-  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz, lap, ctrl;
+  size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz, lap, ctrl, div;
   size_t n_red_node;
   size_t total;
 };

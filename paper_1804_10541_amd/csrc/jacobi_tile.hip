@@ -110,15 +110,17 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
       const int i = BX.lo + tid % ncx, j = BY.lo + tid / ncx;
       const int cxn = (i > 0) + (i < P.nx - 1), cyn = (j > 0) + (j < P.ny - 1), czn = (K > 0) + (K < P.nz - 1);
       const float Lnn = -(cxn * J.ihy2x + cyn * J.ihy2y + czn * J.ihy2z);
-      // curvature: (L^T L)_nn; diffusive: -L_nn
+      // curvature: (L^T L)_nn; diffusive: -L_nn; elastic: -L_nn + kappa (adjacent cells) / (16 hy_d^2)
       const float LL =
           P.reg ? -Lnn : Lnn * Lnn + cxn * J.ihy2x * J.ihy2x + cyn * J.ihy2y * J.ihy2y + czn * J.ihy2z * J.ihy2z;
+      const float ncell = P.reg == 2 ? P.kappa * (float)(cxn * cyn * czn) * 0.0625f : 0.0f;
+      const float ih2[3] = {J.ihy2x, J.ihy2y, J.ihy2z};
       const size_t n = (size_t)K * nxy + (size_t)j * P.nx + i;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         float s = 0.0f;
         for (int k = 0; k < G; ++k) s += sPart[d][tid + k * NC];
-        diag[(size_t)d * P.nbar + n] = fmaf(J.s_ngf, s, J.s_curv * LL);
+        diag[(size_t)d * P.nbar + n] = fmaf(J.s_ngf, s, J.s_curv * fmaf(ncell, ih2[d], LL));
       }
     }
     __syncthreads();

@@ -51,6 +51,8 @@ LbLayout lb_layout(const Geo& g, int mem) {
 }
 
 mfr_status check_geo(const Geo& g) {
+  if (g.reg == MFR_REG_ELASTIC)
+    return fail(MFR_EINVAL, "the H_0 solve needs a regulariser that acts on each component alone (not elastic)");
   for (int d = 0; d < 3; ++d)
     if (g.n[d] > kMaxAxis) return fail(MFR_EINVAL, "my[%d] = %d: the H_0 solve supports at most %d nodes per axis", d,
                                       g.n[d], kMaxAxis);

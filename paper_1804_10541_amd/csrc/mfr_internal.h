@@ -84,7 +84,8 @@ struct TileParams {
   double* red;            // one float64 partial per work-group
   const int* live;        // single-problem launches: skip all work while *live == 0 (nullable)
   int ssd;                // distance: 0 NGF, 1 sum of squared differences (dr/dT = identity)
-  int reg;                // regulariser: 0 curvature, 1 diffusive (for the diagonal kernels)
+  int reg;                // regulariser: 0 curvature, 1 diffusive, 2 elastic (for the diagonal kernels)
+  float kappa;            // elastic: (lambda + mu) / mu
 };
 
 // Parameters of the node pass.
@@ -93,7 +94,9 @@ struct NodeParams {
   float ihy2x, ihy2y, ihy2z;  // 1 / hy^2
   float s_ngf;                // scale of the gathered voxel contributions (+-2 hbar)
   float s_curv;               // 2 alpha hbar^y (curvature) or alpha hbar^y (diffusive)
-  int reg;                    // 0 curvature (L L f), 1 diffusive (-L f)
+  int reg;                    // 0 curvature (L L f), 1 diffusive (-L f), 2 elastic (-L f + kappa B^T B f)
+  float kappa;                // elastic: (lambda + mu) / mu
+  float* div;                 // elastic: divergence per cell ((nx-1)(ny-1)(nz-1) floats), first pass
   int tiles_x, tiles_y;
   int nxt, nyt, nzt;
   const float* part;

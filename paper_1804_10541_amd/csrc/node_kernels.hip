@@ -59,6 +59,30 @@ __device__ __forceinline__ float fwd_sq(const float* __restrict__ f, int i, int 
   return fmaf(dx * dx, ix2, fmaf(dy * dy, iy2, dz * dz * iz2));
 }
 
+// Divergence of f at cell (a, b, c) of the nodal grid (cells: one fewer per
+// axis than nodes): sum over d of the mean of the cell's four edge differences
+// of f_d along d, divided by hy_d (ih4 = 1 / (4 hy)).
+__device__ __forceinline__ float cell_div(const float* __restrict__ f, int nbar, int a, int b, int c, int nx, int ny,
+                                          float ih4x, float ih4y, float ih4z) {
+  const int nxy = nx * ny;
+  const int n0 = a + nx * b + nxy * c;
+  const float* fx = f;
+  const float* fy = f + nbar;
+  const float* fz = f + 2 * (size_t)nbar;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    const int p = o & 1, q = o >> 1;
+    const int ex = n0 + nx * p + nxy * q;   // edge along x at (y + p, z + q)
+    const int ey = n0 + p + nxy * q;        // edge along y at (x + p, z + q)
+    const int ez = n0 + p + nx * q;         // edge along z at (x + p, y + q)
+    sx += fx[ex + 1] - fx[ex];
+    sy += fy[ey + nx] - fy[ey];
+    sz += fz[ez + nxy] - fz[ez];
+  }
+  return fmaf(sx, ih4x, fmaf(sy, ih4y, sz * ih4z));
+}
+
 }  // namespace
 
 // The curvature part runs in two passes over the nodes: the first stores the
@@ -81,10 +105,20 @@ __device__ __forceinline__ void lap_body(const NodeParams& Q, const float* __res
     for (int d = 0; d < 3; ++d) {
       const float L0 = lap7(f + (size_t)d * Q.nbar, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z);
       Q.lap[(size_t)d * Q.nbar + n] = L0;
-      // curvature: sum (L f)^2; diffusive: the squared edge differences
+      // curvature: sum (L f)^2; diffusive and elastic: the squared edge differences
       if (MODE == NP_S)
         local += Q.reg ? (double)fwd_sq(f + (size_t)d * Q.nbar, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z)
                        : (double)L0 * (double)L0;
+    }
+  }
+  if (Q.reg == 2) {   // elastic: divergence of the cell with linear index n, kept for the second pass
+    const int cx = Q.nx - 1, cy = Q.ny - 1, cz = Q.nz - 1;
+    if (n < cx * cy * cz) {
+      const int a = n % cx, b = (n / cx) % cy, c = n / (cx * cy);
+      const float dv = cell_div(f, Q.nbar, a, b, c, Q.nx, Q.ny, 0.25f * sqrtf(Q.ihy2x), 0.25f * sqrtf(Q.ihy2y),
+                                0.25f * sqrtf(Q.ihy2z));
+      Q.div[n] = dv;
+      if (MODE == NP_S) local += (double)Q.kappa * (double)dv * (double)dv;
     }
   }
   if (MODE == NP_S) {
@@ -116,8 +150,22 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     const float Lzm = k > 0 ? Ld[n - nxy] : L0;
     const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
     const float m2 = -2.0f * L0;
-    // curvature: L L f; diffusive: -L f (its Hessian is -hbar^y L)
-    const float LL = Q.reg ? -L0 : fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
+    // curvature: L L f; diffusive: -L f (its Hessian is -hbar^y L); elastic: -L f + kappa (B^T B f)_d
+    float LL = Q.reg ? -L0 : fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
+    if (Q.reg == 2) {
+      const int cx = Q.nx - 1, cy = Q.ny - 1;
+      const int nd = d == 0 ? i : d == 1 ? j : k;
+      const float ih4 = 0.25f * sqrtf(d == 0 ? Q.ihy2x : d == 1 ? Q.ihy2y : Q.ihy2z);
+      float bt = 0.f;
+      for (int c = max(k - 1, 0); c <= min(k, Q.nz - 2); ++c)
+        for (int b = max(j - 1, 0); b <= min(j, Q.ny - 2); ++b)
+          for (int a = max(i - 1, 0); a <= min(i, Q.nx - 2); ++a) {
+            const int cd = d == 0 ? a : d == 1 ? b : c;
+            const float dv = Q.div[a + cx * (b + cy * c)];
+            bt += cd == nd - 1 ? dv : -dv;   // the node is the upper (+) or lower (-) corner along d
+          }
+      LL = fmaf(Q.kappa * ih4, bt, LL);
+    }
     // gather of the transposed conversion: every tile slot overlapping node n
     const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
     float s = 0.0f;
@@ -134,8 +182,11 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     }
     const float q = fmaf(Q.s_ngf, s, Q.s_curv * LL);
     out[(size_t)d * Q.nbar + n] = q;
-    if (MODE == NP_GRAD)
+    if (MODE == NP_GRAD) {
       local = Q.reg ? (double)fwd_sq(fd, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : (double)L0 * (double)L0;
+      if (Q.reg == 2 && d == 0 && n < (Q.nx - 1) * (Q.ny - 1) * (Q.nz - 1))
+        local += (double)Q.kappa * (double)Q.div[n] * (double)Q.div[n];   // once per cell (component row 0)
+    }
     if (MODE == NP_HV) local = (double)fd[n] * (double)q;
   }
   const double s = block_sum<kNodeBlock>(local, sred);
@@ -384,10 +435,13 @@ __global__ __launch_bounds__(kNodeBlock) void jacobi_diag_kernel(const DiagParam
   // curvature part: (L^T L)_{nn} = (L_nn)^2 + sum over in-range neighbours 1/hy_k^4
   const int cxn = (ni > 0) + (ni < P.nx - 1), cyn = (nj > 0) + (nj < P.ny - 1), czn = (nk > 0) + (nk < P.nz - 1);
   const float Lnn = -(cxn * D.ihy2x + cyn * D.ihy2y + czn * D.ihy2z);
-  // curvature: (L^T L)_nn; diffusive: -L_nn
+  // curvature: (L^T L)_nn; diffusive: -L_nn; elastic: -L_nn + kappa (B^T B)_nn, the latter
+  // (adjacent cells) / (16 hy_d^2)
   const float LL = P.reg ? -Lnn : Lnn * Lnn + cxn * D.ihy2x * D.ihy2x + cyn * D.ihy2y * D.ihy2y + czn * D.ihy2z * D.ihy2z;
+  const float ncell = P.reg == 2 ? P.kappa * (float)(cxn * cyn * czn) * 0.0625f : 0.0f;
+  const float ih2[3] = {D.ihy2x, D.ihy2y, D.ihy2z};
 #pragma unroll
-  for (int d = 0; d < 3; ++d) diag[(size_t)d * P.nbar + n] = fmaf(D.s_ngf, acc[d], D.s_curv * LL);
+  for (int d = 0; d < 3; ++d) diag[(size_t)d * P.nbar + n] = fmaf(D.s_ngf, acc[d], D.s_curv * fmaf(ncell, ih2[d], LL));
 }
 
 hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, hipStream_t st) {

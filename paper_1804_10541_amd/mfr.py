@@ -31,7 +31,8 @@ class CGrid(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("my", ctypes.c_int32 * 3),
                 ("mT", ctypes.c_int32 * 3), ("hT", ctypes.c_double * 3),
                 ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("distance", ctypes.c_int32), ("regulariser", ctypes.c_int32)]
+                ("distance", ctypes.c_int32), ("regulariser", ctypes.c_int32),
+                ("lame_mu", ctypes.c_double), ("lame_lambda", ctypes.c_double)]
 
 
 class CPcgOpts(ctypes.Structure):
@@ -182,12 +183,13 @@ def _check(status):
 
 
 DISTANCES = {"ngf": 0, "ssd": 1}   # mfr_grid.distance
-REGULARISERS = {"curvature": 0, "diffusive": 1}   # mfr_grid.regulariser
+REGULARISERS = {"curvature": 0, "diffusive": 1, "elastic": 2}   # mfr_grid.regulariser
 
 
 def make_grid(spec):
     """CGrid from any object with m, h, my, tau, rho, alpha (optional mT, hT,
-    distance "ngf" or "ssd", regulariser "curvature" or "diffusive")."""
+    distance "ngf" or "ssd", regulariser "curvature", "diffusive" or "elastic" with
+    lame_mu, lame_lambda)."""
     g = CGrid()
     for k in range(3):
         g.m[k] = int(spec.m[k])
@@ -206,6 +208,8 @@ def make_grid(spec):
     if reg not in REGULARISERS:
         raise ValueError(f"regulariser must be one of {sorted(REGULARISERS)}, got {reg!r}")
     g.regulariser = REGULARISERS[reg]
+    g.lame_mu = float(getattr(spec, "lame_mu", 1.0))
+    g.lame_lambda = float(getattr(spec, "lame_lambda", 0.0))
     return g
 
 

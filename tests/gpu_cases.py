@@ -17,10 +17,10 @@ def rel_l2(a, b):
 
 
 def blob_case(seed, m, my, h=(1.0, 1.0, 1.0), tau=0.1, rho=0.1, alpha=1.0, amp=0.5, n_probes=3, mT=None,
-              hT=None, T_override=None, distance="ngf", regulariser="curvature"):
+              hT=None, T_override=None, distance="ngf", regulariser="curvature", lame=(1.0, 0.0)):
     """Gaussian-blob pair + smooth displacement + N(0,1) probes, all float32."""
     spec = GridSpec(m=tuple(m), h=tuple(h), my=tuple(my), tau=tau, rho=rho, alpha=alpha, mT=mT, hT=hT,
-                    distance=distance, regulariser=regulariser)
+                    distance=distance, regulariser=regulariser, lame_mu=lame[0], lame_lambda=lame[1])
     R, T, rng = blob_pair(seed, spec.m)
     if mT is not None:
         _, T, rng = blob_pair(seed, tuple(mT))
@@ -30,9 +30,10 @@ def blob_case(seed, m, my, h=(1.0, 1.0, 1.0), tau=0.1, rho=0.1, alpha=1.0, amp=0
     return spec, f32(R), f32(T if T_override is None else T_override), f32(u0), f32(probes)
 
 
-def ct_case(seed, m, my, amp=0.5, n_probes=3, alpha=0.1, eps=50.0, distance="ngf", regulariser="curvature"):
+def ct_case(seed, m, my, amp=0.5, n_probes=3, alpha=0.1, eps=50.0, distance="ngf", regulariser="curvature",
+            lame=(1.0, 0.0)):
     spec = GridSpec(m=tuple(m), h=(1.0, 1.0, 1.0), my=tuple(my), tau=eps, rho=eps, alpha=alpha, distance=distance,
-                    regulariser=regulariser)
+                    regulariser=regulariser, lame_mu=lame[0], lame_lambda=lame[1])
     R, T, _, rng = ct_pair(seed, spec.m)
     u0 = smooth_field(rng, spec.my, amp)
     probes = rng.standard_normal((n_probes,) + u0.shape)

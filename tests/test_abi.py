@@ -109,6 +109,17 @@ def test_distance_field_validation(lib):
     grids = (mfr.CGrid * 1)(mfr.make_grid(dif))
     assert lib.mfr_batch_workspace_size(1, grids, 1, ctypes.byref(n)) == -1
     assert b"curvature" in lib.mfr_last_error()
+    # elastic: Lame parameters validated; no L-BFGS initial-matrix solve for it
+    el = GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1, alpha=1.0, regulariser="elastic",
+                  lame_mu=0.5, lame_lambda=2.0)
+    assert _ws(el) > 0
+    for mu, lam in ((0.0, 1.0), (1.0, -1.5)):
+        with pytest.raises(mfr.MfrError):
+            _ws(GridSpec(m=(16, 16, 16), h=(1, 1, 1), my=(9, 9, 9), tau=1, rho=1, alpha=1.0, regulariser="elastic",
+                         lame_mu=mu, lame_lambda=lam))
+    ge = mfr.make_grid(el)
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(ge), 3, ctypes.byref(n)) == -1
+    assert b"elastic" in lib.mfr_last_error()
 
 
 def test_lbfgs_workspace_validation(lib):
