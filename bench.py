@@ -179,9 +179,9 @@ def ssd_leg(dev, spec, R, T, u0, reps=20):
     return out
 
 
-def diffusive_leg(dev, spec, R, T, u0, steps=2):
-    """Gauss-Newton steps with the diffusive regulariser on the headline pair and
-    start (same step as the headline: 20 Jacobi-PCG iterations, rtol 0), with the
+def regulariser_leg(dev, spec, R, T, u0, regulariser, steps=2, **lame):
+    """Gauss-Newton steps with another regulariser on the headline pair and start
+    (same step as the headline: 20 Jacobi-PCG iterations, rtol 0), with the
     node-pass and Jacobi-diagonal kernel times (events on the context's stream)."""
     import dataclasses
 
@@ -189,7 +189,7 @@ def diffusive_leg(dev, spec, R, T, u0, steps=2):
 
     from paper_1804_10541_amd import mfr
 
-    s = dataclasses.replace(spec, regulariser="diffusive")
+    s = dataclasses.replace(spec, regulariser=regulariser, **lame)
     ctx = mfr.Context(s, dev)
     ctx.set_images(R, T)
     u = u0.clone()
@@ -207,11 +207,12 @@ def diffusive_leg(dev, spec, R, T, u0, steps=2):
     ctx.close()
     avg = lambda k: round(prof[k][1] / max(prof[k][0], 1), 4)
     n_hv = sum(i["pcg_iters"] for i in infos)
-    out = {"workload": "the headline Gauss-Newton step with the diffusive regulariser",
+    out = {"workload": f"the headline Gauss-Newton step with the {regulariser} regulariser"
+                       + (f" (lame_mu {lame['lame_mu']:g}, lame_lambda {lame['lame_lambda']:g})" if lame else ""),
            "ms_per_step": round(dt * 1e3 / steps, 3), "gvoxel_s": round(s.voxels * n_hv / dt / 1e9, 3),
            "J": [round(i["J_after"], 1) for i in infos],
            "tile_hv_ms": avg("tile_hv"), "node_pass_ms": avg("node_pass"), "jacobi_diag_ms": avg("jacobi_diag")}
-    log(f"[bench] diffusive: {out}")
+    log(f"[bench] {regulariser}: {out}")
     return out
 
 
@@ -329,7 +330,7 @@ def main():
     ap.add_argument("--no-pc", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--no-ssd", action="store_true", help="skip the sum-of-squared-differences leg")
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS leg")
-    ap.add_argument("--no-diffusive", action="store_true", help="skip the diffusive-regulariser leg")
+    ap.add_argument("--no-regularisers", action="store_true", help="skip the diffusive and elastic legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -446,9 +447,10 @@ def main():
     if not args.no_lbfgs:
         log("[bench] L-BFGS")
         out["lbfgs"] = lbfgs_leg(dev, spec, R, T, u0)
-    if not args.no_diffusive:
-        log("[bench] diffusive regulariser")
-        out["diffusive"] = diffusive_leg(dev, spec, R, T, u0)
+    if not args.no_regularisers:
+        log("[bench] diffusive and elastic regularisers")
+        out["diffusive"] = regulariser_leg(dev, spec, R, T, u0, "diffusive")
+        out["elastic"] = regulariser_leg(dev, spec, R, T, u0, "elastic", lame_mu=1.0, lame_lambda=1.0)
     del R, T
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
