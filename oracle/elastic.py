@@ -73,3 +73,45 @@ def hess_vec(grid, p, H=None):
 def hessian_diag(grid, H=None):
     H = hessian_matrix(grid) if H is None else H
     return H.diagonal().reshape(3, grid.my[2], grid.my[1], grid.my[0])
+
+
+def _cell_div(grid, f, a, b, c):
+    """Divergence of the node field f (3, nz, ny, nx) at cell (a, b, c)."""
+    tot = 0.0
+    for d in range(3):
+        s = 0.0
+        for oz in (0, 1):
+            for oy in (0, 1):
+                for ox in (0, 1):
+                    off = (ox, oy, oz)
+                    s += (1.0 if off[d] else -1.0) * f[d][c + oz][b + oy][a + ox]
+        tot += s / (4.0 * grid.hy[d])
+    return tot
+
+
+def node_outputs(grid, u, p, node):
+    """Exact (grad S, (nabla^2 S) p, diag nabla^2 S) at one node: mu times the
+    diffusive node outputs plus (lambda + mu) hbar^y sum over the (up to eight)
+    cells at the node of (d div_c / d f_d(node)) div_c."""
+    from . import diffusive as _dif
+    gd, hd, dd = _dif.node_outputs(grid, u, p, node)
+    mu, kap = grid.lame_mu, grid.lame_lambda + grid.lame_mu
+    shp = (3, grid.my[2], grid.my[1], grid.my[0])
+    uf = np.asarray(u, dtype=np.float64).reshape(shp)
+    pf = np.asarray(p, dtype=np.float64).reshape(shp) if p is not None else None
+    i, j, k = (int(x) for x in grid.node_abc(node))
+    g2, h2, d2 = np.zeros(3), np.zeros(3), np.zeros(3)
+    for c in range(max(k - 1, 0), min(k, grid.my[2] - 2) + 1):
+        for b in range(max(j - 1, 0), min(j, grid.my[1] - 2) + 1):
+            for a in range(max(i - 1, 0), min(i, grid.my[0] - 2) + 1):
+                du = _cell_div(grid, uf, a, b, c)
+                dp = _cell_div(grid, pf, a, b, c) if pf is not None else 0.0
+                cell = (a, b, c)
+                nd = (i, j, k)
+                for d in range(3):
+                    w = (1.0 if cell[d] == nd[d] - 1 else -1.0) / (4.0 * grid.hy[d])
+                    g2[d] += w * du
+                    h2[d] += w * dp
+                    d2[d] += w * w
+    s = grid.hybar * kap
+    return mu * gd + s * g2, (mu * hd + s * h2 if p is not None else None), mu * dd + s * d2

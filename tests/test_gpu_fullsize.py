@@ -6,13 +6,13 @@ compared at sampled nodes (corners, faces, tile and z-chunk borders, random
 interior nodes) with the oracle's exact single-node evaluation, which builds
 only the Jacobian rows and regulariser rows that touch each node.  Cases: NGF with
 curvature (the bench's), the sum of squared differences with curvature, and NGF with
-the diffusive regulariser."""
+the diffusive and the linear-elastic regularisers."""
 import numpy as np
 import pytest
 import torch
 
 from gpu_cases import rel_l2
-from oracle import Grid, curvature, diffusive, ngf, ssd
+from oracle import Grid, curvature, diffusive, elastic, ngf, ssd
 from paper_1804_10541_amd import mfr
 from synth import GridSpec, ct_pair, smooth_field
 
@@ -30,14 +30,15 @@ def sample_nodes(grid, rng, n_random=12):
     return [int(grid.node_id(a, b, c)) for a, b, c in picks]
 
 
-@pytest.mark.parametrize("distance,regulariser", [("ngf", "curvature"), ("ssd", "curvature"), ("ngf", "diffusive")])
+@pytest.mark.parametrize("distance,regulariser", [("ngf", "curvature"), ("ssd", "curvature"), ("ngf", "diffusive"),
+                                                   ("ngf", "elastic")])
 def test_bench_workload_sampled_nodes(distance, regulariser):
     print(f"[gpu-case] {distance} {regulariser} 512x512x900 / 129x129x225, tile 32x16 target 4096, seed 0", flush=True)
     m, my = (512, 512, 900), (129, 129, 225)
     spec = GridSpec(m=m, h=(1.0, 1.0, 1.0), my=my, tau=50.0, rho=50.0, alpha=0.1, distance=distance,
-                    regulariser=regulariser)
+                    regulariser=regulariser, lame_mu=1.0, lame_lambda=1.0)
     dist = ssd if distance == "ssd" else ngf
-    reg = diffusive if regulariser == "diffusive" else curvature
+    reg = {"diffusive": diffusive, "elastic": elastic}.get(regulariser, curvature)
     R, T, _, rng = ct_pair(0, m, device=DEV)
     u = torch.from_numpy(smooth_field(rng, my, 0.5).astype("float32")).to(DEV)
     gen = torch.Generator(device=DEV).manual_seed(11)

@@ -784,3 +784,18 @@ def test_elastic_gradient_fd_hessian_symmetric_psd_and_diagonal():
     np.testing.assert_allclose(elastic.hessian_diag(g).ravel(), np.diag(H), rtol=1e-12)
     prob = solver.Problem(g, np.zeros((4, 6, 6)), np.zeros((4, 6, 6)))
     assert abs(prob.objective(u)[2] - elastic.energy(g, u)) <= 1e-12 * elastic.energy(g, u)
+
+
+def test_elastic_node_outputs_match_full_evaluation():
+    rng = np.random.default_rng(33)
+    my = (5, 4, 4)
+    g = Grid((8, 6, 6), (1.0, 1.2, 0.9), my, 1.0, 1.0, 0.5, regulariser="elastic", lame_mu=0.7, lame_lambda=1.4)
+    u = rng.standard_normal((3, my[2], my[1], my[0]))
+    p = rng.standard_normal(u.shape)
+    gr, hv, dg = elastic.gradient(g, u), elastic.hess_vec(g, p), elastic.hessian_diag(g)
+    for node in [0, g.nbar - 1, g.node_id(2, 1, 2), g.node_id(4, 3, 0), g.node_id(1, 2, 3)]:
+        gn, hn, dn = elastic.node_outputs(g, u, p, node)
+        a, b, c = g.node_abc(node)
+        np.testing.assert_allclose(gn, gr[:, c, b, a], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(hn, hv[:, c, b, a], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dn, dg[:, c, b, a], rtol=1e-12, atol=1e-12)
