@@ -47,10 +47,10 @@ SSD_HV_BYTES_PER_VOXEL = 4
 
 # HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload
 # (32x16 tiles, split target 4096), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
-# plain copy kernel (profiles/ngf_tile_hv_512x512x900.md): 2.00 x 1,185,410 KiB +
-# 1.00 x 114,201 KiB.  Only valid for that kernel build and tile configuration; otherwise
+# plain copy kernel (profiles/ngf_tile_hv_512x512x900.md): 2.00 x 1,186,960 KiB +
+# 1.00 x 114,215 KiB.  Only valid for that kernel build and tile configuration; otherwise
 # reported as null.
-HV_TRAFFIC_C3 = {"bytes": 2544619384, "tile": (32, 16, 4096)}
+HV_TRAFFIC_C3 = {"bytes": 2547808066, "tile": (32, 16, 4096)}
 
 
 def log(msg):

@@ -59,7 +59,11 @@ struct TileSmem {
   float sTw[2][NX];
   float sR[2][NX];
   float sA[HV ? 2 : 1][HV ? NX : 1];
-  float sE[NEED_C ? 2 : 1][4][NEED_C ? NX : 1];
+  // row products of the plane exchange, with a zero pad of one block row at both
+  // ends: a neighbour read past the block's edge (or wrapping to the next row,
+  // whose edge column is a ring column that writes 0) then adds exactly 0
+  static constexpr int EP = (NEED_C && !SSD) ? BX : 0;
+  float sE[NEED_C ? 2 : 1][4][NEED_C ? NX + 2 * EP : 1];
   float sV[NEED_C ? 3 : 1][NEED_C ? NT : 1];
   float sW[NEED_C ? 3 : 1][NEED_C ? BY * MAXNX : 1];
   int sColLo[MAXNX], sColHi[MAXNX], sRowLo[MAXNY], sRowHi[MAXNY];
@@ -85,6 +89,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   auto& sR = S.sR;
   auto& sA = S.sA;
   auto& sE = S.sE;
+  constexpr int EP = TileSmem<BX, BY, MODE, SSD>::EP;
   auto& sV = S.sV;
   auto& sW = S.sW;
   auto& sColLo = S.sColLo;
@@ -142,6 +147,12 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     sSz[j] = P.sz[q];
   }
   if constexpr (!NEED_C) __syncthreads();   // (with NEED_C the barrier after sCx / sCy covers it)
+  if constexpr (EP > 0) {   // the pads of sE are never written by the march
+    for (int w = tid; w < 2 * 4 * 2 * EP; w += NT) {
+      const int r = w % (2 * EP), k = (w / (2 * EP)) % 4, sl = w / (8 * EP);
+      sE[sl][k][r < EP ? r : NT + r] = 0.f;
+    }
+  }
   const int nxl = P.cx[x0 - 1 + lxb].n0 + 2 - nox;
   const int nyl = P.cy[y0 - 1 + lyb].n0 + 2 - noy;
   if constexpr (NEED_C) {
@@ -379,10 +390,10 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         }
       }
       if constexpr (NEED_C) {
-        sE[s1][0][tid] = ex_p;
-        sE[s1][1][tid] = ex_m;
-        sE[s1][2][tid] = ey_p;
-        sE[s1][3][tid] = ey_m;
+        sE[s1][0][EP + tid] = ex_p;
+        sE[s1][1][EP + tid] = ex_m;
+        sE[s1][2][EP + tid] = ey_p;
+        sE[s1][3][EP + tid] = ey_m;
       }
     }
 
@@ -404,12 +415,13 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         if (inC) {
           float w = e0[K2];
           if constexpr (!SSD) {
-            // rows of the neighbours within the group (none beyond its edge)
+            // rows of the neighbours within the group (beyond its edge: the zero pad,
+            // or a ring column of the next row, which holds 0)
             const int s2 = c & 1;
-            w += tx < BX - 1 ? sE[s2][1][tid + 1] : 0.f;
-            w += tx > 0 ? sE[s2][0][tid - 1] : 0.f;
-            w += ty < BY - 1 ? sE[s2][3][tid + BX] : 0.f;
-            w += ty > 0 ? sE[s2][2][tid - BX] : 0.f;
+            w += sE[s2][1][EP + tid + 1];
+            w += sE[s2][0][EP + tid - 1];
+            w += sE[s2][3][EP + tid + BX];
+            w += sE[s2][2][EP + tid - BX];
             w += ezm;
             w += ezp[K];
           }
