@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MFR_ABI_VERSION 2
+#define MFR_ABI_VERSION 3
 
 /* Regularisers (mfr_grid.regulariser). */
 #define MFR_REG_CURVATURE 0   /* curvature, eq. CURV_discretized (the paper's)                  */
@@ -68,7 +68,10 @@ typedef enum {
   MFR_EHIP = -3,          /* a HIP runtime call or kernel launch failed                       */
   MFR_ENONFINITE = -4,    /* a scalar result (J, D, S, dot product) is NaN or infinite       */
   MFR_ELINESEARCH = -5,   /* Armijo line search found no sufficient decrease                  */
-  MFR_EBREAKDOWN = -6     /* reserved: CG breakdown is reported in mfr_pcg_info.flag          */
+  MFR_EBREAKDOWN = -6,    /* reserved: CG breakdown is reported in mfr_pcg_info.flag          */
+  MFR_ENOTCONV = -7       /* a CG solve reached max_iter above rtol and the caller asked for
+                             convergence (mfr_pcg_opts.require_converged); info is filled and
+                             s holds the last iterate                                         */
 } mfr_status;
 
 /* Problem description (Sec. 2.2; notation table).  Sizes and spacings are
@@ -118,9 +121,10 @@ mfr_status mfr_objective(mfr_ctx* ctx, const float* u, double* J, double* D, dou
 
 /* g = grad D + alpha grad S at u (eq. gradNGF with the transposed grid
  * conversion of Sec. 4.3, and eq. curvatureMF; SSD: hbar P^T (g_T r) with
- * g_T the template derivative, Sec. 4.4).  g: device [3][n].  If J is not
- * NULL it receives J(u) (and the stream is synchronised). */
-mfr_status mfr_gradient(mfr_ctx* ctx, const float* u, float* g, double* J);
+ * g_T the template derivative, Sec. 4.4).  g: device [3][n].  If J (host) is
+ * not NULL it receives J(u) (and the stream is synchronised).  The argument
+ * order (u, J, g) is that of mfr_objective's results followed by the vector. */
+mfr_status mfr_gradient(mfr_ctx* ctx, const float* u, double* J, float* g);
 
 /* q = (H + alpha nabla^2 S) p with H the Gauss-Newton matrix of D at u
  * (eq. NGF_discretized_hessian, evaluated matrix-free as in eq. hessMult /
@@ -142,6 +146,8 @@ typedef struct {
   int32_t fallback_iters; /* precond 2 only: after this many iterations without
                          convergence, continue with Jacobi-PCG from the current
                          iterate (0: never)                                      */
+  int32_t require_converged; /* != 0: return MFR_ENOTCONV when max_iter is reached
+                         with the relative residual above rtol (flag 1)          */
 } mfr_pcg_opts;
 
 typedef struct {
@@ -199,6 +205,9 @@ typedef struct {
   double armijo_c1;    /* sufficient-decrease constant (e.g. 1e-4)                  */
   int32_t armijo_max;  /* step halvings before the line search gives up             */
   int32_t precond;     /* 0 none, 1 Jacobi                                          */
+  const float* u_init; /* device [3][n] displacement on the COARSEST deformation
+                          grid (mfr_ml_level_grid level 0) the first level starts
+                          from; NULL: u = 0 there                                    */
 } mfr_ml_opts;
 
 typedef struct {
@@ -207,21 +216,49 @@ typedef struct {
   int32_t pcg_total[8];    /* CG iterations per level                                */
   int32_t status[8];       /* 0, or MFR_ELINESEARCH if that level stopped early       */
   double seconds;          /* wall time of the whole call                             */
+  double J_start[8];       /* objective of each level at its starting displacement
+                              (u_init or 0 on the coarsest, the prolongated field above) */
+  double J_level[8];       /* objective of each level at the displacement it hands on  */
 } mfr_ml_report;
 
 /* Bytes of device workspace mfr_register_multilevel needs for `finest`. */
 mfr_status mfr_ml_workspace_size(const mfr_grid* finest, int32_t levels, size_t* bytes);
 
+/* Grid of pyramid level `level` (0 = coarsest, levels - 1 = `finest`) of a
+ * multilevel registration with `levels` levels: ceil(m/2) image cells and
+ * ceil((my-1)/2) deformation cells per coarser level, spacings doubled
+ * (Sec. 2.3, coarse-to-fine; the coarse grids themselves are not specified by
+ * the paper). */
+mfr_status mfr_ml_level_grid(const mfr_grid* finest, int32_t levels, int32_t level, mfr_grid* out);
+
 /* Coarse-to-fine Gauss-Newton registration (Sec. 2.3): image pyramid of
  * 2x2x2 means (ceil(m/2) cells, spacing doubled), deformation grids with
  * ceil((my-1)/2) cells per coarser level, Gauss-Newton with (P)CG and Armijo
  * line search on each level, linear prolongation of u to the next level.
- * u: device [3][n] of the finest grid; in: initial displacement at the
- * finest level is ignored unless levels == 1 (coarsest level starts at 0);
- * out: the registered finest displacement.  Synchronises the stream. */
+ * The coarsest level starts from opts->u_init (NULL: 0).  u: device [3][n]
+ * of the finest grid, output only: the registered finest displacement.
+ * Synchronises the stream. */
 mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* opts, void* hip_stream,
                                    void* workspace, size_t ws_bytes, const float* R, const float* T,
                                    float* u, mfr_ml_report* report);
+
+/* One level of the image pyramid (Sec. 2.3): coarse[c][b][a] = mean of the
+ * fine voxels (2a + i, 2b + j, 2c + k), i, j, k in {0, 1}, an index past the
+ * last fine voxel replaced by the last one (odd sizes).  fine: device
+ * [m_z][m_y][m_x] float32 with m = m[0..2] (x, y, z), 1 <= m; coarse: device
+ * [ceil(m_z/2)][ceil(m_y/2)][ceil(m_x/2)], must not overlap fine.
+ * Asynchronous on hip_stream. */
+mfr_status mfr_restrict_image(const int32_t m[3], const float* fine, float* coarse, void* hip_stream);
+
+/* Prolongation of a displacement to a finer deformation grid (Sec. 2.3):
+ * per dimension, linear interpolation of the coarse node values at the
+ * physical position n hy_fine of each fine node, clamped to the coarse grid's
+ * extent.  uc: device [3][n_c], uf: device [3][n_f] (no overlap); work: device
+ * buffer of at least mfr_prolong_workspace_size(fine) bytes (the per-axis
+ * interpolation tables), 256-byte aligned.  Synchronises the stream. */
+mfr_status mfr_prolong_workspace_size(const mfr_grid* fine, size_t* bytes);
+mfr_status mfr_prolong(const mfr_grid* coarse, const mfr_grid* fine, const float* uc, float* uf, void* work,
+                       size_t work_bytes, void* hip_stream);
 
 /* ---- L-BFGS (Sec. 2.3.2) ------------------------------------------------
  * Limited-memory BFGS on J = D + alpha S from the objective and gradient, with
@@ -311,7 +348,8 @@ mfr_status mfr_batch_set_images(mfr_batch* b, const float* const* R, const float
 mfr_status mfr_batch_hess_vec(mfr_batch* b, const float* const* u, const float* const* p, float* const* q);
 
 /* Coarse-to-fine Gauss-Newton registration of every pair (options as in
- * mfr_register_multilevel; opts->levels must equal the batch's levels).
+ * mfr_register_multilevel; opts->levels must equal the batch's levels;
+ * opts->u_init must be NULL: every pair starts at u = 0).
  * use_graph != 0 replays the CG iterations from captured HIP graphs.
  * u: host array of n device pointers to the finest displacements (output).
  * Synchronises the stream. */

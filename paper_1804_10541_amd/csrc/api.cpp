@@ -774,7 +774,7 @@ mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out)
   inf.J_before = Jv;
   inf.J_after = Jv;
   HIP_TRY(launch_axpy(n3, b, -2.0f, b, b, c->stream));   // b <- -grad J
-  mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond, o->fallback_iters};
+  mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond, o->fallback_iters, 0};
   mfr_pcg_info pinf{};
   MFR_TRY(pcg_run(c, u, b, dir, &po, &pinf));
   inf.pcg_iters = pinf.iters;
@@ -872,7 +872,7 @@ mfr_status mfr_objective(mfr_ctx* c, const float* u, double* J, double* D, doubl
   return read_objective(c, J, D, S);
 }
 
-mfr_status mfr_gradient(mfr_ctx* c, const float* u, float* g, double* J) {
+mfr_status mfr_gradient(mfr_ctx* c, const float* u, double* J, float* g) {
   MFR_TRY(need_images(c));
   MFR_TRY(check_ptr(u, "u"));
   MFR_TRY(check_ptr(g, "g"));
@@ -967,7 +967,13 @@ mfr_status mfr_pcg_solve(mfr_ctx* c, const float* u, const float* b, float* s, c
   if (opts->max_iter < 0 || !(opts->rtol >= 0) || opts->precond < 0 || opts->precond > 2 || opts->fallback_iters < 0)
     return fail(MFR_EINVAL, "invalid PCG options");
   if (s == u || s == b) return fail(MFR_EINVAL, "s must not alias u or b");
-  return pcg_run(c, u, b, s, opts, info);
+  mfr_pcg_info inf{};
+  MFR_TRY(pcg_run(c, u, b, s, opts, &inf));
+  if (info) *info = inf;
+  if (opts->require_converged && inf.flag == 1)
+    return fail(MFR_ENOTCONV, "CG stopped after %d iterations at relative residual %g > rtol %g", inf.iters,
+                inf.relres, opts->rtol);
+  return MFR_OK;
 }
 
 // ---- multilevel ---------------------------------------------------------------
@@ -1046,6 +1052,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
   MFR_TRY(check_ptr(R, "R"));
   MFR_TRY(check_ptr(T, "T"));
   MFR_TRY(check_ptr(u, "u"));
+  if (o->u_init) MFR_TRY(check_ptr(o->u_init, "u_init"));
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(MFR_EINVAL, "workspace must be non-NULL and 256-byte aligned");
   std::vector<Level> L;
@@ -1080,10 +1087,10 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     const Geo& g = L[l].geo;
     float* ul = at<float>(ws, L[l].off_u);
     if (l == 0) {
-      if (nl == 1)
-        HIP_TRY(hipMemcpyAsync(ul, u, sizeof(float) * 3 * g.nbar, hipMemcpyDeviceToDevice, st));
+      if (o->u_init)
+        HIP_TRY(hipMemcpyAsync(ul, o->u_init, sizeof(float) * 3 * g.nbar, hipMemcpyDeviceToDevice, st));
       else
-        HIP_TRY(hipMemsetAsync(ul, 0, sizeof(float) * 3 * g.nbar, st));
+        HIP_TRY(launch_fill(3 * g.nbar, 0.0f, ul, st));
     } else {
       const Geo& gc = L[l - 1].geo;
       auto px = prolong_table(g.n[0], g.hy[0], gc.n[0], gc.hy[0]);
@@ -1108,6 +1115,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     int gn_done = 0, pcg_tot = 0, status = 0;
     double Jv = 0.0;
     MFR_TRY(mfr_objective(c, ul, &Jv, nullptr, nullptr));
+    rep.J_start[l] = Jv;
     for (int k = 0; k < o->gn_iters; ++k) {
       mfr_gn_info gi{};
       MFR_TRY(gn_step(c, ul, &go, &gi));
@@ -1122,6 +1130,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     rep.gn_done[l] = gn_done;
     rep.pcg_total[l] = pcg_tot;
     rep.status[l] = status;
+    rep.J_level[l] = Jv;
     Jfinal = Jv;
   }
   const Level& lf = L[nl - 1];
@@ -1130,6 +1139,70 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
   rep.J_final = Jfinal;
   rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (report) *report = rep;
+  return MFR_OK;
+}
+
+mfr_status mfr_ml_level_grid(const mfr_grid* finest, int32_t levels, int32_t level, mfr_grid* out) {
+  if (!out) return fail(MFR_EINVAL, "out is NULL");
+  std::vector<Level> L;
+  size_t need = 0;
+  MFR_TRY(ml_levels(finest, levels, &L, &need));
+  if (level < 0 || level >= levels) return fail(MFR_EINVAL, "level %d outside 0..%d", level, levels - 1);
+  *out = L[level].grid;
+  return MFR_OK;
+}
+
+mfr_status mfr_restrict_image(const int32_t m[3], const float* fine, float* coarse, void* hip_stream) {
+  if (!m) return fail(MFR_EINVAL, "m is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (m[k] < 1) return fail(MFR_EINVAL, "image size %d x %d x %d is invalid", m[0], m[1], m[2]);
+  const size_t nf = (size_t)m[0] * m[1] * m[2];
+  const size_t nc = (size_t)((m[0] + 1) / 2) * ((m[1] + 1) / 2) * ((m[2] + 1) / 2);
+  if (nf * sizeof(float) >= ((size_t)1 << 40)) return fail(MFR_EINVAL, "image too large");
+  MFR_TRY(check_ptr(fine, "fine"));
+  MFR_TRY(check_ptr(coarse, "coarse"));
+  const char* f0 = reinterpret_cast<const char*>(fine);
+  const char* c0 = reinterpret_cast<const char*>(coarse);
+  if (c0 < f0 + nf * sizeof(float) && f0 < c0 + nc * sizeof(float))
+    return fail(MFR_EINVAL, "coarse must not overlap fine");
+  HIP_TRY(launch_restrict(fine, m[0], m[1], m[2], coarse, reinterpret_cast<hipStream_t>(hip_stream)));
+  return MFR_OK;
+}
+
+mfr_status mfr_prolong_workspace_size(const mfr_grid* fine, size_t* bytes) {
+  if (!bytes) return fail(MFR_EINVAL, "bytes is NULL");
+  Geo g;
+  MFR_TRY(make_geo(fine, &g));
+  *bytes = align_up(sizeof(Conv1) * (size_t)(g.n[0] + g.n[1] + g.n[2]));
+  return MFR_OK;
+}
+
+mfr_status mfr_prolong(const mfr_grid* coarse, const mfr_grid* fine, const float* uc, float* uf, void* work,
+                       size_t work_bytes, void* hip_stream) {
+  Geo gc, gf;
+  MFR_TRY(make_geo(coarse, &gc));
+  MFR_TRY(make_geo(fine, &gf));
+  MFR_TRY(check_ptr(uc, "uc"));
+  MFR_TRY(check_ptr(uf, "uf"));
+  if (!work || reinterpret_cast<uintptr_t>(work) % 256 != 0)
+    return fail(MFR_EINVAL, "work must be non-NULL and 256-byte aligned");
+  size_t need = 0;
+  MFR_TRY(mfr_prolong_workspace_size(fine, &need));
+  if (work_bytes < need) return fail(MFR_ENOMEM, "work buffer of %zu bytes is smaller than the required %zu", work_bytes, need);
+  const char* a0 = reinterpret_cast<const char*>(uc);
+  const char* b0 = reinterpret_cast<const char*>(uf);
+  if (b0 < a0 + 12 * gc.nbar && a0 < b0 + 12 * gf.nbar) return fail(MFR_EINVAL, "uf must not overlap uc");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  auto px = prolong_table(gf.n[0], gf.hy[0], gc.n[0], gc.hy[0]);
+  auto py = prolong_table(gf.n[1], gf.hy[1], gc.n[1], gc.hy[1]);
+  auto pz = prolong_table(gf.n[2], gf.hy[2], gc.n[2], gc.hy[2]);
+  Conv1* dt = reinterpret_cast<Conv1*>(work);
+  HIP_TRY(hipMemcpyAsync(dt, px.data(), sizeof(Conv1) * px.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dt + gf.n[0], py.data(), sizeof(Conv1) * py.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dt + gf.n[0] + gf.n[1], pz.data(), sizeof(Conv1) * pz.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_prolong(uc, gc.n[0], gc.n[1], gc.n[2], uf, gf.n[0], gf.n[1], gf.n[2], dt, dt + gf.n[0],
+                         dt + gf.n[0] + gf.n[1], st));
+  HIP_TRY(hipStreamSynchronize(st));   // the host tables must outlive the copies
   return MFR_OK;
 }
 

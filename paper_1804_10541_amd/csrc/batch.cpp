@@ -427,6 +427,7 @@ mfr_status mfr_batch_register(mfr_batch* b, const mfr_ml_opts* o, int32_t use_gr
       o->armijo_max < 1 || o->precond < 0 || o->precond > 1)
     return fail(MFR_EINVAL, "invalid multilevel options");
   if (!u) return fail(MFR_EINVAL, "u is NULL");
+  if (o->u_init) return fail(MFR_EINVAL, "the batched path starts every pair at u = 0 (opts->u_init must be NULL)");
   if (use_graph && !b->st) return fail(MFR_EINVAL, "graph replay needs a stream other than the null stream");
   for (int k = 0; k < b->n; ++k) MFR_TRY(check_ptr(u[k], "u[k]"));
   const int n = b->n, nl = b->levels;

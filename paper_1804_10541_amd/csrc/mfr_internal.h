@@ -283,6 +283,7 @@ hipError_t launch_dot(int n, const float* x, const float* y, double* red, int bl
 // y = x + eta * s (GN trial points / updates).
 hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* y, hipStream_t st);
 // Image restriction (2 x 2 x 2 mean, ceil(m/2) cells).
+hipError_t launch_fill(size_t n, float v, float* y, hipStream_t st);
 hipError_t launch_restrict(const float* fine, int mx, int my, int mz, float* coarse, hipStream_t st);
 // Node-field prolongation with per-axis (lower index, fraction) tables.
 hipError_t launch_prolong(const float* coarse, int cnx, int cny, int cnz, float* fine, int fnx,

@@ -643,6 +643,20 @@ hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* 
   return hipGetLastError();
 }
 
+// y[i] = v for i < n (a kernel rather than a memset, so that a captured
+// sequence holds no memset node)
+__global__ void fill_kernel(size_t n, float v, float* __restrict__ y) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+hipError_t launch_fill(size_t n, float v, float* y, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, n, v, y);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Pyramid transfers
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libmfr.so")
 
 MFR_OK = 0
 STATUS = {0: "MFR_OK", -1: "MFR_EINVAL", -2: "MFR_ENOMEM", -3: "MFR_EHIP", -4: "MFR_ENONFINITE",
-          -5: "MFR_ELINESEARCH", -6: "MFR_EBREAKDOWN"}
+          -5: "MFR_ELINESEARCH", -6: "MFR_EBREAKDOWN", -7: "MFR_ENOTCONV"}
 
 
 class MfrError(RuntimeError):
@@ -37,7 +37,7 @@ class CGrid(ctypes.Structure):
 
 class CPcgOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double), ("precond", ctypes.c_int32),
-                ("fallback_iters", ctypes.c_int32)]
+                ("fallback_iters", ctypes.c_int32), ("require_converged", ctypes.c_int32)]
 
 
 class CPcgInfo(ctypes.Structure):
@@ -59,12 +59,13 @@ class CGnInfo(ctypes.Structure):
 class CMlOpts(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32), ("pcg_max", ctypes.c_int32),
                 ("pcg_rtol", ctypes.c_double), ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("u_init", ctypes.c_void_p)]
 
 
 class CMlReport(ctypes.Structure):
     _fields_ = [("J_final", ctypes.c_double), ("gn_done", ctypes.c_int32 * 8), ("pcg_total", ctypes.c_int32 * 8),
-                ("status", ctypes.c_int32 * 8), ("seconds", ctypes.c_double)]
+                ("status", ctypes.c_int32 * 8), ("seconds", ctypes.c_double), ("J_start", ctypes.c_double * 8),
+                ("J_level", ctypes.c_double * 8)]
 
 
 class CProfile(ctypes.Structure):
@@ -123,7 +124,7 @@ SIGNATURES = {
     "mfr_destroy": (None, [_VP]),
     "mfr_set_images": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfr_objective": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
-    "mfr_gradient": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_D)]),
+    "mfr_gradient": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), _VP]),
     "mfr_hess_vec": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mfr_jacobi_diag": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
@@ -131,6 +132,10 @@ SIGNATURES = {
     "mfr_ml_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_register_multilevel": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CMlOpts), _VP, _VP, _SZ,
                                                _VP, _VP, _VP, ctypes.POINTER(CMlReport)]),
+    "mfr_ml_level_grid": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, _I, ctypes.POINTER(CGrid)]),
+    "mfr_restrict_image": (ctypes.c_int, [ctypes.POINTER(_I), _VP, _VP, _VP]),
+    "mfr_prolong_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(_SZ)]),
+    "mfr_prolong": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CGrid), _VP, _VP, _VP, _SZ, _VP]),
     "mfr_batch_workspace_size": (ctypes.c_int, [_I, ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_batch_create": (ctypes.c_int, [_I, ctypes.POINTER(CGrid), _I, _VP, _VP, _SZ, ctypes.POINTER(_VP)]),
     "mfr_batch_destroy": (None, [_VP]),
@@ -297,8 +302,8 @@ class Context:
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
         J = ctypes.c_double()
         _check(self.lib.mfr_gradient(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
-                                     _dev_tensor(out, 3 * self.nbar, "g", self.device),
-                                     ctypes.byref(J) if want_J else None))
+                                     ctypes.byref(J) if want_J else None,
+                                     _dev_tensor(out, 3 * self.nbar, "g", self.device)))
         return out, (J.value if want_J else None)
 
     def hess_vec(self, u, p, out=None):
@@ -360,9 +365,10 @@ class Context:
         _check(self.lib.mfr_profile_read(self._h, ctypes.byref(st), 1 if reset else 0))
         return {k: (st.launches[i], st.ms[i]) for i, k in enumerate(PROFILE_KERNELS)}
 
-    def pcg_solve(self, u, b, max_iter=50, rtol=1e-3, precond=1, fallback_iters=0, out=None):
+    def pcg_solve(self, u, b, max_iter=50, rtol=1e-3, precond=1, fallback_iters=0, out=None,
+                  require_converged=False):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
-        opts = CPcgOpts(int(max_iter), float(rtol), int(precond), int(fallback_iters))
+        opts = CPcgOpts(int(max_iter), float(rtol), int(precond), int(fallback_iters), 1 if require_converged else 0)
         info = CPcgInfo()
         _check(self.lib.mfr_pcg_solve(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
                                       _dev_tensor(b, 3 * self.nbar, "b", self.device),
@@ -376,9 +382,19 @@ class Context:
         self._pc = pc
 
 
+def ml_level_grid(spec, levels, level):
+    """CGrid of pyramid level ``level`` (0 = coarsest) of a ``levels``-level registration."""
+    lib = load()
+    g = make_grid(spec)
+    out = CGrid()
+    _check(lib.mfr_ml_level_grid(ctypes.byref(g), int(levels), int(level), ctypes.byref(out)))
+    return out
+
+
 def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=1e-3, armijo_c1=1e-4,
                         armijo_max=10, precond=1, u0=None, device="cuda:0"):
-    """Coarse-to-fine Gauss-Newton registration; returns (u_finest, report dict)."""
+    """Coarse-to-fine Gauss-Newton registration; returns (u_finest, report dict).
+    ``u0``: initial displacement on the COARSEST deformation grid (None: 0)."""
     lib = load()
     device = torch.device(device)
     g = make_grid(spec)
@@ -387,11 +403,15 @@ def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=
     ws, ptr = _alloc_workspace(n.value, device)
     my = tuple(int(k) for k in spec.my)
     nb = my[0] * my[1] * my[2]
-    u = torch.zeros((3, my[2], my[1], my[0]), dtype=torch.float32, device=device) if u0 is None else u0.clone()
+    u = torch.empty((3, my[2], my[1], my[0]), dtype=torch.float32, device=device)
     mbar = int(spec.m[0]) * int(spec.m[1]) * int(spec.m[2])
     mT = getattr(spec, "mT", None) or spec.m
+    init = None
+    if u0 is not None:
+        gc = ml_level_grid(spec, levels, 0)
+        init = _dev_tensor(u0, 3 * gc.my[0] * gc.my[1] * gc.my[2], "u0", device)
     opts = CMlOpts(int(levels), int(gn_iters), int(pcg_max), float(pcg_rtol), float(armijo_c1), int(armijo_max),
-                   int(precond))
+                   int(precond), init)
     rep = CMlReport()
     _check(lib.mfr_register_multilevel(ctypes.byref(g), ctypes.byref(opts), _stream(device), ctypes.c_void_p(ptr),
                                        n.value, _dev_tensor(R, mbar, "R", device),
@@ -399,7 +419,39 @@ def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=
                                        _dev_tensor(u, 3 * nb, "u", device), ctypes.byref(rep)))
     del ws
     return u, dict(J_final=rep.J_final, gn_done=list(rep.gn_done)[:levels], pcg_total=list(rep.pcg_total)[:levels],
-                   status=list(rep.status)[:levels], seconds=rep.seconds)
+                   status=list(rep.status)[:levels], seconds=rep.seconds, J_start=list(rep.J_start)[:levels],
+                   J_level=list(rep.J_level)[:levels])
+
+
+def restrict_image(img):
+    """One pyramid level of a device float32 image [m_z, m_y, m_x] (2x2x2 means)."""
+    lib = load()
+    if img.dim() != 3:
+        raise ValueError("image must be 3-D [m_z, m_y, m_x]")
+    mz, my_, mx = (int(k) for k in img.shape)
+    m = (ctypes.c_int32 * 3)(mx, my_, mz)
+    out = torch.empty(((mz + 1) // 2, (my_ + 1) // 2, (mx + 1) // 2), dtype=torch.float32, device=img.device)
+    _check(lib.mfr_restrict_image(m, _dev_tensor(img, mx * my_ * mz, "fine", img.device),
+                                  _dev_tensor(out, out.numel(), "coarse", img.device), _stream(img.device)))
+    return out
+
+
+def prolong(uc, coarse_spec, fine_spec):
+    """Displacement on the coarse deformation grid -> fine grid (linear, per dimension).
+    The specs may be grid specs or CGrid structures."""
+    lib = load()
+    gc = coarse_spec if isinstance(coarse_spec, CGrid) else make_grid(coarse_spec)
+    gf = fine_spec if isinstance(fine_spec, CGrid) else make_grid(fine_spec)
+    dev = uc.device
+    n = ctypes.c_size_t()
+    _check(lib.mfr_prolong_workspace_size(ctypes.byref(gf), ctypes.byref(n)))
+    work, ptr = _alloc_workspace(n.value, dev)
+    out = torch.empty((3, gf.my[2], gf.my[1], gf.my[0]), dtype=torch.float32, device=dev)
+    _check(lib.mfr_prolong(ctypes.byref(gc), ctypes.byref(gf),
+                           _dev_tensor(uc, 3 * gc.my[0] * gc.my[1] * gc.my[2], "uc", dev),
+                           _dev_tensor(out, out.numel(), "uf", dev), ctypes.c_void_p(ptr), n.value, _stream(dev)))
+    del work
+    return out
 
 
 def set_tile_config(bx, by, chunk_len=0, target_groups=0):

@@ -9,6 +9,8 @@ from .volumes import (  # noqa: F401
     GridSpec,
     blob_pair,
     ct_pair,
+    ct_warp,
+    ct_inverse_target,
     smooth_field,
     quarter_nodes,
     config_c1,

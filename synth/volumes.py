@@ -268,6 +268,52 @@ def ct_pair(seed, m, max_disp=6.0, ctrl_spacing=16.0, noise=20.0, offset=1000.0,
     return R, T, ustar, rng
 
 
+def ct_warp(seed, m, pts, max_disp=6.0, ctrl_spacing=16.0):
+    """The generating displacement u* of ``ct_pair(seed, m)`` evaluated at
+    arbitrary points ``pts`` (..., 3) in voxel units (x, y, z order): the same
+    B-spline coefficients and scale, so at voxel centres it reproduces the
+    u_star that ct_pair returns (up to its float32 rounding).  Returns
+    (..., 3) float64.  Generator arithmetic only."""
+    rng = np.random.default_rng(seed)
+    mx, my_, mz = m
+    _phantom_params(rng, m)
+    Bx, By, Bz = (_bspline_basis(k, ctrl_spacing) for k in (mx, my_, mz))
+    coef = rng.standard_normal((3, Bz.shape[1], By.shape[1], Bx.shape[1]))
+    # the scale ct_pair applies: max Euclidean norm over voxel centres
+    ux = np.einsum("dkji,xi->dkjx", coef, Bx)
+    uxy = np.einsum("dkjx,yj->dkyx", ux, By)
+    nmax = 0.0
+    for z0 in range(0, mz, 32):
+        blk = np.einsum("dkyx,zk->dzyx", uxy, Bz[z0:z0 + 32])
+        nmax = max(nmax, float(np.sqrt((blk ** 2).sum(0)).max()))
+    coef = coef * (max_disp / nmax)
+    pts = np.asarray(pts, dtype=np.float64)
+    flat = pts.reshape(-1, 3)
+
+    def basis(x, n_ctrl):
+        ctrl = (np.arange(n_ctrl) - 1) * ctrl_spacing
+        return _bspline3((x[:, None] - ctrl[None, :]) / ctrl_spacing)
+
+    wx = basis(flat[:, 0], Bx.shape[1])
+    wy = basis(flat[:, 1], By.shape[1])
+    wz = basis(flat[:, 2], Bz.shape[1])
+    out = np.einsum("dkji,pi,pj,pk->pd", coef, wx, wy, wz)
+    return out.reshape(pts.shape)
+
+
+def ct_inverse_target(seed, m, pts, iters=60, **kw):
+    """Displacement u at points x that aligns the pair of ``ct_pair(seed, m)``:
+    the template is the phantom at x - u*(x), so T(x + u(x)) equals the
+    reference phantom at x when u(x) = u*(x + u(x)).  Solved by the fixed-point
+    iteration u <- u*(x + u) (a contraction while |grad u*| < 1).  Returns
+    (..., 3) float64 in x, y, z order."""
+    pts = np.asarray(pts, dtype=np.float64)
+    u = ct_warp(seed, m, pts, **kw)
+    for _ in range(iters):
+        u = ct_warp(seed, m, pts + u, **kw)
+    return u
+
+
 def config_c2(seed=0, device="cpu"):
     """128 x 128 x 96 CT-like pair, finest grid 65 x 65 x 49 nodes, alpha 0.1,
     eps 50 HU; multilevel (3 levels) Gauss-Newton / Jacobi-PCG."""

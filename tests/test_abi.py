@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.mfr_abi_version() == 2
+    assert lib.mfr_abi_version() == 3
 
 
 def _ws(spec):

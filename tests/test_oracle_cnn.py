@@ -181,16 +181,21 @@ def test_fpcg_equals_pcg_for_a_fixed_linear_preconditioner():
 
 
 def test_fpcg_plain_cg_exact_in_n_steps_and_fallback():
+    # inputs drawn here, not from the module's shared generator, so they do not depend
+    # on which tests ran before in the same process
+    rng = np.random.default_rng(12)
     n = 12
-    A = _spd(n)
-    b = rand(n)
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.standard_normal(n)
     s, info = solver.fpcg(lambda p: A @ p, b, lambda r: r, max_iter=n, rtol=1e-10)
     assert info["flag"] == 0 and info["iters"] <= n
     assert np.allclose(A @ s, b, rtol=1e-8)
-    # a useless preconditioner (a fixed random direction) gives up after 3 steps for Jacobi
+    # a poor preconditioner (random positive scales over six decades) has not converged after
+    # 3 steps; the solve then continues with Jacobi and converges
     d = np.diag(A).copy()
-    junk = rand(n)
-    s, info = solver.fpcg(lambda p: A @ p, b, lambda r: junk * np.sign(junk @ r + 1e-300), max_iter=60,
+    w = 10.0 ** rng.uniform(-3.0, 3.0, n)
+    s, info = solver.fpcg(lambda p: A @ p, b, lambda r: w * r, max_iter=60,
                           rtol=1e-8, fallback=lambda r: r / d, fallback_iters=3)
     assert info["used_fallback"] == 1 and info["flag"] == 0
     assert np.allclose(A @ s, b, rtol=1e-6, atol=1e-8)

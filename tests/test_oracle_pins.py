@@ -491,6 +491,78 @@ def test_prolongation_exact_for_linear_fields_and_restriction_of_constants():
     np.testing.assert_allclose(Ic, 2.5)
 
 
+def _restrict_loops(I):
+    """The 2x2x2 mean by explicit loops over coarse voxels and their (up to 8)
+    fine children, an index past the end replaced by the last one."""
+    mz, my, mx = I.shape
+    out = np.zeros(((mz + 1) // 2, (my + 1) // 2, (mx + 1) // 2))
+    for c in range(out.shape[0]):
+        for b in range(out.shape[1]):
+            for a in range(out.shape[2]):
+                acc = 0.0
+                for k in (0, 1):
+                    for j in (0, 1):
+                        for i in (0, 1):
+                            acc += I[min(2 * c + k, mz - 1), min(2 * b + j, my - 1), min(2 * a + i, mx - 1)]
+                out[c, b, a] = acc / 8.0
+    return out
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (5, 7, 3), (1, 2, 3), (3, 1, 1), (9, 4, 6)])
+def test_restriction_brute_force_loops_odd_and_even(shape):
+    # Sec. 2.3 (coarse-to-fine): one pyramid level of random images of odd and even sizes
+    I = np.random.default_rng(sum(shape)).standard_normal(shape)
+    np.testing.assert_allclose(multilevel.restrict_image(I), _restrict_loops(I), rtol=0, atol=1e-14)
+
+
+def test_restriction_reproduces_linear_fields_at_coarse_centres():
+    # a field linear in the position, sampled at fine cell centres (a + 1/2) h, restricts to
+    # the same field at the coarse cell centres (a' + 1/2) 2h: this fixes the voxel pairing
+    # (a shifted pairing moves it by h, subsampling by h/2); with odd sizes the last coarse
+    # cell is the mean of the last fine cell with itself, i.e. that cell's value
+    mz, my, mx = 6, 8, 10
+    z, y, x = np.meshgrid(np.arange(mz) + 0.5, np.arange(my) + 0.5, np.arange(mx) + 0.5, indexing="ij")
+    I = 0.7 * x - 1.3 * y + 0.4 * z + 2.0
+    zc, yc, xc = np.meshgrid(2 * (np.arange(3) + 0.5), 2 * (np.arange(4) + 0.5), 2 * (np.arange(5) + 0.5),
+                             indexing="ij")
+    np.testing.assert_allclose(multilevel.restrict_image(I), 0.7 * xc - 1.3 * yc + 0.4 * zc + 2.0, atol=1e-13)
+    I2 = (0.5 * (np.arange(7) + 0.5))[None, None, :] * np.ones((2, 2, 7))   # odd x: 7 cells
+    Ic = multilevel.restrict_image(I2)[0, 0]
+    np.testing.assert_allclose(Ic[:3], 0.5 * 2 * (np.arange(3) + 0.5), atol=1e-14)
+    assert Ic[3] == I2[0, 0, 6]
+
+
+def test_restriction_preserves_the_mean_and_annihilates_the_checkerboard():
+    rng = np.random.default_rng(11)
+    I = rng.standard_normal((6, 4, 8))
+    assert abs(multilevel.restrict_image(I).mean() - I.mean()) < 1e-14
+    z, y, x = np.meshgrid(np.arange(6), np.arange(4), np.arange(8), indexing="ij")
+    np.testing.assert_allclose(multilevel.restrict_image((-1.0) ** (x + y + z)), 0.0, atol=1e-15)
+    np.testing.assert_allclose(multilevel.restrict_image((-1.0) ** x), 0.0, atol=1e-15)
+
+
+def test_prolongation_exact_at_coincident_nodes_and_partition_of_unity():
+    # every other fine node sits on a coarse node (ceil((my - 1)/2) coarse cells of twice
+    # the spacing): the prolongated field takes the coarse value there exactly; constants stay
+    g = Grid((16, 12, 8), (1, 1, 1), (9, 7, 5), 1, 1, 1)
+    gc = multilevel.coarse_grid(g)
+    uc = np.random.default_rng(3).standard_normal((3, gc.my[2], gc.my[1], gc.my[0]))
+    uf = multilevel.prolong(uc, gc, g)
+    np.testing.assert_allclose(uf[:, ::2, ::2, ::2], uc, atol=1e-14)
+    np.testing.assert_allclose(multilevel.prolong(np.full_like(uc, 1.5), gc, g), 1.5, atol=1e-14)
+    # odd deformation-cell counts (5 fine cells -> 3 coarse ones of spacing 10/3): fine
+    # nodes no longer coincide with coarse ones, linear fields are still reproduced
+    g2 = Grid((10, 9, 7), (1, 1, 1), (6, 4, 4), 1, 1, 1)
+    gc2 = multilevel.coarse_grid(g2)
+    assert gc2.my == (4, 3, 3)
+    xc = gc2.node_positions()
+    xf = g2.node_positions()
+    lin = lambda X: np.stack([0.2 * X[0] + 0.1 * X[1], -0.3 * X[2] + 0.5, 0.05 * X[0] - 0.2 * X[1]])
+    inside = (xf[1] <= xc[1].max() + 1e-12) & (xf[2] <= xc[2].max() + 1e-12)
+    uf2 = multilevel.prolong(lin(xc), gc2, g2)
+    np.testing.assert_allclose(uf2[:, inside], lin(xf)[:, inside], atol=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Sum-of-squared-differences distance (Sec. 4.4: dr/dT = identity)
 # ---------------------------------------------------------------------------
