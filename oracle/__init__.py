@@ -20,9 +20,11 @@ distance (Sec. 4.4: the residual Jacobian becomes the identity).
 alternatives to curvature.
 ``lbfgs`` is the limited-memory BFGS alternative of Sec. 2.3.2 with the
 regulariser's Hessian in the initial matrix.
+``plane`` is the two-dimensional case (d = 2) of the whole path, written
+separately (the paper's GPU experiments are 2D).
 ``cnn`` defines the learned preconditioner, an extension of the method
 (convolutions, network, features, loss), and ``solver.fpcg`` the flexible CG
 that uses it.
 """
 from .grid import Grid  # noqa: F401
-from . import interp, ngf, ssd, curvature, diffusive, elastic, solver, multilevel, lbfgs, cnn  # noqa: F401
+from . import interp, ngf, ssd, curvature, diffusive, elastic, solver, multilevel, lbfgs, cnn, plane  # noqa: F401

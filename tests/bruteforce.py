@@ -155,3 +155,65 @@ def elastic_S(my, hy, u, mu, lam):
                     div += tot / (4.0 * hy[d])
                 S += 0.5 * hyb * (lam + mu) * div * div
     return S
+
+
+# --- two dimensions (d = 2), loop by loop -------------------------------------
+
+def _bil(T, mT, hT, p):
+    s = [p[d] / hT[d] - 0.5 for d in range(2)]
+    k = [int(math.floor(s[d])) for d in range(2)]
+    f = [s[d] - k[d] for d in range(2)]
+    tot = 0.0
+    for oy in (0, 1):
+        for ox in (0, 1):
+            ix, iy = k[0] + ox, k[1] + oy
+            if 0 <= ix < mT[0] and 0 <= iy < mT[1]:
+                tot += (f[0] if ox else 1 - f[0]) * (f[1] if oy else 1 - f[1]) * T[iy][ix]
+    return tot
+
+
+def objective_D_2d(m, h, my, tau, rho, R, T, u, mT=None, hT=None):
+    """D(y) of a 2D problem: R, T [y][x]; u [2][ny][nx]; bilinear conversion
+    and template, four short differences per voxel, clamped neighbours."""
+    mT = mT or m
+    hT = hT or h
+    mx, my_ = m
+    hy = [m[d] * h[d] / (my[d] - 1) for d in range(2)]
+    Tw = [[0.0] * mx for _ in range(my_)]
+    for b in range(my_):
+        for a in range(mx):
+            yhat = [0.0, 0.0]
+            for (i, wi) in _node_weights_1d(a, mx, my[0]):
+                for (j, wj) in _node_weights_1d(b, my_, my[1]):
+                    node = (i * hy[0], j * hy[1])
+                    for d in range(2):
+                        yhat[d] += wi * wj * (node[d] + u[d][j][i])
+            Tw[b][a] = _bil(T, mT, hT, yhat)
+
+    def grad4(I, a, b):
+        return [(I[b][a] - I[b][max(a - 1, 0)]) / h[0], (I[b][a] - I[max(b - 1, 0)][a]) / h[1],
+                (I[b][min(a + 1, mx - 1)] - I[b][a]) / h[0], (I[min(b + 1, my_ - 1)][a] - I[b][a]) / h[1]]
+
+    D = 0.0
+    for b in range(my_):
+        for a in range(mx):
+            gT, gR = grad4(Tw, a, b), grad4(R, a, b)
+            num = 0.5 * sum(x * y for x, y in zip(gT, gR)) + tau * rho
+            nT = math.sqrt(0.5 * sum(x * x for x in gT) + tau * tau)
+            nR = math.sqrt(0.5 * sum(x * x for x in gR) + rho * rho)
+            r = num / (nT * nR)
+            D += h[0] * h[1] * (1.0 - r * r)
+    return D
+
+
+def curvature_S_2d(my, hy, u):
+    nx, ny = my
+    S = 0.0
+    for d in range(2):
+        for j in range(ny):
+            for i in range(nx):
+                c0 = u[d][j][i]
+                lap = ((u[d][j][max(i - 1, 0)] - 2 * c0 + u[d][j][min(i + 1, nx - 1)]) / hy[0] ** 2
+                       + (u[d][max(j - 1, 0)][i] - 2 * c0 + u[d][min(j + 1, ny - 1)][i]) / hy[1] ** 2)
+                S += hy[0] * hy[1] * lap * lap
+    return S
