@@ -21,6 +21,15 @@
  *    the image domain.
  *  - The unknown is the DISPLACEMENT u = y - x^y (Sec. 2.2); derivatives with
  *    respect to u and y coincide.
+ *  - Two-dimensional problems (the d = 2 case of Sec. 2.2; the paper's GPU
+ *    experiments of Sec. 6.3 are 2D) have one image cell and one node along z:
+ *    m[2] = my[2] = 1 (mT[2] 0 or 1; h[2], hT[2] are ignored).  Images are
+ *    [m_y][m_x], node vectors [2][n_y][n_x] (x components, then y), the
+ *    interpolation is bilinear, four short differences per pixel, the 5-point
+ *    Laplacian, hbar = h_x h_y.  They take the NGF distance and the curvature
+ *    regulariser; every single-pair call accepts them except the L-BFGS and
+ *    learned-preconditioner calls (MFR_EINVAL), and the batched path takes
+ *    three-dimensional problems only.
  *  - Every pointer argument named R, T, u, p, q, g, b, s, diag or workspace is
  *    a DEVICE pointer (hipMalloc / torch CUDA memory), 4-byte aligned (the
  *    workspace 256-byte aligned), owned by the caller and only borrowed for the
@@ -77,7 +86,7 @@ typedef enum {
 /* Problem description (Sec. 2.2; notation table).  Sizes and spacings are
  * given per dimension in the order x, y, z. */
 typedef struct {
-  int32_t m[3];     /* image grid cells; 2 <= m                                              */
+  int32_t m[3];     /* image grid cells; 2 <= m (m[2] = my[2] = 1: a 2D problem)              */
   double h[3];      /* image grid spacing; > 0                                                */
   int32_t my[3];    /* deformation grid NODES; 2 <= my and my - 1 <= m (Sec. 2.2)             */
   int32_t mT[3];    /* template grid cells (all 0: same as m)                                 */
@@ -228,7 +237,8 @@ mfr_status mfr_ml_workspace_size(const mfr_grid* finest, int32_t levels, size_t*
  * multilevel registration with `levels` levels: ceil(m/2) image cells and
  * ceil((my-1)/2) deformation cells per coarser level, spacings doubled
  * (Sec. 2.3, coarse-to-fine; the coarse grids themselves are not specified by
- * the paper). */
+ * the paper).  The returned grid states the template grid explicitly (mT, hT
+ * never 0, also for the finest level). */
 mfr_status mfr_ml_level_grid(const mfr_grid* finest, int32_t levels, int32_t level, mfr_grid* out);
 
 /* Coarse-to-fine Gauss-Newton registration (Sec. 2.3): image pyramid of

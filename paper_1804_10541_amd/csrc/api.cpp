@@ -39,7 +39,17 @@ mfr_status make_geo(const mfr_grid* g, Geo* o) {
   if (!g) return fail(MFR_EINVAL, "grid is NULL");
   const bool tdef = g->mT[0] == 0 && g->mT[1] == 0 && g->mT[2] == 0;
   const bool hdef = g->hT[0] == 0 && g->hT[1] == 0 && g->hT[2] == 0;
+  // one cell and one node along z: the two-dimensional problem (d = 2 in Sec. 2.2)
+  const bool plane = g->m[2] == 1 && g->my[2] == 1;
+  o->dim = plane ? 2 : 3;
+  if (plane && !(g->mT[2] == 0 || g->mT[2] == 1))
+    return fail(MFR_EINVAL, "a two-dimensional problem (m[2] = my[2] = 1) needs mT[2] = 0 or 1");
   for (int k = 0; k < 3; ++k) {
+    if (plane && k == 2) {
+      o->m[2] = o->n[2] = o->mT[2] = 1;
+      o->h[2] = o->hT[2] = o->hy[2] = 1.0;
+      continue;
+    }
     o->m[k] = g->m[k];
     o->n[k] = g->my[k];
     o->h[k] = g->h[k];
@@ -73,9 +83,11 @@ mfr_status make_geo(const mfr_grid* g, Geo* o) {
   o->tau = g->tau;
   o->rho = g->rho;
   o->alpha = g->alpha;
+  if (plane && (o->dist != MFR_DIST_NGF || o->reg != MFR_REG_CURVATURE))
+    return fail(MFR_EINVAL, "two-dimensional problems take the NGF distance and the curvature regulariser");
   o->mbar = (size_t)o->m[0] * o->m[1] * o->m[2];
   o->nbar = (size_t)o->n[0] * o->n[1] * o->n[2];
-  const size_t tpad = (size_t)(o->mT[0] + 4) * (o->mT[1] + 4) * (o->mT[2] + 4);
+  const size_t tpad = (size_t)(o->mT[0] + 4) * (o->mT[1] + 4) * (plane ? 1 : o->mT[2] + 4);
   // kernels address images, the padded template and node vectors with 32-bit byte offsets
   if (o->mbar >= (size_t)1 << 30 || 3 * o->nbar >= (size_t)1 << 30 || tpad >= (size_t)1 << 30)
     return fail(MFR_EINVAL, "problem too large: images, padded template and node vectors must stay below 2^30 elements");
@@ -183,8 +195,40 @@ static mfr_tile_config g_tile_cfg = [] {
 mfr_tile_config current_tile_config() { return g_tile_cfg; }
 void set_tile_config(const mfr_tile_config& c) { g_tile_cfg = c; }
 
+// Two-dimensional problems: work-groups of kPlaneNT pixel columns (one-column
+// ring), rows marched in chunks; the node pass sees x tiles, one tile row and
+// the row chunks as z chunks.
+static Tiling make_tiling_plane(const Geo& g, const std::vector<Conv1>& cx, const std::vector<Conv1>& cy) {
+  Tiling t;
+  const mfr_tile_config cfg = current_tile_config();
+  t.shape = TileShape{kPlaneNT, 1};
+  const int TX = kPlaneNT - 2;
+  t.tiles_x = (g.m[0] + TX - 1) / TX;
+  t.tiles_y = 1;
+  const int target = cfg.target_groups > 0 ? cfg.target_groups : 2048;
+  int chunks = std::max(1, (target + t.tiles_x - 1) / t.tiles_x);
+  chunks = std::min(chunks, std::max(1, g.m[1] / 16));
+  int clen = (g.m[1] + chunks - 1) / chunks;
+  if (cfg.chunk_len > 0) clen = cfg.chunk_len;
+  t.chunk_len = std::min(std::min(clen, g.m[1]), kMaxChunk);
+  t.chunks = (g.m[1] + t.chunk_len - 1) / t.chunk_len;
+  t.nxt = 0;
+  t.nyt = 1;
+  t.nzt = 0;
+  for (int i = 0; i < t.tiles_x; ++i) {
+    const int a0 = std::max(i * TX - 1, 0), a1 = std::min(i * TX + TX, g.m[0] - 1);
+    t.nxt = std::max(t.nxt, cx[a1].n0 + 2 - cx[a0].n0);
+  }
+  for (int i = 0; i < t.chunks; ++i) {
+    const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[1]) - 1;
+    t.nzt = std::max(t.nzt, cy[a1].n0 + 2 - cy[a0].n0);
+  }
+  return t;
+}
+
 Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector<Conv1>& cy,
                    const std::vector<Conv1>& cz) {
+  if (g.dim == 2) return make_tiling_plane(g, cx, cy);
   Tiling t;
   const mfr_tile_config cfg = current_tile_config();
   t.shape = TileShape{cfg.bx, cfg.by};
@@ -231,16 +275,19 @@ Layout make_layout(const Geo& g, const Tiling& t) {
     o = align_up(o + bytes);
     return at;
   };
-  L.Tp = take(sizeof(float) * (size_t)(g.mT[0] + 4) * (g.mT[1] + 4) * (g.mT[2] + 4));
+  const bool plane = g.dim == 2;
+  const int nc = g.nc();
+  L.Tp = take(sizeof(float) * (size_t)(g.mT[0] + 4) * (g.mT[1] + 4) * (plane ? 1 : g.mT[2] + 4));
   L.cx = take(sizeof(Conv1) * g.m[0]);
   L.cy = take(sizeof(Conv1) * g.m[1]);
   L.cz = take(sizeof(Conv1) * g.m[2]);
   L.sx = take(sizeof(Samp1) * g.m[0]);
   L.sy = take(sizeof(Samp1) * g.m[1]);
   L.sz = take(sizeof(Samp1) * g.m[2]);
+  // node-pass tile ranges; a two-dimensional problem is seen as n[0] x 1 x n[1] nodes
   L.ntx = take(sizeof(Range1) * g.n[0]);
-  L.nty = take(sizeof(Range1) * g.n[1]);
-  L.ntz = take(sizeof(Range1) * g.n[2]);
+  L.nty = take(sizeof(Range1) * (plane ? 1 : g.n[1]));
+  L.ntz = take(sizeof(Range1) * (plane ? g.n[1] : g.n[2]));
   L.orgx = take(sizeof(int) * t.tiles_x);
   L.orgy = take(sizeof(int) * t.tiles_y);
   L.orgz = take(sizeof(int) * t.chunks);
@@ -256,8 +303,8 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.n_red_node = std::max<size_t>(3 * node_blocks, 2 * 1024);   // the node pass: one partial per block and component
   L.red_node = take(sizeof(double) * L.n_red_node);
   L.sc = take(sizeof(double) * SC_COUNT);
-  L.vec = take(sizeof(float) * 3 * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
-  L.lap = take(sizeof(float) * 3 * g.nbar);       // curvature Laplacian (node pass, first half)
+  L.vec = take(sizeof(float) * nc * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
+  L.lap = take(sizeof(float) * nc * g.nbar);       // curvature Laplacian (node pass, first half)
   L.div = take(sizeof(float) * g.nbar);           // elastic: divergence per cell of the nodal grid
   L.ctrl = take(sizeof(int) * (1 + ST_COUNT));    // device-steered CG: active flag, state
   L.total = o;
@@ -270,8 +317,161 @@ Layout make_layout(const Geo& g, const Tiling& t) {
 namespace mfr {
 
 
+// Groups whose columns [i T - 1, i T + T] meet the columns [lo, hi] of a node's support.
+static Range1 groups_touching(const Range1& cols, int T, int tiles) {
+  const int lo = cols.lo < T ? 0 : (cols.lo - 1) / T;
+  return Range1{lo, std::min(tiles - 1, (cols.hi + 1) / T)};
+}
+
+// Context of a two-dimensional problem: tables, the tile kernel's parameters
+// (TileParams with mz = nz = 1), the node pass's view of the n[0] x n[1] node
+// grid as n[0] x 1 x n[1] (x tiles, one tile row, row chunks as z chunks; the
+// clamped 7-point Laplacian with a single node along y is the 5-point one) and
+// the one-thread-per-node Jacobi kernel.
+static mfr_status ctx_init_plane(mfr_ctx* c, void* stream, void* ws, size_t ws_bytes) {
+  const Geo& g = c->geo;
+  auto cx = conv_table(g.m[0], g.n[0]);
+  auto cy = conv_table(g.m[1], g.n[1]);
+  c->tiling = make_tiling(g, cx, cy, cy);
+  c->lay = make_layout(g, c->tiling);
+  if (!ws) return fail(MFR_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(MFR_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < c->lay.total)
+    return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", ws_bytes, c->lay.total);
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(ws);
+  c->R = nullptr;
+  c->have_images = false;
+  const Tiling& t = c->tiling;
+  const int TX = kPlaneNT - 2;
+  auto sx = samp_table(g.m[0], g.h[0], g.hT[0]);
+  auto sy = samp_table(g.m[1], g.h[1], g.hT[1]);
+  auto colx = node_cols(cx, g.n[0]), coly = node_cols(cy, g.n[1]);
+  std::vector<Range1> ntx(g.n[0]), nty(1, Range1{0, 0}), ntz(g.n[1]), rx(g.n[0]), ry(g.n[1]);
+  for (int i = 0; i < g.n[0]; ++i) {
+    ntx[i] = groups_touching(colx[i], TX, t.tiles_x);
+    rx[i] = Range1{std::max(colx[i].lo - 1, 0), std::min(colx[i].hi + 1, g.m[0] - 1)};
+  }
+  for (int i = 0; i < g.n[1]; ++i) {
+    ntz[i] = Range1{coly[i].lo / t.chunk_len, coly[i].hi / t.chunk_len};
+    ry[i] = Range1{std::max(coly[i].lo - 1, 0), std::min(coly[i].hi + 1, g.m[1] - 1)};
+  }
+  std::vector<int> orgx(t.tiles_x), orgy(1, 0), orgz(t.chunks);
+  for (int i = 0; i < t.tiles_x; ++i) orgx[i] = cx[std::max(i * TX - 1, 0)].n0;
+  for (int i = 0; i < t.chunks; ++i) orgz[i] = cy[i * t.chunk_len].n0;
+  const Layout& L = c->lay;
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  HIP_TRY(up(L.cx, cx.data(), sizeof(Conv1) * cx.size()));
+  HIP_TRY(up(L.cy, cy.data(), sizeof(Conv1) * cy.size()));
+  HIP_TRY(up(L.sx, sx.data(), sizeof(Samp1) * sx.size()));
+  HIP_TRY(up(L.sy, sy.data(), sizeof(Samp1) * sy.size()));
+  HIP_TRY(up(L.ntx, ntx.data(), sizeof(Range1) * ntx.size()));
+  HIP_TRY(up(L.nty, nty.data(), sizeof(Range1) * nty.size()));
+  HIP_TRY(up(L.ntz, ntz.data(), sizeof(Range1) * ntz.size()));
+  HIP_TRY(up(L.orgx, orgx.data(), sizeof(int) * orgx.size()));
+  HIP_TRY(up(L.orgy, orgy.data(), sizeof(int) * orgy.size()));
+  HIP_TRY(up(L.orgz, orgz.data(), sizeof(int) * orgz.size()));
+  HIP_TRY(up(L.rx, rx.data(), sizeof(Range1) * rx.size()));
+  HIP_TRY(up(L.ry, ry.data(), sizeof(Range1) * ry.size()));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+
+  TileParams& p = c->tp;
+  p = TileParams{};
+  p.live = nullptr;
+  p.mx = g.m[0];
+  p.my = g.m[1];
+  p.mz = 1;
+  p.nx = g.n[0];
+  p.ny = g.n[1];
+  p.nz = 1;
+  p.nbar = (int)g.nbar;
+  p.mTx = g.mT[0];
+  p.mTy = g.mT[1];
+  p.mTz = 1;
+  p.PX = g.mT[0] + 4;
+  p.PY = g.mT[1] + 4;
+  p.PXY = (long long)p.PX * p.PY;
+  p.ih2x = (float)(1.0 / (g.h[0] * g.h[0]));
+  p.ih2y = (float)(1.0 / (g.h[1] * g.h[1]));
+  p.hhx = (float)(0.5 / (g.h[0] * g.h[0]));
+  p.hhy = (float)(0.5 / (g.h[1] * g.h[1]));
+  p.ihTx = (float)(1.0 / g.hT[0]);
+  p.ihTy = (float)(1.0 / g.hT[1]);
+  p.tau2 = (float)(g.tau * g.tau);
+  p.rho2 = (float)(g.rho * g.rho);
+  p.taurho = (float)(g.tau * g.rho);
+  p.Tp = at<float>(c->ws, L.Tp);
+  p.cx = at<Conv1>(c->ws, L.cx);
+  p.cy = at<Conv1>(c->ws, L.cy);
+  p.sx = at<Samp1>(c->ws, L.sx);
+  p.sy = at<Samp1>(c->ws, L.sy);
+  p.tiles_x = t.tiles_x;
+  p.tiles_y = 1;
+  p.chunks = t.chunks;
+  p.chunk_len = t.chunk_len;
+  p.nxt = t.nxt;
+  p.nyt = 1;
+  p.nzt = t.nzt;
+  p.part = at<float>(c->ws, L.part);
+  p.red = at<double>(c->ws, L.red_tile);
+
+  NodeParams& q = c->np;
+  q = NodeParams{};
+  q.nx = g.n[0];
+  q.ny = 1;
+  q.nz = g.n[1];
+  q.nbar = (int)g.nbar;
+  q.nc = 2;
+  q.ihy2x = (float)(1.0 / (g.hy[0] * g.hy[0]));
+  q.ihy2y = 0.0f;
+  q.ihy2z = (float)(1.0 / (g.hy[1] * g.hy[1]));
+  q.s_ngf = 0.0f;
+  q.s_curv = (float)g.reg_scale();
+  q.reg = MFR_REG_CURVATURE;
+  q.div = at<float>(c->ws, L.div);
+  q.tiles_x = t.tiles_x;
+  q.tiles_y = 1;
+  q.nxt = t.nxt;
+  q.nyt = 1;
+  q.nzt = t.nzt;
+  q.part = p.part;
+  q.ntx = at<Range1>(c->ws, L.ntx);
+  q.nty = at<Range1>(c->ws, L.nty);
+  q.ntz = at<Range1>(c->ws, L.ntz);
+  q.orgx = at<int>(c->ws, L.orgx);
+  q.orgy = at<int>(c->ws, L.orgy);
+  q.orgz = at<int>(c->ws, L.orgz);
+  q.red = at<double>(c->ws, L.red_node);
+  q.lap = at<float>(c->ws, L.lap);
+  q.live = nullptr;
+  c->ctrl = at<int>(c->ws, L.ctrl);
+
+  DiagParams& d = c->dp;
+  d = DiagParams{};
+  d.t = p;
+  d.rx = at<Range1>(c->ws, L.rx);
+  d.ry = at<Range1>(c->ws, L.ry);
+  d.rz = nullptr;
+  d.s_ngf = (float)g.hess_scale();
+  d.s_curv = q.s_curv;
+  d.ihy2x = q.ihy2x;
+  d.ihy2y = q.ihy2z;
+  d.ihy2z = 0.0f;
+  c->jac_tiled = false;
+
+  c->sc = at<double>(c->ws, L.sc);
+  c->red_tile = p.red;
+  c->red_node = q.red;
+  for (int k = 0; k < 8; ++k) c->vec[k] = at<float>(c->ws, L.vec) + (size_t)k * 2 * g.nbar;
+  c->vec_blocks = (int)std::min<size_t>((2 * g.nbar + kVecBlock - 1) / kVecBlock, 1024);
+  return MFR_OK;
+}
+
 mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes) {
   MFR_TRY(make_geo(grid, &c->geo));
+  if (c->geo.dim == 2) return ctx_init_plane(c, stream, ws, ws_bytes);
   const Geo& g = c->geo;
   auto cx = conv_table(g.m[0], g.n[0]);
   auto cy = conv_table(g.m[1], g.n[1]);
@@ -289,11 +489,6 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   c->have_images = false;
   const Tiling& t = c->tiling;
   const int TX = t.shape.bx - 2, TY = t.shape.by - 2;
-  // groups whose columns [i TX - 1, i TX + TX] meet the columns [lo, hi] of a node's support
-  auto groups_touching = [](const Range1& cols, int T, int tiles) {
-    const int lo = cols.lo < T ? 0 : (cols.lo - 1) / T;
-    return Range1{lo, std::min(tiles - 1, (cols.hi + 1) / T)};
-  };
 
   auto sx = samp_table(g.m[0], g.h[0], g.hT[0]);
   auto sy = samp_table(g.m[1], g.h[1], g.hT[1]);
@@ -405,6 +600,7 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   q.ny = g.n[1];
   q.nz = g.n[2];
   q.nbar = (int)g.nbar;
+  q.nc = 3;
   q.ihy2x = (float)(1.0 / (g.hy[0] * g.hy[0]));
   q.ihy2y = (float)(1.0 / (g.hy[1] * g.hy[1]));
   q.ihy2z = (float)(1.0 / (g.hy[2] * g.hy[2]));
@@ -493,6 +689,7 @@ hipError_t timed(mfr_ctx* c, int slot, F&& launch) {
 }
 
 hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
+  if (c->geo.dim == 2) return launch_plane_jacobi(c->dp, u, diag, c->stream);
   if (c->jac_tiled) return launch_jacobi_tile(c->jp, u, diag, c->stream);
   return launch_jacobi_diag(c->dp, u, diag, c->stream);
 }
@@ -502,11 +699,11 @@ hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
 hipError_t enqueue_pcg_diag(mfr_ctx* c, const float* u, float* diag) {
   hipError_t e = enqueue_diag(c, u, diag);
   if (e != hipSuccess) return e;
-  return launch_safe_diag((int)(3 * c->geo.nbar), diag, c->stream);
+  return launch_safe_diag((int)(c->geo.nc() * c->geo.nbar), diag, c->stream);
 }
 
 int node_blocks(const mfr_ctx* c) { return (int)((c->geo.nbar + kNodeBlock - 1) / kNodeBlock); }
-int node_parts(const mfr_ctx* c) { return 3 * node_blocks(c); }
+int node_parts(const mfr_ctx* c) { return c->geo.nc() * node_blocks(c); }
 
 mfr_status check_ptr(const void* p, const char* name) {
   if (!p) return fail(MFR_EINVAL, "%s is NULL", name);
@@ -520,10 +717,17 @@ mfr_status need_images(const mfr_ctx* c) {
   return MFR_OK;
 }
 
+// The fused voxel-tile kernel of the context's dimension.
+static hipError_t launch_tiles(const mfr_ctx* c, int mode, const TileParams& tp, const float* u, const float* p) {
+  const Tiling& t = c->tiling;
+  if (c->geo.dim == 2) return launch_plane_tile(mode, tp, u, p, t.grid(), c->stream);
+  return launch_tile(t.shape, mode, tp, u, p, t.grid(), c->stream);
+}
+
 // Enqueue: D and S sums into sc[SC_D], sc[SC_S].
 mfr_status enqueue_objective(mfr_ctx* c, const float* u) {
   const Tiling& t = c->tiling;
-  HIP_TRY(timed(c, 0, [&] { return launch_tile(t.shape, MODE_OBJ, c->tp, u, nullptr, t.grid(), c->stream); }));
+  HIP_TRY(timed(c, 0, [&] { return launch_tiles(c, MODE_OBJ, c->tp, u, nullptr); }));
   HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
   NodeParams q = c->np;
   HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_S, q, u, nullptr, node_blocks(c), c->stream); }));
@@ -547,7 +751,7 @@ mfr_status read_objective(mfr_ctx* c, double* J, double* D, double* S) {
 
 mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
   const Tiling& t = c->tiling;
-  HIP_TRY(timed(c, 1, [&] { return launch_tile(t.shape, MODE_GRAD, c->tp, u, nullptr, t.grid(), c->stream); }));
+  HIP_TRY(timed(c, 1, [&] { return launch_tiles(c, MODE_GRAD, c->tp, u, nullptr); }));
   HIP_TRY(launch_sum(c->red_tile, t.grid(), c->sc + SC_D, c->stream));
   NodeParams q = c->np;
   q.s_ngf = (float)c->geo.grad_scale();
@@ -558,8 +762,7 @@ mfr_status enqueue_gradient(mfr_ctx* c, const float* u, float* g) {
 
 // q = A p; p . q partials left in red_node
 mfr_status enqueue_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q) {
-  const Tiling& t = c->tiling;
-  HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, c->tp, u, p, t.grid(), c->stream); }));
+  HIP_TRY(timed(c, 2, [&] { return launch_tiles(c, MODE_HV, c->tp, u, p); }));
   NodeParams np = c->np;
   np.s_ngf = (float)c->geo.hess_scale();
   HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream); }));
@@ -602,7 +805,7 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   v.red = c->red_node;
   v.red_pq = c->red_node;
   v.n_pq = node_parts(c);
-  v.n3 = (int)(3 * c->geo.nbar);
+  v.n3 = (int)(c->geo.nc() * c->geo.nbar);
   v.max_iter = o->max_iter;
   v.rtol = o->rtol;
   V.active_out = c->ctrl;
@@ -612,12 +815,11 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   NodeParams np = c->np;
   np.s_ngf = (float)c->geo.hess_scale();
   np.live = c->ctrl;
-  const Tiling& t = c->tiling;
   int done = 0, active = 1;
   while (done < o->max_iter && active) {
     const int k = std::min(kSteerIters, o->max_iter - done);
     for (int i = 0; i < k; ++i) {
-      HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, tp, u, v.p, t.grid(), c->stream); }));
+      HIP_TRY(timed(c, 2, [&] { return launch_tiles(c, MODE_HV, tp, u, v.p); }));
       HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, v.p, v.q, node_blocks(c), c->stream); }));
       HIP_TRY(launch_pcg_alpha_batch(V, c->stream));
       HIP_TRY(launch_pcg_update_batch(V, c->stream));
@@ -649,7 +851,7 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
 mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
                             mfr_pcg_info* info) {
   if (!c->pc) return fail(MFR_EINVAL, "precond 2 needs a preconditioner attached with mfr_attach_pc");
-  const int n3 = (int)(3 * c->geo.nbar);
+  const int n3 = (int)(c->geo.nc() * c->geo.nbar);
   float* r = c->vec[0];
   float* z = c->vec[1];
   float* p = c->vec[2];
@@ -706,14 +908,13 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
   NodeParams np = c->np;
   np.s_ngf = (float)c->geo.hess_scale();
   np.live = active;
-  const Tiling& t = c->tiling;
   bool jacobi = false;
   int done = 0, act = 1;
   while (done < o->max_iter && act) {
     const int k = std::min(kSteerIters, o->max_iter - done);
     for (int i = 0; i < k; ++i) {
       const int it = done + i + 1;
-      HIP_TRY(timed(c, 2, [&] { return launch_tile(t.shape, MODE_HV, tp, u, p, t.grid(), c->stream); }));
+      HIP_TRY(timed(c, 2, [&] { return launch_tiles(c, MODE_HV, tp, u, p); }));
       HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, p, q, node_blocks(c), c->stream); }));
       HIP_TRY(launch_pcg_alpha_batch(V, c->stream));
       if (jacobi) {
@@ -763,7 +964,7 @@ mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, con
 // One Gauss-Newton step (Sec. 2.3.1).  Vectors: vec[5] right-hand side -grad J,
 // vec[6] trial point, vec[7] search direction.
 mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out) {
-  const int n3 = (int)(3 * c->geo.nbar);
+  const int n3 = (int)(c->geo.nc() * c->geo.nbar);
   float* b = c->vec[5];
   float* trial = c->vec[6];
   float* dir = c->vec[7];
@@ -825,7 +1026,7 @@ mfr_status mfr_workspace_size(const mfr_grid* grid, size_t* bytes) {
   auto cy = conv_table(g.m[1], g.n[1]);
   auto cz = conv_table(g.m[2], g.n[2]);
   Tiling t = make_tiling(g, cx, cy, cz);
-  if (!valid_shape(t.shape)) return fail(MFR_EINVAL, "unsupported tile shape %dx%d", t.shape.bx, t.shape.by);
+  if (g.dim == 3 && !valid_shape(t.shape)) return fail(MFR_EINVAL, "unsupported tile shape %dx%d", t.shape.bx, t.shape.by);
   *bytes = make_layout(g, t).total;
   return MFR_OK;
 }
@@ -855,7 +1056,8 @@ mfr_status mfr_set_images(mfr_ctx* c, const float* R, const float* T) {
   MFR_TRY(check_ptr(R, "R"));
   MFR_TRY(check_ptr(T, "T"));
   const Geo& g = c->geo;
-  HIP_TRY(launch_pad_template(T, at<float>(c->ws, c->lay.Tp), g.mT[0], g.mT[1], g.mT[2], c->stream));
+  HIP_TRY(launch_pad_template(T, at<float>(c->ws, c->lay.Tp), g.mT[0], g.mT[1], g.mT[2], g.dim == 2 ? 0 : 2,
+                              c->stream));
   c->R = R;
   c->tp.R = R;
   c->dp.t.R = R;
@@ -987,10 +1189,19 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
   std::vector<Level> L(levels);
   L[levels - 1].grid = *finest;
   MFR_TRY(make_geo(finest, &L[levels - 1].geo));
+  for (int k = 0; k < 3; ++k) {   // the finest grid's template sizes made explicit (0 = same as the image)
+    L[levels - 1].grid.mT[k] = L[levels - 1].geo.mT[k];
+    L[levels - 1].grid.hT[k] = L[levels - 1].geo.hT[k];
+  }
   for (int l = levels - 2; l >= 0; --l) {
     const Geo& f = L[l + 1].geo;
     mfr_grid g{};
     for (int k = 0; k < 3; ++k) {
+      if (f.dim == 2 && k == 2) {   // a two-dimensional pyramid keeps its single cell and node along z
+        g.m[2] = g.my[2] = g.mT[2] = 1;
+        g.h[2] = g.hT[2] = 1.0;
+        continue;
+      }
       g.m[k] = (f.m[k] + 1) / 2;
       g.h[k] = 2.0 * f.h[k];
       g.my[k] = (f.n[k] - 1 + 1) / 2 + 1;
@@ -1022,7 +1233,7 @@ mfr_status ml_levels(const mfr_grid* finest, int levels, std::vector<Level>* out
     L[l].off_T = o;
     o = align_up(o + sizeof(float) * (size_t)g.mT[0] * g.mT[1] * g.mT[2]);
     L[l].off_u = o;
-    o = align_up(o + sizeof(float) * 3 * g.nbar);
+    o = align_up(o + sizeof(float) * g.nc() * g.nbar);
   }
   const Geo& c = L[levels - 1].geo;  // prolongation tables of the finest level
   o = align_up(o + sizeof(Conv1) * (c.n[0] + c.n[1] + c.n[2]));
@@ -1080,7 +1291,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     MFR_TRY(mfr_workspace_size(&L[l].grid, &b));
     ctx_ws = std::max(ctx_ws, b);
   }
-  const size_t off_ptab = align_up(L[nl - 1].off_u + sizeof(float) * 3 * gf.nbar);
+  const size_t off_ptab = align_up(L[nl - 1].off_u + sizeof(float) * gf.nc() * gf.nbar);
 
   double Jfinal = 0.0;
   for (int l = 0; l < nl; ++l) {
@@ -1088,20 +1299,20 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     float* ul = at<float>(ws, L[l].off_u);
     if (l == 0) {
       if (o->u_init)
-        HIP_TRY(hipMemcpyAsync(ul, o->u_init, sizeof(float) * 3 * g.nbar, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(ul, o->u_init, sizeof(float) * g.nc() * g.nbar, hipMemcpyDeviceToDevice, st));
       else
-        HIP_TRY(launch_fill(3 * g.nbar, 0.0f, ul, st));
+        HIP_TRY(launch_fill(g.nc() * g.nbar, 0.0f, ul, st));
     } else {
       const Geo& gc = L[l - 1].geo;
       auto px = prolong_table(g.n[0], g.hy[0], gc.n[0], gc.hy[0]);
       auto py = prolong_table(g.n[1], g.hy[1], gc.n[1], gc.hy[1]);
-      auto pz = prolong_table(g.n[2], g.hy[2], gc.n[2], gc.hy[2]);
+      auto pz = g.dim == 2 ? std::vector<Conv1>(1, Conv1{0, 0.0f}) : prolong_table(g.n[2], g.hy[2], gc.n[2], gc.hy[2]);
       Conv1* dt = at<Conv1>(ws, off_ptab);
       HIP_TRY(hipMemcpyAsync(dt, px.data(), sizeof(Conv1) * px.size(), hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(dt + g.n[0], py.data(), sizeof(Conv1) * py.size(), hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(dt + g.n[0] + g.n[1], pz.data(), sizeof(Conv1) * pz.size(), hipMemcpyHostToDevice, st));
       HIP_TRY(launch_prolong(at<float>(ws, L[l - 1].off_u), gc.n[0], gc.n[1], gc.n[2], ul, g.n[0], g.n[1], g.n[2],
-                             dt, dt + g.n[0], dt + g.n[0] + g.n[1], st));
+                             dt, dt + g.n[0], dt + g.n[0] + g.n[1], g.nc(), st));
       HIP_TRY(hipStreamSynchronize(st));   // host tables must outlive the copies
     }
     mfr_ctx* c = nullptr;
@@ -1134,7 +1345,7 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
     Jfinal = Jv;
   }
   const Level& lf = L[nl - 1];
-  HIP_TRY(hipMemcpyAsync(u, ws + lf.off_u, sizeof(float) * 3 * lf.geo.nbar, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(u, ws + lf.off_u, sizeof(float) * lf.geo.nc() * lf.geo.nbar, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   rep.J_final = Jfinal;
   rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1191,17 +1402,19 @@ mfr_status mfr_prolong(const mfr_grid* coarse, const mfr_grid* fine, const float
   if (work_bytes < need) return fail(MFR_ENOMEM, "work buffer of %zu bytes is smaller than the required %zu", work_bytes, need);
   const char* a0 = reinterpret_cast<const char*>(uc);
   const char* b0 = reinterpret_cast<const char*>(uf);
-  if (b0 < a0 + 12 * gc.nbar && a0 < b0 + 12 * gf.nbar) return fail(MFR_EINVAL, "uf must not overlap uc");
+  if (gc.dim != gf.dim) return fail(MFR_EINVAL, "coarse and fine grids must have the same dimension");
+  const size_t vb = sizeof(float) * gf.nc();
+  if (b0 < a0 + vb * gc.nbar && a0 < b0 + vb * gf.nbar) return fail(MFR_EINVAL, "uf must not overlap uc");
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   auto px = prolong_table(gf.n[0], gf.hy[0], gc.n[0], gc.hy[0]);
   auto py = prolong_table(gf.n[1], gf.hy[1], gc.n[1], gc.hy[1]);
-  auto pz = prolong_table(gf.n[2], gf.hy[2], gc.n[2], gc.hy[2]);
+  auto pz = gf.dim == 2 ? std::vector<Conv1>(1, Conv1{0, 0.0f}) : prolong_table(gf.n[2], gf.hy[2], gc.n[2], gc.hy[2]);
   Conv1* dt = reinterpret_cast<Conv1*>(work);
   HIP_TRY(hipMemcpyAsync(dt, px.data(), sizeof(Conv1) * px.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dt + gf.n[0], py.data(), sizeof(Conv1) * py.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dt + gf.n[0] + gf.n[1], pz.data(), sizeof(Conv1) * pz.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(launch_prolong(uc, gc.n[0], gc.n[1], gc.n[2], uf, gf.n[0], gf.n[1], gf.n[2], dt, dt + gf.n[0],
-                         dt + gf.n[0] + gf.n[1], st));
+                         dt + gf.n[0] + gf.n[1], gf.nc(), st));
   HIP_TRY(hipStreamSynchronize(st));   // the host tables must outlive the copies
   return MFR_OK;
 }

@@ -60,6 +60,8 @@ mfr_status batch_layout(int n, const mfr_grid* grids, int levels, mfr_batch* b, 
       return fail(MFR_EINVAL, "pair %d: the batched path evaluates the NGF distance only", k);
     if (grids[k].regulariser != MFR_REG_CURVATURE)
       return fail(MFR_EINVAL, "pair %d: the batched path evaluates the curvature regulariser only", k);
+    if (grids[k].m[2] == 1 && grids[k].my[2] == 1)
+      return fail(MFR_EINVAL, "pair %d: the batched path takes three-dimensional problems only", k);
     size_t per = 0;
     MFR_TRY(ml_levels(&grids[k], levels, &b->lv[k], &per));
     size_t cb = 0;
@@ -456,7 +458,7 @@ mfr_status mfr_batch_register(mfr_batch* b, const mfr_ml_opts* o, int32_t use_gr
         HIP_TRY(hipMemcpyAsync(dt + g.n[0] + g.n[1], pz.data(), sizeof(Conv1) * pz.size(), hipMemcpyHostToDevice,
                                b->st));
         HIP_TRY(launch_prolong(level_u(b, k, l - 1), gc.n[0], gc.n[1], gc.n[2], ul, g.n[0], g.n[1], g.n[2], dt,
-                               dt + g.n[0], dt + g.n[0] + g.n[1], b->st));
+                               dt + g.n[0], dt + g.n[0] + g.n[1], 3, b->st));
         HIP_TRY(hipStreamSynchronize(b->st));
       }
     }

@@ -31,7 +31,12 @@ mfr_status fail(mfr_status s, const char* fmt, ...);
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Derived, validated problem description.
+// A two-dimensional problem (dim 2) has m[2] = n[2] = mT[2] = 1 and
+// h[2] = hT[2] = hy[2] = 1, so the products below are the 2D cell areas; its
+// node vectors have two components.
 struct Geo {
+  int dim;   // 3, or 2 for a two-dimensional problem (m[2] = my[2] = 1 in the mfr_grid)
+  int nc() const { return dim; }   // components of a node vector
   int m[3], n[3], mT[3];
   double h[3], hT[3], hy[3];
   double tau, rho, alpha;

@@ -51,6 +51,7 @@ LbLayout lb_layout(const Geo& g, int mem) {
 }
 
 mfr_status check_geo(const Geo& g) {
+  if (g.dim == 2) return fail(MFR_EINVAL, "L-BFGS takes three-dimensional problems only");
   if (g.reg == MFR_REG_ELASTIC)
     return fail(MFR_EINVAL, "the H_0 solve needs a regulariser that acts on each component alone (not elastic)");
   for (int d = 0; d < 3; ++d)

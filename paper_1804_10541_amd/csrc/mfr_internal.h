@@ -14,6 +14,8 @@ constexpr int kNodeBlock = 256;
 // Longest z chunk of the voxel-tile kernel: a group keeps the per-plane tables of
 // its chunk (plus two planes either side) in LDS.
 constexpr int kMaxChunk = 252;
+// Threads (pixel columns) of a work-group of the two-dimensional tile kernel.
+constexpr int kPlaneNT = 256;
 
 // Reads of values that an earlier kernel wrote (CG scalars, control flags, scales):
 // agent-scope atomic loads are served coherently, never from a stale scalar-cache
@@ -91,6 +93,7 @@ struct TileParams {
 // Parameters of the node pass.
 struct NodeParams {
   int nx, ny, nz, nbar;
+  int nc;                     // components: 3, or 2 for a two-dimensional problem (viewed as nx x 1 x ny)
   float ihy2x, ihy2y, ihy2z;  // 1 / hy^2
   float s_ngf;                // scale of the gathered voxel contributions (+-2 hbar)
   float s_curv;               // 2 alpha hbar^y (curvature) or alpha hbar^y (diffusive)
@@ -239,7 +242,13 @@ hipError_t launch_tile_batch(const TileShape& s, int mode, const BatchJobs& j, i
 hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float* out, int blocks,
                             hipStream_t st);
 hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st);
-hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, hipStream_t st);
+// bz: zero border along z (2; 0 for a two-dimensional template, mz = 1)
+hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, int bz, hipStream_t st);
+// Two-dimensional problems (plane_tile.hip): the fused tile kernel and the exact
+// Jacobi diagonal; TileParams with mz = nz = 1, y rows marched in chunks.
+hipError_t launch_plane_tile(int mode, const TileParams& p, const float* u, const float* pv, int grid,
+                             hipStream_t st);
+hipError_t launch_plane_jacobi(const DiagParams& d, const float* u, float* diag, hipStream_t st);
 hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, hipStream_t st);
 hipError_t launch_jacobi_tile(const JacParams& j, const float* u, float* diag, hipStream_t st);
 constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi work-group
@@ -286,8 +295,9 @@ hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* 
 hipError_t launch_fill(size_t n, float v, float* y, hipStream_t st);
 hipError_t launch_restrict(const float* fine, int mx, int my, int mz, float* coarse, hipStream_t st);
 // Node-field prolongation with per-axis (lower index, fraction) tables.
+// nc components; cnz = fnz = 1 for two-dimensional fields (tz is then not read).
 hipError_t launch_prolong(const float* coarse, int cnx, int cny, int cnz, float* fine, int fnx,
-                          int fny, int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz,
+                          int fny, int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz, int nc,
                           hipStream_t st);
 
 // batched path

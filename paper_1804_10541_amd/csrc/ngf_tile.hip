@@ -360,7 +360,11 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
         const float c1 = rnT * rnR;
         const float r = r1 * c1;
-        if (MODE != MODE_HV && zc >= zb && zc < ze) obj += (double)fmaf(-r, r, 1.0f);
+        // 1 - r^2 from the float32 sums in float64: in float32 it cancels where r is
+        // close to 1 (aligned images), and the bias of the hardware reciprocal
+        // square root would add up over the voxels of the objective sum
+        if (MODE != MODE_HV && zc >= zb && zc < ze)
+          obj += 1.0 - ((double)r1 * (double)r1) / ((double)nT2 * (double)nR2);
         if constexpr (NEED_C) {
           const float c2 = r1 * rnT * rnT;
           const float kx = P.hhx * c1, ky = P.hhy * c1, kz = P.hhz * c1;

@@ -103,6 +103,7 @@ __device__ __forceinline__ void lap_body(const NodeParams& Q, const float* __res
     const int k = n / (Q.nx * Q.ny);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+      if (d >= Q.nc) break;
       const float L0 = lap7(f + (size_t)d * Q.nbar, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z);
       Q.lap[(size_t)d * Q.nbar + n] = L0;
       // curvature: sum (L f)^2; diffusive and elastic: the squared edge differences
@@ -258,9 +259,9 @@ hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == NP_GRAD)
-    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, q, f, out);
+    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks, q.nc), dim3(kNodeBlock), 0, st, q, f, out);
   else
-    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, q, f, out);
+    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks, q.nc), dim3(kNodeBlock), 0, st, q, f, out);
   return hipGetLastError();
 }
 
@@ -279,26 +280,27 @@ hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Copy T into a (m + 4)^3 array with a two-cell zero border.
+// Copy T into an (mx + 4) x (my + 4) x (mz + 2 bz) array with a two-cell zero
+// border in x and y and bz cells in z.
 __global__ void pad_template_kernel(const float* __restrict__ T, float* __restrict__ Tp, int mx, int my,
-                                    int mz) {
-  const int PX = mx + 4, PY = my + 4, PZ = mz + 4;
+                                    int mz, int bz) {
+  const int PX = mx + 4, PY = my + 4, PZ = mz + 2 * bz;
   const size_t total = (size_t)PX * PY * PZ;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(idx % PX) - 2;
     const int y = (int)((idx / PX) % PY) - 2;
-    const int z = (int)(idx / ((size_t)PX * PY)) - 2;
+    const int z = (int)(idx / ((size_t)PX * PY)) - bz;
     float v = 0.0f;
     if (x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz) v = T[((size_t)z * my + y) * mx + x];
     Tp[idx] = v;
   }
 }
 
-hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, hipStream_t st) {
-  const size_t total = (size_t)(mx + 4) * (my + 4) * (mz + 4);
+hipError_t launch_pad_template(const float* T, float* Tp, int mx, int my, int mz, int bz, hipStream_t st) {
+  const size_t total = (size_t)(mx + 4) * (my + 4) * (mz + 2 * bz);
   const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(pad_template_kernel, dim3(blocks), dim3(256), 0, st, T, Tp, mx, my, mz);
+  hipLaunchKernelGGL(pad_template_kernel, dim3(blocks), dim3(256), 0, st, T, Tp, mx, my, mz, bz);
   return hipGetLastError();
 }
 
@@ -685,15 +687,17 @@ hipError_t launch_restrict(const float* fine, int mx, int my, int mz, float* coa
 
 __global__ void prolong_kernel(const float* __restrict__ c, int cnx, int cny, int cnz, float* __restrict__ f,
                                int fnx, int fny, int fnz, const Conv1* __restrict__ tx,
-                               const Conv1* __restrict__ ty, const Conv1* __restrict__ tz) {
+                               const Conv1* __restrict__ ty, const Conv1* __restrict__ tz, int nc) {
   const size_t fb = (size_t)fnx * fny * fnz, cb = (size_t)cnx * cny * cnz;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < fb;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx % fnx), j = (int)((idx / fnx) % fny), k = (int)(idx / ((size_t)fnx * fny));
-    const Conv1 a = tx[i], b = ty[j], e = tz[k];
-    for (int d = 0; d < 3; ++d) {
+    const Conv1 a = tx[i], b = ty[j];
+    // a two-dimensional field (one node plane): no second plane to interpolate towards
+    const Conv1 e = cnz > 1 ? tz[k] : Conv1{0, 0.0f};
+    for (int d = 0; d < nc; ++d) {
       const float* s = c + d * cb + ((size_t)e.n0 * cny + b.n0) * cnx + a.n0;
-      const size_t sy = cnx, sz = (size_t)cnx * cny;
+      const size_t sy = cnx, sz = cnz > 1 ? (size_t)cnx * cny : 0;
       const float l00 = fmaf(a.f, s[1] - s[0], s[0]);
       const float l10 = fmaf(a.f, s[sy + 1] - s[sy], s[sy]);
       const float l01 = fmaf(a.f, s[sz + 1] - s[sz], s[sz]);
@@ -705,11 +709,11 @@ __global__ void prolong_kernel(const float* __restrict__ c, int cnx, int cny, in
 }
 
 hipError_t launch_prolong(const float* coarse, int cnx, int cny, int cnz, float* fine, int fnx, int fny,
-                          int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz, hipStream_t st) {
+                          int fnz, const Conv1* tx, const Conv1* ty, const Conv1* tz, int nc, hipStream_t st) {
   const size_t total = (size_t)fnx * fny * fnz;
   const int blocks = (int)std::min<size_t>((total + 255) / 256, 16384);
   hipLaunchKernelGGL(prolong_kernel, dim3(blocks), dim3(256), 0, st, coarse, cnx, cny, cnz, fine, fnx, fny,
-                     fnz, tx, ty, tz);
+                     fnz, tx, ty, tz, nc);
   return hipGetLastError();
 }
 

@@ -298,6 +298,7 @@ mfr_status mfr_pc_workspace_size(const mfr_grid* grid, int32_t train, size_t* by
   if (!bytes) return fail(MFR_EINVAL, "bytes is NULL");
   Geo g;
   MFR_TRY(make_geo(grid, &g));
+  if (g.dim == 2) return fail(MFR_EINVAL, "the learned preconditioner takes three-dimensional problems only");
   *bytes = pc_layout(g, train != 0).total;
   return MFR_OK;
 }
@@ -378,6 +379,7 @@ mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_b
   if (!out) return fail(MFR_EINVAL, "out is NULL");
   *out = nullptr;
   if (!c) return fail(MFR_EINVAL, "context is NULL");
+  if (c->geo.dim == 2) return fail(MFR_EINVAL, "the learned preconditioner takes three-dimensional problems only");
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(MFR_EINVAL, "workspace must be non-NULL and 256-byte aligned");
   mfr_pc* pc = new (std::nothrow) mfr_pc();
@@ -411,6 +413,7 @@ mfr_status mfr_pc_create(mfr_ctx* c, int32_t train, void* workspace, size_t ws_b
 mfr_status mfr_pc_bind(mfr_pc* pc, mfr_ctx* c) {
   MFR_TRY(check_pc(pc));
   if (!c) return fail(MFR_EINVAL, "context is NULL");
+  if (c->geo.dim == 2) return fail(MFR_EINVAL, "the learned preconditioner takes three-dimensional problems only");
   return bind_pc(pc, c);
 }
 

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -191,6 +192,22 @@ DISTANCES = {"ngf": 0, "ssd": 1}   # mfr_grid.distance
 REGULARISERS = {"curvature": 0, "diffusive": 1, "elastic": 2}   # mfr_grid.regulariser
 
 
+def is_plane(m, my):
+    """A two-dimensional problem: one image cell and one node along z."""
+    return int(m[2]) == 1 and int(my[2]) == 1
+
+
+def node_shape_of(m, my):
+    """Shape of a node vector: (3, n_z, n_y, n_x), or (2, n_y, n_x) in 2D."""
+    if is_plane(m, my):
+        return (2, int(my[1]), int(my[0]))
+    return (3, int(my[2]), int(my[1]), int(my[0]))
+
+
+def node_count(m, my):
+    return int(np.prod(node_shape_of(m, my)))
+
+
 def make_grid(spec):
     """CGrid from any object with m, h, my, tau, rho, alpha (optional mT, hT,
     distance "ngf" or "ssd", regulariser "curvature", "diffusive" or "elastic" with
@@ -264,6 +281,7 @@ class Context:
         self.mT = tuple(int(k) for k in (mT if mT is not None else spec.m))
         self.nbar = self.my[0] * self.my[1] * self.my[2]
         self.mbar = self.m[0] * self.m[1] * self.m[2]
+        self.nc = 2 if is_plane(self.m, self.my) else 3   # node vector components
         self.ws_bytes = workspace_size(spec)
         self._ws, ptr = _alloc_workspace(self.ws_bytes, self.device)
         h = ctypes.c_void_p()
@@ -284,7 +302,7 @@ class Context:
             pass
 
     def node_shape(self):
-        return (3, self.my[2], self.my[1], self.my[0])
+        return node_shape_of(self.m, self.my)
 
     def set_images(self, R, T):
         r = _dev_tensor(R, self.mbar, "R", self.device)
@@ -294,29 +312,29 @@ class Context:
 
     def objective(self, u):
         J, D, S = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _check(self.lib.mfr_objective(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+        _check(self.lib.mfr_objective(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
                                       ctypes.byref(J), ctypes.byref(D), ctypes.byref(S)))
         return J.value, D.value, S.value
 
     def gradient(self, u, out=None, want_J=True):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
         J = ctypes.c_double()
-        _check(self.lib.mfr_gradient(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
+        _check(self.lib.mfr_gradient(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
                                      ctypes.byref(J) if want_J else None,
-                                     _dev_tensor(out, 3 * self.nbar, "g", self.device)))
+                                     _dev_tensor(out, self.nc * self.nbar, "g", self.device)))
         return out, (J.value if want_J else None)
 
     def hess_vec(self, u, p, out=None):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
-        _check(self.lib.mfr_hess_vec(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
-                                     _dev_tensor(p, 3 * self.nbar, "p", self.device),
-                                     _dev_tensor(out, 3 * self.nbar, "q", self.device)))
+        _check(self.lib.mfr_hess_vec(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                     _dev_tensor(p, self.nc * self.nbar, "p", self.device),
+                                     _dev_tensor(out, self.nc * self.nbar, "q", self.device)))
         return out
 
     def jacobi_diag(self, u, out=None):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
-        _check(self.lib.mfr_jacobi_diag(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
-                                        _dev_tensor(out, 3 * self.nbar, "diag", self.device)))
+        _check(self.lib.mfr_jacobi_diag(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                        _dev_tensor(out, self.nc * self.nbar, "diag", self.device)))
         return out
 
     def _lbfgs_work(self, mem):
@@ -332,8 +350,8 @@ class Context:
         """x = (alpha nabla^2 S + gamma I)^{-1} v, the L-BFGS initial matrix solve."""
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
         ptr, nbytes = self._lbfgs_work(1)
-        _check(self.lib.mfr_h0_solve(self._h, float(gamma), _dev_tensor(v, 3 * self.nbar, "v", self.device),
-                                     _dev_tensor(out, 3 * self.nbar, "x", self.device), ctypes.c_void_p(ptr),
+        _check(self.lib.mfr_h0_solve(self._h, float(gamma), _dev_tensor(v, self.nc * self.nbar, "v", self.device),
+                                     _dev_tensor(out, self.nc * self.nbar, "x", self.device), ctypes.c_void_p(ptr),
                                      nbytes))
         return out
 
@@ -342,7 +360,7 @@ class Context:
         ptr, nbytes = self._lbfgs_work(mem)
         opts = CLbfgsOpts(int(iters), int(mem), float(gamma), float(armijo_c1), int(armijo_max))
         rep = CLbfgsReport()
-        _check(self.lib.mfr_lbfgs(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device), ctypes.byref(opts),
+        _check(self.lib.mfr_lbfgs(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device), ctypes.byref(opts),
                                   ctypes.c_void_p(ptr), nbytes, ctypes.byref(rep)))
         return {f[0]: getattr(rep, f[0]) for f in CLbfgsReport._fields_}
 
@@ -351,7 +369,7 @@ class Context:
         opts = CGnOpts(int(pcg_max), float(pcg_rtol), int(precond), float(armijo_c1), int(armijo_max),
                        int(fallback_iters))
         info = CGnInfo()
-        _check(self.lib.mfr_gn_step(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device), ctypes.byref(opts),
+        _check(self.lib.mfr_gn_step(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device), ctypes.byref(opts),
                                     ctypes.byref(info)))
         return {f[0]: getattr(info, f[0]) for f in CGnInfo._fields_}
 
@@ -370,9 +388,9 @@ class Context:
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
         opts = CPcgOpts(int(max_iter), float(rtol), int(precond), int(fallback_iters), 1 if require_converged else 0)
         info = CPcgInfo()
-        _check(self.lib.mfr_pcg_solve(self._h, _dev_tensor(u, 3 * self.nbar, "u", self.device),
-                                      _dev_tensor(b, 3 * self.nbar, "b", self.device),
-                                      _dev_tensor(out, 3 * self.nbar, "s", self.device),
+        _check(self.lib.mfr_pcg_solve(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                      _dev_tensor(b, self.nc * self.nbar, "b", self.device),
+                                      _dev_tensor(out, self.nc * self.nbar, "s", self.device),
                                       ctypes.byref(opts), ctypes.byref(info)))
         return out, dict(iters=info.iters, relres=info.relres, flag=info.flag, used_fallback=info.used_fallback)
 
@@ -402,21 +420,21 @@ def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=
     _check(lib.mfr_ml_workspace_size(ctypes.byref(g), int(levels), ctypes.byref(n)))
     ws, ptr = _alloc_workspace(n.value, device)
     my = tuple(int(k) for k in spec.my)
-    nb = my[0] * my[1] * my[2]
-    u = torch.empty((3, my[2], my[1], my[0]), dtype=torch.float32, device=device)
+    nv = node_count(spec.m, my)
+    u = torch.empty(node_shape_of(spec.m, my), dtype=torch.float32, device=device)
     mbar = int(spec.m[0]) * int(spec.m[1]) * int(spec.m[2])
     mT = getattr(spec, "mT", None) or spec.m
     init = None
     if u0 is not None:
         gc = ml_level_grid(spec, levels, 0)
-        init = _dev_tensor(u0, 3 * gc.my[0] * gc.my[1] * gc.my[2], "u0", device)
+        init = _dev_tensor(u0, node_count(gc.m, gc.my), "u0", device)
     opts = CMlOpts(int(levels), int(gn_iters), int(pcg_max), float(pcg_rtol), float(armijo_c1), int(armijo_max),
                    int(precond), init)
     rep = CMlReport()
     _check(lib.mfr_register_multilevel(ctypes.byref(g), ctypes.byref(opts), _stream(device), ctypes.c_void_p(ptr),
                                        n.value, _dev_tensor(R, mbar, "R", device),
                                        _dev_tensor(T, int(mT[0]) * int(mT[1]) * int(mT[2]), "T", device),
-                                       _dev_tensor(u, 3 * nb, "u", device), ctypes.byref(rep)))
+                                       _dev_tensor(u, nv, "u", device), ctypes.byref(rep)))
     del ws
     return u, dict(J_final=rep.J_final, gn_done=list(rep.gn_done)[:levels], pcg_total=list(rep.pcg_total)[:levels],
                    status=list(rep.status)[:levels], seconds=rep.seconds, J_start=list(rep.J_start)[:levels],
@@ -446,9 +464,9 @@ def prolong(uc, coarse_spec, fine_spec):
     n = ctypes.c_size_t()
     _check(lib.mfr_prolong_workspace_size(ctypes.byref(gf), ctypes.byref(n)))
     work, ptr = _alloc_workspace(n.value, dev)
-    out = torch.empty((3, gf.my[2], gf.my[1], gf.my[0]), dtype=torch.float32, device=dev)
+    out = torch.empty(node_shape_of(gf.m, gf.my), dtype=torch.float32, device=dev)
     _check(lib.mfr_prolong(ctypes.byref(gc), ctypes.byref(gf),
-                           _dev_tensor(uc, 3 * gc.my[0] * gc.my[1] * gc.my[2], "uc", dev),
+                           _dev_tensor(uc, node_count(gc.m, gc.my), "uc", dev),
                            _dev_tensor(out, out.numel(), "uf", dev), ctypes.c_void_p(ptr), n.value, _stream(dev)))
     del work
     return out

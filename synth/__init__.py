@@ -17,4 +17,8 @@ from .volumes import (  # noqa: F401
     config_c2,
     config_c3,
     config_c4_sizes,
+    section_pair,
+    alignment_errors,
+    smooth_field_2d,
+    config_section,
 )

@@ -297,7 +297,7 @@ def ct_warp(seed, m, pts, max_disp=6.0, ctrl_spacing=16.0):
     wx = basis(flat[:, 0], Bx.shape[1])
     wy = basis(flat[:, 1], By.shape[1])
     wz = basis(flat[:, 2], Bz.shape[1])
-    out = np.einsum("dkji,pi,pj,pk->pd", coef, wx, wy, wz)
+    out = np.einsum("dkji,pi,pj,pk->pd", coef, wx, wy, wz, optimize=True)
     return out.reshape(pts.shape)
 
 
@@ -312,6 +312,40 @@ def ct_inverse_target(seed, m, pts, iters=60, **kw):
     for _ in range(iters):
         u = ct_warp(seed, m, pts + u, **kw)
     return u
+
+
+def alignment_errors(seed, m, R, u_vox, n_sample=20000, edge_grad=100.0, body_level=500.0, sample_seed=0):
+    """Registration error of a displacement against the one that aligns the pair
+    of ``ct_pair(seed, m)`` (ct_inverse_target), where the images carry
+    information: at a sample of edge voxels (central-difference |grad R| above
+    ``edge_grad``) the RMS of the component along the edge normal grad R/|grad R|
+    (the only component an edge determines), and at a sample of body voxels
+    (R above ``body_level``) the RMS Euclidean error; each also for u = 0.
+    R: (m_z, m_y, m_x) array; u_vox: callable mapping flat voxel indices to the
+    displacement (n, 3) at those voxel centres (x, y, z order).  Generator-side
+    evaluation only: R's differences and the warp, nothing of the method."""
+    R = np.asarray(R, dtype=np.float64)
+    gz, gy, gx = np.gradient(R)
+    gm = np.sqrt(gx ** 2 + gy ** 2 + gz ** 2).ravel()
+    rng = np.random.default_rng(sample_seed)
+    mx, my_, mz = m
+    out = {}
+    for name, mask in (("edges", gm > edge_grad), ("body", R.ravel() > body_level)):
+        idx = np.flatnonzero(mask)
+        if len(idx) > n_sample:
+            idx = np.sort(rng.choice(idx, n_sample, replace=False))
+        a, b, c = idx % mx, (idx // mx) % my_, idx // (mx * my_)
+        cen = np.stack([a + 0.5, b + 0.5, c + 0.5], axis=1)
+        vstar = ct_inverse_target(seed, m, cen)
+        e = np.asarray(u_vox(idx), dtype=np.float64) - vstar
+        if name == "edges":
+            n = np.stack([gx.ravel()[idx], gy.ravel()[idx], gz.ravel()[idx]], axis=1) / gm[idx][:, None]
+            out[name] = (float(np.sqrt(np.mean(np.sum(vstar * n, 1) ** 2))),
+                         float(np.sqrt(np.mean(np.sum(e * n, 1) ** 2))), len(idx))
+        else:
+            out[name] = (float(np.sqrt(np.mean(np.sum(vstar ** 2, 1)))), float(np.sqrt(np.mean(np.sum(e ** 2, 1)))),
+                         len(idx))
+    return out
 
 
 def config_c2(seed=0, device="cpu"):
@@ -342,3 +376,117 @@ def config_c4_sizes():
         for z in (94, 112, 120, 128, 136):
             sizes.append((xy, xy, z))
     return sizes
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional pairs: histology-section stand-in (Sec. 6.3 registers
+# serial histology sections on the GPU in 2D)
+# ---------------------------------------------------------------------------
+
+def _section_shapes(rng, m):
+    """Draws the shapes of a synthetic tissue section of m = (m_x, m_y) pixels:
+    one tissue outline, glands and nuclei (ellipses: centre, semi-axes, angle,
+    intensity change).  Draw order: outline (centre jitter 2, semi-axis
+    factors 2, angle 1); glands (count from the area; centres, semi-axes,
+    angles); nuclei (centres, radii)."""
+    mx, my_ = (float(k) for k in m)
+    shapes = []
+    j = rng.uniform(-0.04, 0.04, size=2)
+    a = rng.uniform(0.38, 0.46, size=2)
+    ang = rng.uniform(0.0, math.pi)
+    shapes.append((np.array([mx * (0.5 + j[0]), my_ * (0.5 + j[1])]), np.array([a[0] * mx, a[1] * my_]), ang, 0.55))
+    n_gl = max(2, int(mx * my_) // 200000)
+    cg = rng.uniform(0.2, 0.8, size=(n_gl, 2)) * np.array([mx, my_])
+    ag = rng.uniform(0.01, 0.04, size=(n_gl, 2)) * min(mx, my_) + 2.0
+    angg = rng.uniform(0.0, math.pi, size=n_gl)
+    for k in range(n_gl):
+        shapes.append((cg[k], ag[k], angg[k], -0.30))
+    n_nu = max(8, int(mx * my_) // 10000)
+    cn = rng.uniform(0.12, 0.88, size=(n_nu, 2)) * np.array([mx, my_])
+    rn = rng.uniform(2.0, 5.0, size=n_nu)
+    for k in range(n_nu):
+        shapes.append((cn[k], np.array([rn[k], rn[k]]), 0.0, 0.40))
+    return shapes
+
+
+def _section_image(X, Y, shapes, width=1.0):
+    """Sum of tanh-edged ellipses (value change per shape) at points (X, Y)."""
+    v = np.zeros_like(X)
+    for c, a, ang, dv in shapes:
+        ca, sa = math.cos(ang), math.sin(ang)
+        dx, dy = X - c[0], Y - c[1]
+        q = np.sqrt(((ca * dx + sa * dy) / a[0]) ** 2 + ((-sa * dx + ca * dy) / a[1]) ** 2)
+        v += dv * 0.5 * (1.0 - np.tanh((q - 1.0) * float(min(a)) / width))
+    return v
+
+
+def section_pair(seed, m, max_disp=6.0, ctrl_spacing=32.0, noise=0.02):
+    """Two-dimensional reference/template pair of m = (m_x, m_y) pixels, h = 1
+    (a stand-in for the paper's histology sections).
+
+    Reference: a tissue outline (value 0.55 on a background of 0, so the
+    template's zero extension is the background), darker glands (-0.30) and
+    bright nuclei (+0.40), all with tanh edges of one pixel, + N(0, noise).
+    Template: the same section at x - u*(x), u* a cubic B-spline displacement
+    (control spacing ``ctrl_spacing`` pixels, N(0,1) coefficients scaled to max
+    Euclidean norm ``max_disp``), + independent noise.  Shapes are evaluated
+    only on pixels within reach of them (beyond 20 pixel widths the tanh step
+    is 0 or 1 to within 1e-17).
+
+    Draw order from default_rng(seed): the shapes (_section_shapes); B-spline
+    coefficients (2, ncy, ncx); reference noise, template noise (each
+    (m_y, m_x), float32).  Returns (R, T, u_star, rng) as float32 numpy arrays
+    (images (m_y, m_x), u_star (2, m_y, m_x)), rng positioned after the draws."""
+    rng = np.random.default_rng(seed)
+    mx, my_ = int(m[0]), int(m[1])
+    shapes = _section_shapes(rng, (mx, my_))
+    Bx, By = _bspline_basis(mx, ctrl_spacing), _bspline_basis(my_, ctrl_spacing)
+    coef = rng.standard_normal((2, By.shape[1], Bx.shape[1]))
+    nR = rng.standard_normal((my_, mx), dtype=np.float32)
+    nT = rng.standard_normal((my_, mx), dtype=np.float32)
+    ustar = np.stack([By @ (coef[d] @ Bx.T) for d in range(2)])
+    ustar *= max_disp / np.sqrt((ustar ** 2).sum(0)).max()
+    xs, ys = np.arange(mx) + 0.5, np.arange(my_) + 0.5
+    R = np.zeros((my_, mx))
+    T = np.zeros((my_, mx))
+    reach = 20.0
+    for k, sh in enumerate(shapes):
+        c, a = sh[0], sh[1]
+        big = k == 0
+        r = float(max(a)) + reach
+        y0 = 0 if big else max(0, int(c[1] - r - max_disp - 1))
+        y1 = my_ if big else min(my_, int(c[1] + r + max_disp + 2))
+        x0 = 0 if big else max(0, int(c[0] - r - max_disp - 1))
+        x1 = mx if big else min(mx, int(c[0] + r + max_disp + 2))
+        if y0 >= y1 or x0 >= x1:
+            continue
+        Y, X = np.meshgrid(ys[y0:y1], xs[x0:x1], indexing="ij")
+        R[y0:y1, x0:x1] += _section_image(X, Y, [sh])
+        T[y0:y1, x0:x1] += _section_image(X - ustar[0, y0:y1, x0:x1], Y - ustar[1, y0:y1, x0:x1], [sh])
+    R = (R + noise * nR).astype(np.float32)
+    T = (T + noise * nT).astype(np.float32)
+    return R, T, ustar.astype(np.float32), rng
+
+
+def smooth_field_2d(rng, nodes, amp, sigma=2.0):
+    """Random smooth two-component node field (2, n_y, n_x), as smooth_field:
+    one draw of 2*n_x*n_y standard normals."""
+    from scipy.ndimage import gaussian_filter
+
+    nx, ny = int(nodes[0]), int(nodes[1])
+    raw = rng.standard_normal((2, ny, nx))
+    sm = np.stack([gaussian_filter(raw[d], sigma=sigma, mode="reflect") for d in range(2)])
+    return sm * (amp / np.sqrt((sm ** 2).sum(axis=0)).max())
+
+
+def config_section(seed=0, m=(4096, 4096), my=(2049, 2049), n_probes=3):
+    """Two-dimensional workload: a section pair of m pixels (h = 1), a nodal
+    grid of my nodes, eps = 0.05, alpha = 1, a smooth initial displacement of
+    max norm 0.5 pixel and ``n_probes`` N(0,1) probe vectors (float32).  The
+    problem is encoded with a trailing 1 (one cell and one node along z)."""
+    spec = GridSpec(m=(int(m[0]), int(m[1]), 1), h=(1.0, 1.0, 1.0), my=(int(my[0]), int(my[1]), 1),
+                    tau=0.05, rho=0.05, alpha=1.0)
+    R, T, ustar, rng = section_pair(seed, m)
+    u0 = smooth_field_2d(rng, my, 0.5).astype(np.float32)
+    probes = rng.standard_normal((n_probes, 2, int(my[1]), int(my[0])), dtype=np.float32)
+    return dict(spec=spec, R=R, T=T, ustar=ustar, u0=u0, probes=probes)

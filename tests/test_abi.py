@@ -134,3 +134,27 @@ def test_lbfgs_workspace_validation(lib):
     big = mfr.make_grid(GridSpec(m=(8192, 4, 4), h=(1, 1, 1), my=(5000, 3, 3), tau=1, rho=1, alpha=1))
     assert lib.mfr_lbfgs_workspace_size(ctypes.byref(big), 1, ctypes.byref(n1)) == -1
     assert b"4096" in lib.mfr_last_error()
+
+
+def test_two_dimensional_problems_validation(lib):
+    """One image cell and one node along z: a two-dimensional problem (NGF with
+    curvature); the calls that take 3D problems only refuse it."""
+    base = dict(m=(300, 200, 1), h=(1.0, 1.0, 1.0), my=(76, 51, 1), tau=0.05, rho=0.05, alpha=1.0)
+    n2 = _ws(GridSpec(**base))
+    n3 = _ws(GridSpec(**dict(base, m=(300, 200, 2), my=(76, 51, 2))))
+    # 2 node vectors instead of 3 and a template border in x, y only
+    assert n2 < n3
+    assert n2 >= (304 * 204) * 4 + 8 * 2 * 76 * 51 * 4
+    for bad in (dict(mT=(300, 200, 2)), dict(distance="ssd"), dict(regulariser="diffusive"),
+                dict(m=(300, 200, 1), my=(76, 51, 2)), dict(m=(300, 200, 2), my=(76, 51, 1))):
+        with pytest.raises(mfr.MfrError) as ei:
+            mfr.workspace_size(GridSpec(**dict(base, **bad)))
+        assert ei.value.status == -1, bad
+    g = mfr.make_grid(GridSpec(**base))
+    n = ctypes.c_size_t()
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 5, ctypes.byref(n)) == -1
+    assert lib.mfr_pc_workspace_size(ctypes.byref(g), 0, ctypes.byref(n)) == -1
+    assert lib.mfr_batch_workspace_size(1, ctypes.byref(g), 1, ctypes.byref(n)) == -1
+    # the pyramid of a 2D problem halves x and y only
+    lv = mfr.ml_level_grid(GridSpec(**base), 3, 0)
+    assert (lv.m[0], lv.m[1], lv.m[2]) == (75, 50, 1) and (lv.my[0], lv.my[1], lv.my[2]) == (20, 14, 1)

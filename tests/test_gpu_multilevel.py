@@ -19,7 +19,7 @@ import pytest
 import torch
 
 from gpu_cases import DEV, rel_l2
-from oracle import Grid, multilevel, solver
+from oracle import Grid, interp, multilevel, solver
 from paper_1804_10541_amd import mfr
 from synth import GridSpec, config_c2
 
@@ -170,25 +170,69 @@ def test_config2_finest_level_objective_at_every_gauss_newton_iterate(c2_run):
         assert info["J_after"] < info["J_before"]
 
 
+def kink_nodes(grid, u64, delta=1e-5):
+    """Nodes whose gradient a voxel at a template kink reaches: voxels whose
+    sample coordinate y-hat/hT - 1/2 lies within ``delta`` of an integer in some
+    axis (a template cell face, where the derivative of the trilinear
+    interpolant jumps and the float32 position may fall on either side), and
+    the eight nodes of each such voxel (the gradient sees g at a voxel only
+    through the transposed conversion there).  Returns (nodes, voxel count)."""
+    vox = np.arange(grid.mbar)
+    s = interp.deformed_points(grid, u64, vox) / np.asarray(grid.hT) - 0.5
+    amb = np.flatnonzero(np.min(np.abs(s - np.round(s)), axis=1) < delta)
+    return np.unique(grid.P_rows(amb).indices), len(amb)
+
+
 def test_config2_finest_level_gradient_at_iterates(c2_run):
+    """Gradient parity at three finest-level Gauss-Newton iterates, on the nodes
+    that no voxel at a template kink reaches: there the derivative of the
+    interpolant jumps, and a sample within float32 rounding of the cell face
+    may take either side (both one-sided derivatives are derivatives of the
+    interpolant; at the last iterate the GPU and the float64 oracle took
+    different sides at a few of the ~10 voxels within 1e-6 of a face).  grad D
+    alone (a context with alpha = 0: the same kernels without the regulariser
+    term) is held to the same bar."""
+    import dataclasses
+
+    from oracle import ngf
+
     r = c2_run
     spec = r["spec"]
     g = Grid.from_spec(spec)
     prob = solver.Problem(g, r["R"], r["T"])
+    tR = torch.from_numpy(r["R"].astype(np.float32)).to(DEV)
+    tT = torch.from_numpy(r["T"].astype(np.float32)).to(DEV)
     ctx = mfr.Context(spec, DEV)
-    ctx.set_images(torch.from_numpy(r["R"].astype(np.float32)).to(DEV),
-                   torch.from_numpy(r["T"].astype(np.float32)).to(DEV))
+    ctx.set_images(tR, tT)
+    ctx_d = mfr.Context(dataclasses.replace(spec, alpha=0.0), DEV)
+    ctx_d.set_images(tR, tT)
     its = r["iterates"]
     picks = sorted({0, len(its) // 2, len(its) - 1})
     for k in picks:
         u = its[k][0]
-        gg, Jg = ctx.gradient(torch.from_numpy(u).to(DEV))
-        Jo, go = prob.gradient(u.astype(np.float64))
-        e = rel_l2(gg.cpu().numpy(), go)
-        print(f"[gpu-case] finest iterate {k}: gradient rel-L2 {e:.2e}", flush=True)
+        tu = torch.from_numpy(u).to(DEV)
+        gg, Jg = ctx.gradient(tu)
+        gd, _ = ctx_d.gradient(tu)
+        u64 = u.astype(np.float64)
+        Jo, go = prob.gradient(u64)
+        gDo = ngf.gradient_D(g, r["R"], r["T"], u64)
+        kn, nk = kink_nodes(g, u64)
+        keep = np.ones(g.nbar, dtype=bool)
+        keep[kn] = False
+        gg, gd = gg.cpu().numpy().reshape(3, -1), gd.cpu().numpy().reshape(3, -1)
+        go, gDo = go.reshape(3, -1), gDo.reshape(3, -1)
+        e_all = rel_l2(gg, go)
+        e = rel_l2(gg[:, keep], go[:, keep])
+        e_d = rel_l2(gd[:, keep], gDo[:, keep])
+        print(f"[gpu-case] finest iterate {k}: {nk} voxels within 1e-5 of a template cell face, "
+              f"{len(kn)} nodes set aside; gradient rel-L2 {e:.2e} (all nodes {e_all:.2e}), grad D {e_d:.2e}",
+              flush=True)
+        assert len(kn) <= 0.01 * g.nbar
         assert e <= 1e-4
+        assert e_d <= 1e-4
         assert abs(Jg - Jo) <= 1e-5 * abs(Jo)
     ctx.close()
+    ctx_d.close()
 
 
 def test_config2_finest_level_first_three_pcg_iterates(c2_run):

@@ -53,16 +53,16 @@ def test_multilevel_config2_monotone_and_final_objective_parity():
     assert abs(rep["J_final"] - Jo) <= 1e-5 * abs(Jo)
     J0 = prob.objective(np.zeros_like(u64))[0]
     assert Jo < J0
-    # the registration aligns the images: mismatch of the warped template inside the body falls
-    from oracle import interp
+    # the registration recovers the displacement that aligns the pair where the images
+    # determine it: along the edge normals.  Elsewhere no bound holds: in the air around
+    # the body both images are constant, and in homogeneous tissue only the noise
+    # differs, so NGF carries no information there (the body-voxel error is reported)
+    from synth import alignment_errors
+
     g = Grid.from_spec(spec)
-    vox = np.arange(g.mbar)
-    Rf = R.numpy().astype(np.float64).ravel()
-    Tf = T.numpy().astype(np.float64)
-    body = Rf > 500.0                             # fat / soft tissue / bone (+1000 offset)
-    tw0, _ = interp.warped_template(g, Tf, np.zeros_like(u64), vox)
-    tw1, _ = interp.warped_template(g, Tf, u64, vox)
-    ssd0 = float(np.mean((tw0 - Rf)[body] ** 2))
-    ssd1 = float(np.mean((tw1 - Rf)[body] ** 2))
-    print(f"[gpu-case] J {J0:.4e} -> {Jo:.4e}; body intensity MSE {ssd0:.1f} -> {ssd1:.1f}", flush=True)
-    assert ssd1 < 0.5 * ssd0
+    uf = u64.reshape(3, -1)
+    err = alignment_errors(0, spec.m, R.numpy(), lambda idx: (g.P_rows(idx) @ uf.T))
+    (n0, n1, ne), (b0, b1, nb) = err["edges"], err["body"]
+    print(f"[gpu-case] J {J0:.4e} -> {Jo:.4e}; edge-normal error {n0:.3f} -> {n1:.3f} voxels ({ne} edge voxels), "
+          f"body error {b0:.3f} -> {b1:.3f} ({nb} body voxels)", flush=True)
+    assert n1 <= 0.6 * n0   # measured ratios 0.50-0.51 (trajectories vary with the tile configuration)
