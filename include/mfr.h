@@ -142,6 +142,25 @@ mfr_status mfr_gradient(mfr_ctx* ctx, const float* u, double* J, float* g);
  * q must not alias u or p.  Asynchronous. */
 mfr_status mfr_hess_vec(mfr_ctx* ctx, const float* u, const float* p, float* q);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * q of mfr_hess_vec for `grid`, images R, T, displacement u and direction p,
+ * with the workspace taken from a fixed device array of
+ * MFR_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it runs
+ * on until the process ends.  Same kernels, same result bit for bit as
+ * mfr_create + mfr_set_images + mfr_hess_vec with the same tile configuration.
+ * Allocates no device memory and needs no context or workspace.  All pointers
+ * are device pointers on the current device; work is enqueued on hip_stream,
+ * which must belong to that device.  Returns MFR_ENOMEM if the problem's
+ * workspace (mfr_workspace_size) exceeds the array.  Every call on one GPU
+ * uses the same array: calls that overlap in time (other streams, other host
+ * threads) race and must not be issued; calls in order on one stream are
+ * safe, each one rewriting what it reads.  Asynchronous after the table
+ * uploads of its set-up, which synchronise the stream. */
+#define MFR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mfr_status mfr_hess_vec_noalloc(const mfr_grid* grid, void* hip_stream, const float* R, const float* T,
+                                const float* u, const float* p, float* q);
+
 /* diag = diag(H + alpha nabla^2 S) at u, exactly (the Jacobi preconditioner
  * of the conjugate-gradient solve; the paper leaves CG unpreconditioned).
  * Entries may be 0 when alpha = 0.  Asynchronous. */

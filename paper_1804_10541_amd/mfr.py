@@ -127,6 +127,7 @@ SIGNATURES = {
     "mfr_objective": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mfr_gradient": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), _VP]),
     "mfr_hess_vec": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mfr_hess_vec_noalloc": (ctypes.c_int, [ctypes.POINTER(CGrid), _VP, _VP, _VP, _VP, _VP, _VP]),
     "mfr_jacobi_diag": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
     "mfr_gn_step": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(CGnOpts), ctypes.POINTER(CGnInfo)]),
@@ -259,6 +260,23 @@ def workspace_size(spec):
     n = ctypes.c_size_t()
     _check(lib.mfr_workspace_size(ctypes.byref(g), ctypes.byref(n)))
     return n.value
+
+
+def hess_vec_noalloc(spec, R, T, u, p, out):
+    """q = (H + alpha nabla^2 S) p through mfr_hess_vec_noalloc: no context, no
+    workspace; the library's fixed scratch array of the current device serves
+    as workspace.  Every tensor is caller-provided (out included)."""
+    lib = load()
+    g = make_grid(spec)
+    m, my = tuple(int(k) for k in spec.m), tuple(int(k) for k in spec.my)
+    mT = getattr(spec, "mT", None)
+    mT = tuple(int(k) for k in (mT if mT is not None else m))
+    dev = u.device
+    nv = node_count(m, my)
+    args = (_dev_tensor(R, m[0] * m[1] * m[2], "R", dev), _dev_tensor(T, mT[0] * mT[1] * mT[2], "T", dev),
+            _dev_tensor(u, nv, "u", dev), _dev_tensor(p, nv, "p", dev), _dev_tensor(out, nv, "q", dev))
+    _check(lib.mfr_hess_vec_noalloc(ctypes.byref(g), _stream(dev), *args))
+    return out
 
 
 def _alloc_workspace(nbytes, device):

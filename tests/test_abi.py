@@ -136,6 +136,20 @@ def test_lbfgs_workspace_validation(lib):
     assert b"4096" in lib.mfr_last_error()
 
 
+def test_noalloc_entry_rejects_a_problem_beyond_its_scratch_array(lib):
+    """mfr_hess_vec_noalloc checks the workspace the problem needs against its
+    fixed array before it touches any pointer or the GPU."""
+    big = GridSpec(m=(512, 512, 128), h=(1, 1, 1), my=(129, 129, 33), tau=50.0, rho=50.0, alpha=0.1)
+    assert _ws(big) > (64 << 20)
+    fake = ctypes.c_void_p(256)
+    st = lib.mfr_hess_vec_noalloc(ctypes.byref(mfr.make_grid(big)), None, fake, fake, fake, fake, fake)
+    assert st == -2   # MFR_ENOMEM
+    assert b"mfr_hess_vec_noalloc has 67108864" in lib.mfr_last_error()
+    small = GridSpec(m=(8, 8, 8), h=(1, 1, 1), my=(5, 5, 5), tau=0.1, rho=0.1, alpha=1.0)
+    st = lib.mfr_hess_vec_noalloc(ctypes.byref(mfr.make_grid(small)), None, fake, None, fake, fake, fake)
+    assert st == -1   # MFR_EINVAL: T is NULL
+
+
 def test_two_dimensional_problems_validation(lib):
     """One image cell and one node along z: a two-dimensional problem (NGF with
     curvature); the calls that take 3D problems only refuse it."""
