@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -399,10 +400,12 @@ static mfr_status ctx_init_plane(mfr_ctx* c, void* stream, void* ws, size_t ws_b
   p.hhy = (float)(0.5 / (g.h[1] * g.h[1]));
   p.ihTx = (float)(1.0 / g.hT[0]);
   p.ihTy = (float)(1.0 / g.hT[1]);
-  p.tau2 = (float)(g.tau * g.tau);
-  p.rho2 = (float)(g.rho * g.rho);
+  p.tau2 = std::max((float)(g.tau * g.tau), FLT_MIN);
+  p.rho2 = std::max((float)(g.rho * g.rho), FLT_MIN);
   p.taurho = (float)(g.tau * g.rho);
   p.Tp = at<float>(c->ws, L.Tp);
+  p.Rbytes = (unsigned)(sizeof(float) * g.mbar);
+  p.Tbytes = (unsigned)(sizeof(float) * (size_t)(g.mT[0] + 4) * (g.mT[1] + 4));
   p.cx = at<Conv1>(c->ws, L.cx);
   p.cy = at<Conv1>(c->ws, L.cy);
   p.sx = at<Samp1>(c->ws, L.sx);
@@ -574,11 +577,16 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   p.ssd = ssd ? 1 : 0;
   p.reg = g.reg;
   p.kappa = (float)g.kappa();
-  p.tau2 = ssd ? 1.0f : (float)(g.tau * g.tau);
-  p.rho2 = ssd ? 1.0f : (float)(g.rho * g.rho);
+  // tau^2 and rho^2 at least the smallest normal float: the NGF norms the kernels
+  // take reciprocal square roots of are then never denormal
+  p.tau2 = ssd ? 1.0f : std::max((float)(g.tau * g.tau), FLT_MIN);
+  p.rho2 = ssd ? 1.0f : std::max((float)(g.rho * g.rho), FLT_MIN);
   p.taurho = ssd ? 1.0f : (float)(g.tau * g.rho);
   p.R = nullptr;
   p.Tp = at<float>(c->ws, L.Tp);
+  p.Rbytes = (unsigned)(sizeof(float) * g.mbar);
+  p.Tbytes = (unsigned)(sizeof(float) * (size_t)(g.mT[0] + 4) * (g.mT[1] + 4) * (g.mT[2] + 4));
+  p.pxy24 = p.PXY < (1LL << 24) ? 1 : 0;
   p.cx = at<Conv1>(c->ws, L.cx);
   p.cy = at<Conv1>(c->ws, L.cy);
   p.cz = at<Conv1>(c->ws, L.cz);

@@ -74,6 +74,8 @@ struct TileParams {
   float tau2, rho2, taurho;
   const float* R;         // reference [mz][my][mx]
   const float* Tp;        // padded template [mTz+4][mTy+4][mTx+4]
+  unsigned Rbytes, Tbytes; // their sizes in bytes (< 2^32; buffer descriptors)
+  int pxy24;              // PXY < 2^24: plane offsets by 24-bit multiplies
   const Conv1* cx;        // per-voxel conversion tables (x, y, z)
   const Conv1* cy;
   const Conv1* cz;
@@ -258,6 +260,7 @@ constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi
 // eigenvalues of the Neumann second difference (lam: x, then y, then z).
 struct H0Tables {
   int n[3];
+  int nc;   // components (3; 2 for a two-dimensional problem, n[2] = 1)
   const float* C[3];
   const float* Ct[3];
   const float* lam;

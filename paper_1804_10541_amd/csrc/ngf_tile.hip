@@ -56,9 +56,12 @@ struct TileSmem {
   static constexpr int NT = BX * BY, MAXNX = BX + 1, MAXNY = BY + 1;
   static constexpr bool HV = (MODE == MODE_HV), NEED_C = (MODE != MODE_OBJ);
   static constexpr int NX = SSD ? 1 : NT;   // plane exchange (NGF differences only)
-  float sTw[2][NX];
-  float sR[2][NX];
-  float sA[HV ? 2 : 1][HV ? NX : 1];
+  // with a zero pad of one block row at both ends, so that every lane's four
+  // neighbour reads stay inside the arrays and read finite values
+  static constexpr int XP = SSD ? 0 : BX;
+  float sTw[2][NX + 2 * XP];
+  float sR[2][NX + 2 * XP];
+  float sA[HV ? 2 : 1][HV ? NX + 2 * XP : 1];
   // row products of the plane exchange, with a zero pad of one block row at both
   // ends: a neighbour read past the block's edge (or wrapping to the next row,
   // whose edge column is a ring column that writes 0) then adds exactly 0
@@ -124,6 +127,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   const bool own = (tx >= 1) && (tx < BX - 1) && (ty >= 1) && (ty < BY - 1);
   const bool inB = own && in_img;
   const bool inC = in_img;
+  const float own_row = inB ? 1.0f : 0.0f;   // scales z_l: 0 for rows this group does not own
 
   // own column, clamped into the image
   const int cxi = min(max(gx, 0), P.mx - 1), cyi = min(max(gy, 0), P.my - 1);
@@ -147,6 +151,16 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     sSz[j] = P.sz[q];
   }
   if constexpr (!NEED_C) __syncthreads();   // (with NEED_C the barrier after sCx / sCy covers it)
+  constexpr int XP = TileSmem<BX, BY, MODE, SSD>::XP;
+  if constexpr (XP > 0) {   // nor are the pads of the plane exchange
+    for (int w = tid; w < 2 * 2 * XP; w += NT) {
+      const int r = w % (2 * XP), sl = w / (2 * XP);
+      const int q = r < XP ? r : NT + r;
+      sTw[sl][q] = 0.f;
+      sR[sl][q] = 0.f;
+      if constexpr (HV) sA[sl][q] = 0.f;
+    }
+  }
   if constexpr (EP > 0) {   // the pads of sE are never written by the march
     for (int w = tid; w < 2 * 4 * 2 * EP; w += NT) {
       const int r = w % (2 * EP), k = (w / (2 * EP)) % 4, sl = w / (8 * EP);
@@ -189,48 +203,50 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   // reduce the per-column sums acc over x, then y, into the slot's node block.
   const int nrow = lyb - lya + 1;
   auto flush = [&](const float (&acc)[3], int kloc) {
-    if (inC) {
-      sV[0][tid] = acc[0];
-      sV[1][tid] = acc[1];
-      sV[2][tid] = acc[2];
-    }
-    __syncthreads();
-    for (int w = tid; w < nxl * nrow; w += NT) {   // x reduction: node column fj, local row ly
-      const int fj = w % nxl, ly = lya + w / nxl;
-      const int jg = nox + fj;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-      for (int l = sColLo[fj]; l <= sColHi[fj]; ++l) {
-        const Conv1 c = sCx[l];
-        const float wt = (c.n0 == jg) ? 1.0f - c.f : c.f;
-        const int q = ly * BX + l;
-        s0 = fmaf(wt, sV[0][q], s0);
-        s1 = fmaf(wt, sV[1][q], s1);
-        s2 = fmaf(wt, sV[2][q], s2);
+    if constexpr (NEED_C) {   // (only the derivative modes gather)
+      if (inC) {
+        sV[0][tid] = acc[0];
+        sV[1][tid] = acc[1];
+        sV[2][tid] = acc[2];
       }
-      sW[0][ly * MAXNX + fj] = s0;
-      sW[1][ly * MAXNX + fj] = s1;
-      sW[2][ly * MAXNX + fj] = s2;
-    }
-    __syncthreads();
-    for (int w = tid; w < nxl * nyl; w += NT) {   // y reduction: node (fj, fr)
-      const int fj = w % nxl, fr = w / nxl;
-      const int ig = noy + fr;
-      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-      for (int l = sRowLo[fr]; l <= sRowHi[fr]; ++l) {
-        const Conv1 c = sCy[l];
-        const float wt = (c.n0 == ig) ? 1.0f - c.f : c.f;
-        const int q = l * MAXNX + fj;
-        s0 = fmaf(wt, sW[0][q], s0);
-        s1 = fmaf(wt, sW[1][q], s1);
-        s2 = fmaf(wt, sW[2][q], s2);
+      __syncthreads();
+      for (int w = tid; w < nxl * nrow; w += NT) {   // x reduction: node column fj, local row ly
+        const int fj = w % nxl, ly = lya + w / nxl;
+        const int jg = nox + fj;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int l = sColLo[fj]; l <= sColHi[fj]; ++l) {
+          const Conv1 c = sCx[l];
+          const float wt = (c.n0 == jg) ? 1.0f - c.f : c.f;
+          const int q = ly * BX + l;
+          s0 = fmaf(wt, sV[0][q], s0);
+          s1 = fmaf(wt, sV[1][q], s1);
+          s2 = fmaf(wt, sV[2][q], s2);
+        }
+        sW[0][ly * MAXNX + fj] = s0;
+        sW[1][ly * MAXNX + fj] = s1;
+        sW[2][ly * MAXNX + fj] = s2;
       }
-      const size_t o = ((size_t)kloc * P.nyt + fr) * P.nxt + fj;
-      const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
-      part[o] = s0;
-      part[o + dstride] = s1;
-      part[o + 2 * dstride] = s2;
+      __syncthreads();
+      for (int w = tid; w < nxl * nyl; w += NT) {   // y reduction: node (fj, fr)
+        const int fj = w % nxl, fr = w / nxl;
+        const int ig = noy + fr;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int l = sRowLo[fr]; l <= sRowHi[fr]; ++l) {
+          const Conv1 c = sCy[l];
+          const float wt = (c.n0 == ig) ? 1.0f - c.f : c.f;
+          const int q = l * MAXNX + fj;
+          s0 = fmaf(wt, sW[0][q], s0);
+          s1 = fmaf(wt, sW[1][q], s1);
+          s2 = fmaf(wt, sW[2][q], s2);
+        }
+        const size_t o = ((size_t)kloc * P.nyt + fr) * P.nxt + fj;
+        const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
+        part[o] = s0;
+        part[o + dstride] = s1;
+        part[o + 2 * dstride] = s2;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   };
 
   // Register windows of the own column; slot (t - tfirst) mod 3.
@@ -241,10 +257,16 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
   int KL = noz;
   double obj = 0.0;
 
-  // xy-interpolated u and p at the two node planes bracketing the current plane.
+  // xy-interpolated u and p at the two node planes bracketing the current plane,
+  // and their differences (the z interpolation of every plane in between is one FMA)
   int Kp = -0x7fffffff;
-  float ulo[3] = {0.f, 0.f, 0.f}, uhi[3] = {0.f, 0.f, 0.f};
-  float plo[3] = {0.f, 0.f, 0.f}, phi[3] = {0.f, 0.f, 0.f};
+  float ulo[3] = {0.f, 0.f, 0.f}, uhi[3] = {0.f, 0.f, 0.f}, udz[3] = {0.f, 0.f, 0.f};
+  float plo[3] = {0.f, 0.f, 0.f}, phi[3] = {0.f, 0.f, 0.f}, pdz[3] = {0.f, 0.f, 0.f};
+  // template and reference through buffer descriptors: the corner loads share one
+  // vector offset, the reference load needs only the plane's scalar offset
+  const __amdgpu_buffer_rsrc_t rsT = raw_buffer(P.Tp, P.Tbytes), rsR = raw_buffer(P.R, P.Rbytes);
+  const CornerOffsets co{4u * (unsigned)P.PX, 4u * (unsigned)P.PXY, 4u * (unsigned)(P.PX + P.PXY)};
+  const unsigned rcol = colxy << 2;
   auto xy_interp = [&](const float* __restrict__ f, int k, float (&o)[3]) {
     const unsigned i00 = (unsigned)k * nxy + nodexy;
 #pragma unroll
@@ -265,6 +287,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     const int jz = tt - zb + 2;   // LDS slot of plane tt (entries are clamped into the image)
     Conv1 cvz = sCz[jz];
     cvz.n0 = __builtin_amdgcn_readfirstlane(cvz.n0);   // uniform: keeps the plane logic scalar
+    cvz.f = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, cvz.f)));
     if (cvz.n0 != Kp) {
       if (cvz.n0 == Kp + 1) {
 #pragma unroll
@@ -278,17 +301,22 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
       }
       xy_interp(u, cvz.n0 + 1, uhi);
       if (HV) xy_interp(pv, cvz.n0 + 1, phi);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        udz[d] = uhi[d] - ulo[d];
+        if (HV) pdz[d] = phi[d] - plo[d];
+      }
       Kp = cvz.n0;
     }
     const float fz = cvz.f;
-    const int kx = template_cell(spx, fmaf(fz, uhi[0] - ulo[0], ulo[0]), P.ihTx, nx_fx);
-    const int ky = template_cell(spy, fmaf(fz, uhi[1] - ulo[1], ulo[1]), P.ihTy, nx_fy);
-    const int kz = template_cell(sSz[jz], fmaf(fz, uhi[2] - ulo[2], ulo[2]), P.ihTz, nx_fz);
-    template_corners32(P, kx, ky, kz, nx_t);
-    nx_R = ld32(P.R, (unsigned)tc * plane + colxy);
+    const int kx = template_cell(spx, fmaf(fz, udz[0], ulo[0]), P.ihTx, nx_fx);
+    const int ky = template_cell(spy, fmaf(fz, udz[1], ulo[1]), P.ihTy, nx_fy);
+    const int kz = template_cell(sSz[jz], fmaf(fz, udz[2], ulo[2]), P.ihTz, nx_fz);
+    template_corners_buf(P, rsT, co, kx, ky, kz, nx_t);
+    nx_R = buf_ld(rsR, rcol, (unsigned)tc * plane * 4u);
     if (HV) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) nx_pp[d] = fmaf(fz, phi[d] - plo[d], plo[d]);
+      for (int d = 0; d < 3; ++d) nx_pp[d] = fmaf(fz, pdz[d], plo[d]);
     }
   };
 
@@ -310,9 +338,9 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
       if (HV) av[K] = fmaf(s.gx, nx_pp[0], fmaf(s.gy, nx_pp[1], s.gz * nx_pp[2]));
       if constexpr (!SSD) {
         const int sl = t & 1;
-        sTw[sl][tid] = Tw[K];
-        sR[sl][tid] = Rv[K];
-        if (HV) sA[sl][tid] = av[K];
+        sTw[sl][XP + tid] = Tw[K];
+        sR[sl][XP + tid] = Rv[K];
+        if (HV) sA[sl][XP + tid] = av[K];
       }
     }
     if (t < tlast) issue(t + 1);
@@ -325,7 +353,8 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     float ezm = 0.f;
     e0[K1] = 0.f;
     ezp[K1] = 0.f;
-    if (SSD && zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
+    const bool zin = zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz;   // uniform
+    if (SSD && zin) {
       if (inB) {
         const float r = Tw[K1] - Rv[K1];
         if (MODE != MODE_HV && zc >= zb && zc < ze) {
@@ -334,70 +363,67 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
         }
         if constexpr (NEED_C) e0[K1] = HV ? av[K1] : r;
       }
-    } else if (!SSD && zc >= zb - 1 && zc <= ze && zc >= 0 && zc < P.mz) {
+    } else if (!SSD && zin) {
+      // Every lane evaluates the row (ring columns and columns outside the image
+      // read finite neighbours: clamped samples or the zero pads), and a lane
+      // that does not own its row scales z by 0, which zeroes all its products:
+      // no divergent branch and no per-step clearing of the products.
       const int s1 = zc & 1;
-      float ex_p = 0.f, ex_m = 0.f, ey_p = 0.f, ey_m = 0.f;
-      if (inB) {
-        const float Tc = Tw[K1], Rc = Rv[K1];
-        const float dTxm = sTw[s1][tid - 1] - Tc, dTxp = sTw[s1][tid + 1] - Tc;
-        const float dTym = sTw[s1][tid - BX] - Tc, dTyp = sTw[s1][tid + BX] - Tc;
-        const float dTzm = Tw[K2] - Tc, dTzp = Tw[K] - Tc;
-        const float dRxm = sR[s1][tid - 1] - Rc, dRxp = sR[s1][tid + 1] - Rc;
-        const float dRym = sR[s1][tid - BX] - Rc, dRyp = sR[s1][tid + BX] - Rc;
-        const float dRzm = Rv[K2] - Rc, dRzp = Rv[K] - Rc;
-        const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x,
-                               fmaf(fmaf(dTym, dTym, dTyp * dTyp), P.ih2y,
-                                    fmaf(dTzm, dTzm, dTzp * dTzp) * P.ih2z));
-        const float sRR = fmaf(fmaf(dRxm, dRxm, dRxp * dRxp), P.ih2x,
-                               fmaf(fmaf(dRym, dRym, dRyp * dRyp), P.ih2y,
-                                    fmaf(dRzm, dRzm, dRzp * dRzp) * P.ih2z));
-        const float sTR = fmaf(fmaf(dTxm, dRxm, dTxp * dRxp), P.ih2x,
-                               fmaf(fmaf(dTym, dRym, dTyp * dRyp), P.ih2y,
-                                    fmaf(dTzm, dRzm, dTzp * dRzp) * P.ih2z));
-        const float nT2 = fmaf(0.5f, sTT, P.tau2);
-        const float nR2 = fmaf(0.5f, sRR, P.rho2);
-        const float r1 = fmaf(0.5f, sTR, P.taurho);
-        const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
-        const float c1 = rnT * rnR;
-        const float r = r1 * c1;
-        // 1 - r^2 from the float32 sums in float64: in float32 it cancels where r is
-        // close to 1 (aligned images), and the bias of the hardware reciprocal
-        // square root would add up over the voxels of the objective sum
-        if (MODE != MODE_HV && zc >= zb && zc < ze)
-          obj += 1.0 - ((double)r1 * (double)r1) / ((double)nT2 * (double)nR2);
-        if constexpr (NEED_C) {
-          const float c2 = r1 * rnT * rnT;
-          const float kx = P.hhx * c1, ky = P.hhy * c1, kz = P.hhz * c1;
-          const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
-          const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
-          const float rzm = kz * fmaf(-c2, dTzm, dRzm), rzp = kz * fmaf(-c2, dTzp, dRzp);
-          const float r0 = -(((rxm + rxp) + (rym + ryp)) + (rzm + rzp));
-          float zl;
-          if constexpr (HV) {
-            zl = r0 * av[K1];
-            zl = fmaf(rxm, sA[s1][tid - 1], zl);
-            zl = fmaf(rxp, sA[s1][tid + 1], zl);
-            zl = fmaf(rym, sA[s1][tid - BX], zl);
-            zl = fmaf(ryp, sA[s1][tid + BX], zl);
-            zl = fmaf(rzm, av[K2], zl);
-            zl = fmaf(rzp, av[K], zl);
-          } else {
-            zl = r;
-          }
-          ex_p = rxp * zl;
-          ex_m = rxm * zl;
-          ey_p = ryp * zl;
-          ey_m = rym * zl;
-          ezp[K1] = rzp * zl;
-          ezm = rzm * zl;
-          e0[K1] = r0 * zl;
-        }
-      }
+      const int q = XP + tid;
+      const float Tc = Tw[K1], Rc = Rv[K1];
+      const float dTxm = sTw[s1][q - 1] - Tc, dTxp = sTw[s1][q + 1] - Tc;
+      const float dTym = sTw[s1][q - BX] - Tc, dTyp = sTw[s1][q + BX] - Tc;
+      const float dTzm = Tw[K2] - Tc, dTzp = Tw[K] - Tc;
+      const float dRxm = sR[s1][q - 1] - Rc, dRxp = sR[s1][q + 1] - Rc;
+      const float dRym = sR[s1][q - BX] - Rc, dRyp = sR[s1][q + BX] - Rc;
+      const float dRzm = Rv[K2] - Rc, dRzp = Rv[K] - Rc;
+      const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x,
+                             fmaf(fmaf(dTym, dTym, dTyp * dTyp), P.ih2y,
+                                  fmaf(dTzm, dTzm, dTzp * dTzp) * P.ih2z));
+      const float sRR = fmaf(fmaf(dRxm, dRxm, dRxp * dRxp), P.ih2x,
+                             fmaf(fmaf(dRym, dRym, dRyp * dRyp), P.ih2y,
+                                  fmaf(dRzm, dRzm, dRzp * dRzp) * P.ih2z));
+      const float sTR = fmaf(fmaf(dTxm, dRxm, dTxp * dRxp), P.ih2x,
+                             fmaf(fmaf(dTym, dRym, dTyp * dRyp), P.ih2y,
+                                  fmaf(dTzm, dRzm, dTzp * dRzp) * P.ih2z));
+      const float nT2 = fmaf(0.5f, sTT, P.tau2);
+      const float nR2 = fmaf(0.5f, sRR, P.rho2);
+      const float r1 = fmaf(0.5f, sTR, P.taurho);
+      const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
+      const float c1 = rnT * rnR;
+      const float r = r1 * c1;
+      // 1 - r^2 from the float32 sums in float64: in float32 it cancels where r is
+      // close to 1 (aligned images), and the bias of the hardware reciprocal
+      // square root would add up over the voxels of the objective sum
+      if (MODE != MODE_HV && inB && zc >= zb && zc < ze)
+        obj += 1.0 - ((double)r1 * (double)r1) / ((double)nT2 * (double)nR2);
       if constexpr (NEED_C) {
-        sE[s1][0][EP + tid] = ex_p;
-        sE[s1][1][EP + tid] = ex_m;
-        sE[s1][2][EP + tid] = ey_p;
-        sE[s1][3][EP + tid] = ey_m;
+        const float c2 = r1 * rnT * rnT;
+        const float kx = P.hhx * c1, ky = P.hhy * c1, kz = P.hhz * c1;
+        const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
+        const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
+        const float rzm = kz * fmaf(-c2, dTzm, dRzm), rzp = kz * fmaf(-c2, dTzp, dRzp);
+        const float r0 = -(((rxm + rxp) + (rym + ryp)) + (rzm + rzp));
+        float zl;
+        if constexpr (HV) {
+          zl = r0 * av[K1];
+          zl = fmaf(rxm, sA[s1][q - 1], zl);
+          zl = fmaf(rxp, sA[s1][q + 1], zl);
+          zl = fmaf(rym, sA[s1][q - BX], zl);
+          zl = fmaf(ryp, sA[s1][q + BX], zl);
+          zl = fmaf(rzm, av[K2], zl);
+          zl = fmaf(rzp, av[K], zl);
+        } else {
+          zl = r;
+        }
+        zl *= own_row;
+        sE[s1][0][EP + tid] = rxp * zl;
+        sE[s1][1][EP + tid] = rxm * zl;
+        sE[s1][2][EP + tid] = ryp * zl;
+        sE[s1][3][EP + tid] = rym * zl;
+        ezp[K1] = rzp * zl;
+        ezm = rzm * zl;
+        e0[K1] = r0 * zl;
       }
     }
 
@@ -407,6 +433,7 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
       if (c >= zb && c < ze) {
         Conv1 cvz = sCz[c - zb + 2];
         cvz.n0 = __builtin_amdgcn_readfirstlane(cvz.n0);
+        cvz.f = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, cvz.f)));
         if (cvz.n0 != KL) {  // node plane KL is complete
           flush(acc_lo, KL - noz);
 #pragma unroll

@@ -44,8 +44,10 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
   if (P.live && !ld_coherent(P.live)) return;   // a device-steered solve has stopped
   constexpr int NT = kPlaneNT, TX = NT - 2, MAXNX = NT + 1;
   constexpr bool HV = (MODE == MODE_HV), NEED_C = (MODE != MODE_OBJ);
-  __shared__ float sTw[2][NT], sR[2][NT];
-  __shared__ float sA[HV ? 2 : 1][HV ? NT : 1];
+  // row exchange with one zero pad at both ends, so every lane's neighbour reads
+  // stay inside the arrays and read finite values
+  __shared__ float sTw[2][NT + 2], sR[2][NT + 2];
+  __shared__ float sA[HV ? 2 : 1][HV ? NT + 2 : 1];
   // x products of a row (+x, -x) with a zero pad at both ends: the reads of the
   // edge columns' missing neighbours then add exactly 0
   __shared__ float sE[NEED_C ? 2 : 1][2][NEED_C ? NT + 2 : 1];
@@ -65,6 +67,7 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
   const int gx = x0 - 1 + tid;
   const bool in_img = gx >= 0 && gx < P.mx;
   const bool inB = in_img && tid >= 1 && tid < NT - 1;
+  const float own_row = inB ? 1.0f : 0.0f;   // scales z_l: 0 for rows this group does not own
   const int cxi = min(max(gx, 0), P.mx - 1);
   const Conv1 cvx = P.cx[cxi];
   const Samp1 spx = P.sx[cxi];
@@ -81,6 +84,12 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
     sSy[j] = P.sy[q];
   }
   const int nxl = P.cx[x0 - 1 + lxb].n0 + 2 - nox;
+  if (tid < 4) {   // pads of the row exchange
+    const int sl = tid >> 1, q = (tid & 1) ? NT + 1 : 0;
+    sTw[sl][q] = 0.f;
+    sR[sl][q] = 0.f;
+    if constexpr (HV) sA[sl][q] = 0.f;
+  }
   if constexpr (NEED_C) {
     sCx[tid] = cvx;
     if (tid < 8) sE[tid >> 2][(tid >> 1) & 1][(tid & 1) ? NT + 1 : 0] = 0.f;   // the pads
@@ -107,25 +116,27 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
   // Writes node row kloc of the transposed conversion: reduce the per-column
   // sums over x into the slot's node block.
   auto flush = [&](const float (&acc)[2], int kloc) {
-    if (in_img) {
-      sV[0][tid] = acc[0];
-      sV[1][tid] = acc[1];
-    }
-    __syncthreads();
-    for (int fj = tid; fj < nxl; fj += NT) {
-      const int jg = nox + fj;
-      float s0 = 0.f, s1 = 0.f;
-      for (int l = sColLo[fj]; l <= sColHi[fj]; ++l) {
-        const Conv1 c = sCx[l];
-        const float wt = (c.n0 == jg) ? 1.0f - c.f : c.f;
-        s0 = fmaf(wt, sV[0][l], s0);
-        s1 = fmaf(wt, sV[1][l], s1);
+    if constexpr (NEED_C) {   // (only the derivative modes gather)
+      if (in_img) {
+        sV[0][tid] = acc[0];
+        sV[1][tid] = acc[1];
       }
-      const size_t o = (size_t)kloc * P.nxt + fj;
-      part[o] = s0;
-      part[o + dstride] = s1;
+      __syncthreads();
+      for (int fj = tid; fj < nxl; fj += NT) {
+        const int jg = nox + fj;
+        float s0 = 0.f, s1 = 0.f;
+        for (int l = sColLo[fj]; l <= sColHi[fj]; ++l) {
+          const Conv1 c = sCx[l];
+          const float wt = (c.n0 == jg) ? 1.0f - c.f : c.f;
+          s0 = fmaf(wt, sV[0][l], s0);
+          s1 = fmaf(wt, sV[1][l], s1);
+        }
+        const size_t o = (size_t)kloc * P.nxt + fj;
+        part[o] = s0;
+        part[o + dstride] = s1;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   };
 
   // register windows of the column, slot (t - tfirst) mod 3
@@ -136,9 +147,15 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
   int KL = noy;
   double obj = 0.0;
 
-  // x-interpolated u and p at the two node rows bracketing the current row
+  // x-interpolated u and p at the two node rows bracketing the current row, and
+  // their differences (the y interpolation of every row in between is one FMA)
   int Kp = -0x7fffffff;
-  float ulo[2] = {0.f, 0.f}, uhi[2] = {0.f, 0.f}, plo[2] = {0.f, 0.f}, phi[2] = {0.f, 0.f};
+  float ulo[2] = {0.f, 0.f}, uhi[2] = {0.f, 0.f}, udy[2] = {0.f, 0.f};
+  float plo[2] = {0.f, 0.f}, phi[2] = {0.f, 0.f}, pdy[2] = {0.f, 0.f};
+  // template and reference through buffer descriptors: the two corner loads share
+  // one vector offset, the reference load needs only the row's scalar offset
+  const __amdgpu_buffer_rsrc_t rsT = raw_buffer(P.Tp, P.Tbytes), rsR = raw_buffer(P.R, P.Rbytes);
+  const unsigned rcol = (unsigned)cxi << 2;
   auto x_interp = [&](const float* __restrict__ f, int k, float (&o)[2]) {
     const unsigned i0 = (unsigned)k * nxu + (unsigned)cvx.n0;
 #pragma unroll
@@ -157,6 +174,7 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
     const int jy = tt - yb + 2;   // LDS slot of row tt (entries clamped into the image)
     Conv1 cvy = sCy[jy];
     cvy.n0 = __builtin_amdgcn_readfirstlane(cvy.n0);   // uniform: the row logic stays scalar
+    cvy.f = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, cvy.f)));
     if (cvy.n0 != Kp) {
       if (cvy.n0 == Kp + 1) {
 #pragma unroll
@@ -170,24 +188,29 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
       }
       x_interp(u, cvy.n0 + 1, uhi);
       if (HV) x_interp(pv, cvy.n0 + 1, phi);
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        udy[d] = uhi[d] - ulo[d];
+        if (HV) pdy[d] = phi[d] - plo[d];
+      }
       Kp = cvy.n0;
     }
     const float fy = cvy.f;
-    int kx = template_cell(spx, fmaf(fy, uhi[0] - ulo[0], ulo[0]), P.ihTx, nfx);
-    int ky = template_cell(sSy[jy], fmaf(fy, uhi[1] - ulo[1], ulo[1]), P.ihTy, nfy);
+    int kx = template_cell(spx, fmaf(fy, udy[0], ulo[0]), P.ihTx, nfx);
+    int ky = template_cell(sSy[jy], fmaf(fy, udy[1], ulo[1]), P.ihTy, nfy);
     // clamping to [-2, mT] maps only samples entirely outside onto the zero border
-    kx = min(max(kx, -2), P.mTx);
-    ky = min(max(ky, -2), P.mTy);
-    const unsigned i0 = (unsigned)(ky + 2) * PX + (unsigned)(kx + 2);
-    const FPair a = ld32x2(P.Tp, i0), b = ld32x2(P.Tp, i0 + PX);
+    kx = clamp_m2(kx, P.mTx);
+    ky = clamp_m2(ky, P.mTy);
+    const unsigned v = (__umul24((unsigned)(ky + 2), PX) + (unsigned)(kx + 2)) << 2;
+    const FPair a = buf_ld2(rsT, v, 0), b = buf_ld2(rsT, v, 4u * PX);
     nt00 = a.a;
     nt10 = a.b;
     nt01 = b.a;
     nt11 = b.b;
-    nR = ld32(P.R, (unsigned)tc * (unsigned)P.mx + (unsigned)cxi);
+    nR = buf_ld(rsR, rcol, (unsigned)tc * (unsigned)P.mx * 4u);
     if (HV) {
 #pragma unroll
-      for (int d = 0; d < 2; ++d) npp[d] = fmaf(fy, phi[d] - plo[d], plo[d]);
+      for (int d = 0; d < 2; ++d) npp[d] = fmaf(fy, pdy[d], plo[d]);
     }
   };
 
@@ -208,9 +231,9 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
       Rv[K] = nR;
       if (HV) av[K] = fmaf(g[K][0], npp[0], g[K][1] * npp[1]);
       const int sl = t & 1;
-      sTw[sl][tid] = Tw[K];
-      sR[sl][tid] = Rv[K];
-      if (HV) sA[sl][tid] = av[K];
+      sTw[sl][1 + tid] = Tw[K];
+      sR[sl][1 + tid] = Rv[K];
+      if (HV) sA[sl][1 + tid] = av[K];
     }
     if (t < tlast) issue(t + 1);
     // No barrier here: stage B reads only LDS slots of row t-1 (written in the
@@ -218,59 +241,57 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
     // barrier that ended the previous step.
 
     // ---------------- stage B: row yc = t-1 ----------------
+    // Every lane evaluates its row (ring columns and columns outside the image read
+    // finite neighbours: clamped samples or the zero pads); a lane that does not own
+    // its row scales z by 0, which zeroes all its products.
     const int yc = t - 1;
     float eym = 0.f;
     e0[K1] = 0.f;
     eyp[K1] = 0.f;
     if (yc >= yb - 1 && yc <= ye && yc >= 0 && yc < P.my) {
       const int s1 = yc & 1;
-      float ex_p = 0.f, ex_m = 0.f;
-      if (inB) {
-        const float Tc = Tw[K1], Rc = Rv[K1];
-        const float dTxm = sTw[s1][tid - 1] - Tc, dTxp = sTw[s1][tid + 1] - Tc;
-        const float dTym = Tw[K2] - Tc, dTyp = Tw[K] - Tc;
-        const float dRxm = sR[s1][tid - 1] - Rc, dRxp = sR[s1][tid + 1] - Rc;
-        const float dRym = Rv[K2] - Rc, dRyp = Rv[K] - Rc;
-        const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x, fmaf(dTym, dTym, dTyp * dTyp) * P.ih2y);
-        const float sRR = fmaf(fmaf(dRxm, dRxm, dRxp * dRxp), P.ih2x, fmaf(dRym, dRym, dRyp * dRyp) * P.ih2y);
-        const float sTR = fmaf(fmaf(dTxm, dRxm, dTxp * dRxp), P.ih2x, fmaf(dTym, dRym, dTyp * dRyp) * P.ih2y);
-        const float nT2 = fmaf(0.5f, sTT, P.tau2);
-        const float nR2 = fmaf(0.5f, sRR, P.rho2);
-        const float r1 = fmaf(0.5f, sTR, P.taurho);
-        const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
-        const float c1 = rnT * rnR;
-        const float r = r1 * c1;
-        // 1 - r^2 from the float32 sums in float64: in float32 it cancels where r is
-        // close to 1 (aligned images), and the bias of the hardware reciprocal
-        // square root would add up over the voxels of the objective sum
-        if (MODE != MODE_HV && yc >= yb && yc < ye)
-          obj += 1.0 - ((double)r1 * (double)r1) / ((double)nT2 * (double)nR2);
-        if constexpr (NEED_C) {
-          const float c2 = r1 * rnT * rnT;
-          const float kx = P.hhx * c1, ky = P.hhy * c1;
-          const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
-          const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
-          const float r0 = -((rxm + rxp) + (rym + ryp));
-          float zl;
-          if constexpr (HV) {
-            zl = r0 * av[K1];
-            zl = fmaf(rxm, sA[s1][tid - 1], zl);
-            zl = fmaf(rxp, sA[s1][tid + 1], zl);
-            zl = fmaf(rym, av[K2], zl);
-            zl = fmaf(ryp, av[K], zl);
-          } else {
-            zl = r;
-          }
-          ex_p = rxp * zl;
-          ex_m = rxm * zl;
-          eyp[K1] = ryp * zl;
-          eym = rym * zl;
-          e0[K1] = r0 * zl;
-        }
-      }
+      const int q = 1 + tid;
+      const float Tc = Tw[K1], Rc = Rv[K1];
+      const float dTxm = sTw[s1][q - 1] - Tc, dTxp = sTw[s1][q + 1] - Tc;
+      const float dTym = Tw[K2] - Tc, dTyp = Tw[K] - Tc;
+      const float dRxm = sR[s1][q - 1] - Rc, dRxp = sR[s1][q + 1] - Rc;
+      const float dRym = Rv[K2] - Rc, dRyp = Rv[K] - Rc;
+      const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x, fmaf(dTym, dTym, dTyp * dTyp) * P.ih2y);
+      const float sRR = fmaf(fmaf(dRxm, dRxm, dRxp * dRxp), P.ih2x, fmaf(dRym, dRym, dRyp * dRyp) * P.ih2y);
+      const float sTR = fmaf(fmaf(dTxm, dRxm, dTxp * dRxp), P.ih2x, fmaf(dTym, dRym, dTyp * dRyp) * P.ih2y);
+      const float nT2 = fmaf(0.5f, sTT, P.tau2);
+      const float nR2 = fmaf(0.5f, sRR, P.rho2);
+      const float r1 = fmaf(0.5f, sTR, P.taurho);
+      const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
+      const float c1 = rnT * rnR;
+      const float r = r1 * c1;
+      // 1 - r^2 from the float32 sums in float64: in float32 it cancels where r is
+      // close to 1 (aligned images), and the bias of the hardware reciprocal
+      // square root would add up over the voxels of the objective sum
+      if (MODE != MODE_HV && inB && yc >= yb && yc < ye)
+        obj += 1.0 - ((double)r1 * (double)r1) / ((double)nT2 * (double)nR2);
       if constexpr (NEED_C) {
-        sE[s1][0][1 + tid] = ex_p;
-        sE[s1][1][1 + tid] = ex_m;
+        const float c2 = r1 * rnT * rnT;
+        const float kx = P.hhx * c1, ky = P.hhy * c1;
+        const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
+        const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
+        const float r0 = -((rxm + rxp) + (rym + ryp));
+        float zl;
+        if constexpr (HV) {
+          zl = r0 * av[K1];
+          zl = fmaf(rxm, sA[s1][q - 1], zl);
+          zl = fmaf(rxp, sA[s1][q + 1], zl);
+          zl = fmaf(rym, av[K2], zl);
+          zl = fmaf(ryp, av[K], zl);
+        } else {
+          zl = r;
+        }
+        zl *= own_row;
+        sE[s1][0][1 + tid] = rxp * zl;
+        sE[s1][1][1 + tid] = rxm * zl;
+        eyp[K1] = ryp * zl;
+        eym = rym * zl;
+        e0[K1] = r0 * zl;
       }
     }
 
@@ -280,6 +301,7 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
       if (c >= yb && c < ye) {
         Conv1 cvy = sCy[c - yb + 2];
         cvy.n0 = __builtin_amdgcn_readfirstlane(cvy.n0);
+        cvy.f = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, cvy.f)));
         if (cvy.n0 != KL) {   // node row KL is complete
           flush(acc_lo, KL - noy);
           acc_lo[0] = acc_hi[0];

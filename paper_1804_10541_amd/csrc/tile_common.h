@@ -121,19 +121,73 @@ __device__ __forceinline__ Tri sample_template(const TileParams& P, int kx, int 
   return trilinear(P, t, fx, fy, fz);
 }
 
-// Template coordinate along one axis for voxel-table entry s and displacement d:
-// returns the lower template cell and writes the fraction.
-__device__ __forceinline__ int template_cell(const Samp1 s, float d, float ihT, float& frac) {
-  const float q = fminf(fmaxf(fmaf(d, ihT, s.frac), -1.0e7f), 1.0e7f);
-  const float fl = floorf(q);
-  frac = q - fl;
-  return s.base + (int)fl;
+// floor(q) as an integer in one instruction (convert with round-down).
+__device__ __forceinline__ int floor_to_int(float q) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(q));
+  return r;
 }
 
-// 1/sqrt(x) by the hardware reciprocal square root; the argument is clamped to
-// the smallest normal float, which leaves the NGF norms (>= tau^2, rho^2 > 0)
-// untouched and spares the range scaling that rsqrtf applies for denormals.
-__device__ __forceinline__ float rsq_norm(float x) { return __builtin_amdgcn_rsqf(fmaxf(x, 1.17549435e-38f)); }
+// max(-2, min(k, hi)) for hi >= -2 in one instruction.
+__device__ __forceinline__ int clamp_m2(int k, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, -2, %2" : "=v"(r) : "v"(k), "s"(hi));
+  return r;
+}
+
+// Template coordinate along one axis for voxel-table entry s and displacement d:
+// returns the lower template cell and writes the fraction (q - floor(q), at most
+// the float below 1).
+__device__ __forceinline__ int template_cell(const Samp1 s, float d, float ihT, float& frac) {
+  const float q = __builtin_amdgcn_fmed3f(fmaf(d, ihT, s.frac), -1.0e7f, 1.0e7f);
+  frac = __builtin_amdgcn_fractf(q);
+  return s.base + floor_to_int(q);
+}
+
+// 1/sqrt(x) by the hardware reciprocal square root.  Its NGF arguments are
+// sums of squares plus tau^2 or rho^2, which the host raises to at least the
+// smallest normal float, so no denormal ever reaches it.
+__device__ __forceinline__ float rsq_norm(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Buffer descriptor of a raw float array of `bytes` bytes: loads at byte
+// offsets voffset (vector) + soffset (scalar); loads past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const float* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float buf_ld(const __amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ FPair buf_ld2(const __amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(FPair, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+
+// The eight corners of the template cell (kx, ky, kz) through the template's
+// buffer descriptor: one vector byte offset for the lower x-pair of corners,
+// the other three x-pairs at the scalar offsets of the next row, plane and both.
+struct CornerOffsets {
+  unsigned row, plane, both;   // bytes: 4 PX, 4 PXY, 4 (PX + PXY)
+};
+__device__ __forceinline__ void template_corners_buf(const TileParams& P, const __amdgpu_buffer_rsrc_t rs,
+                                                     const CornerOffsets o, int kx, int ky, int kz, float (&t)[8]) {
+  kx = clamp_m2(kx, P.mTx);
+  ky = clamp_m2(ky, P.mTy);
+  kz = clamp_m2(kz, P.mTz);
+  // a 24-bit multiply (full rate) for planes below 2^24 elements, else a 32-bit one
+  const unsigned zo = P.pxy24 ? __umul24((unsigned)(kz + 2), (unsigned)P.PXY) : (unsigned)(kz + 2) * (unsigned)P.PXY;
+  const unsigned i0 = zo + __umul24((unsigned)(ky + 2), (unsigned)P.PX) + (unsigned)(kx + 2);
+  const unsigned v = i0 << 2;
+  const FPair a = buf_ld2(rs, v, 0), b = buf_ld2(rs, v, o.row), c = buf_ld2(rs, v, o.plane), d = buf_ld2(rs, v, o.both);
+  t[0] = a.a;
+  t[1] = a.b;
+  t[2] = b.a;
+  t[3] = b.b;
+  t[4] = c.a;
+  t[5] = c.b;
+  t[6] = d.a;
+  t[7] = d.b;
+}
 
 // Weight of node index n for a voxel with conversion entry c (0 outside its pair).
 __device__ __forceinline__ float conv_weight(const Conv1 c, int n) {

@@ -1,0 +1,44 @@
+"""Resource use of the voxel-tile kernels, read from the gfx950 code-object
+metadata that hipcc writes for them: no private (scratch) memory, which a
+register array indexed at run time would silently move there (every access
+then goes through the vector-memory path), and no register spills."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1804_10541_amd", "csrc")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def _kernel_metadata(src, tmp_path):
+    if not os.path.exists(HIPCC) and shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    out = tmp_path / (os.path.basename(src) + ".s")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include"), "--cuda-device-only", "-S",
+           os.path.join(CSRC, src), "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    text = out.read_text()
+    meta = {}
+    for blk in re.findall(r"(- \.agpr_count.*?\.wavefront_size:\s+\d+)", text, re.S):
+        name = re.search(r"\.name:\s+(\S+)", blk).group(1)
+        field = lambda k: int(re.search(r"\." + k + r":\s+(\d+)", blk).group(1))
+        meta[name] = {k: field(k) for k in ("private_segment_fixed_size", "vgpr_spill_count", "sgpr_spill_count",
+                                            "vgpr_count")}
+    return meta
+
+
+@pytest.mark.parametrize("src,kernel", [("ngf_tile.hip", "ngf_tile_kernel"), ("plane_tile.hip", "plane_tile_kernel")])
+def test_tile_kernels_use_no_scratch_memory(src, kernel, tmp_path):
+    meta = _kernel_metadata(src, tmp_path)
+    tiles = {k: v for k, v in meta.items() if kernel in k}
+    assert tiles, f"no {kernel} instances in {src}"
+    for name, m in tiles.items():
+        assert m["private_segment_fixed_size"] == 0, (name, m)
+        assert m["vgpr_spill_count"] == 0 and m["sgpr_spill_count"] == 0, (name, m)
+        # at most 128 VGPRs: four waves per SIMD, what a 512-thread group needs for two groups per CU
+        assert m["vgpr_count"] <= 128, (name, m)
