@@ -27,7 +27,7 @@
  *    [m_y][m_x], node vectors [2][n_y][n_x] (x components, then y), the
  *    interpolation is bilinear, four short differences per pixel, the 5-point
  *    Laplacian, hbar = h_x h_y.  They take the NGF distance and the curvature
- *    regulariser; every single-pair call accepts them except the L-BFGS and
+ *    regulariser; every single-pair call accepts them except the
  *    learned-preconditioner calls (MFR_EINVAL), and the batched path takes
  *    three-dimensional problems only.
  *  - Every pointer argument named R, T, u, p, q, g, b, s, diag or workspace is

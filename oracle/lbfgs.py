@@ -47,13 +47,14 @@ class H0Solver:
         self._solve = spla.factorized(self.A)
 
     def apply(self, v):
-        vc = np.asarray(v, dtype=np.float64).reshape(3, self.grid.nbar)
-        x = np.stack([self._solve(vc[d]) for d in range(3)])
+        """Per component (as many as v holds: three, or two on a two-dimensional grid)."""
+        vc = np.asarray(v, dtype=np.float64).reshape(-1, self.grid.nbar)
+        x = np.stack([self._solve(vc[d]) for d in range(len(vc))])
         return x.reshape(np.shape(v))
 
     def matvec(self, x):
-        xc = np.asarray(x, dtype=np.float64).reshape(3, self.grid.nbar)
-        return np.stack([self.A @ xc[d] for d in range(3)]).reshape(np.shape(x))
+        xc = np.asarray(x, dtype=np.float64).reshape(-1, self.grid.nbar)
+        return np.stack([self.A @ xc[d] for d in range(len(xc))]).reshape(np.shape(x))
 
 
 def two_loop(g, pairs, h0_inv):
@@ -77,7 +78,8 @@ def two_loop(g, pairs, h0_inv):
 def lbfgs(problem, u0, iters=10, mem=5, gamma=1.0, c1=1e-4, max_ls=10, callback=None):
     """L-BFGS iterations from u0.  Returns (u, history) with one dict per
     iteration (J before, gradient norm, step length, whether the pair was kept)."""
-    h0 = H0Solver(problem.grid, gamma, problem.L if problem.reg is curvature else None)
+    # (a two-dimensional problem carries its 5-point Laplacian and no regulariser choice)
+    h0 = H0Solver(problem.grid, gamma, problem.L if getattr(problem, "reg", curvature) is curvature else None)
     u = np.array(u0, dtype=np.float64, copy=True)
     Jv, g = problem.gradient(u)
     pairs = []

@@ -43,7 +43,7 @@ LbLayout lb_layout(const Geo& g, int mem) {
   L.lam = o;
   o = align_up(o + sizeof(float) * (size_t)(g.n[0] + g.n[1] + g.n[2]));
   L.vec = o;
-  L.vbytes = align_up(sizeof(float) * 3 * g.nbar);
+  L.vbytes = align_up(sizeof(float) * g.nc() * g.nbar);
   // ta, tb (transform scratch), g, gn, d, trial, and mem + 1 slots of (s, y)
   L.nvec = 6 + 2 * (mem + 1);
   L.total = o + L.vbytes * (size_t)L.nvec;
@@ -51,7 +51,6 @@ LbLayout lb_layout(const Geo& g, int mem) {
 }
 
 mfr_status check_geo(const Geo& g) {
-  if (g.dim == 2) return fail(MFR_EINVAL, "L-BFGS takes three-dimensional problems only");
   if (g.reg == MFR_REG_ELASTIC)
     return fail(MFR_EINVAL, "the H_0 solve needs a regulariser that acts on each component alone (not elastic)");
   for (int d = 0; d < 3; ++d)
@@ -97,6 +96,7 @@ mfr_status upload_tables(mfr_ctx* c, const LbLayout& L, char* work, H0Tables* t)
   HIP_TRY(hipMemcpyAsync(work + L.lam, c->h0_lam.data(), sizeof(float) * c->h0_lam.size(), hipMemcpyHostToDevice,
                          c->stream));
   t->lam = reinterpret_cast<const float*>(work + L.lam);
+  t->nc = g.nc();
   return MFR_OK;
 }
 
@@ -110,7 +110,7 @@ mfr_status check_work(const mfr_ctx* c, const LbLayout& L, const void* work, siz
 
 // float64 dot product of two node vectors (synchronises the stream)
 mfr_status dot(mfr_ctx* c, const float* a, const float* b, double* out) {
-  const int n3 = (int)(3 * c->geo.nbar);
+  const int n3 = (int)(c->geo.nc() * c->geo.nbar);
   HIP_TRY(launch_dot(n3, a, b, c->red_node, c->vec_blocks, c->stream));
   HIP_TRY(launch_sum(c->red_node, c->vec_blocks, c->sc + SC_DOT, c->stream));
   HIP_TRY(hipMemcpyAsync(out, c->sc + SC_DOT, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -127,7 +127,7 @@ void h0_coeffs(const Geo& g, float* c2, float* c1) {
 mfr_status lbfgs_run(mfr_ctx* c, float* u, const mfr_lbfgs_opts* o, char* work, const LbLayout& L,
                      mfr_lbfgs_report* rep) {
   const auto t0 = std::chrono::steady_clock::now();
-  const int n3 = (int)(3 * c->geo.nbar);
+  const int n3 = (int)(c->geo.nc() * c->geo.nbar);
   H0Tables tab{};
   MFR_TRY(upload_tables(c, L, work, &tab));
   auto vec = [&](int k) { return reinterpret_cast<float*>(work + L.vec + (size_t)k * L.vbytes); };
@@ -280,7 +280,7 @@ mfr_status mfr_lbfgs(mfr_ctx* c, float* u, const mfr_lbfgs_opts* o, void* work, 
   MFR_TRY(check_work(c, L, work, work_bytes));
   const char* w = static_cast<const char*>(work);
   const char* ub = reinterpret_cast<const char*>(u);
-  if (ub + sizeof(float) * 3 * c->geo.nbar > w && ub < w + L.total)
+  if (ub + sizeof(float) * c->geo.nc() * c->geo.nbar > w && ub < w + L.total)
     return fail(MFR_EINVAL, "u must not point into the work buffer");
   return lbfgs_run(c, u, o, static_cast<char*>(work), L, rep);
 }

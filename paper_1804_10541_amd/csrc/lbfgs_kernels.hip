@@ -79,8 +79,8 @@ __global__ __launch_bounds__(256) void axis_transform_kernel(const float* __rest
 
 // x = v / (c2 l^2 + c1 l + gamma), l = lx[i] + ly[j] + lz[k], in the cosine basis.
 __global__ __launch_bounds__(256) void h0_scale_kernel(float* __restrict__ x, const float* __restrict__ lam, int nx,
-                                                       int ny, int nz, float c2, float c1, float gamma) {
-  const size_t nb = (size_t)nx * ny * nz, total = 3 * nb;
+                                                       int ny, int nz, int nc, float c2, float c1, float gamma) {
+  const size_t nb = (size_t)nx * ny * nz, total = (size_t)nc * nb;
   const float* lx = lam;
   const float* ly = lam + nx;
   const float* lz = lam + nx + ny;
@@ -109,20 +109,26 @@ hipError_t transform(const float* M, int n, const float* in, float* out, long lo
 // x may alias v.
 hipError_t launch_h0_solve(const H0Tables& t, const float* v, float* x, float* ta, float* tb, float c2, float c1,
                            float gamma, hipStream_t st) {
-  const int nx = t.n[0], ny = t.n[1], nz = t.n[2];
+  const int nx = t.n[0], ny = t.n[1], nz = t.n[2], nc = t.nc;
   const long long nxy = (long long)nx * ny, nb = nxy * nz;
   hipError_t e;
-  // forward: z (per component), y (per component and plane), x (all lines)
-  if ((e = transform(t.C[2], nz, v, ta, nb, nxy, 1, (int)nxy, 3, false, st)) != hipSuccess) return e;
-  if ((e = transform(t.C[1], ny, ta, tb, nxy, nx, 1, nx, 3 * nz, false, st)) != hipSuccess) return e;
-  if ((e = transform(t.C[0], nx, tb, ta, 0, 1, nx, (int)(3 * nz * ny), 1, true, st)) != hipSuccess) return e;
-  const int blocks = (int)std::min<long long>((3 * nb + 255) / 256, 8192);
-  hipLaunchKernelGGL(h0_scale_kernel, dim3(blocks), dim3(256), 0, st, ta, t.lam, nx, ny, nz, c2, c1, gamma);
+  // forward: z (per component), y (per component and plane), x (all lines); a
+  // two-dimensional field (nz = 1) has no z transform (its cosine matrix is 1)
+  const float* in = v;
+  if (nz > 1) {
+    if ((e = transform(t.C[2], nz, v, tb, nb, nxy, 1, (int)nxy, nc, false, st)) != hipSuccess) return e;
+    in = tb;
+  }
+  if ((e = transform(t.C[1], ny, in, ta, nxy, nx, 1, nx, nc * nz, false, st)) != hipSuccess) return e;
+  if ((e = transform(t.C[0], nx, ta, tb, 0, 1, nx, (int)(nc * nz * ny), 1, true, st)) != hipSuccess) return e;
+  const int blocks = (int)std::min<long long>((nc * nb + 255) / 256, 8192);
+  hipLaunchKernelGGL(h0_scale_kernel, dim3(blocks), dim3(256), 0, st, tb, t.lam, nx, ny, nz, nc, c2, c1, gamma);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // inverse: the transposed matrices in reverse order
-  if ((e = transform(t.Ct[0], nx, ta, tb, 0, 1, nx, (int)(3 * nz * ny), 1, true, st)) != hipSuccess) return e;
-  if ((e = transform(t.Ct[1], ny, tb, ta, nxy, nx, 1, nx, 3 * nz, false, st)) != hipSuccess) return e;
-  return transform(t.Ct[2], nz, ta, x, nb, nxy, 1, (int)nxy, 3, false, st);
+  if ((e = transform(t.Ct[0], nx, tb, ta, 0, 1, nx, (int)(nc * nz * ny), 1, true, st)) != hipSuccess) return e;
+  if (nz == 1) return transform(t.Ct[1], ny, ta, x, nxy, nx, 1, nx, nc, false, st);
+  if ((e = transform(t.Ct[1], ny, ta, tb, nxy, nx, 1, nx, nc * nz, false, st)) != hipSuccess) return e;
+  return transform(t.Ct[2], nz, tb, x, nb, nxy, 1, (int)nxy, nc, false, st);
 }
 
 }  // namespace mfr

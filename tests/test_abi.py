@@ -166,7 +166,9 @@ def test_two_dimensional_problems_validation(lib):
         assert ei.value.status == -1, bad
     g = mfr.make_grid(GridSpec(**base))
     n = ctypes.c_size_t()
-    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 5, ctypes.byref(n)) == -1
+    assert lib.mfr_lbfgs_workspace_size(ctypes.byref(g), 5, ctypes.byref(n)) == 0   # L-BFGS takes 2D problems
+    # cosine tables of two axes (the z one is 1 x 1) and 6 + 2 (mem + 1) two-component vectors
+    assert n.value >= 4 * 2 * (76 * 76 + 51 * 51) + (6 + 12) * 4 * 2 * 76 * 51
     assert lib.mfr_pc_workspace_size(ctypes.byref(g), 0, ctypes.byref(n)) == -1
     assert lib.mfr_batch_workspace_size(1, ctypes.byref(g), 1, ctypes.byref(n)) == -1
     # the pyramid of a 2D problem halves x and y only

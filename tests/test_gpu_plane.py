@@ -265,3 +265,92 @@ def test_plane_full_size_sampled_nodes():
     print(f"[gpu-case] sampled rel-L2: gradient {e_g:.2e}, Hv {e_h:.2e}, diagonal {e_d:.2e}", flush=True)
     assert e_g <= 1e-4 and e_h <= 1e-4 and e_d <= 1e-4
     assert np.all(dg > 0)
+
+
+H0_PLANE_CASES = [
+    # name, m, my, h, alpha, gamma
+    ("ragged", (61, 37), (16, 13), (1.0, 1.3), 0.5, 0.2),
+    ("ratio-one", (20, 14), (21, 15), (1.0, 1.0), 1.0, 1.0),
+    ("two-nodes", (5, 4), (2, 2), (1.0, 1.0), 1.0, 0.5),
+    ("long-axis", (300, 30), (301, 9), (1.0, 1.0), 0.1, 0.05),
+    ("no-regulariser", (24, 20), (9, 8), (1.0, 1.0), 0.0, 2.0),
+]
+
+
+@pytest.mark.parametrize("name,m,my,h,alpha,gamma", H0_PLANE_CASES, ids=[c[0] for c in H0_PLANE_CASES])
+def test_plane_h0_solve_matches_oracle(name, m, my, h, alpha, gamma):
+    """L-BFGS initial-matrix solve (Sec. 2.3.2) with two cosine axes against the
+    oracle's solve of (2 alpha hbar^y L^T L + gamma I) x = v (5-point L)."""
+    from oracle import lbfgs
+
+    print(f"[gpu-case] plane h0 {name} {m} / {my}", flush=True)
+    spec, R, T, u, probes = plane_case(2, m, my, n_probes=2, h=h, alpha=alpha)
+    ctx = mfr.Context(spec, DEV)
+    g = plane.Grid2.from_spec(spec)
+    h0 = lbfgs.H0Solver(g, gamma, plane.laplacian(g))
+    for p in probes:
+        want = h0.apply(p.astype(np.float64))
+        x = ctx.h0_solve(to_dev(p), gamma).cpu().numpy()
+        assert x.shape == p.shape
+        assert rel_l2(x, want) <= 1e-4, rel_l2(x, want)
+        t = to_dev(p)
+        ctx.h0_solve(t, gamma, out=t)   # in place
+        assert rel_l2(t.cpu().numpy(), want) <= 1e-4
+    ctx.close()
+
+
+def test_plane_lbfgs_first_iterate_and_objective_per_iterate():
+    """The two-dimensional L-BFGS run (the optimiser of the paper's 2D GPU
+    registrations): the first step from the same start against the oracle's
+    (two-loop recursion with an empty memory, Armijo backtracking), then six
+    iterations whose final J the oracle re-evaluates at the GPU's iterate;
+    bitwise repeatable."""
+    from oracle import lbfgs
+
+    print("[gpu-case] plane lbfgs 192x160 / 49x41", flush=True)
+    spec, R, T, u0, _ = plane_case(7, (192, 160), (49, 41), amp=0.0, n_probes=0)
+    prob = plane.Problem2(plane.Grid2.from_spec(spec), R.astype(np.float64), T.astype(np.float64))
+    gamma = 1e2
+    ctx = mfr.Context(spec, DEV)
+    ctx.set_images(to_dev(R), to_dev(T))
+    tu = to_dev(u0)
+    rep = ctx.lbfgs(tu, iters=1, mem=5, gamma=gamma)
+    assert rep["iters"] == 1 and rep["status"] == 0, rep
+    uo, hist = lbfgs.lbfgs(prob, u0.astype(np.float64), iters=1, mem=5, gamma=gamma)
+    e = rel_l2(tu.cpu().numpy().astype(np.float64) - u0, uo - u0)
+    print(f"[gpu-case] first step rel-L2 {e:.2e}, eta {hist[0]['eta']}", flush=True)
+    assert e <= 1e-4
+    assert abs(rep["J_initial"] - hist[0]["J"]) <= 1e-5 * abs(hist[0]["J"])
+    tu = to_dev(u0)
+    rep = ctx.lbfgs(tu, iters=6, mem=3, gamma=gamma)
+    assert rep["status"] == 0 and rep["iters"] == 6, rep
+    assert rep["J_final"] < rep["J_initial"]
+    Jo = prob.objective(tu.cpu().numpy().astype(np.float64))[0]
+    assert abs(rep["J_final"] - Jo) <= 1e-5 * abs(Jo), (rep["J_final"], Jo)
+    tu2 = to_dev(u0)
+    ctx.lbfgs(tu2, iters=6, mem=3, gamma=gamma)
+    assert torch.equal(tu, tu2)
+    ctx.close()
+
+
+def test_plane_lbfgs_pure_regulariser_closed_form_first_step():
+    """Zero images: D = 0 and J = alpha S, whose Hessian A = 2 alpha hbar^y L^T L
+    (5-point L); the first step from u0 is -(A + gamma I)^{-1} A u0."""
+    print("[gpu-case] plane lbfgs closed form", flush=True)
+    spec, R, T, u0, _ = plane_case(4, (30, 24), (11, 9), amp=0.7, n_probes=0, alpha=0.6)
+    Z = np.zeros_like(R)
+    ctx = mfr.Context(spec, DEV)
+    ctx.set_images(to_dev(Z), to_dev(Z))
+    gamma = 0.05
+    tu = to_dev(u0)
+    rep = ctx.lbfgs(tu, iters=1, mem=2, gamma=gamma)
+    assert rep["iters"] == 1, rep
+    g = plane.Grid2.from_spec(spec)
+    L = plane.laplacian(g).toarray()
+    A = 2.0 * g.alpha * g.hybar * (L.T @ L)
+    M = A + gamma * np.eye(g.nbar)
+    u64 = u0.astype(np.float64)
+    want = np.stack([u64[d].ravel() - np.linalg.solve(M, A @ u64[d].ravel()) for d in range(2)]).reshape(u0.shape)
+    e = rel_l2(tu.cpu().numpy() - u64, want - u64)
+    assert e <= 1e-4, f"closed-form step rel-L2 {e:.3e}"
+    ctx.close()

@@ -279,3 +279,43 @@ def test_node_outputs_match_full_evaluation():
         np.testing.assert_allclose(a, grad[:, node], rtol=1e-12, atol=1e-13)
         np.testing.assert_allclose(b, hv[:, node], rtol=1e-12, atol=1e-13)
         np.testing.assert_allclose(c, dg[:, node], rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("my,gamma", [((7, 5), 0.3), ((2, 9), 2.0), ((11, 11), 0.05)])
+def test_h0_solver_two_dimensional_on_cosine_eigenvectors(my, gamma):
+    """L-BFGS initial matrix (Sec. 2.3.2) on a two-dimensional grid: the 5-point
+    Neumann Laplacian's eigenvectors are products of DCT-II cosines
+    cos(pi k (i + 1/2) / n), eigenvalue -4 sin^2(pi k / 2n) / hy^2 per axis, so
+    H_0 = 2 alpha hbar^y L^T L + gamma I scales them by 2 alpha hbar^y lam^2 + gamma."""
+    from oracle import lbfgs
+
+    g = plane.Grid2((13, 10), (1.0, 1.3), my, 1.0, 1.0, 0.7)
+    h0 = lbfgs.H0Solver(g, gamma, plane.laplacian(g))
+    for ks in [(0, 0), (1, 2), (my[0] - 1, my[1] - 1), (2, 1)]:
+        ks = tuple(min(k, n - 1) for k, n in zip(ks, my))
+        ax = [np.cos(np.pi * ks[d] * (np.arange(my[d]) + 0.5) / my[d]) for d in range(2)]
+        v = np.outer(ax[1], ax[0])
+        lam = -sum(4.0 * np.sin(np.pi * ks[d] / (2 * my[d])) ** 2 / g.hy[d] ** 2 for d in range(2))
+        mu = 2.0 * g.alpha * g.hybar * lam * lam + gamma
+        V = np.stack([v, -3.0 * v])
+        np.testing.assert_allclose(h0.apply(V), V / mu, rtol=1e-9, atol=1e-12)
+
+
+def test_lbfgs_two_dimensional_first_step_is_the_regularised_newton_step():
+    """With T = R = 0, D = 0 and J = alpha S is quadratic with Hessian
+    A = 2 alpha hbar^y L^T L: the first L-BFGS step from u0 is
+    -(A + gamma I)^{-1} A u0 and eta = 1 passes the Armijo test."""
+    from oracle import lbfgs
+
+    g = plane.Grid2((11, 9), (1.0, 1.0), (6, 5), 0.3, 0.3, 0.6)
+    Z = np.zeros((9, 11))
+    prob = plane.Problem2(g, Z, Z)
+    u0 = np.random.default_rng(4).standard_normal((2, 5, 6))
+    gamma = 0.05
+    u1, hist = lbfgs.lbfgs(prob, u0, iters=1, gamma=gamma)
+    L = plane.laplacian(g).toarray()
+    A = 2.0 * g.alpha * g.hybar * (L.T @ L)
+    M = A + gamma * np.eye(g.nbar)
+    want = np.stack([u0[d].ravel() - np.linalg.solve(M, A @ u0[d].ravel()) for d in range(2)]).reshape(u0.shape)
+    assert hist[0]["eta"] == 1.0
+    np.testing.assert_allclose(u1, want, rtol=1e-9, atol=1e-11)
