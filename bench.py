@@ -45,12 +45,33 @@ HV_BYTES_PER_NODE = 36
 SSD_HV_FLOP_PER_VOXEL = 98
 SSD_HV_BYTES_PER_VOXEL = 4
 
-# HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload
-# (32x16 tiles, split target 4096), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a
-# plain copy kernel (profiles/ngf_tile_hv_512x512x900.md): 2.00 x 1,186,960 KiB +
-# 1.00 x 114,215 KiB.  Only valid for that kernel build and tile configuration; otherwise
-# reported as null.
-HV_TRAFFIC_C3 = {"bytes": 2547808066, "tile": (32, 16, 4096)}
+# HBM bytes per launch of the Hessian-vector tile kernel at the 512x512x900 workload come
+# from the committed rocprofv3 summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the
+# counter reads for a plain copy kernel).  The summary records a hash of the kernel's
+# sources and the tile configuration it was taken with; for other sources or another
+# configuration the traffic is reported as null.
+HV_PROFILE = os.path.join(ROOT, "profiles", "ngf_tile_hv_512x512x900.md")
+
+
+def profiled_traffic(tile_cfg):
+    """Measured HBM bytes per launch of the Hessian-vector kernel from the committed
+    profile summary, if it was taken with the current kernel sources and tile
+    configuration; else None."""
+    import re
+
+    if not tile_cfg or not os.path.exists(HV_PROFILE):
+        return None
+    text = open(HV_PROFILE).read()
+    m_hash = re.search(r"Kernel sources \(sha256, 16 hex\): `([0-9a-f]+)`", text)
+    m_tile = re.search(r"Tile configuration: (\d+)x(\d+), split target (\d+)", text)
+    m_bytes = re.search(r"HBM traffic per launch: ([0-9,]+) bytes", text)
+    from paper_1804_10541_amd.profsum import kernel_source_hash
+
+    if not (m_hash and m_tile and m_bytes) or m_hash.group(1) != kernel_source_hash():
+        return None
+    if (tile_cfg["bx"], tile_cfg["by"], tile_cfg["target_groups"]) != tuple(int(g) for g in m_tile.groups()):
+        return None
+    return int(m_bytes.group(1).replace(",", ""))
 
 
 def log(msg):
@@ -276,26 +297,119 @@ def pc_leg(dev):
     return out
 
 
-def cpu_baseline(R, T, u0, spec, budget_s=25.0):
-    """The float64 oracle, as it stands, on a crop of the same volume: one
-    Gauss-Newton step's derivative work (objective, gradient, Jacobi diagonal,
-    and HV_PER_STEP Hessian-vector products reusing the assembled Jacobian)."""
+def memory_leg():
+    """Device memory of the library at 512 x 512 x 900 and 512 x 512 x 450 voxels
+    (same 129 x 129 node grid in x, y; 225 / 113 node planes): the workspace of
+    a context (exact size query) split into the zero-bordered template copy,
+    which grows with the voxels, and the rest (tables, transposed-conversion
+    partials, reductions and the node vectors of CG / Gauss-Newton: the
+    derivative memory, independent of the voxel count), beside the images."""
+    from paper_1804_10541_amd import mfr
+
+    out = {}
+    for name in ("c3", "c3-half"):
+        s = workload_spec(name)
+        ws = mfr.workspace_size(s)
+        tpl = 4 * (s.m[0] + 4) * (s.m[1] + 4) * (s.m[2] + 4)
+        out[name] = {"voxels": s.voxels, "nodes": s.nodes, "images_bytes": 8 * s.voxels, "workspace_bytes": ws,
+                     "template_copy_bytes": tpl, "derivative_bytes": ws - tpl,
+                     "derivative_bytes_per_node": round((ws - tpl) / s.nodes, 1)}
+    log(f"[bench] memory: {out}")
+    return out
+
+
+def plane_leg(dev, levels=3):
+    """The two-dimensional path at 4096 x 4096 pixels / 2049 x 2049 nodes (the
+    largest size of the paper's two-dimensional GPU table): kernel times of the
+    objective, gradient and Hessian-vector product (HIP events on the context's
+    stream), a Gauss-Newton step with 20 Hessian-vector products, and a
+    three-level registration (10 Gauss-Newton steps per level, Jacobi-PCG <= 50
+    at rtol 1e-3)."""
+    import torch
+
+    from paper_1804_10541_amd import mfr
+    from synth import config_section
+
+    c = config_section(0, n_probes=1)
+    spec = c["spec"]
+    R, T = torch.from_numpy(c["R"]).to(dev), torch.from_numpy(c["T"]).to(dev)
+    u0 = torch.from_numpy(c["u0"]).to(dev)
+    p = torch.from_numpy(c["probes"][0]).to(dev)
+    ctx = mfr.Context(spec, dev)
+    ctx.set_images(R, T)
+    q = torch.empty_like(p)
+    for _ in range(3):
+        ctx.objective(u0)
+        ctx.gradient(u0)
+        ctx.hess_vec(u0, p, out=q)
+    torch.cuda.synchronize()
+    reps = 20
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.gradient(u0)   # objective value included (one synchronisation)
+    torch.cuda.synchronize()
+    t_grad = (time.perf_counter() - t0) / reps
+    for _ in range(reps):
+        ctx.objective(u0)
+        ctx.hess_vec(u0, p, out=q)
+    ctx.jacobi_diag(u0)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    u = u0.clone()
+    gn = dict(pcg_max=HV_PER_STEP, pcg_rtol=0.0, precond=1, armijo_c1=1e-4, armijo_max=10)
+    ctx.gn_step(u, **gn)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = ctx.gn_step(u, **gn)
+    torch.cuda.synchronize()
+    t_gn = time.perf_counter() - t0
+    ctx.close()
+    avg = lambda k: round(prof[k][1] / max(prof[k][0], 1), 4)
+    mbar, nbar = spec.m[0] * spec.m[1], spec.my[0] * spec.my[1]
+    hv_ms = avg("tile_hv")
+    ml_opts = dict(levels=levels, gn_iters=10, pcg_max=50, pcg_rtol=1e-3, armijo_c1=1e-4, armijo_max=10, precond=1)
+    mfr.register_multilevel(spec, R, T, **dict(ml_opts, gn_iters=1))   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = mfr.register_multilevel(spec, R, T, **ml_opts)
+    torch.cuda.synchronize()
+    t_ml = time.perf_counter() - t0
+    out = {"workload": f"two-dimensional section pair {spec.m[0]}x{spec.m[1]} pixels, {spec.my[0]}x{spec.my[1]} "
+                       "nodes, eps 0.05, alpha 1",
+           "pixels": mbar, "nodes": nbar,
+           "gradient_call_ms": round(t_grad * 1e3, 4),
+           "kernel_ms": {k: avg(k) for k in ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass")},
+           "hv_kernel_gpixel_s": round(mbar / (hv_ms * 1e-3) / 1e9, 2),
+           "hv_hbm_algorithmic_gbs": round((8 * mbar + 24 * nbar) / (hv_ms * 1e-3) / 1e9, 1),
+           "gn_step_ms": round(t_gn * 1e3, 3), "gn_step_J": [info["J_before"], info["J_after"]],
+           "registration_s": round(t_ml, 4), "registration_gn_steps": rep["gn_done"],
+           "registration_pcg_iters": rep["pcg_total"], "registration_J": [rep["J_start"][0], rep["J_final"]],
+           "paper_context": "GTX 980, float32: gradient 35.3 ms, full three-level L-BFGS registration 1.51 s "
+                            "(Table objfunGradRuntime_CUDA, Fig. multiLevelRuntime_CUDA; another GPU and "
+                            "another optimiser)"}
+    log(f"[bench] plane: {out}")
+    return out
+
+
+CPU_CROP = (128, 128, 64)   # voxels of one oracle sample (x, y, z)
+CPU_CROP_NODES = (33, 33, 17)
+
+
+def _oracle_crop_work(Rc, Tc, spec, seed, budget_s):
+    """One sample of the cpu_baseline: the float64 oracle's derivative work of a
+    Gauss-Newton step on a crop (spec: the crop's grid; objective, gradient,
+    Jacobi diagonal and up to HV_PER_STEP Hessian-vector products with the
+    assembled Jacobian).  Returns (Hessian-vector products done, seconds)."""
     import numpy as np
 
     from oracle import Grid, solver
-
-    # crop: 128 x 128 x 64 voxels from the centre, deformation ratio 4 as in the workload
-    cm = (128, 128, 64)
-    cn = (33, 33, 17)
-    mx, my_, mz = spec.m
-    x0, y0, z0 = (mx - cm[0]) // 2, (my_ - cm[1]) // 2, (mz - cm[2]) // 2
-    Rc = R[z0:z0 + cm[2], y0:y0 + cm[1], x0:x0 + cm[0]].double().cpu().numpy()
-    Tc = T[z0:z0 + cm[2], y0:y0 + cm[1], x0:x0 + cm[0]].double().cpu().numpy()
-    rng = np.random.default_rng(1)
     from synth import smooth_field
 
-    u = smooth_field(rng, cn, 0.5)
-    g = Grid(cm, spec.h, cn, spec.tau, spec.rho, spec.alpha)
+    u = smooth_field(np.random.default_rng(seed), spec.my, 0.5)
+    g = Grid(spec.m, spec.h, spec.my, spec.tau, spec.rho, spec.alpha)
     t0 = time.perf_counter()
     prob = solver.Problem(g, Rc, Tc)
     prob.objective(u)
@@ -310,12 +424,104 @@ def cpu_baseline(R, T, u0, spec, budget_s=25.0):
         n_hv += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
+    return n_hv, time.perf_counter() - t0
+
+
+def _cpu_worker(path, seed, budget_s, min_s):
+    """Entry of a cpu_baseline worker process (never touches the GPU): loads its
+    crop from ``path``, repeats the step's derivative work on it (a new
+    displacement each time) until ``min_s`` seconds have passed (at most four
+    times) and prints one JSON line."""
+    import numpy as np
+
+    from synth import GridSpec
+
+    d = np.load(path)
+    spec = GridSpec(m=tuple(d["m"]), h=tuple(d["h"]), my=tuple(d["my"]), tau=float(d["eps"]), rho=float(d["eps"]),
+                    alpha=float(d["alpha"]))
+    n, t, reps = 0, 0.0, 0
+    while True:
+        n_hv, dt = _oracle_crop_work(d["R"], d["T"], spec, seed + 100 * reps, budget_s)
+        n, t, reps = n + n_hv, t + dt, reps + 1
+        if t >= min_s or reps >= 4:
+            break
+    print(json.dumps({"n_hv": n, "seconds": t, "reps": reps}), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(R, T, u0, spec, budget_s=25.0, max_workers=16):
+    """The float64 oracle, as it stands (scipy.sparse, one thread per process),
+    on crops of the same volume: single-thread on rank 0 at N = 1, and on all
+    host cores as independent worker processes, one crop each (the oracle has
+    no parallel path of its own).  Crops of 128 x 128 x 64 voxels / 33 x 33 x 17
+    nodes (the workload's grid ratio), centred and shifted along z per worker."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    mx, my_, mz = spec.m
+    cm = CPU_CROP
+
+    def crop(k):
+        x0, y0 = (mx - cm[0]) // 2, (my_ - cm[1]) // 2
+        z0 = min(max((mz - cm[2]) // 2 + (k - 8) * cm[2] // 2, 0), mz - cm[2])
+        sl = (slice(z0, z0 + cm[2]), slice(y0, y0 + cm[1]), slice(x0, x0 + cm[0]))
+        return R[sl].double().cpu().numpy(), T[sl].double().cpu().numpy()
+
     vox = cm[0] * cm[1] * cm[2]
-    return {"value": vox * n_hv / dt / 1e9, "unit": "Gvoxel/s", "cores": 1, "kind": "oracle",
-            "sample": f"crop {cm[0]}x{cm[1]}x{cm[2]} voxels / {cn[0]}x{cn[1]}x{cn[2]} nodes of the same volume; "
-                      f"objective + gradient + Jacobi diagonal + {n_hv} Hessian-vector products "
-                      f"(assembled float64 Jacobian, scipy.sparse, single thread) in {dt:.1f} s"}
+    cores = os.cpu_count() or 1
+    workers = max(1, min(cores, max_workers))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+
+    def launch(path, seed, min_s):
+        return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", path, str(seed),
+                                 str(budget_s), str(min_s)], stdout=subprocess.PIPE, env=env)
+
+    def result(pr):
+        outp, _ = pr.communicate()
+        return json.loads(outp.decode().strip().splitlines()[-1]) if pr.returncode == 0 else None
+
+    with tempfile.TemporaryDirectory() as tmp:
+        files = []
+        for k in range(workers):
+            Rk, Tk = crop(k)
+            path = os.path.join(tmp, f"crop{k}.npz")
+            np.savez(path, R=Rk, T=Tk, m=np.array(cm), h=np.array(spec.h), my=np.array(CPU_CROP_NODES),
+                     eps=spec.tau, alpha=spec.alpha)
+            files.append(path)
+        # one thread: one worker process alone, the centre crop, about 10 s of work
+        one = result(launch(files[8 % workers], 1, 10.0))
+        # all host cores: one worker per core at once, one pass each
+        procs = [launch(path, k + 1, 0.0) for k, path in enumerate(files)]
+        res = [r for r in (result(pr) for pr in procs) if r is not None]
+    # the workers' timed sections overlap (all start after the same imports): the
+    # longest one is the wall time of the concurrent work
+    wall = max((r["seconds"] for r in res), default=0.0)
+    n_all = sum(r["n_hv"] for r in res)
+    single = vox * one["n_hv"] / one["seconds"] / 1e9 if one else None
+    allc = vox * n_all / wall / 1e9 if res else None
+    return {"value": single, "unit": "Gvoxel/s", "cores": 1, "kind": "oracle",
+            "sample": f"crop {cm[0]}x{cm[1]}x{cm[2]} voxels / {CPU_CROP_NODES[0]}x{CPU_CROP_NODES[1]}x"
+                      f"{CPU_CROP_NODES[2]} nodes of the same volume, one worker process with one thread; "
+                      f"{one['reps'] if one else 0} x (objective + gradient + Jacobi diagonal + "
+                      f"{HV_PER_STEP} Hessian-vector products with the assembled float64 Jacobian, scipy.sparse): "
+                      f"{one['n_hv'] if one else 0} Hessian-vector products in "
+                      f"{one['seconds'] if one else 0.0:.1f} s",
+            "all_cores": {"value": allc, "unit": "Gvoxel/s", "processes": len(res), "host_cpus": cores,
+                          "sample": f"{len(res)} single-thread worker processes at once, one crop each (z-shifted), "
+                                    f"one step's work per crop; {n_all} Hessian-vector products, longest worker {wall:.1f} s"},
+            "cpu_model": _cpu_model()}
 
 
 def main():
@@ -331,9 +537,14 @@ def main():
     ap.add_argument("--no-ssd", action="store_true", help="skip the sum-of-squared-differences leg")
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS leg")
     ap.add_argument("--no-regularisers", action="store_true", help="skip the diffusive and elastic legs")
+    ap.add_argument("--no-plane", action="store_true", help="skip the two-dimensional leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--cpu-worker", nargs=4, metavar=("CROP", "SEED", "BUDGET", "MIN_S"), help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:   # a cpu_baseline worker process: oracle only, no GPU
+        _cpu_worker(args.cpu_worker[0], int(args.cpu_worker[1]), float(args.cpu_worker[2]), float(args.cpu_worker[3]))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -402,10 +613,7 @@ def main():
     achieved_tflops = flops / (hv_avg_ms * 1e-3) / 1e12
     alg_bytes = HV_BYTES_PER_VOXEL * mbar + HV_BYTES_PER_NODE * nbar
     hv_hbm_gbs = alg_bytes / (hv_avg_ms * 1e-3) / 1e9
-    traffic = None
-    if args.workload == "c3" and tile_cfg and \
-            (tile_cfg["bx"], tile_cfg["by"], tile_cfg["target_groups"]) == HV_TRAFFIC_C3["tile"]:
-        traffic = HV_TRAFFIC_C3["bytes"]
+    traffic = profiled_traffic(tile_cfg) if args.workload == "c3" else None
     out = {
         "metric": "GN Hessian-vector Gvoxel/s + % HBM peak; PCG solve time, learned vs Jacobi",
         "value": round(value, 3),
@@ -435,6 +643,7 @@ def main():
         "kernel_ms": {k: (v[0], round(v[1] / max(v[0], 1), 4)) for k, v in prof.items()},
         "peak_device_bytes": int(peak_mem),
         "workspace_bytes": int(ctx.ws_bytes),
+        "memory": memory_leg(),
         "tile_config": tile_cfg,
     }
     if not args.no_cpu_baseline:
@@ -452,6 +661,9 @@ def main():
         out["diffusive"] = regulariser_leg(dev, spec, R, T, u0, "diffusive")
         out["elastic"] = regulariser_leg(dev, spec, R, T, u0, "elastic", lame_mu=1.0, lame_lambda=1.0)
     del R, T
+    if not args.no_plane:
+        log("[bench] two-dimensional path")
+        out["plane"] = plane_leg(dev)
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
         out["batch"] = batch_leg(dev, not args.no_autotune)

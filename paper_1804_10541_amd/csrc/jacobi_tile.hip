@@ -76,8 +76,9 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
   const int pslot = kgrp * NC + jcol;   // partial-sum slot (flush reads node column jc at jc + k NC)
   const int nxn = BX.lo + jcol % ncx, nyn = BY.lo + jcol / ncx;
   const Range1 rxr = J.rx[nxn], ryr = J.ry[nyn];
-  const int rw = rxr.hi - rxr.lo + 1;
-  const int nrows = rw * (ryr.hi - ryr.lo + 1);
+  const int rw = rxr.hi - rxr.lo + 1, rh = ryr.hi - ryr.lo + 1;
+  // this thread's first row of the window (x fastest) and its stride G as (x, y) steps
+  const int ra0 = kgrp % rw, rb0 = kgrp / rw, dra = G % rw, drb = G / rw;
   __syncthreads();   // sCx, sCy
   for (int q = tid; q < ncx * AX; q += NT) {
     const int jc = q / AX, la = q % AX, a = BX.a0 + la;
@@ -239,7 +240,6 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
       const bool hzm = c > 0, hzp = c < P.mz - 1;
       const Conv1 czm = P.cz[max(c - 1, 0)], cz0 = P.cz[c], czp = P.cz[min(c + 1, P.mz - 1)];
       float wz0[4], wzp[4], wzm[4];
-      int qmask = 0;   // node planes this row plane reaches (the others add exactly 0)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int nz = kflush + q;
@@ -247,14 +247,28 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
         wz0[q] = ok ? conv_weight(cz0, nz) : 0.0f;
         wzp[q] = (ok && hzp && !SSD) ? conv_weight(czp, nz) : 0.0f;
         wzm[q] = (ok && hzm && !SSD) ? conv_weight(czm, nz) : 0.0f;
-        if (wz0[q] != 0.0f || wzp[q] != 0.0f || wzm[q] != 0.0f) qmask |= 1 << q;
       }
-      qmask = __builtin_amdgcn_readfirstlane(qmask);   // uniform: c and kflush are
+      // Node planes this row plane reaches: kflush (the lower node plane of row
+      // plane c-1, the lowest any of its three planes touches) up to the upper
+      // node plane of row plane c+1; the accumulators of planes beyond that
+      // would only add exact zeros, so the row loop is instantiated per count.
+      const int top = SSD ? cz0.n0 + 1 : max(cz0.n0, hzp ? czp.n0 : 0) + 1;
+      const int nq = __builtin_amdgcn_readfirstlane(min(max(top - kflush + 1, 1), 4));
       const int sc = (c + 3) % 3, sp = (c + 4) % 3, sm = (c + 2) % 3;
-      if (gathers) {
-        for (int r = kgrp; r < nrows; r += G) {
-          const int a = rxr.lo + r % rw, b = ryr.lo + r / rw;
-          const int la = a - BX.a0, lb = b - BY.a0;
+      auto rows = [&](auto NQc) {
+        constexpr int NQ = decltype(NQc)::value;
+        if (!gathers) return;
+        // row r = kgrp + i G of the node column's rw x (rows in y) window, as
+        // (ra, rb) advanced by (G mod rw, G div rw) with a carry
+        int ra = ra0, rb = rb0;
+        while (rb < rh) {
+          const int la = rxr.lo + ra - BX.a0, lb = ryr.lo + rb - BY.a0;
+          ra += dra;
+          rb += drb;
+          if (ra >= rw) {
+            ra -= rw;
+            rb += 1;
+          }
           const int li = lb * SP + la;
           const float vx0 = wxr[la], vxm = wxr[la - 1], vxp = wxr[la + 1];
           const float vy0 = wyr[lb], vym = wyr[lb - 1], vyp = wyr[lb + 1];
@@ -265,11 +279,9 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
             for (int d = 0; d < 3; ++d) {
               const float pxy = al0 * sG[sc][d][li];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                if (qmask & (1 << q)) {
-                  const float zz = wz0[q] * pxy;
-                  acc[q][d] = fmaf(zz, zz, acc[q][d]);
-                }
+              for (int q = 0; q < NQ; ++q) {
+                const float zz = wz0[q] * pxy;
+                acc[q][d] = fmaf(zz, zz, acc[q][d]);
               }
             }
             continue;
@@ -288,14 +300,18 @@ __global__ __launch_bounds__(AX* AY) void jacobi_tile_kernel(const JacParams J, 
             const float zp = alzp * sG[sp][d][li];
             const float zm = alzm * sG[sm][d][li];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              if (qmask & (1 << q)) {
-                const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
-                acc[q][d] = fmaf(zz, zz, acc[q][d]);
-              }
+            for (int q = 0; q < NQ; ++q) {
+              const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
+              acc[q][d] = fmaf(zz, zz, acc[q][d]);
             }
           }
         }
+      };
+      switch (nq) {
+        case 1: rows(std::integral_constant<int, 1>{}); break;
+        case 2: rows(std::integral_constant<int, 2>{}); break;
+        case 3: rows(std::integral_constant<int, 3>{}); break;
+        default: rows(std::integral_constant<int, 4>{}); break;
       }
       // node planes below the window of the next row plane are complete
       while (kflush <= BZ.hi && kflush < cz0.n0) flush(kflush++);

@@ -271,7 +271,7 @@ def main():
         for r in rows:
             log(f"[eval] seed {r['seed']} GN {r['gn']}: Jacobi {r['jacobi_iters']} ({1e3 * r['jacobi_s']:.2f} ms), "
                 f"learned {r['learned_iters']} ({1e3 * r['learned_s']:.2f} ms), CG {r['cg_iters']}")
-        print(json.dumps(summarize(rows)), flush=True)
+        print(json.dumps(summarize_by_workload(rows)), flush=True)
         return
     init = np.load(args.init) if args.init else None
     t0 = time.perf_counter()
@@ -282,8 +282,18 @@ def main():
         f"loss {np.mean(hist[:10]):.4f} -> {np.mean(hist[-10:]):.4f}")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, params)
+    t0 = time.perf_counter()
     rows = evaluate(params, parse_range(args.eval), args.gn_iters, mix=not args.c2_only)
-    print(json.dumps(summarize(rows)), flush=True)
+    log(f"[eval] {len(rows)} systems in {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(summarize_by_workload(rows)), flush=True)
+
+
+def summarize_by_workload(rows):
+    """summarize() over all rows and per image size."""
+    out = {"all": summarize(rows)}
+    for m in sorted({tuple(r["m"]) for r in rows}):
+        out["x".join(map(str, m))] = summarize([r for r in rows if tuple(r["m"]) == m])
+    return out
 
 
 if __name__ == "__main__":
