@@ -224,6 +224,7 @@ static Tiling make_tiling_plane(const Geo& g, const std::vector<Conv1>& cx, cons
     const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[1]) - 1;
     t.nzt = std::max(t.nzt, cy[a1].n0 + 2 - cy[a0].n0);
   }
+  t.dg = DiagTiling{};
   return t;
 }
 
@@ -258,6 +259,31 @@ Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector
     const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[2]) - 1;
     t.nzt = std::max(t.nzt, cz[a1].n0 + 2 - cz[a0].n0);
   }
+  // the diagonal's own tiling: 2048 groups (two per CU resident, eight rounds);
+  // a group's z node block spans the planes its rows' z stencils reach
+  DiagTiling& d = t.dg;
+  const int DX = kDiagBX - 2, DY = kDiagBY - 2;
+  d.tiles_x = (g.m[0] + DX - 1) / DX;
+  d.tiles_y = (g.m[1] + DY - 1) / DY;
+  const int dxy = d.tiles_x * d.tiles_y;
+  int dch = std::min(std::max(1, (4096 + dxy - 1) / dxy), std::max(1, g.m[2] / 16));
+  d.chunk_len = std::min(std::min((g.m[2] + dch - 1) / dch, g.m[2]), kMaxChunk);
+  d.chunks = (g.m[2] + d.chunk_len - 1) / d.chunk_len;
+  d.nxt = d.nyt = d.nzt = 0;
+  for (int i = 0; i < d.tiles_x; ++i) {
+    const int a0 = std::max(i * DX - 1, 0), a1 = std::min(i * DX + DX, g.m[0] - 1);
+    d.nxt = std::max(d.nxt, cx[a1].n0 + 2 - cx[a0].n0);
+  }
+  for (int i = 0; i < d.tiles_y; ++i) {
+    const int a0 = std::max(i * DY - 1, 0), a1 = std::min(i * DY + DY, g.m[1] - 1);
+    d.nyt = std::max(d.nyt, cy[a1].n0 + 2 - cy[a0].n0);
+  }
+  for (int i = 0; i < d.chunks; ++i) {
+    const int zb = i * d.chunk_len, ze = std::min(zb + d.chunk_len, g.m[2]);
+    d.nzt = std::max(d.nzt, cz[std::min(ze, g.m[2] - 1)].n0 + 2 - cz[std::max(zb - 1, 0)].n0);
+  }
+  d.on = g.n[0] <= g.m[0] + 1 && g.n[1] <= g.m[1] + 1 && g.n[2] <= g.m[2] + 1 &&
+         d.nxt <= kDiagBX + 1 && d.nyt <= kDiagBY + 1 && d.nxt * d.nyt <= kDiagBX * kDiagBY / 2;
   return t;
 }
 
@@ -299,6 +325,14 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.jby = take(sizeof(NodeBlock) * g.n[1]);
   L.jbz = take(sizeof(NodeBlock) * g.n[2]);
   L.part = take(sizeof(float) * (size_t)t.grid() * 3 * t.nzt * t.nyt * t.nxt);
+  const DiagTiling& dg = t.dg;
+  L.dntx = take(dg.on ? sizeof(Range1) * g.n[0] : 0);
+  L.dnty = take(dg.on ? sizeof(Range1) * g.n[1] : 0);
+  L.dntz = take(dg.on ? sizeof(Range1) * g.n[2] : 0);
+  L.dorgx = take(dg.on ? sizeof(int) * dg.tiles_x : 0);
+  L.dorgy = take(dg.on ? sizeof(int) * dg.tiles_y : 0);
+  L.dorgz = take(dg.on ? sizeof(int) * dg.chunks : 0);
+  L.dpart = take(dg.on ? sizeof(float) * (size_t)dg.grid() * 3 * dg.nzt * dg.nyt * dg.nxt : 0);
   L.red_tile = take(sizeof(double) * (size_t)t.grid());
   const size_t node_blocks = (g.nbar + kNodeBlock - 1) / kNodeBlock;
   L.n_red_node = std::max<size_t>(3 * node_blocks, 2 * 1024);   // the node pass: one partial per block and component
@@ -547,6 +581,45 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
     HIP_TRY(up(L.jby, jby.data(), sizeof(NodeBlock) * jby.size()));
     HIP_TRY(up(L.jbz, jbz.data(), sizeof(NodeBlock) * jbz.size()));
   }
+  // voxel-tiled diagonal: the groups and chunks holding each node, the first
+  // node of each group's block (z: the planes its rows' z stencils reach)
+  const DiagTiling& dg = t.dg;
+  std::vector<Range1> dntx, dnty, dntz;
+  std::vector<int> dorgx, dorgy, dorgz;
+  if (dg.on) {
+    const int DX = kDiagBX - 2, DY = kDiagBY - 2;
+    dntx.resize(g.n[0]);
+    dnty.resize(g.n[1]);
+    dntz.resize(g.n[2]);
+    dorgx.resize(dg.tiles_x);
+    dorgy.resize(dg.tiles_y);
+    dorgz.resize(dg.chunks);
+    std::vector<int> dzend(dg.chunks);
+    for (int i = 0; i < g.n[0]; ++i) dntx[i] = groups_touching(colx[i], DX, dg.tiles_x);
+    for (int i = 0; i < g.n[1]; ++i) dnty[i] = groups_touching(coly[i], DY, dg.tiles_y);
+    for (int i = 0; i < dg.tiles_x; ++i) dorgx[i] = cx[std::max(i * DX - 1, 0)].n0;
+    for (int i = 0; i < dg.tiles_y; ++i) dorgy[i] = cy[std::max(i * DY - 1, 0)].n0;
+    for (int i = 0; i < dg.chunks; ++i) {
+      const int zb = i * dg.chunk_len, ze = std::min(zb + dg.chunk_len, g.m[2]);
+      dorgz[i] = cz[std::max(zb - 1, 0)].n0;
+      dzend[i] = cz[std::min(ze, g.m[2] - 1)].n0 + 2;
+    }
+    for (int k = 0; k < g.n[2]; ++k) {   // the chunks whose blocks hold node plane k (contiguous)
+      int lo = dg.chunks, hi = -1;
+      for (int i = 0; i < dg.chunks; ++i)
+        if (dorgz[i] <= k && k < dzend[i]) {
+          lo = std::min(lo, i);
+          hi = std::max(hi, i);
+        }
+      dntz[k] = Range1{lo, hi};
+    }
+    HIP_TRY(up(L.dntx, dntx.data(), sizeof(Range1) * dntx.size()));
+    HIP_TRY(up(L.dnty, dnty.data(), sizeof(Range1) * dnty.size()));
+    HIP_TRY(up(L.dntz, dntz.data(), sizeof(Range1) * dntz.size()));
+    HIP_TRY(up(L.dorgx, dorgx.data(), sizeof(int) * dorgx.size()));
+    HIP_TRY(up(L.dorgy, dorgy.data(), sizeof(int) * dorgy.size()));
+    HIP_TRY(up(L.dorgz, dorgz.data(), sizeof(int) * dorgz.size()));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
 
   TileParams& p = c->tp;
@@ -661,6 +734,32 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   jp.ihy2y = d.ihy2y;
   jp.ihy2z = d.ihy2z;
 
+  DiagTileParams& dt = c->dtp;
+  dt = DiagTileParams{};
+  dt.t = p;
+  dt.t.tiles_x = dg.tiles_x;
+  dt.t.tiles_y = dg.tiles_y;
+  dt.t.chunks = dg.chunks;
+  dt.t.chunk_len = dg.chunk_len;
+  dt.t.nxt = dg.nxt;
+  dt.t.nyt = dg.nyt;
+  dt.t.nzt = dg.nzt;
+  dt.t.part = at<float>(c->ws, L.dpart);
+  dt.t.red = nullptr;
+  dt.rx = d.rx;
+  dt.ry = d.ry;
+  dt.ntx = at<Range1>(c->ws, L.dntx);
+  dt.nty = at<Range1>(c->ws, L.dnty);
+  dt.ntz = at<Range1>(c->ws, L.dntz);
+  dt.orgx = at<int>(c->ws, L.dorgx);
+  dt.orgy = at<int>(c->ws, L.dorgy);
+  dt.orgz = at<int>(c->ws, L.dorgz);
+  dt.s_ngf = d.s_ngf;
+  dt.s_curv = d.s_curv;
+  dt.ihy2x = d.ihy2x;
+  dt.ihy2y = d.ihy2y;
+  dt.ihy2z = d.ihy2z;
+
   c->sc = at<double>(c->ws, L.sc);
   c->red_tile = p.red;
   c->red_node = q.red;
@@ -698,6 +797,7 @@ hipError_t timed(mfr_ctx* c, int slot, F&& launch) {
 
 hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
   if (c->geo.dim == 2) return launch_plane_jacobi(c->dp, u, diag, c->stream);
+  if (c->tiling.dg.on) return launch_diag_tile(c->dtp, u, diag, c->stream);
   if (c->jac_tiled) return launch_jacobi_tile(c->jp, u, diag, c->stream);
   return launch_jacobi_diag(c->dp, u, diag, c->stream);
 }
@@ -1070,6 +1170,7 @@ mfr_status mfr_set_images(mfr_ctx* c, const float* R, const float* T) {
   c->tp.R = R;
   c->dp.t.R = R;
   c->jp.t.R = R;
+  c->dtp.t.R = R;
   c->have_images = true;
   ++c->image_version;
   return MFR_OK;

@@ -72,10 +72,21 @@ std::vector<Samp1> samp_table(int m, double h, double hT);
 std::vector<Range1> node_cols(const std::vector<Conv1>& c, int n);
 std::vector<Conv1> prolong_table(int nf, double hyf, int nc, double hyc);
 
+// Tiling of the voxel-tiled Jacobi diagonal (kDiagBX x kDiagBY groups, its own
+// chunks); `on` when the node grid fits its per-group tables (at most one node
+// per voxel along each axis, at most half a group's threads of node columns).
+struct DiagTiling {
+  bool on;
+  int tiles_x, tiles_y, chunks, chunk_len;
+  int nxt, nyt, nzt;
+  int grid() const { return tiles_x * tiles_y * chunks; }
+};
+
 struct Tiling {
   TileShape shape;
   int tiles_x, tiles_y, chunks, chunk_len;
   int nxt, nyt, nzt;
+  DiagTiling dg;
   int grid() const { return tiles_x * tiles_y * chunks; }
 };
 
@@ -88,6 +99,7 @@ void set_tile_config(const mfr_tile_config& c);
 struct Layout {
   size_t Tp, cx, cy, cz, sx, sy, sz, ntx, nty, ntz, orgx, orgy, orgz, rx, ry, rz;
   size_t part, red_tile, red_node, sc, vec, jbx, jby, jbz, lap, ctrl, div;
+  size_t dntx, dnty, dntz, dorgx, dorgy, dorgz, dpart;   // voxel-tiled diagonal
   size_t n_red_node;
   size_t total;
 };
@@ -122,6 +134,7 @@ struct mfr_ctx {
   mfr::NodeParams np;
   mfr::DiagParams dp;
   mfr::JacParams jp;
+  mfr::DiagTileParams dtp;
   bool jac_tiled;
   double* sc;
   double* red_tile;

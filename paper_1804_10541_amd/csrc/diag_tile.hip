@@ -1,0 +1,482 @@
+// Exact diagonal of the Gauss-Newton system, diag(H + alpha nabla^2 S), on
+// voxel tiles (the Jacobi preconditioner of the conjugate-gradient solve).
+//
+// With J = dr dT P (eq. NGF_discretized_hessian) the NGF part of entry (d, n) is
+//   2 hbar sum_l ( sum_{k in K} rho-hat_l(k) g_{l+k,d} W_n(l+k) )^2,
+// a sum over the rows l of dr (eq. dr, eq. hatRho) whose 7-point stencil meets
+// the support of node n; W_n is the trilinear conversion weight of the node
+// (eq. grid_conversion) and g the template derivative (eq. dT).
+//
+// A work-group covers BX x BY voxel columns like the fused tile kernel: it
+// owns the rows of dr at the inner (BX-2) x (BY-2) columns, samples the
+// template on a one-column ring around them as well, and marches through a
+// chunk of z planes.  Per plane t it samples T, g and R (stage A), and at the
+// row plane t-1 each own column forms its row of dr and the 21 products
+// rho-hat_l(k) g_{l+k,d} (k in K, d = x, y, z), which go to LDS.  Then the
+// group's threads, split over the node columns its rows reach in proportion
+// to the rows each one has, add (sum_k P_l(k, d) W_n(l+k))^2 over their rows
+// for the (up to four) node planes the row plane reaches, in registers.  When
+// no later row plane can reach a node plane, the threads of each node column
+// are summed in a fixed order and the group writes its partial node block.  A
+// node pass sums the blocks of the groups overlapping each node (fixed order)
+// and adds the regulariser's diagonal: deterministic, no atomics, nothing per
+// voxel in HBM.  Each row's products are formed once; a ring column's rows
+// are the neighbouring group's.
+//
+// For the sum-of-squared-differences distance (Sec. 4.4) dr is the identity:
+// each row has the single coefficient 1 at its own voxel, so the products are
+// g_{l,d} and the entry is hbar sum_l (g_{l,d} W_n(l))^2.
+#include <type_traits>
+
+#include "tile_common.h"
+
+namespace mfr {
+
+namespace {
+
+template <bool SSD>
+struct DiagSmem {
+  static constexpr int BX = kDiagBX, BY = kDiagBY, NT = BX * BY;
+  static constexpr int MAXNX = BX + 1, MAXNY = BY + 1, MAXNC = NT / 2;
+  // plane exchange with a zero pad of one block row at both ends (NGF only)
+  static constexpr int XP = SSD ? 0 : BX, NX = SSD ? 1 : NT + 2 * BX;
+  static constexpr int NPROD = SSD ? 3 : 21;   // products of a row, index 3 k + d
+  float sTw[2][NX];
+  float sR[2][NX];
+  float sG[2][3][NX];
+  float sP[NPROD][NT];   // the flush reuses the first three rows
+  // conversion weight of local column la (row lb) for node column jx (row jy);
+  // 0 for columns outside the image
+  float sWx[MAXNX][BX];
+  float sWy[MAXNY][BY];
+  int sPre[MAXNC + 1];   // first gather thread of each node column (prefix of the thread counts)
+  Conv1 sCx[BX], sCy[BY];
+  Conv1 sCz[kMaxChunk + 4];
+  Samp1 sSz[kMaxChunk + 4];
+  int sTotal;
+};
+
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+__device__ __forceinline__ Conv1 uniform_conv(Conv1 c) {
+  c.n0 = __builtin_amdgcn_readfirstlane(c.n0);
+  c.f = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, c.f)));
+  return c;
+}
+
+}  // namespace
+
+template <bool SSD>
+__global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_eu(4))) void diag_tile_kernel(
+    const DiagTileParams D,
+                                                                     const float* __restrict__ u) {
+  using Sm = DiagSmem<SSD>;
+  constexpr int BX = Sm::BX, BY = Sm::BY, NT = Sm::NT, XP = Sm::XP;
+  constexpr int TX = BX - 2, TY = BY - 2;
+  __shared__ Sm S;
+  const TileParams& P = D.t;
+
+  const int tid = threadIdx.x;
+  const int tx = tid % BX, ty = tid / BX;
+  const int bid = xcd_block_id();
+  const int tile_x = bid % P.tiles_x;
+  const int rest = bid / P.tiles_x;
+  const int tile_y = rest % P.tiles_y;
+  const int chunk = rest / P.tiles_y;
+  const int x0 = tile_x * TX, y0 = tile_y * TY;
+  const int zb = chunk * P.chunk_len;
+  const int ze = min(P.mz, zb + P.chunk_len);
+
+  const int gx = x0 - 1 + tx, gy = y0 - 1 + ty;
+  const int cxi = min(max(gx, 0), P.mx - 1), cyi = min(max(gy, 0), P.my - 1);
+  const Conv1 cvx = P.cx[cxi], cvy = P.cy[cyi];
+  const Samp1 spx = P.sx[cxi], spy = P.sy[cyi];
+  const float wx0 = 1.0f - cvx.f, wx1 = cvx.f, wy0 = 1.0f - cvy.f, wy1 = cvy.f;
+  const unsigned nxy = (unsigned)(P.nx * P.ny);
+  const unsigned nodexy = (unsigned)(cvy.n0 * P.nx + cvx.n0);
+  const unsigned plane = (unsigned)(P.mx * P.my);
+  const unsigned colxy = (unsigned)(cyi * P.mx + cxi);
+  const unsigned nb = (unsigned)P.nbar, nxu = (unsigned)P.nx;
+
+  // The group's node block: nodes of its columns inside the image (own and
+  // ring) in x and y, and in z the node planes of the planes its rows' z
+  // stencils reach.
+  const int lxa = x0 == 0 ? 1 : 0, lya = y0 == 0 ? 1 : 0;
+  const int lxb = min(BX - 1, P.mx - x0), lyb = min(BY - 1, P.my - y0);
+  const int nox = P.cx[x0 - 1 + lxa].n0, noy = P.cy[y0 - 1 + lya].n0;
+  const int nxl = P.cx[x0 - 1 + lxb].n0 + 2 - nox, nyl = P.cy[y0 - 1 + lyb].n0 + 2 - noy;
+  const int NC = nxl * nyl;
+  const int noz = P.cz[max(zb - 1, 0)].n0;
+  const int nzend = P.cz[min(ze, P.mz - 1)].n0 + 2;   // one past the block's last node plane
+
+  for (int j = tid; j < ze - zb + 4; j += NT) {
+    const int q = min(max(zb - 2 + j, 0), P.mz - 1);
+    S.sCz[j] = P.cz[q];
+    S.sSz[j] = P.sz[q];
+  }
+  if (tid < BX) S.sCx[tid] = P.cx[min(max(x0 - 1 + tid, 0), P.mx - 1)];
+  if (tid < BY) S.sCy[tid] = P.cy[min(max(y0 - 1 + tid, 0), P.my - 1)];
+  if constexpr (XP > 0) {   // the pads of the plane exchange are never written by the march
+    for (int w = tid; w < 2 * 2 * XP; w += NT) {
+      const int r = w % (2 * XP), sl = w / (2 * XP);
+      const int q = r < XP ? r : NT + r;
+      S.sTw[sl][q] = 0.f;
+      S.sR[sl][q] = 0.f;
+      S.sG[sl][0][q] = S.sG[sl][1][q] = S.sG[sl][2][q] = 0.f;
+    }
+  }
+  if (tid == 0) S.sTotal = 0;
+
+  // Row window of node column j (local x node jx, y node jy): the own columns
+  // inside the image whose dr rows touch the node's support.
+  auto window = [&](int j, int& ax0, int& cw, int& ay0, int& ch) {
+    const Range1 rx = D.rx[nox + j % nxl], ry = D.ry[noy + j / nxl];
+    ax0 = max(rx.lo, x0);
+    cw = max(0, min(rx.hi, min(x0 + TX - 1, P.mx - 1)) - ax0 + 1);
+    ay0 = max(ry.lo, y0);
+    ch = max(0, min(ry.hi, min(y0 + TY - 1, P.my - 1)) - ay0 + 1);
+  };
+  __syncthreads();   // tables, sTotal
+  for (int q = tid; q < nxl * BX; q += NT) {
+    const int jx = q / BX, la = q % BX, a = x0 - 1 + la;
+    S.sWx[jx][la] = (a >= 0 && a < P.mx) ? conv_weight(S.sCx[la], nox + jx) : 0.0f;
+  }
+  for (int q = tid; q < nyl * BY; q += NT) {
+    const int jy = q / BY, lb = q % BY, b = y0 - 1 + lb;
+    S.sWy[jy][lb] = (b >= 0 && b < P.my) ? conv_weight(S.sCy[lb], noy + jy) : 0.0f;
+  }
+  // threads per node column: one each, the remaining NT - NC in proportion to the rows
+  int rows_j = 0;
+  if (tid < NC) {
+    int ax0, cw, ay0, ch;
+    window(tid, ax0, cw, ay0, ch);
+    rows_j = cw * ch;
+    atomicAdd(&S.sTotal, rows_j);   // an integer sum: order-free
+  }
+  __syncthreads();
+  if (tid < NC) S.sPre[tid + 1] = 1 + (int)(((long long)rows_j * (NT - NC)) / max(S.sTotal, 1));
+  __syncthreads();
+  if (tid == 0) {
+    S.sPre[0] = 0;
+    for (int j = 0; j < NC; ++j) S.sPre[j + 1] += S.sPre[j];
+  }
+  __syncthreads();
+
+  // This thread's node column (binary search in the prefix) and its rows:
+  // r = s, s + G, ... of the column's cw x ch window (x fastest), stepped as
+  // (x, y) increments with a carry.
+  const bool gathers = tid < S.sPre[NC];
+  int jc = 0;
+  {
+    int lo = 0, hi = NC - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (S.sPre[mid] <= tid) lo = mid; else hi = mid - 1;
+    }
+    jc = lo;
+  }
+  const int G = S.sPre[jc + 1] - S.sPre[jc], sidx = tid - S.sPre[jc];
+  int trips = 0, ra0 = 0, rb0 = 0, dra = 0, drb = 0, la0 = 0, lb0 = 0, cw = 1;
+  if (gathers) {
+    int ax0, ay0, ch;
+    window(jc, ax0, cw, ay0, ch);
+    const int rows = cw * ch;
+    if (rows > sidx) {
+      trips = (rows - sidx + G - 1) / G;
+      ra0 = sidx % cw;
+      rb0 = sidx / cw;
+      dra = G % cw;
+      drb = G / cw;
+    }
+    la0 = ax0 - (x0 - 1);
+    lb0 = ay0 - (y0 - 1);
+  }
+  const float* const wxr = S.sWx[jc % nxl];
+  const float* const wyr = S.sWy[jc / nxl];
+
+  const int slot = tile_x + P.tiles_x * (tile_y + P.tiles_y * chunk);
+  float* const part = P.part + (size_t)slot * 3 * P.nzt * P.nyt * P.nxt;
+  const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
+
+  // acc[q][d]: node plane kflush + q (kflush: lowest node plane not yet written)
+  float acc[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0f;
+  int kflush = noz;
+  auto flush = [&]() {
+    __syncthreads();   // every gather of the plane is done with sP
+    if (gathers) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) S.sP[d][tid] = acc[0][d];
+    }
+    __syncthreads();
+    for (int w = tid; w < 3 * NC; w += NT) {
+      const int d = w / NC, j = w % NC;
+      float s = 0.0f;
+      for (int i = S.sPre[j]; i < S.sPre[j + 1]; ++i) s += S.sP[d][i];
+      part[(size_t)d * dstride + ((size_t)(kflush - noz) * P.nyt + j / nxl) * P.nxt + j % nxl] = s;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      acc[0][d] = acc[1][d];
+      acc[1][d] = acc[2][d];
+      acc[2][d] = acc[3][d];
+      acc[3][d] = 0.0f;
+    }
+    ++kflush;
+  };
+
+  // Register windows of the own column; slot (t - tfirst) mod 3.
+  float Tw[3] = {0.f, 0.f, 0.f}, Rv[3] = {0.f, 0.f, 0.f};
+  float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+
+  int Kp = -0x7fffffff;
+  float ulo[3] = {0.f, 0.f, 0.f}, uhi[3] = {0.f, 0.f, 0.f}, udz[3] = {0.f, 0.f, 0.f};
+  const __amdgpu_buffer_rsrc_t rsT = raw_buffer(P.Tp, P.Tbytes), rsR = raw_buffer(P.R, P.Rbytes);
+  const CornerOffsets co{4u * (unsigned)P.PX, 4u * (unsigned)P.PXY, 4u * (unsigned)(P.PX + P.PXY)};
+  const unsigned rcol = colxy << 2;
+  auto xy_interp = [&](int k, float (&o)[3]) {
+    const unsigned i00 = (unsigned)k * nxy + nodexy;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const unsigned b = (unsigned)d * nb + i00;
+      const float lo = fmaf(wx1, ld32(u, b + 1), wx0 * ld32(u, b));
+      const float hi = fmaf(wx1, ld32(u, b + nxu + 1), wx0 * ld32(u, b + nxu));
+      o[d] = fmaf(wy1, hi, wy0 * lo);
+    }
+  };
+
+  // stage-A inputs of the next plane, loaded one step ahead
+  float nx_t[8];
+  float nx_fx = 0.f, nx_fy = 0.f, nx_fz = 0.f, nx_R = 0.f;
+  auto issue = [&](int tt) {
+    const int tc = min(max(tt, 0), P.mz - 1);
+    const int jz = tt - zb + 2;
+    const Conv1 cvz = uniform_conv(S.sCz[jz]);
+    if (cvz.n0 != Kp) {
+      if (cvz.n0 == Kp + 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ulo[d] = uhi[d];
+      } else {
+        xy_interp(cvz.n0, ulo);
+      }
+      xy_interp(cvz.n0 + 1, uhi);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) udz[d] = uhi[d] - ulo[d];
+      Kp = cvz.n0;
+    }
+    const float fz = cvz.f;
+    const int kx = template_cell(spx, fmaf(fz, udz[0], ulo[0]), P.ihTx, nx_fx);
+    const int ky = template_cell(spy, fmaf(fz, udz[1], ulo[1]), P.ihTy, nx_fy);
+    const int kz = template_cell(S.sSz[jz], fmaf(fz, udz[2], ulo[2]), P.ihTz, nx_fz);
+    template_corners_buf(P, rsT, co, kx, ky, kz, nx_t);
+    nx_R = buf_ld(rsR, rcol, (unsigned)tc * plane * 4u);
+  };
+
+  // The rows of row plane c, for NQ reached node planes from kflush.
+  auto gather = [&](auto NQc, int c) {
+    constexpr int NQ = decltype(NQc)::value;
+    const bool hzm = c > 0, hzp = c < P.mz - 1;
+    const Conv1 cz0 = uniform_conv(S.sCz[c - zb + 2]);
+    const Conv1 czm = uniform_conv(S.sCz[c - zb + 1]), czp = uniform_conv(S.sCz[c - zb + 3]);
+    float wz0[NQ], wzp[NQ], wzm[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      // uniform: scalar registers
+      wz0[q] = uniform_f(conv_weight(cz0, kflush + q));
+      wzp[q] = uniform_f((hzp && !SSD) ? conv_weight(czp, kflush + q) : 0.0f);
+      wzm[q] = uniform_f((hzm && !SSD) ? conv_weight(czm, kflush + q) : 0.0f);
+    }
+    int ra = ra0, rb = rb0;
+    for (int it = 0; it < trips; ++it) {
+      const int la = la0 + ra, lb = lb0 + rb;
+      ra += dra;
+      rb += drb;
+      if (ra >= cw) {
+        ra -= cw;
+        rb += 1;
+      }
+      const int li = lb * BX + la;
+      const float vx0 = wxr[la], vy0 = wyr[lb];
+      const float w00 = vx0 * vy0;
+      if constexpr (SSD) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float pxy = w00 * S.sP[d][li];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const float zz = wz0[q] * pxy;
+            acc[q][d] = fmaf(zz, zz, acc[q][d]);
+          }
+        }
+      } else {
+        const float wxm = wxr[la - 1] * vy0, wxp = wxr[la + 1] * vy0;
+        const float wym = vx0 * wyr[lb - 1], wyp = vx0 * wyr[lb + 1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          float pxy = w00 * S.sP[d][li];
+          pxy = fmaf(wxm, S.sP[3 + d][li], pxy);
+          pxy = fmaf(wxp, S.sP[6 + d][li], pxy);
+          pxy = fmaf(wym, S.sP[9 + d][li], pxy);
+          pxy = fmaf(wyp, S.sP[12 + d][li], pxy);
+          const float zm = w00 * S.sP[15 + d][li], zp = w00 * S.sP[18 + d][li];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
+            acc[q][d] = fmaf(zz, zz, acc[q][d]);
+          }
+        }
+      }
+    }
+  };
+
+  const int tfirst = zb - 1, tlast = ze;
+
+  auto step = [&](auto Kc, int t) {
+    constexpr int K = decltype(Kc)::value;   // slot of plane t
+    constexpr int K1 = (K + 2) % 3;          // slot of plane t-1
+    constexpr int K2 = (K + 1) % 3;          // slot of plane t-2
+
+    // ---------------- stage A: plane t ----------------
+    {
+      const Tri s = trilinear(P, nx_t, nx_fx, nx_fy, nx_fz);
+      Tw[K] = s.v;
+      g[K][0] = s.gx;
+      g[K][1] = s.gy;
+      g[K][2] = s.gz;
+      Rv[K] = nx_R;
+      if constexpr (!SSD) {
+        const int sl = t & 1;
+        S.sTw[sl][XP + tid] = Tw[K];
+        S.sR[sl][XP + tid] = Rv[K];
+        S.sG[sl][0][XP + tid] = s.gx;
+        S.sG[sl][1][XP + tid] = s.gy;
+        S.sG[sl][2][XP + tid] = s.gz;
+      }
+    }
+    if (t < tlast) issue(t + 1);
+
+    // ---------------- row plane c = t-1: products, then the gather ----------------
+    const int c = t - 1;
+    if (c < zb) {   // uniform: the first two steps sample planes zb-1 and zb only
+      __syncthreads();
+      return;
+    }
+    if constexpr (SSD) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) S.sP[d][tid] = g[K1][d];
+    } else {
+      // the row of dr at this column (every lane evaluates it; the gather reads
+      // own rows inside the image only)
+      const int s1 = c & 1;
+      const int q = XP + tid;
+      const float Tc = Tw[K1], Rc = Rv[K1];
+      const float dTxm = S.sTw[s1][q - 1] - Tc, dTxp = S.sTw[s1][q + 1] - Tc;
+      const float dTym = S.sTw[s1][q - BX] - Tc, dTyp = S.sTw[s1][q + BX] - Tc;
+      const float dTzm = Tw[K2] - Tc, dTzp = Tw[K] - Tc;
+      const float dRxm = S.sR[s1][q - 1] - Rc, dRxp = S.sR[s1][q + 1] - Rc;
+      const float dRym = S.sR[s1][q - BX] - Rc, dRyp = S.sR[s1][q + BX] - Rc;
+      const float dRzm = Rv[K2] - Rc, dRzp = Rv[K] - Rc;
+      const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x,
+                             fmaf(fmaf(dTym, dTym, dTyp * dTyp), P.ih2y, fmaf(dTzm, dTzm, dTzp * dTzp) * P.ih2z));
+      const float sRR = fmaf(fmaf(dRxm, dRxm, dRxp * dRxp), P.ih2x,
+                             fmaf(fmaf(dRym, dRym, dRyp * dRyp), P.ih2y, fmaf(dRzm, dRzm, dRzp * dRzp) * P.ih2z));
+      const float sTR = fmaf(fmaf(dTxm, dRxm, dTxp * dRxp), P.ih2x,
+                             fmaf(fmaf(dTym, dRym, dTyp * dRyp), P.ih2y, fmaf(dTzm, dRzm, dTzp * dRzp) * P.ih2z));
+      const float nT2 = fmaf(0.5f, sTT, P.tau2);
+      const float nR2 = fmaf(0.5f, sRR, P.rho2);
+      const float r1 = fmaf(0.5f, sTR, P.taurho);
+      const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
+      const float c1 = rnT * rnR;
+      const float c2 = r1 * rnT * rnT;
+      const float kx = P.hhx * c1, ky = P.hhy * c1, kz = P.hhz * c1;
+      const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
+      const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
+      const float rzm = kz * fmaf(-c2, dTzm, dRzm), rzp = kz * fmaf(-c2, dTzp, dRzp);
+      const float r0 = -(((rxm + rxp) + (rym + ryp)) + (rzm + rzp));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        S.sP[d][tid] = r0 * g[K1][d];
+        S.sP[3 + d][tid] = rxm * S.sG[s1][d][q - 1];
+        S.sP[6 + d][tid] = rxp * S.sG[s1][d][q + 1];
+        S.sP[9 + d][tid] = rym * S.sG[s1][d][q - BX];
+        S.sP[12 + d][tid] = ryp * S.sG[s1][d][q + BX];
+        S.sP[15 + d][tid] = rzm * g[K2][d];
+        S.sP[18 + d][tid] = rzp * g[K][d];
+      }
+    }
+    __syncthreads();   // the products of the row plane
+
+    // node planes the row plane reaches: kflush (the lower node plane of plane
+    // c-1, the lowest any of its three planes touches) up to the upper node
+    // plane of plane c+1; the accumulators of further planes would add exact zeros
+    const int n0c = __builtin_amdgcn_readfirstlane(S.sCz[c - zb + 2].n0);
+    const int n0p = __builtin_amdgcn_readfirstlane(S.sCz[c - zb + 3].n0);
+    const int top = (SSD ? n0c : max(n0c, n0p)) + 1;
+    const int nq = min(max(top - kflush + 1, 1), 4);
+    switch (nq) {
+      case 1: gather(std::integral_constant<int, 1>{}, c); break;
+      case 2: gather(std::integral_constant<int, 2>{}, c); break;
+      case 3: gather(std::integral_constant<int, 3>{}, c); break;
+      default: gather(std::integral_constant<int, 4>{}, c); break;
+    }
+    // node planes below those of the next row plane are complete
+    while (kflush < n0c) flush();
+    __syncthreads();   // sP and the plane-exchange slots are free for the next step
+  };
+
+  issue(tfirst);
+  for (int t = tfirst; t <= tlast; t += 3) {
+    step(std::integral_constant<int, 0>{}, t);
+    if (t + 1 <= tlast) step(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 <= tlast) step(std::integral_constant<int, 2>{}, t + 2);
+  }
+  while (kflush < nzend) flush();
+}
+
+// Node pass of the diagonal: the partial blocks of every group overlapping
+// node n (fixed order), scaled, plus the regulariser's diagonal:
+// curvature (L^T L)_nn = L_nn^2 + sum over present neighbours of 1/hy^4,
+// diffusive -L_nn, elastic -L_nn + kappa (adjacent cells) / (16 hy_d^2).
+__global__ __launch_bounds__(256) void diag_node_kernel(const DiagTileParams D, float* __restrict__ diag) {
+  const TileParams& P = D.t;
+  const int n = blockIdx.x * 256 + threadIdx.x, d = blockIdx.y;
+  if (n >= P.nbar) return;
+  const int i = n % P.nx, j = (n / P.nx) % P.ny, k = n / (P.nx * P.ny);
+  const Range1 rx = D.ntx[i], ry = D.nty[j], rz = D.ntz[k];
+  float s = 0.0f;
+  for (int cz = rz.lo; cz <= rz.hi; ++cz) {
+    const int kz = k - D.orgz[cz];
+    for (int cy = ry.lo; cy <= ry.hi; ++cy) {
+      const int iy = j - D.orgy[cy];
+      for (int cx = rx.lo; cx <= rx.hi; ++cx) {
+        const int jx = i - D.orgx[cx];
+        const size_t slot = (size_t)cx + (size_t)P.tiles_x * ((size_t)cy + (size_t)P.tiles_y * cz);
+        s += P.part[(((slot * 3 + d) * P.nzt + kz) * P.nyt + iy) * P.nxt + jx];
+      }
+    }
+  }
+  const int cxn = (i > 0) + (i < P.nx - 1), cyn = (j > 0) + (j < P.ny - 1), czn = (k > 0) + (k < P.nz - 1);
+  const float Lnn = -(cxn * D.ihy2x + cyn * D.ihy2y + czn * D.ihy2z);
+  const float LL =
+      P.reg ? -Lnn : Lnn * Lnn + cxn * D.ihy2x * D.ihy2x + cyn * D.ihy2y * D.ihy2y + czn * D.ihy2z * D.ihy2z;
+  const float ncell = P.reg == 2 ? P.kappa * (float)(cxn * cyn * czn) * 0.0625f : 0.0f;
+  const float ih2 = d == 0 ? D.ihy2x : d == 1 ? D.ihy2y : D.ihy2z;
+  diag[(size_t)d * P.nbar + n] = fmaf(D.s_ngf, s, D.s_curv * fmaf(ncell, ih2, LL));
+}
+
+hipError_t launch_diag_tile(const DiagTileParams& d, const float* u, float* diag, hipStream_t st) {
+  const int grid = d.t.tiles_x * d.t.tiles_y * d.t.chunks;
+  if (d.t.ssd)
+    hipLaunchKernelGGL((diag_tile_kernel<true>), dim3(grid), dim3(kDiagBX * kDiagBY), 0, st, d, u);
+  else
+    hipLaunchKernelGGL((diag_tile_kernel<false>), dim3(grid), dim3(kDiagBX * kDiagBY), 0, st, d, u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_node_kernel, dim3((d.t.nbar + 255) / 256, 3), dim3(256), 0, st, d, diag);
+  return hipGetLastError();
+}
+
+}  // namespace mfr

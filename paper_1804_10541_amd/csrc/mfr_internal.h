@@ -127,6 +127,26 @@ struct DiagParams {
   float ihy2x, ihy2y, ihy2z;
 };
 
+// Parameters of the voxel-tiled Jacobi diagonal: the tile kernel's tables and
+// images with a tiling of its own (t.tiles_x, tiles_y, chunks, chunk_len, nxt,
+// nyt, nzt and part describe it: kDiagBX x kDiagBY groups), and the node pass
+// that sums the partial diagonal blocks of the tiles overlapping each node.
+constexpr int kDiagBX = 32, kDiagBY = 16;
+struct DiagTileParams {
+  TileParams t;
+  const Range1* rx;   // per node index: voxel rows whose dr row touches the node's support
+  const Range1* ry;
+  const Range1* ntx;  // per node index: the x tiles, y tiles and z chunks whose blocks hold it
+  const Range1* nty;
+  const Range1* ntz;
+  const int* orgx;    // per tile / chunk: first node index of its partial block
+  const int* orgy;
+  const int* orgz;
+  float s_ngf;        // 2 hbar (hbar for SSD)
+  float s_curv;       // regulariser scale
+  float ihy2x, ihy2y, ihy2z;
+};
+
 // A block of nodes along one axis for the Jacobi-diagonal kernel: node range
 // [lo, hi] and a0, the voxel index of the block's first column (x, y) or, for
 // z, one before its first voxel plane; for z, pad holds its last voxel plane.
@@ -253,6 +273,7 @@ hipError_t launch_plane_tile(int mode, const TileParams& p, const float* u, cons
 hipError_t launch_plane_jacobi(const DiagParams& d, const float* u, float* diag, hipStream_t st);
 hipError_t launch_jacobi_diag(const DiagParams& d, const float* u, float* diag, hipStream_t st);
 hipError_t launch_jacobi_tile(const JacParams& j, const float* u, float* diag, hipStream_t st);
+hipError_t launch_diag_tile(const DiagTileParams& d, const float* u, float* diag, hipStream_t st);
 constexpr int kJacAX = 32, kJacAY = 32;   // voxel columns covered by one Jacobi work-group
 
 // L-BFGS initial-matrix solve (lbfgs_kernels.hip): orthonormal DCT-II matrices
