@@ -30,6 +30,10 @@
 
 #include "tile_common.h"
 
+#ifndef DIAG_WP
+#define DIAG_WP 1
+#endif
+
 namespace mfr {
 
 namespace {
@@ -40,15 +44,20 @@ struct DiagSmem {
   static constexpr int MAXNX = BX + 1, MAXNY = BY + 1, MAXNC = NT / 2;
   // plane exchange with a zero pad of one block row at both ends (NGF only)
   static constexpr int XP = SSD ? 0 : BX, NX = SSD ? 1 : NT + 2 * BX;
-  static constexpr int NPROD = SSD ? 3 : 21;   // products of a row, index 3 k + d
+  // products of a row, index 7 d + k: the first NV in float4 groups per column
+  // (a pitch of 20 floats keeps eight lanes' 16-byte reads on distinct banks),
+  // the 21st apart; SSD: the three g_d and a pad
+  static constexpr int NV = SSD ? 4 : 20;
+  static constexpr int WX = BX + DIAG_WP, WY = BY + DIAG_WP;
   float sTw[2][NX];
   float sR[2][NX];
   float sG[2][3][NX];
-  float sP[NPROD][NT];   // the flush reuses the first three rows
+  float4 sPv[NT][NV / 4];   // the flush reuses it as a flat float array
+  float sPs[SSD ? 1 : NT];
   // conversion weight of local column la (row lb) for node column jx (row jy);
   // 0 for columns outside the image
-  float sWx[MAXNX][BX];
-  float sWy[MAXNY][BY];
+  float sWx[MAXNX][WX];
+  float sWy[MAXNY][WY];
   int sPre[MAXNC + 1];   // first gather thread of each node column (prefix of the thread counts)
   Conv1 sCx[BX], sCy[BY];
   Conv1 sCz[kMaxChunk + 4];
@@ -178,11 +187,14 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
     jc = lo;
   }
   const int G = S.sPre[jc + 1] - S.sPre[jc], sidx = tid - S.sPre[jc];
-  int trips = 0, ra0 = 0, rb0 = 0, dra = 0, drb = 0, la0 = 0, lb0 = 0, cw = 1;
+  // the row walk, packed into two registers (every field < 256: windows are at
+  // most BX columns, at most NT rows per thread); it is the same every plane
+  unsigned walk0 = 0, walk1 = 1u << 16;   // (ra0, rb0, dra, drb), (la0, lb0, cw, trips)
   if (gathers) {
-    int ax0, ay0, ch;
+    int ax0, cw, ay0, ch;
     window(jc, ax0, cw, ay0, ch);
     const int rows = cw * ch;
+    int trips = 0, ra0 = 0, rb0 = 0, dra = 0, drb = 0;
     if (rows > sidx) {
       trips = (rows - sidx + G - 1) / G;
       ra0 = sidx % cw;
@@ -190,8 +202,9 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
       dra = G % cw;
       drb = G / cw;
     }
-    la0 = ax0 - (x0 - 1);
-    lb0 = ay0 - (y0 - 1);
+    walk0 = (unsigned)ra0 | ((unsigned)rb0 << 8) | ((unsigned)dra << 16) | ((unsigned)drb << 24);
+    walk1 = (unsigned)(ax0 - (x0 - 1)) | ((unsigned)(ay0 - (y0 - 1)) << 8) | ((unsigned)max(cw, 1) << 16) |
+            ((unsigned)trips << 24);
   }
   const float* const wxr = S.sWx[jc % nxl];
   const float* const wyr = S.sWy[jc / nxl];
@@ -207,15 +220,16 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
   int kflush = noz;
   auto flush = [&]() {
     __syncthreads();   // every gather of the plane is done with sP
+    float* const buf = reinterpret_cast<float*>(S.sPv);   // 3 NT floats
     if (gathers) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) S.sP[d][tid] = acc[0][d];
+      for (int d = 0; d < 3; ++d) buf[d * NT + tid] = acc[0][d];
     }
     __syncthreads();
     for (int w = tid; w < 3 * NC; w += NT) {
       const int d = w / NC, j = w % NC;
       float s = 0.0f;
-      for (int i = S.sPre[j]; i < S.sPre[j + 1]; ++i) s += S.sP[d][i];
+      for (int i = S.sPre[j]; i < S.sPre[j + 1]; ++i) s += buf[d * NT + i];
       part[(size_t)d * dstride + ((size_t)(kflush - noz) * P.nyt + j / nxl) * P.nxt + j % nxl] = s;
     }
 #pragma unroll
@@ -233,7 +247,7 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
   float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 
   int Kp = -0x7fffffff;
-  float ulo[3] = {0.f, 0.f, 0.f}, uhi[3] = {0.f, 0.f, 0.f}, udz[3] = {0.f, 0.f, 0.f};
+  float ulo[3] = {0.f, 0.f, 0.f}, udz[3] = {0.f, 0.f, 0.f};
   const __amdgpu_buffer_rsrc_t rsT = raw_buffer(P.Tp, P.Tbytes), rsR = raw_buffer(P.R, P.Rbytes);
   const CornerOffsets co{4u * (unsigned)P.PX, 4u * (unsigned)P.PXY, 4u * (unsigned)(P.PX + P.PXY)};
   const unsigned rcol = colxy << 2;
@@ -255,13 +269,9 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
     const int tc = min(max(tt, 0), P.mz - 1);
     const int jz = tt - zb + 2;
     const Conv1 cvz = uniform_conv(S.sCz[jz]);
-    if (cvz.n0 != Kp) {
-      if (cvz.n0 == Kp + 1) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) ulo[d] = uhi[d];
-      } else {
-        xy_interp(cvz.n0, ulo);
-      }
+    if (cvz.n0 != Kp) {   // both node planes are interpolated again (cached reads; fewer live registers)
+      float uhi[3];
+      xy_interp(cvz.n0, ulo);
       xy_interp(cvz.n0 + 1, uhi);
 #pragma unroll
       for (int d = 0; d < 3; ++d) udz[d] = uhi[d] - ulo[d];
@@ -289,7 +299,9 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
       wzp[q] = uniform_f((hzp && !SSD) ? conv_weight(czp, kflush + q) : 0.0f);
       wzm[q] = uniform_f((hzm && !SSD) ? conv_weight(czm, kflush + q) : 0.0f);
     }
-    int ra = ra0, rb = rb0;
+    int ra = walk0 & 255, rb = (walk0 >> 8) & 255;
+    const int dra = (walk0 >> 16) & 255, drb = walk0 >> 24;
+    const int la0 = walk1 & 255, lb0 = (walk1 >> 8) & 255, cw = (walk1 >> 16) & 255, trips = walk1 >> 24;
     for (int it = 0; it < trips; ++it) {
       const int la = la0 + ra, lb = lb0 + rb;
       ra += dra;
@@ -302,9 +314,11 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
       const float vx0 = wxr[la], vy0 = wyr[lb];
       const float w00 = vx0 * vy0;
       if constexpr (SSD) {
+        const float4 gv = S.sPv[li][0];
+        const float pv[3] = {gv.x, gv.y, gv.z};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const float pxy = w00 * S.sP[d][li];
+          const float pxy = w00 * pv[d];
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             const float zz = wz0[q] * pxy;
@@ -312,16 +326,27 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
           }
         }
       } else {
+        float pv[21];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const float4 a = S.sPv[li][v];
+          pv[4 * v] = a.x;
+          pv[4 * v + 1] = a.y;
+          pv[4 * v + 2] = a.z;
+          pv[4 * v + 3] = a.w;
+        }
+        pv[20] = S.sPs[li];
         const float wxm = wxr[la - 1] * vy0, wxp = wxr[la + 1] * vy0;
         const float wym = vx0 * wyr[lb - 1], wyp = vx0 * wyr[lb + 1];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          float pxy = w00 * S.sP[d][li];
-          pxy = fmaf(wxm, S.sP[3 + d][li], pxy);
-          pxy = fmaf(wxp, S.sP[6 + d][li], pxy);
-          pxy = fmaf(wym, S.sP[9 + d][li], pxy);
-          pxy = fmaf(wyp, S.sP[12 + d][li], pxy);
-          const float zm = w00 * S.sP[15 + d][li], zp = w00 * S.sP[18 + d][li];
+          const float* pd = pv + 7 * d;
+          float pxy = w00 * pd[0];
+          pxy = fmaf(wxm, pd[1], pxy);
+          pxy = fmaf(wxp, pd[2], pxy);
+          pxy = fmaf(wym, pd[3], pxy);
+          pxy = fmaf(wyp, pd[4], pxy);
+          const float zm = w00 * pd[5], zp = w00 * pd[6];
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             const float zz = fmaf(wz0[q], pxy, fmaf(wzp[q], zp, wzm[q] * zm));
@@ -365,8 +390,7 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
       return;
     }
     if constexpr (SSD) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) S.sP[d][tid] = g[K1][d];
+      S.sPv[tid][0] = make_float4(g[K1][0], g[K1][1], g[K1][2], 0.0f);
     } else {
       // the row of dr at this column (every lane evaluates it; the gather reads
       // own rows inside the image only)
@@ -396,16 +420,21 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
       const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
       const float rzm = kz * fmaf(-c2, dTzm, dRzm), rzp = kz * fmaf(-c2, dTzp, dRzp);
       const float r0 = -(((rxm + rxp) + (rym + ryp)) + (rzm + rzp));
+      float pv[21];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        S.sP[d][tid] = r0 * g[K1][d];
-        S.sP[3 + d][tid] = rxm * S.sG[s1][d][q - 1];
-        S.sP[6 + d][tid] = rxp * S.sG[s1][d][q + 1];
-        S.sP[9 + d][tid] = rym * S.sG[s1][d][q - BX];
-        S.sP[12 + d][tid] = ryp * S.sG[s1][d][q + BX];
-        S.sP[15 + d][tid] = rzm * g[K2][d];
-        S.sP[18 + d][tid] = rzp * g[K][d];
+        float* pd = pv + 7 * d;
+        pd[0] = r0 * g[K1][d];
+        pd[1] = rxm * S.sG[s1][d][q - 1];
+        pd[2] = rxp * S.sG[s1][d][q + 1];
+        pd[3] = rym * S.sG[s1][d][q - BX];
+        pd[4] = ryp * S.sG[s1][d][q + BX];
+        pd[5] = rzm * g[K2][d];
+        pd[6] = rzp * g[K][d];
       }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) S.sPv[tid][v] = make_float4(pv[4 * v], pv[4 * v + 1], pv[4 * v + 2], pv[4 * v + 3]);
+      S.sPs[tid] = pv[20];
     }
     __syncthreads();   // the products of the row plane
 
