@@ -1,7 +1,8 @@
 """Resource use of the voxel-tile kernels, read from the gfx950 code-object
 metadata that hipcc writes for them: no private (scratch) memory, which a
-register array indexed at run time would silently move there (every access
-then goes through the vector-memory path), and no register spills."""
+register array indexed at run time or a vector-register spill would silently
+bring in (every access then goes through the vector-memory path).  Scalar
+registers may spill into lanes of vector registers, which needs no memory."""
 import os
 import re
 import shutil
@@ -40,6 +41,6 @@ def test_tile_kernels_use_no_scratch_memory(src, kernel, tmp_path):
     assert tiles, f"no {kernel} instances in {src}"
     for name, m in tiles.items():
         assert m["private_segment_fixed_size"] == 0, (name, m)
-        assert m["vgpr_spill_count"] == 0 and m["sgpr_spill_count"] == 0, (name, m)
+        assert m["vgpr_spill_count"] == 0, (name, m)
         # at most 128 VGPRs: four waves per SIMD, what a 512-thread group needs for two groups per CU
         assert m["vgpr_count"] <= 128, (name, m)
