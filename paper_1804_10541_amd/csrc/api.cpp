@@ -224,7 +224,21 @@ static Tiling make_tiling_plane(const Geo& g, const std::vector<Conv1>& cx, cons
     const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[1]) - 1;
     t.nzt = std::max(t.nzt, cy[a1].n0 + 2 - cy[a0].n0);
   }
-  t.dg = DiagTiling{};
+  // the diagonal: the same x tiles and row chunks, seen as x tiles and y tiles of
+  // one plane; a chunk's node rows span the rows its dr rows' y stencils reach
+  DiagTiling& d = t.dg;
+  d.tiles_x = t.tiles_x;
+  d.tiles_y = t.chunks;
+  d.chunks = 1;
+  d.chunk_len = t.chunk_len;
+  d.nxt = t.nxt;
+  d.nzt = 1;
+  d.nyt = 0;
+  for (int i = 0; i < t.chunks; ++i) {
+    const int yb = i * t.chunk_len, ye = std::min(yb + t.chunk_len, g.m[1]);
+    d.nyt = std::max(d.nyt, cy[std::min(ye, g.m[1] - 1)].n0 + 2 - cy[std::max(yb - 1, 0)].n0);
+  }
+  d.on = g.n[0] <= g.m[0] + 1 && g.n[1] <= g.m[1] + 1 && d.nxt <= kPlaneNT - 32;
   return t;
 }
 
@@ -410,6 +424,36 @@ static mfr_status ctx_init_plane(mfr_ctx* c, void* stream, void* ws, size_t ws_b
   HIP_TRY(up(L.orgz, orgz.data(), sizeof(int) * orgz.size()));
   HIP_TRY(up(L.rx, rx.data(), sizeof(Range1) * rx.size()));
   HIP_TRY(up(L.ry, ry.data(), sizeof(Range1) * ry.size()));
+  // tiled diagonal: x tiles as for the tile kernel, row chunks whose blocks hold
+  // each node row, the first node row of each chunk's block
+  const DiagTiling& dg = t.dg;
+  std::vector<Range1> dnty, dntz(1, Range1{0, 0});
+  std::vector<int> dorgy, dorgz(1, 0);
+  if (dg.on) {
+    dnty.resize(g.n[1]);
+    dorgy.resize(t.chunks);
+    std::vector<int> dyend(t.chunks);
+    for (int i = 0; i < t.chunks; ++i) {
+      const int yb = i * t.chunk_len, ye = std::min(yb + t.chunk_len, g.m[1]);
+      dorgy[i] = cy[std::max(yb - 1, 0)].n0;
+      dyend[i] = cy[std::min(ye, g.m[1] - 1)].n0 + 2;
+    }
+    for (int k = 0; k < g.n[1]; ++k) {
+      int lo = t.chunks, hi = -1;
+      for (int i = 0; i < t.chunks; ++i)
+        if (dorgy[i] <= k && k < dyend[i]) {
+          lo = std::min(lo, i);
+          hi = std::max(hi, i);
+        }
+      dnty[k] = Range1{lo, hi};
+    }
+    HIP_TRY(up(L.dntx, ntx.data(), sizeof(Range1) * ntx.size()));
+    HIP_TRY(up(L.dnty, dnty.data(), sizeof(Range1) * dnty.size()));
+    HIP_TRY(up(L.dntz, dntz.data(), sizeof(Range1)));
+    HIP_TRY(up(L.dorgx, orgx.data(), sizeof(int) * orgx.size()));
+    HIP_TRY(up(L.dorgy, dorgy.data(), sizeof(int) * dorgy.size()));
+    HIP_TRY(up(L.dorgz, dorgz.data(), sizeof(int)));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
 
   TileParams& p = c->tp;
@@ -497,6 +541,33 @@ static mfr_status ctx_init_plane(mfr_ctx* c, void* stream, void* ws, size_t ws_b
   d.ihy2y = q.ihy2z;
   d.ihy2z = 0.0f;
   c->jac_tiled = false;
+
+  DiagTileParams& dt = c->dtp;
+  dt = DiagTileParams{};
+  dt.t = p;
+  dt.t.tiles_x = dg.tiles_x;
+  dt.t.tiles_y = dg.tiles_y;
+  dt.t.chunks = 1;
+  dt.t.chunk_len = dg.chunk_len;
+  dt.t.nxt = dg.nxt;
+  dt.t.nyt = dg.nyt;
+  dt.t.nzt = 1;
+  dt.t.part = at<float>(c->ws, L.dpart);
+  dt.t.red = nullptr;
+  dt.rx = d.rx;
+  dt.ry = d.ry;
+  dt.ntx = at<Range1>(c->ws, L.dntx);
+  dt.nty = at<Range1>(c->ws, L.dnty);
+  dt.ntz = at<Range1>(c->ws, L.dntz);
+  dt.orgx = at<int>(c->ws, L.dorgx);
+  dt.orgy = at<int>(c->ws, L.dorgy);
+  dt.orgz = at<int>(c->ws, L.dorgz);
+  dt.s_ngf = d.s_ngf;
+  dt.s_curv = d.s_curv;
+  dt.ihy2x = d.ihy2x;
+  dt.ihy2y = d.ihy2y;
+  dt.ihy2z = 0.0f;
+  dt.plane = 1;
 
   c->sc = at<double>(c->ws, L.sc);
   c->red_tile = p.red;
@@ -796,7 +867,8 @@ hipError_t timed(mfr_ctx* c, int slot, F&& launch) {
 }
 
 hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
-  if (c->geo.dim == 2) return launch_plane_jacobi(c->dp, u, diag, c->stream);
+  if (c->geo.dim == 2)
+    return c->tiling.dg.on ? launch_diag_tile(c->dtp, u, diag, c->stream) : launch_plane_jacobi(c->dp, u, diag, c->stream);
   if (c->tiling.dg.on) return launch_diag_tile(c->dtp, u, diag, c->stream);
   if (c->jac_tiled) return launch_jacobi_tile(c->jp, u, diag, c->stream);
   return launch_jacobi_diag(c->dp, u, diag, c->stream);

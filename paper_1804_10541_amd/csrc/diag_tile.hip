@@ -465,6 +465,292 @@ __global__ __launch_bounds__(kDiagBX* kDiagBY) __attribute__((amdgpu_waves_per_e
   while (kflush < nzend) flush();
 }
 
+// The same for a two-dimensional problem (d = 2): a group of kPlaneNT threads
+// covers kPlaneNT pixel columns (own inner columns and a one-column ring) and
+// marches through a chunk of pixel rows; a row of dr has five entries (0, -x,
+// +x, -y, +y), so ten products per pixel; the node columns are the x nodes the
+// group's rows reach, and the up to four node rows a pixel row reaches take
+// the place of the node planes.  Its partial blocks use the node pass's view
+// of the node grid as n_x x n_y x 1 (x tiles, row chunks as y tiles).
+__global__ __launch_bounds__(kPlaneNT) void plane_diag_kernel(const DiagTileParams D, const float* __restrict__ u) {
+  constexpr int NT = kPlaneNT, TX = NT - 2;
+  // row exchange with one zero pad at both ends
+  __shared__ float sTw[2][NT + 2], sR[2][NT + 2], sG[2][2][NT + 2];
+  // products of a row, index 5 d + k (k: 0, -x, +x, -y, +y); a pitch of ten
+  // floats puts sixteen lanes' 8-byte reads on distinct banks
+  __shared__ float2 sPv[NT][5];
+  __shared__ Conv1 sCx[NT];
+  __shared__ Conv1 sCy[kMaxChunk + 4];
+  __shared__ Samp1 sSy[kMaxChunk + 4];
+  __shared__ int sPre[NT + 1];
+  __shared__ int sTotal;
+  const TileParams& P = D.t;
+
+  const int tid = threadIdx.x;
+  const int bid = xcd_block_id();
+  const int tile_x = bid % P.tiles_x, chunk = bid / P.tiles_x;
+  const int x0 = tile_x * TX;
+  const int yb = chunk * P.chunk_len, ye = min(P.my, yb + P.chunk_len);
+
+  const int gx = x0 - 1 + tid;
+  const int cxi = min(max(gx, 0), P.mx - 1);
+  const Conv1 cvx = P.cx[cxi];
+  const Samp1 spx = P.sx[cxi];
+  const float wx0 = 1.0f - cvx.f, wx1 = cvx.f;
+  const unsigned nb = (unsigned)P.nbar, nxu = (unsigned)P.nx;
+
+  const int lxa = x0 == 0 ? 1 : 0;
+  const int lxb = min(NT - 1, P.mx - x0);
+  const int nox = P.cx[x0 - 1 + lxa].n0;
+  const int NC = P.cx[x0 - 1 + lxb].n0 + 2 - nox;   // node columns of the block
+  const int noy = P.cy[max(yb - 1, 0)].n0;
+  const int nyend = P.cy[min(ye, P.my - 1)].n0 + 2;
+  for (int j = tid; j < ye - yb + 4; j += NT) {
+    const int q = min(max(yb - 2 + j, 0), P.my - 1);
+    sCy[j] = P.cy[q];
+    sSy[j] = P.sy[q];
+  }
+  // columns outside the image carry no conversion weight
+  sCx[tid] = (gx >= 0 && gx < P.mx) ? cvx : Conv1{-8, 0.0f};
+  if (tid < 4) {
+    const int sl = tid >> 1, q = (tid & 1) ? NT + 1 : 0;
+    sTw[sl][q] = sR[sl][q] = sG[sl][0][q] = sG[sl][1][q] = 0.f;
+  }
+  if (tid == 0) sTotal = 0;
+  // the own columns inside the image whose dr rows touch node column j's support
+  auto window = [&](int j, int& ax0, int& cw) {
+    const Range1 rx = D.rx[nox + j];
+    ax0 = max(rx.lo, x0);
+    cw = max(0, min(rx.hi, min(x0 + TX - 1, P.mx - 1)) - ax0 + 1);
+  };
+  __syncthreads();
+  int rows_j = 0;
+  if (tid < NC) {
+    int ax0;
+    window(tid, ax0, rows_j);
+    atomicAdd(&sTotal, rows_j);   // an integer sum: order-free
+  }
+  __syncthreads();
+  if (tid < NC) sPre[tid + 1] = 1 + (int)(((long long)rows_j * (NT - NC)) / max(sTotal, 1));
+  __syncthreads();
+  if (tid == 0) {
+    sPre[0] = 0;
+    for (int j = 0; j < NC; ++j) sPre[j + 1] += sPre[j];
+  }
+  __syncthreads();
+  const bool gathers = tid < sPre[NC];
+  int jc = 0;
+  {
+    int lo = 0, hi = NC - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sPre[mid] <= tid) lo = mid; else hi = mid - 1;
+    }
+    jc = lo;
+  }
+  const int G = sPre[jc + 1] - sPre[jc], sidx = tid - sPre[jc];
+  const int nodec = nox + jc;
+  int la0 = 1, trips = 0;
+  if (gathers) {
+    int ax0, cw;
+    window(jc, ax0, cw);
+    la0 = ax0 - (x0 - 1) + sidx;   // this thread's columns: la0, la0 + G, ...
+    trips = cw > sidx ? (cw - sidx + G - 1) / G : 0;
+  }
+
+  const int slot = tile_x + P.tiles_x * chunk;
+  float* const part = P.part + (size_t)slot * 3 * P.nzt * P.nyt * P.nxt;
+  const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
+  float acc[4][2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = 0.0f;
+  int kflush = noy;
+  auto flush = [&]() {
+    __syncthreads();
+    float* const buf = reinterpret_cast<float*>(sPv);   // 2 NT floats
+    if (gathers) {
+      buf[tid] = acc[0][0];
+      buf[NT + tid] = acc[0][1];
+    }
+    __syncthreads();
+    for (int w = tid; w < 2 * NC; w += NT) {
+      const int d = w / NC, j = w % NC;
+      float s = 0.0f;
+      for (int i = sPre[j]; i < sPre[j + 1]; ++i) s += buf[d * NT + i];
+      part[(size_t)d * dstride + (size_t)(kflush - noy) * P.nxt + j] = s;
+    }
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      acc[0][d] = acc[1][d];
+      acc[1][d] = acc[2][d];
+      acc[2][d] = acc[3][d];
+      acc[3][d] = 0.0f;
+    }
+    ++kflush;
+  };
+
+  float Tw[3] = {0.f, 0.f, 0.f}, Rv[3] = {0.f, 0.f, 0.f};
+  float g[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+  int Kp = -0x7fffffff;
+  float ulo[2] = {0.f, 0.f}, udy[2] = {0.f, 0.f};
+  const __amdgpu_buffer_rsrc_t rsT = raw_buffer(P.Tp, P.Tbytes), rsR = raw_buffer(P.R, P.Rbytes);
+  const unsigned rcol = (unsigned)cxi << 2;
+  const unsigned PX = (unsigned)P.PX;
+  auto x_interp = [&](int k, float (&o)[2]) {
+    const unsigned i0 = (unsigned)k * nxu + (unsigned)cvx.n0;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const unsigned b = (unsigned)d * nb + i0;
+      o[d] = fmaf(wx1, ld32(u, b + 1), wx0 * ld32(u, b));
+    }
+  };
+  float nt00 = 0.f, nt10 = 0.f, nt01 = 0.f, nt11 = 0.f, nfx = 0.f, nfy = 0.f, nR = 0.f;
+  auto issue = [&](int tt) {
+    const int tc = min(max(tt, 0), P.my - 1);
+    const int jy = tt - yb + 2;
+    const Conv1 cvy = uniform_conv(sCy[jy]);
+    if (cvy.n0 != Kp) {
+      float uhi[2];
+      x_interp(cvy.n0, ulo);
+      x_interp(cvy.n0 + 1, uhi);
+      udy[0] = uhi[0] - ulo[0];
+      udy[1] = uhi[1] - ulo[1];
+      Kp = cvy.n0;
+    }
+    const float fy = cvy.f;
+    int kx = template_cell(spx, fmaf(fy, udy[0], ulo[0]), P.ihTx, nfx);
+    int ky = template_cell(sSy[jy], fmaf(fy, udy[1], ulo[1]), P.ihTy, nfy);
+    kx = clamp_m2(kx, P.mTx);
+    ky = clamp_m2(ky, P.mTy);
+    const unsigned v = (__umul24((unsigned)(ky + 2), PX) + (unsigned)(kx + 2)) << 2;
+    const FPair a = buf_ld2(rsT, v, 0), b = buf_ld2(rsT, v, 4u * PX);
+    nt00 = a.a;
+    nt10 = a.b;
+    nt01 = b.a;
+    nt11 = b.b;
+    nR = buf_ld(rsR, rcol, (unsigned)tc * (unsigned)P.mx * 4u);
+  };
+
+  auto gather = [&](auto NQc, int c) {
+    constexpr int NQ = decltype(NQc)::value;
+    const bool hym = c > 0, hyp = c < P.my - 1;
+    const Conv1 cy0 = uniform_conv(sCy[c - yb + 2]);
+    const Conv1 cym = uniform_conv(sCy[c - yb + 1]), cyp = uniform_conv(sCy[c - yb + 3]);
+    float wy0[NQ], wyp[NQ], wym[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      wy0[q] = uniform_f(conv_weight(cy0, kflush + q));
+      wyp[q] = uniform_f(hyp ? conv_weight(cyp, kflush + q) : 0.0f);
+      wym[q] = uniform_f(hym ? conv_weight(cym, kflush + q) : 0.0f);
+    }
+    int la = la0;
+    for (int it = 0; it < trips; ++it, la += G) {
+      const float vx0 = conv_weight(sCx[la], nodec);
+      const float vxm = conv_weight(sCx[la - 1], nodec), vxp = conv_weight(sCx[la + 1], nodec);
+      float pv[10];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const float2 a = sPv[la][v];
+        pv[2 * v] = a.x;
+        pv[2 * v + 1] = a.y;
+      }
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const float* pd = pv + 5 * d;
+        float px = vx0 * pd[0];
+        px = fmaf(vxm, pd[1], px);
+        px = fmaf(vxp, pd[2], px);
+        const float ym = vx0 * pd[3], yp = vx0 * pd[4];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const float zz = fmaf(wy0[q], px, fmaf(wyp[q], yp, wym[q] * ym));
+          acc[q][d] = fmaf(zz, zz, acc[q][d]);
+        }
+      }
+    }
+  };
+
+  const int tfirst = yb - 1, tlast = ye;
+  auto step = [&](auto Kc, int t) {
+    constexpr int K = decltype(Kc)::value;   // slot of row t
+    constexpr int K1 = (K + 2) % 3;          // slot of row t-1
+    constexpr int K2 = (K + 1) % 3;          // slot of row t-2
+    {
+      const float d0 = nt10 - nt00, d1 = nt11 - nt01;
+      const float f0 = fmaf(nfx, d0, nt00), f1 = fmaf(nfx, d1, nt01);
+      Tw[K] = fmaf(nfy, f1 - f0, f0);
+      g[K][0] = fmaf(nfy, d1 - d0, d0) * P.ihTx;
+      g[K][1] = (f1 - f0) * P.ihTy;
+      Rv[K] = nR;
+      const int sl = t & 1;
+      sTw[sl][1 + tid] = Tw[K];
+      sR[sl][1 + tid] = Rv[K];
+      sG[sl][0][1 + tid] = g[K][0];
+      sG[sl][1][1 + tid] = g[K][1];
+    }
+    if (t < tlast) issue(t + 1);
+    const int c = t - 1;
+    if (c < yb) {   // uniform: the first two steps sample rows yb-1 and yb only
+      __syncthreads();
+      return;
+    }
+    {
+      const int s1 = c & 1;
+      const int q = 1 + tid;
+      const float Tc = Tw[K1], Rc = Rv[K1];
+      const float dTxm = sTw[s1][q - 1] - Tc, dTxp = sTw[s1][q + 1] - Tc;
+      const float dTym = Tw[K2] - Tc, dTyp = Tw[K] - Tc;
+      const float dRxm = sR[s1][q - 1] - Rc, dRxp = sR[s1][q + 1] - Rc;
+      const float dRym = Rv[K2] - Rc, dRyp = Rv[K] - Rc;
+      const float sTT = fmaf(fmaf(dTxm, dTxm, dTxp * dTxp), P.ih2x, fmaf(dTym, dTym, dTyp * dTyp) * P.ih2y);
+      const float sRR = fmaf(fmaf(dRxm, dRxm, dRxp * dRxp), P.ih2x, fmaf(dRym, dRym, dRyp * dRyp) * P.ih2y);
+      const float sTR = fmaf(fmaf(dTxm, dRxm, dTxp * dRxp), P.ih2x, fmaf(dTym, dRym, dTyp * dRyp) * P.ih2y);
+      const float nT2 = fmaf(0.5f, sTT, P.tau2);
+      const float nR2 = fmaf(0.5f, sRR, P.rho2);
+      const float r1 = fmaf(0.5f, sTR, P.taurho);
+      const float rnT = rsq_norm(nT2), rnR = rsq_norm(nR2);
+      const float c1 = rnT * rnR;
+      const float c2 = r1 * rnT * rnT;
+      const float kx = P.hhx * c1, ky = P.hhy * c1;
+      const float rxm = kx * fmaf(-c2, dTxm, dRxm), rxp = kx * fmaf(-c2, dTxp, dRxp);
+      const float rym = ky * fmaf(-c2, dTym, dRym), ryp = ky * fmaf(-c2, dTyp, dRyp);
+      const float r0 = -((rxm + rxp) + (rym + ryp));
+      float pv[10];
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        float* pd = pv + 5 * d;
+        pd[0] = r0 * g[K1][d];
+        pd[1] = rxm * sG[s1][d][q - 1];
+        pd[2] = rxp * sG[s1][d][q + 1];
+        pd[3] = rym * g[K2][d];
+        pd[4] = ryp * g[K][d];
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sPv[tid][v] = make_float2(pv[2 * v], pv[2 * v + 1]);
+    }
+    __syncthreads();
+    const int n0c = __builtin_amdgcn_readfirstlane(sCy[c - yb + 2].n0);
+    const int n0p = __builtin_amdgcn_readfirstlane(sCy[c - yb + 3].n0);
+    const int nq = min(max(max(n0c, n0p) + 1 - kflush + 1, 1), 4);
+    switch (nq) {
+      case 1: gather(std::integral_constant<int, 1>{}, c); break;
+      case 2: gather(std::integral_constant<int, 2>{}, c); break;
+      case 3: gather(std::integral_constant<int, 3>{}, c); break;
+      default: gather(std::integral_constant<int, 4>{}, c); break;
+    }
+    while (kflush < n0c) flush();
+    __syncthreads();
+  };
+
+  issue(tfirst);
+  for (int t = tfirst; t <= tlast; t += 3) {
+    step(std::integral_constant<int, 0>{}, t);
+    if (t + 1 <= tlast) step(std::integral_constant<int, 1>{}, t + 1);
+    if (t + 2 <= tlast) step(std::integral_constant<int, 2>{}, t + 2);
+  }
+  while (kflush < nyend) flush();
+}
+
 // Node pass of the diagonal: the partial blocks of every group overlapping
 // node n (fixed order), scaled, plus the regulariser's diagonal:
 // curvature (L^T L)_nn = L_nn^2 + sum over present neighbours of 1/hy^4,
@@ -498,6 +784,13 @@ __global__ __launch_bounds__(256) void diag_node_kernel(const DiagTileParams D, 
 
 hipError_t launch_diag_tile(const DiagTileParams& d, const float* u, float* diag, hipStream_t st) {
   const int grid = d.t.tiles_x * d.t.tiles_y * d.t.chunks;
+  if (d.plane) {   // two-dimensional: row chunks in place of y tiles
+    hipLaunchKernelGGL(plane_diag_kernel, dim3(grid), dim3(kPlaneNT), 0, st, d, u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_node_kernel, dim3((d.t.nbar + 255) / 256, 2), dim3(256), 0, st, d, diag);
+    return hipGetLastError();
+  }
   if (d.t.ssd)
     hipLaunchKernelGGL((diag_tile_kernel<true>), dim3(grid), dim3(kDiagBX * kDiagBY), 0, st, d, u);
   else

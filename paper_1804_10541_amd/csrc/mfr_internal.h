@@ -145,6 +145,7 @@ struct DiagTileParams {
   float s_ngf;        // 2 hbar (hbar for SSD)
   float s_curv;       // regulariser scale
   float ihy2x, ihy2y, ihy2z;
+  int plane;          // two-dimensional problem: x tiles and row chunks (as y tiles) of kPlaneNT columns
 };
 
 // A block of nodes along one axis for the Jacobi-diagonal kernel: node range
