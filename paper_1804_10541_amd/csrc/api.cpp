@@ -199,6 +199,28 @@ void set_tile_config(const mfr_tile_config& c) { g_tile_cfg = c; }
 // Two-dimensional problems: work-groups of kPlaneNT pixel columns (one-column
 // ring), rows marched in chunks; the node pass sees x tiles, one tile row and
 // the row chunks as z chunks.
+// Groups whose columns [i T - 1, i T + T] meet the columns [lo, hi] of a node's support.
+static Range1 groups_touching(const Range1& cols, int T, int tiles) {
+  const int lo = cols.lo < T ? 0 : (cols.lo - 1) / T;
+  return Range1{lo, std::min(tiles - 1, (cols.hi + 1) / T)};
+}
+
+// The most groups (columns of width T with a one-column ring) overlapping one node's
+// support, and the most chunks of `len` planes holding one node plane.
+static int most_groups(const std::vector<Conv1>& c, int n, int T, int tiles) {
+  int most = 1;
+  for (const Range1& r : node_cols(c, n)) {
+    const Range1 t = groups_touching(r, T, tiles);
+    most = std::max(most, t.hi - t.lo + 1);
+  }
+  return most;
+}
+static int most_chunks(const std::vector<Conv1>& c, int n, int len) {
+  int most = 1;
+  for (const Range1& r : node_cols(c, n)) most = std::max(most, r.hi / len - r.lo / len + 1);
+  return most;
+}
+
 static Tiling make_tiling_plane(const Geo& g, const std::vector<Conv1>& cx, const std::vector<Conv1>& cy) {
   Tiling t;
   const mfr_tile_config cfg = current_tile_config();
@@ -224,6 +246,9 @@ static Tiling make_tiling_plane(const Geo& g, const std::vector<Conv1>& cx, cons
     const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[1]) - 1;
     t.nzt = std::max(t.nzt, cy[a1].n0 + 2 - cy[a0].n0);
   }
+  t.smx = most_groups(cx, g.n[0], TX, t.tiles_x);
+  t.smy = 1;
+  t.smz = most_chunks(cy, g.n[1], t.chunk_len);
   // the diagonal: the same x tiles and row chunks, seen as x tiles and y tiles of
   // one plane; a chunk's node rows span the rows its dr rows' y stencils reach
   DiagTiling& d = t.dg;
@@ -273,6 +298,9 @@ Tiling make_tiling(const Geo& g, const std::vector<Conv1>& cx, const std::vector
     const int a0 = i * t.chunk_len, a1 = std::min(a0 + t.chunk_len, g.m[2]) - 1;
     t.nzt = std::max(t.nzt, cz[a1].n0 + 2 - cz[a0].n0);
   }
+  t.smx = most_groups(cx, g.n[0], TX, t.tiles_x);
+  t.smy = most_groups(cy, g.n[1], TY, t.tiles_y);
+  t.smz = most_chunks(cz, g.n[2], t.chunk_len);
   // the diagonal's own tiling: 2048 groups (two per CU resident, eight rounds);
   // a group's z node block spans the planes its rows' z stencils reach
   DiagTiling& d = t.dg;
@@ -338,7 +366,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.jbx = take(sizeof(NodeBlock) * g.n[0]);
   L.jby = take(sizeof(NodeBlock) * g.n[1]);
   L.jbz = take(sizeof(NodeBlock) * g.n[2]);
-  L.part = take(sizeof(float) * (size_t)t.grid() * 3 * t.nzt * t.nyt * t.nxt);
+  L.part = take(sizeof(float) * (size_t)t.smx * t.smy * t.smz * 3 * g.nbar);
   const DiagTiling& dg = t.dg;
   L.dntx = take(dg.on ? sizeof(Range1) * g.n[0] : 0);
   L.dnty = take(dg.on ? sizeof(Range1) * g.n[1] : 0);
@@ -366,11 +394,6 @@ Layout make_layout(const Geo& g, const Tiling& t) {
 namespace mfr {
 
 
-// Groups whose columns [i T - 1, i T + T] meet the columns [lo, hi] of a node's support.
-static Range1 groups_touching(const Range1& cols, int T, int tiles) {
-  const int lo = cols.lo < T ? 0 : (cols.lo - 1) / T;
-  return Range1{lo, std::min(tiles - 1, (cols.hi + 1) / T)};
-}
 
 // Context of a two-dimensional problem: tables, the tile kernel's parameters
 // (TileParams with mz = nz = 1), the node pass's view of the n[0] x n[1] node
@@ -496,6 +519,9 @@ static mfr_status ctx_init_plane(mfr_ctx* c, void* stream, void* ws, size_t ws_b
   p.nyt = 1;
   p.nzt = t.nzt;
   p.part = at<float>(c->ws, L.part);
+  p.smx = t.smx;
+  p.smy = t.smy;
+  p.smz = t.smz;
   p.red = at<double>(c->ws, L.red_tile);
 
   NodeParams& q = c->np;
@@ -518,6 +544,9 @@ static mfr_status ctx_init_plane(mfr_ctx* c, void* stream, void* ws, size_t ws_b
   q.nyt = 1;
   q.nzt = t.nzt;
   q.part = p.part;
+  q.smx = t.smx;
+  q.smy = t.smy;
+  q.smz = t.smz;
   q.ntx = at<Range1>(c->ws, L.ntx);
   q.nty = at<Range1>(c->ws, L.nty);
   q.ntz = at<Range1>(c->ws, L.ntz);
@@ -745,6 +774,9 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   p.nyt = t.nyt;
   p.nzt = t.nzt;
   p.part = at<float>(c->ws, L.part);
+  p.smx = t.smx;
+  p.smy = t.smy;
+  p.smz = t.smz;
   p.red = at<double>(c->ws, L.red_tile);
 
   NodeParams& q = c->np;
@@ -767,6 +799,9 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
   q.nyt = t.nyt;
   q.nzt = t.nzt;
   q.part = p.part;
+  q.smx = t.smx;
+  q.smy = t.smy;
+  q.smz = t.smz;
   q.ntx = at<Range1>(c->ws, L.ntx);
   q.nty = at<Range1>(c->ws, L.nty);
   q.ntz = at<Range1>(c->ws, L.ntz);

@@ -86,6 +86,7 @@ struct Tiling {
   TileShape shape;
   int tiles_x, tiles_y, chunks, chunk_len;
   int nxt, nyt, nzt;
+  int smx, smy, smz;   // partial slots per axis: the most groups overlapping one node along it
   DiagTiling dg;
   int grid() const { return tiles_x * tiles_y * chunks; }
 };

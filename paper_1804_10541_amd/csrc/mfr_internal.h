@@ -84,7 +84,11 @@ struct TileParams {
   const Samp1* sz;
   int tiles_x, tiles_y, chunks, chunk_len;
   int nxt, nyt, nzt;      // node extents of one tile's partial block
-  float* part;            // transposed-conversion partial blocks
+  // transposed-conversion partials: slot (chunk mod smz, tile_y mod smy, tile_x
+  // mod smx) holds, per component, one float per node of the grid (index of the
+  // node pass), written by the one group of that slot that overlaps the node
+  int smx, smy, smz;
+  float* part;
   double* red;            // one float64 partial per work-group
   const int* live;        // single-problem launches: skip all work while *live == 0 (nullable)
   int ssd;                // distance: 0 NGF, 1 sum of squared differences (dr/dT = identity)
@@ -104,6 +108,7 @@ struct NodeParams {
   float* div;                 // elastic: divergence per cell ((nx-1)(ny-1)(nz-1) floats), first pass
   int tiles_x, tiles_y;
   int nxt, nyt, nzt;
+  int smx, smy, smz;          // partial slots per axis (see TileParams)
   const float* part;
   const Range1* ntx;          // per node index: range of x tiles / y tiles / z chunks
   const Range1* nty;

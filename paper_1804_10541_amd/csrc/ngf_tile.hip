@@ -196,8 +196,10 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
     }
   }
 
-  const int slot = tile_x + P.tiles_x * (tile_y + P.tiles_y * chunk);
-  float* const part = P.part + (size_t)slot * 3 * P.nzt * P.nyt * P.nxt;
+  // the group's partial slot: node n of component d at part[d nbar + n], n the
+  // node's index in the grid, so the node pass reads its slots coalesced
+  const int pslot = ((chunk % P.smz) * P.smy + tile_y % P.smy) * P.smx + tile_x % P.smx;
+  float* const part = P.part + (size_t)pslot * 3 * (size_t)P.nbar;
 
   // Writes one node plane (local index kloc) of the transposed conversion:
   // reduce the per-column sums acc over x, then y, into the slot's node block.
@@ -239,11 +241,10 @@ __device__ __forceinline__ void tile_body(const TileParams& P, const int bid, co
           s1 = fmaf(wt, sW[1][q], s1);
           s2 = fmaf(wt, sW[2][q], s2);
         }
-        const size_t o = ((size_t)kloc * P.nyt + fr) * P.nxt + fj;
-        const size_t dstride = (size_t)P.nzt * P.nyt * P.nxt;
+        const size_t o = ((size_t)(noz + kloc) * P.ny + (noy + fr)) * P.nx + (nox + fj);
         part[o] = s0;
-        part[o + dstride] = s1;
-        part[o + 2 * dstride] = s2;
+        part[o + (size_t)P.nbar] = s1;
+        part[o + 2 * (size_t)P.nbar] = s2;
       }
       __syncthreads();
     }

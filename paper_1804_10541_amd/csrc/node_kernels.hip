@@ -168,16 +168,15 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
       LL = fmaf(Q.kappa * ih4, bt, LL);
     }
     // gather of the transposed conversion: every tile slot overlapping node n
+    // (the groups overlapping a node have distinct slots: at most smx of them
+    // along x, and so on)
     const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
     float s = 0.0f;
     for (int cz = rz.lo; cz <= rz.hi; ++cz) {
-      const int kz = k - Q.orgz[cz];
       for (int cy = ry.lo; cy <= ry.hi; ++cy) {
-        const int iy = j - Q.orgy[cy];
         for (int cx = rx.lo; cx <= rx.hi; ++cx) {
-          const int jx = i - Q.orgx[cx];
-          const size_t slot = (size_t)cx + (size_t)Q.tiles_x * ((size_t)cy + (size_t)Q.tiles_y * cz);
-          s += Q.part[(((slot * 3 + d) * Q.nzt + kz) * Q.nyt + iy) * Q.nxt + jx];
+          const size_t ps = ((size_t)(cz % Q.smz) * Q.smy + cy % Q.smy) * Q.smx + cx % Q.smx;
+          s += Q.part[(ps * 3 + d) * Q.nbar + n];
         }
       }
     }

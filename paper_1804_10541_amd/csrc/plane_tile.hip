@@ -109,9 +109,11 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
   }
   __syncthreads();
 
-  const int slot = tile_x + P.tiles_x * chunk;
-  float* const part = P.part + (size_t)slot * 3 * P.nzt * P.nxt;
-  const size_t dstride = (size_t)P.nzt * P.nxt;
+  // the group's partial slot, one float per node and component (node index of
+  // the grid: row-major), read coalesced by the node pass
+  const int pslot = (chunk % P.smz) * P.smx + tile_x % P.smx;
+  float* const part = P.part + (size_t)pslot * 3 * (size_t)P.nbar;
+  const size_t dstride = (size_t)P.nbar;
 
   // Writes node row kloc of the transposed conversion: reduce the per-column
   // sums over x into the slot's node block.
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kPlaneNT) void plane_tile_kernel(const TileParams P
           s0 = fmaf(wt, sV[0][l], s0);
           s1 = fmaf(wt, sV[1][l], s1);
         }
-        const size_t o = (size_t)kloc * P.nxt + fj;
+        const size_t o = (size_t)(noy + kloc) * P.nx + (nox + fj);
         part[o] = s0;
         part[o + dstride] = s1;
       }
