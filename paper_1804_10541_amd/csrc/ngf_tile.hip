@@ -497,9 +497,10 @@ __global__ __launch_bounds__(BX* BY) void ngf_tile_kernel(const TileParams P, co
 // Persistent form over a batch of problems: every group takes tiles from a
 // shared work counter until all tiles of all active problems are done.  A
 // tile's results depend only on its problem and tile id, so the output equals
-// one launch per problem bit for bit.
+// one launch per problem bit for bit.  At most 128 VGPRs (four waves per SIMD):
+// two groups of 512 threads per CU, as for the single-problem kernel.
 template <int BX, int BY, int MODE>
-__global__ __launch_bounds__(BX* BY) void ngf_tile_batch_kernel(const BatchJobs J) {
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(4))) void ngf_tile_batch_kernel(const BatchJobs J) {
   __shared__ TileSmem<BX, BY, MODE, false> S;
   __shared__ int sItem;
   for (;;) {

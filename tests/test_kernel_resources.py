@@ -33,8 +33,8 @@ def _kernel_metadata(src, tmp_path):
     return meta
 
 
-@pytest.mark.parametrize("src,kernel", [("ngf_tile.hip", "ngf_tile_kernel"), ("plane_tile.hip", "plane_tile_kernel"),
-                                        ("diag_tile.hip", "diag_tile_kernel")])
+@pytest.mark.parametrize("src,kernel", [("ngf_tile.hip", "ngf_tile_kernel"), ("ngf_tile.hip", "ngf_tile_batch_kernel"),
+                                        ("plane_tile.hip", "plane_tile_kernel"), ("diag_tile.hip", "diag_tile_kernel")])
 def test_tile_kernels_use_no_scratch_memory(src, kernel, tmp_path):
     meta = _kernel_metadata(src, tmp_path)
     tiles = {k: v for k, v in meta.items() if kernel in k}
