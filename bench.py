@@ -538,6 +538,8 @@ def main():
     ap.add_argument("--no-lbfgs", action="store_true", help="skip the L-BFGS leg")
     ap.add_argument("--no-regularisers", action="store_true", help="skip the diffusive and elastic legs")
     ap.add_argument("--no-plane", action="store_true", help="skip the two-dimensional leg")
+    ap.add_argument("--plane-only", action="store_true",
+                    help="run only the two-dimensional leg (for profiling it) and print its result")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--cpu-worker", nargs=4, metavar=("CROP", "SEED", "BUDGET", "MIN_S"), help=argparse.SUPPRESS)
@@ -556,6 +558,16 @@ def main():
     from synth import ct_pair, smooth_field
 
     dev = torch.device("cuda:0")
+    if args.plane_only:
+        if args.copy_calibration:
+            src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                torch.neg(src, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps({"plane": plane_leg(dev)}), flush=True)
+        return
     spec = workload_spec(args.workload)
     log(f"[bench] generating {args.workload}: {spec.m} voxels, {spec.my} nodes")
     t0 = time.perf_counter()
