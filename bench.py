@@ -394,6 +394,109 @@ def plane_leg(dev, levels=3):
     return out
 
 
+def _stats_ms(xs):
+    import numpy as np
+
+    a = np.array(xs) * 1e3
+    return {"median": round(float(np.median(a)), 4), "min": round(float(a.min()), 4), "max": round(float(a.max()), 4),
+            "reps": len(xs)}
+
+
+def ops_leg(dev, reps=30, warm=3):
+    """Per-operation times at configuration 1 (32^3 voxels / 17^3 nodes, blobs, eps 0.1,
+    alpha 1) and configuration 2's finest level (128x128x96 CT-like / 65x65x49 nodes):
+    each library call (objective, gradient, Hessian-vector product, Jacobi diagonal)
+    timed by host wall clock around the call with the device synchronised before and
+    after, 3 warm-ups then 30 repetitions (median, min, max); and the float64 oracle's
+    same operations (single-thread worker process) at configuration 1, 30 repetitions,
+    and at configuration 2, one."""
+    import subprocess
+
+    import numpy as np
+    import torch
+
+    from paper_1804_10541_amd import mfr
+    from synth import GridSpec, config_c1, ct_pair, smooth_field
+
+    out = {}
+    c1 = config_c1(0, n_probes=1)
+    s2 = GridSpec(m=(128, 128, 96), h=(1.0, 1.0, 1.0), my=(65, 65, 49), tau=50.0, rho=50.0, alpha=0.1)
+    R2, T2, _, rng2 = ct_pair(0, s2.m, device=dev)
+    u2 = torch.from_numpy(smooth_field(rng2, s2.my, 0.5).astype("float32")).to(dev)
+    cases = {
+        "configuration 1: 32x32x32 / 17x17x17": (
+            c1["spec"], torch.from_numpy(c1["R"].astype("float32")).to(dev),
+            torch.from_numpy(c1["T"].astype("float32")).to(dev), torch.from_numpy(c1["u0"].astype("float32")).to(dev)),
+        "configuration 2, finest level: 128x128x96 / 65x65x49": (s2, R2, T2, u2),
+    }
+    for name, (spec, R, T, u) in cases.items():
+        ctx = mfr.Context(spec, dev)
+        ctx.set_images(R, T)
+        p = torch.randn(u.shape, generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+        q, g, d = torch.empty_like(p), torch.empty_like(p), torch.empty_like(p)
+        calls = {"objective": lambda: ctx.objective(u), "gradient": lambda: ctx.gradient(u, out=g),
+                 "hess_vec": lambda: ctx.hess_vec(u, p, out=q), "jacobi_diag": lambda: ctx.jacobi_diag(u, out=d)}
+        res = {}
+        for op, call in calls.items():
+            for _ in range(warm):
+                call()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                call()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[op] = _stats_ms(ts)
+        ctx.close()
+        out[name] = {"voxels": spec.voxels, "nodes": spec.nodes, "gpu_call_ms": res}
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    for name, which, n in (("configuration 1: 32x32x32 / 17x17x17", "c1", reps),
+                           ("configuration 2, finest level: 128x128x96 / 65x65x49", "c2", 1)):
+        pr = subprocess.run([sys.executable, os.path.abspath(__file__), "--ops-worker", which, str(n)],
+                            stdout=subprocess.PIPE, env=env, timeout=600)
+        if pr.returncode == 0:
+            out[name]["oracle_ms"] = json.loads(pr.stdout.decode().strip().splitlines()[-1])
+            out[name]["oracle_threads"] = 1
+    log(f"[bench] ops: {out}")
+    return out
+
+
+def _ops_worker(which, reps):
+    """The oracle's per-operation times (float64, assembled sparse Jacobian, one
+    thread): objective, gradient, Jacobian assembly, Hessian-vector product with the
+    assembled Jacobian, Jacobi diagonal; prints one JSON line."""
+    import numpy as np
+
+    from oracle import Grid, solver
+    from synth import GridSpec, config_c1, ct_pair, smooth_field
+
+    if which == "c1":
+        c = config_c1(0, n_probes=1)
+        spec, R, T, u = c["spec"], c["R"], c["T"], c["u0"]
+    else:
+        spec = GridSpec(m=(128, 128, 96), h=(1.0, 1.0, 1.0), my=(65, 65, 49), tau=50.0, rho=50.0, alpha=0.1)
+        R, T, _, rng = ct_pair(0, spec.m)
+        u = smooth_field(rng, spec.my, 0.5)
+        R, T = R.double().numpy(), T.double().numpy()
+    prob = solver.Problem(Grid.from_spec(spec), np.asarray(R, dtype=np.float64), np.asarray(T, dtype=np.float64))
+    u = np.asarray(u, dtype=np.float64)
+    p = np.random.default_rng(3).standard_normal(u.shape)
+    Jac = prob.jacobian(u)
+    ops = {"objective": lambda: prob.objective(u), "gradient": lambda: prob.gradient(u),
+           "jacobian_assembly": lambda: prob.jacobian(u), "hess_vec": lambda: prob.hess_vec(u, p, Jac),
+           "jacobi_diag": lambda: prob.jacobi_diag(u, Jac)}
+    res = {}
+    for op, call in ops.items():
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            call()
+            ts.append(time.perf_counter() - t0)
+        res[op] = _stats_ms(ts)
+    print(json.dumps(res), flush=True)
+
+
 CPU_CROP = (128, 128, 64)   # voxels of one oracle sample (x, y, z)
 CPU_CROP_NODES = (33, 33, 17)
 
@@ -542,10 +645,15 @@ def main():
                     help="run only the two-dimensional leg (for profiling it) and print its result")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-ops", action="store_true", help="skip the per-operation times at configurations 1 and 2")
     ap.add_argument("--cpu-worker", nargs=4, metavar=("CROP", "SEED", "BUDGET", "MIN_S"), help=argparse.SUPPRESS)
+    ap.add_argument("--ops-worker", nargs=2, metavar=("CONFIG", "REPS"), help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:   # a cpu_baseline worker process: oracle only, no GPU
         _cpu_worker(args.cpu_worker[0], int(args.cpu_worker[1]), float(args.cpu_worker[2]), float(args.cpu_worker[3]))
+        return
+    if args.ops_worker:   # oracle per-operation times, no GPU
+        _ops_worker(args.ops_worker[0], int(args.ops_worker[1]))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -676,6 +784,9 @@ def main():
     if not args.no_plane:
         log("[bench] two-dimensional path")
         out["plane"] = plane_leg(dev)
+    if not args.no_ops and args.workload == "c3":
+        log("[bench] per-operation times at configurations 1 and 2")
+        out["ops"] = ops_leg(dev)
     if not args.no_batch and args.workload != "small":
         log("[bench] ten-pair batched registration")
         out["batch"] = batch_leg(dev, not args.no_autotune)
