@@ -94,7 +94,7 @@ class Systems:
         key = (tuple(spec.m), tuple(spec.my))
         if key not in self.ctxs:
             if R is not None:
-                from . import autotune
+                from paper_1804_10541_amd import autotune
 
                 u0 = torch.zeros((3, spec.my[2], spec.my[1], spec.my[0]), dtype=torch.float32, device=self.device)
                 autotune.apply(spec, R, T, u0, device=self.device)
