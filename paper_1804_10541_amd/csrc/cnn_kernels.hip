@@ -4,15 +4,15 @@
 //
 // Layouts: activations channels-last [z][y][x][16] bf16 (one node = 32 bytes);
 // weights [27 taps][16 in][16 out] bf16 with tap t = 9 (dz+1) + 3 (dy+1) + (dx+1);
-// zero padding outside the grid.  One wave computes a 16 x 16 output tile:
-// 16 output channels x 16 consecutive nodes of one x-row, reducing over
-// K = 27 taps x 16 input channels = 14 MFMA steps of 32 (two taps each, the
-// last half zero).  Operands: A = weights (row = output channel), B = the
-// shifted activations (column = node), so each lane loads 16 contiguous bytes
-// of one node per step and stores 4 contiguous output channels of one node.
+// zero padding outside the grid.  One MFMA computes 16 output channels x 16
+// consecutive nodes of one x-row over K = 32: two taps x 16 input channels.
+// Operands: A = weights (row = output channel), B = the shifted activations
+// (column = node), so each lane loads 16 contiguous bytes of one node and
+// stores 4 contiguous output channels of one node.
 #include <algorithm>
 
 #include "mfr_internal.h"
+#include "tile_common.h"
 
 namespace mfr {
 
@@ -20,11 +20,20 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
 
 constexpr int kTaps = 27;
 constexpr int kCh = 16;
-constexpr int kSteps = 14;   // ceil(27 / 2)
-constexpr int kTx = 16, kTy = 4, kTz = 4;   // output tile of the convolution kernel
+constexpr int kTx = 16, kTy = 8, kTz = 4;   // output tile of the convolution kernel
+constexpr int kHx = kTx + 2, kHy = kTy + 2, kHz = kTz + 2;   // with its one-node halo
+constexpr int kTile = kTx * kTy * kTz;
+static_assert(kTz == 4 && kTile % 256 == 0, "one wave per z plane of the tile");
+static_assert(3 * kTile * 4 <= kHz * kHy * kHx * 32, "the last layer stages z over the input tile");
+// The nine (dz, dx) offsets m = 3 (dz+1) + (dx+1) go in pairs (2p, 2p+1) into
+// the two K halves of an MFMA; m = 9 is a zero-weight half.  The three dy
+// offsets of a pair share one activation load per x-row.
+constexpr int kPairs = 5;
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -42,16 +51,7 @@ __device__ __forceinline__ void tap_offset(int t, int& dz, int& dy, int& dx) {
   dx = t % 3 - 1;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ bf16x8 zero8() {
-  uint4 z = make_uint4(0u, 0u, 0u, 0u);
-  return __builtin_bit_cast(bf16x8, z);
-}
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 }  // namespace
 
@@ -62,176 +62,209 @@ __device__ __forceinline__ bf16x8 zero8() {
 // layers with out-major weights: kHidden (bf16 input; ReLU; bf16 output), kLast
 // (bf16 input; output z = r / diag + scale * y[0..2]) and kBwd (transposed
 // weights, ReLU mask, bf16 output: backward-data of the training pass).
+//
+// A work-group takes output tiles of 16 (x) x 8 (y) x 4 (z) nodes; wave w owns
+// the plane z = w of the tile, eight x-rows with one accumulator each.  For each
+// (dz, dx) pair the wave walks the ten staged rows y = -1 .. 8 of its shifted
+// planes once: the activations of row s serve dy = -1, 0, +1 of output rows
+// s, s - 1, s - 2 (three MFMAs per LDS load).
 enum ConvMode : int { kGeneric = 0, kHidden = 2, kLast = 3, kBwd = 4 };
 
 template <int kMode>
-__global__ __launch_bounds__(256) void cnn_conv_kernel(const ConvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void cnn_conv_kernel(const ConvArgs a) {
   constexpr bool kRelu = kMode == kHidden;
   constexpr bool kOutZ = kMode == kLast;
   constexpr bool kOut16 = kMode == kHidden || kMode == kBwd;
   if (a.live && !ld_coherent(a.live)) return;   // a device-steered solve has stopped
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 15, quad = lane >> 4;
-  const size_t nn = (size_t)a.nx * a.ny * a.nz;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int nn = nx * ny * nz;   // < 2^26 nodes
   const bool transpose = kMode == kBwd || (kMode == kGeneric && a.transpose);
   const bool out_major = kMode == kHidden || kMode == kLast || (kMode == kGeneric && a.w_out_major);
 
-  // LDS: the block's weights as the A operand wants them, [tap][row][k channel]
-  // (tap 27 zero: the padding half of the last step), and the input tile with a
-  // one-node halo.  A wave's A operand of step j is the 1 KB at taps 2j, 2j + 1.
-  __shared__ __align__(16) uint16_t wl[kTaps + 1][kCh][kCh];
-  __shared__ __align__(16) uint16_t xs[kTz + 2][kTy + 2][kTx + 2][kCh];
-  if (transpose || out_major) {
-    // 16-byte chunks: forward out-major weights are [t][out][in] already; the
-    // transposed operand of tap t is the in-major block of tap 26 - t
-    for (int q = tid; q < (kTaps + 1) * kCh * 2; q += 256) {
-      const int t = q >> 5, rest = q & 31;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (t < kTaps)
-        v = *reinterpret_cast<const uint4*>(a.w + (size_t)(transpose ? kTaps - 1 - t : t) * kCh * kCh + 8 * rest);
-      *reinterpret_cast<uint4*>(&wl[t][0][0] + 8 * rest) = v;
-    }
-  } else {
-    // in-major forward weights [t][in][out]: transpose each tap's block
-    for (int q = tid; q < (kTaps + 1) * kCh * kCh; q += 256) {
-      const int t = q >> 8, o = (q >> 4) & 15, c = q & 15;
-      wl[t][o][c] = t < kTaps ? a.w[((size_t)t * kCh + c) * kCh + o] : (uint16_t)0;
+  // LDS: the A operands [pair][dy][quad][row][8 k] (a lane's 16 bytes of one
+  // step are contiguous, a wave's 1 KB too), and the input tile with its halo
+  // as [z][y][channel half][x][8], so that the 16 lanes of one half read 256
+  // contiguous bytes.
+  __shared__ __align__(16) uint16_t wl[kPairs][3][4][kCh][8];
+  __shared__ __align__(16) uint16_t xs[kHz][kHy][2][kHx][8];
+  constexpr int kWChunks = kPairs * 3 * 4 * kCh;   // 16-byte chunks of wl
+  constexpr int kWPer = (kWChunks + 255) / 256;
+  constexpr int kXChunks = kHz * kHy * kHx * 2;
+  constexpr int kXPer = (kXChunks + 255) / 256;
+
+  // weight chunk q of this thread: its tap, or -1 for the zero half
+  auto w_tap = [&](int q) {
+    const int p = q / 192, dyi = (q / 64) % 3, qd = (q / 16) % 4;
+    const int m = 2 * p + (qd >> 1);
+    return m > 8 ? -1 : 9 * (m / 3) + 3 * dyi + m % 3;
+  };
+  if (!(transpose || out_major)) {
+    // in-major forward weights [t][in][out] (public entry point): gather each
+    // row's input channels; once per work-group
+    for (int q = tid; q < kWChunks; q += 256) {
+      const int t = w_tap(q), row = q % 16, c0 = 8 * ((q / 16) % 2);
+      uint16_t* dst = &wl[0][0][0][0][0] + 8 * q;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dst[e] = t < 0 ? (uint16_t)0 : a.w[((size_t)t * kCh + c0 + e) * kCh + row];
     }
   }
   float bias[4] = {0.f, 0.f, 0.f, 0.f};
   if (a.bias) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bias[i] = a.bias[4 * quad + i];
+    const float4 b4 = *reinterpret_cast<const float4*>(a.bias + 4 * quad);
+    bias[0] = b4.x;
+    bias[1] = b4.y;
+    bias[2] = b4.z;
+    bias[3] = b4.w;
   }
   float scale = 0.f;
   if constexpr (kOutZ) scale = (float)ld_coherent(a.scale);
   double zr = 0.0, zrp = 0.0;
 
-  // Output tiles of 16 (x) x 4 (y) x 4 (z) nodes, one per work-group; wave w
-  // computes the x-rows (y, z) = rows w, w + 4, w + 8, w + 12 of the tile with
-  // four independent accumulators.
-  const int tnx = (a.nx + kTx - 1) / kTx, tny = (a.ny + kTy - 1) / kTy, tnz = (a.nz + kTz - 1) / kTz;
+  const int tnx = (nx + kTx - 1) / kTx, tny = (ny + kTy - 1) / kTy, tnz = (nz + kTz - 1) / kTz;
   const int tiles = tnx * tny * tnz;
-  constexpr int kChunks = (kTz + 2) * (kTy + 2) * (kTx + 2) * 2;   // 16-byte halves
-  // this lane's A operand: tap 2 j + (quad >> 1), row col, k channels 8 (quad & 1) ..
-  const uint16_t* arow = &wl[quad >> 1][col][8 * (quad & 1)];
-  const int tap_hi = quad >> 1;
-  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  bool first = true;
+  for (int tile = xcd_block_id(); tile < tiles; tile += gridDim.x) {
     const int x0 = (tile % tnx) * kTx, y0 = ((tile / tnx) % tny) * kTy, z0 = (tile / (tnx * tny)) * kTz;
-    // all loads of the tile first, then the LDS stores (one memory latency per tile)
-    constexpr int kPer = (kChunks + 255) / 256;
-    uint4 v[kPer];
+    // all loads first (the weights with the first tile), then the LDS stores:
+    // one memory latency per tile
+    uint4 wv[kWPer];
+    if (first && (transpose || out_major)) {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
+      for (int k = 0; k < kWPer; ++k) {
+        const int q = tid + 256 * k;
+        wv[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (q < kWChunks) {
+          const int t = w_tap(q);
+          if (t >= 0)
+            wv[k] = *reinterpret_cast<const uint4*>(a.w + (size_t)(transpose ? kTaps - 1 - t : t) * kCh * kCh +
+                                                    (q % 16) * kCh + 8 * ((q / 16) % 2));
+        }
+      }
+    }
+    uint4 v[kXPer];
+#pragma unroll
+    for (int k = 0; k < kXPer; ++k) {
       const int q = tid + 256 * k;
       v[k] = make_uint4(0u, 0u, 0u, 0u);
-      if (q < kChunks) {
+      if (q < kXChunks) {
         const int half = q & 1, rest = q >> 1;
-        const int lx = rest % (kTx + 2), ly = (rest / (kTx + 2)) % (kTy + 2), lz = rest / ((kTx + 2) * (kTy + 2));
+        const int lx = rest % kHx, ly = (rest / kHx) % kHy, lz = rest / (kHx * kHy);
         const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
-        if (xx >= 0 && xx < a.nx && yy >= 0 && yy < a.ny && zz >= 0 && zz < a.nz) {
+        if (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
           const size_t node = ((size_t)zz * a.ny + yy) * a.nx + xx;
           v[k] = *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
         }
       }
     }
+    if (first && (transpose || out_major)) {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
+      for (int k = 0; k < kWPer; ++k) {
+        const int q = tid + 256 * k;
+        if (q < kWChunks) *reinterpret_cast<uint4*>(&wl[0][0][0][0][0] + 8 * q) = wv[k];
+      }
+    }
+    first = false;
+#pragma unroll
+    for (int k = 0; k < kXPer; ++k) {
       const int q = tid + 256 * k;
-      if (q < kChunks) *reinterpret_cast<uint4*>(&xs[0][0][0][0] + 8 * q) = v[k];
+      if (q < kXChunks) {
+        const int half = q & 1, rest = q >> 1;
+        const int lx = rest % kHx, lyz = rest / kHx;   // lyz = lz * kHy + ly
+        *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * ((lyz * 2 + half) * kHx + lx)) = v[k];
+      }
     }
     __syncthreads();
-    f32x4 acc[4];
+    f32x4 acc[kTy];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // B operand of (step j, row i): 16 bytes of node col + dx of the shifted row
-    auto load_b = [&](int j, int i) {
-      const int t = 2 * j + tap_hi;
-      int dz, dy, dx;
-      tap_offset(t < kTaps ? t : 13, dz, dy, dx);   // padding half of the last step: zero weights
-      const int row = wave + 4 * i, ly = row % kTy, lz = row / kTy;
-      return *reinterpret_cast<const uint4*>(&xs[lz + 1 + dz][ly + 1 + dy][col + 1 + dx][8 * (quad & 1)]);
-    };
-    uint4 bc[4], bn[4];
-    uint4 ac = *reinterpret_cast<const uint4*>(arow), an;
+    for (int i = 0; i < kTy; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bc[i] = load_b(0, i);
+    for (int p = 0; p < kPairs; ++p) {
+      // this lane's (dz, dx): the first or second member of the pair; the zero
+      // half reads any staged row (its weights are zero)
+      const int m0 = 2 * p + (quad >> 1), m = m0 > 8 ? 4 : m0;
+      const uint16_t* brow = &xs[wave + m / 3][0][quad & 1][col + m % 3][0];
+      const uint4 a0 = *reinterpret_cast<const uint4*>(&wl[p][0][quad][col][0]);
+      const uint4 a1 = *reinterpret_cast<const uint4*>(&wl[p][1][quad][col][0]);
+      const uint4 a2 = *reinterpret_cast<const uint4*>(&wl[p][2][quad][col][0]);
 #pragma unroll
-    for (int j = 0; j < kSteps; ++j) {
-      if (j + 1 < kSteps) {   // operands of the next step in flight during this one
-        an = *reinterpret_cast<const uint4*>(arow + (size_t)(j + 1) * 2 * kCh * kCh);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bn[i] = load_b(j + 1, i);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ac),
-                                                         __builtin_bit_cast(bf16x8, bc[i]), acc[i], 0, 0, 0);
-      if (j + 1 < kSteps) {
-        ac = an;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bc[i] = bn[i];
+      for (int s = 0; s < kHy; ++s) {
+        const uint4 b = *reinterpret_cast<const uint4*>(brow + s * (2 * kHx * 8));
+        if (s < kTy) acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a0), as_bf16x8(b), acc[s], 0, 0, 0);
+        if (s >= 1 && s <= kTy)
+          acc[s - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a1), as_bf16x8(b), acc[s - 1], 0, 0, 0);
+        if (s >= 2)
+          acc[s - 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a2), as_bf16x8(b), acc[s - 2], 0, 0, 0);
       }
     }
     if constexpr (kOutZ) {
       // z = r / diag + scale * y[0..2] over the whole tile: the three channels go
       // through LDS (over the staged input) so that every lane takes one node
       __syncthreads();
-      float* zs = reinterpret_cast<float*>(&xs[0][0][0][0]);   // [3][256]
+      float* zs = reinterpret_cast<float*>(&xs[0][0][0][0][0]);   // [3][kTile]
       if (quad == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int nl = (wave + 4 * i) * kTx + col;
+        for (int i = 0; i < kTy; ++i) {
+          const int nl = (wave * kTy + i) * kTx + col;
 #pragma unroll
-          for (int r = 0; r < 3; ++r) zs[r * 256 + nl] = acc[i][r] + bias[r];
+          for (int r = 0; r < 3; ++r) zs[r * kTile + nl] = acc[i][r] + bias[r];
         }
       }
       __syncthreads();
-      const int x = x0 + (tid & 15), row = tid >> 4, y = y0 + row % kTy, z = z0 + row / kTy;
-      if (x < a.nx && y < a.ny && z < a.nz) {
-        const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const size_t id = (size_t)d * nn + node;
-          const float rv = a.r[id];
-          const float zi = fmaf(scale, zs[d * 256 + tid], rv / a.diag[id]);
-          a.z[id] = zi;
-          if (a.zred) {
-            zr += (double)zi * rv;
-            zrp += (double)zi * a.rprev[id];
+      for (int k = 0; k < kTile / 256; ++k) {
+        const int nl = tid + 256 * k, row = nl / kTx;
+        const int x = x0 + nl % kTx, y = y0 + row % kTy, z = z0 + row / kTy;
+        if (x < nx && y < ny && z < nz) {
+          const int node = (z * ny + y) * nx + x;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int id = d * nn + node;
+            const float rv = a.r[id];
+            const float zi = fmaf(scale, zs[d * kTile + nl], rv / a.diag[id]);
+            a.z[id] = zi;
+            if (a.zred) {
+              zr += (double)zi * rv;
+              zrp += (double)zi * a.rprev[id];
+            }
           }
         }
       }
     } else {
+      // this lane holds output channels 4 quad + r of node (x0 + col, y0 + i, z0 + w)
+      const int x = x0 + col, z = z0 + wave;
+      const int rows = min(kTy, ny - y0);   // wave-uniform
+      if (x < nx && z < nz) {
+        int node = (z * ny + y0) * nx + x;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = wave + 4 * i;
-        const int x = x0 + col, y = y0 + row % kTy, z = z0 + row / kTy;
-        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-        // this lane holds output channels 4 quad + r of node (x, y, z)
-        const size_t node = ((size_t)z * a.ny + y) * a.nx + x;
-        float v[4];
+        for (int i = 0; i < kTy; ++i, node += nx) {
+          if (i >= rows) break;
+          float v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          v[r] = acc[i][r] + bias[r];
-          if (kRelu || (kMode == kGeneric && a.relu)) v[r] = fmaxf(v[r], 0.f);
-        }
-        if (kMode == kBwd || (kMode == kGeneric && a.mask)) {
-          const uint2 m = *reinterpret_cast<const uint2*>(a.mask + node * kCh + 4 * quad);
-          const uint16_t mh[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffff),
-                                  (uint16_t)(m.y >> 16)};
+          for (int r = 0; r < 4; ++r) {
+            v[r] = acc[i][r] + bias[r];
+            if (kRelu || (kMode == kGeneric && a.relu)) v[r] = fmaxf(v[r], 0.f);
+          }
+          if (kMode == kBwd || (kMode == kGeneric && a.mask)) {
+            const uint2 mk = *reinterpret_cast<const uint2*>(a.mask + (size_t)node * kCh + 4 * quad);
+            const uint16_t mh[4] = {(uint16_t)(mk.x & 0xffff), (uint16_t)(mk.x >> 16), (uint16_t)(mk.y & 0xffff),
+                                    (uint16_t)(mk.y >> 16)};
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (!(bf2f(mh[r]) > 0.f)) v[r] = 0.f;
+            for (int r = 0; r < 4; ++r)
+              if (!(bf2f(mh[r]) > 0.f)) v[r] = 0.f;
+          }
+          if (kOut16 || (kMode == kGeneric && a.y16)) {
+            // round to nearest even in hardware (the same rounding as f2bf for non-NaN values)
+            const bf16x2 lo = __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2);
+            const bf16x2 hi = __builtin_convertvector((f32x2){v[2], v[3]}, bf16x2);
+            *reinterpret_cast<uint2*>(a.y16 + (size_t)node * kCh + 4 * quad) =
+                make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+          }
+          if (kMode == kGeneric && a.y32)
+            *reinterpret_cast<float4*>(a.y32 + (size_t)node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
         }
-        if (kOut16 || (kMode == kGeneric && a.y16)) {
-          uint2 o;
-          o.x = f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-          o.y = f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-          *reinterpret_cast<uint2*>(a.y16 + node * kCh + 4 * quad) = o;
-        }
-        if (kMode == kGeneric && a.y32)
-          *reinterpret_cast<float4*>(a.y32 + node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
       }
     }
     __syncthreads();   // the next tile overwrites the staged input

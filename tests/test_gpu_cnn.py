@@ -28,7 +28,8 @@ def f32(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
 
 
-GRIDS = [(21, 7, 5), (16, 3, 2), (1, 1, 1), (37, 2, 3)]
+# several output tiles (16 x 8 x 4 nodes) per axis with ragged tails, single-tile and degenerate grids
+GRIDS = [(21, 7, 5), (16, 3, 2), (1, 1, 1), (37, 2, 3), (19, 17, 9), (34, 10, 6)]
 
 
 @pytest.mark.parametrize("shape", GRIDS)

@@ -1,4 +1,4 @@
-"""Resource use of the voxel-tile kernels, read from the gfx950 code-object
+"""Resource use of the tile kernels (voxel tiles, the tiled diagonal and the convolution), read from the
 metadata that hipcc writes for them: no private (scratch) memory, which a
 register array indexed at run time or a vector-register spill would silently
 bring in (every access then goes through the vector-memory path).  Scalar
@@ -33,14 +33,19 @@ def _kernel_metadata(src, tmp_path):
     return meta
 
 
-@pytest.mark.parametrize("src,kernel", [("ngf_tile.hip", "ngf_tile_kernel"), ("ngf_tile.hip", "ngf_tile_batch_kernel"),
-                                        ("plane_tile.hip", "plane_tile_kernel"), ("diag_tile.hip", "diag_tile_kernel")])
-def test_tile_kernels_use_no_scratch_memory(src, kernel, tmp_path):
+# VGPR bounds: 128 = four waves per SIMD (two 512-thread groups per CU); the
+# convolution's 256-thread groups are held to three per CU by their 50 KB of
+# LDS, so three waves per SIMD (168 VGPRs) suffice there.
+@pytest.mark.parametrize("src,kernel,max_vgpr", [("ngf_tile.hip", "ngf_tile_kernel", 128),
+                                                 ("ngf_tile.hip", "ngf_tile_batch_kernel", 128),
+                                                 ("plane_tile.hip", "plane_tile_kernel", 128),
+                                                 ("diag_tile.hip", "diag_tile_kernel", 128),
+                                                 ("cnn_kernels.hip", "cnn_conv_kernel", 168)])
+def test_tile_kernels_use_no_scratch_memory(src, kernel, max_vgpr, tmp_path):
     meta = _kernel_metadata(src, tmp_path)
     tiles = {k: v for k, v in meta.items() if kernel in k}
     assert tiles, f"no {kernel} instances in {src}"
     for name, m in tiles.items():
         assert m["private_segment_fixed_size"] == 0, (name, m)
         assert m["vgpr_spill_count"] == 0, (name, m)
-        # at most 128 VGPRs: four waves per SIMD, what a 512-thread group needs for two groups per CU
-        assert m["vgpr_count"] <= 128, (name, m)
+        assert m["vgpr_count"] <= max_vgpr, (name, m)
