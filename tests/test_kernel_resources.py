@@ -1,4 +1,4 @@
-"""Resource use of the tile kernels (voxel tiles, the tiled diagonal and the convolution), read from the
+"""Resource use of the tile kernels (voxel tiles, the tiled diagonal and the convolution), read from the gfx950 code-object
 metadata that hipcc writes for them: no private (scratch) memory, which a
 register array indexed at run time or a vector-register spill would silently
 bring in (every access then goes through the vector-memory path).  Scalar
