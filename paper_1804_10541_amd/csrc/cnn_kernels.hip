@@ -61,20 +61,23 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast
 // public convolution entry points); the others are the preconditioner's own
 // layers with out-major weights: kHidden (bf16 input; ReLU; bf16 output), kLast
 // (bf16 input; output z = r / diag + scale * y[0..2]) and kBwd (transposed
-// weights, ReLU mask, bf16 output: backward-data of the training pass).
+// weights, ReLU mask, bf16 output: backward-data of the training pass) and
+// kFirst (kHidden whose input, the network features, is computed from r, the
+// diagonal and |grad R| while the tile is staged: no separate feature pass).
 //
 // A work-group takes output tiles of 16 (x) x 8 (y) x 4 (z) nodes; wave w owns
 // the plane z = w of the tile, eight x-rows with one accumulator each.  For each
 // (dz, dx) pair the wave walks the ten staged rows y = -1 .. 8 of its shifted
 // planes once: the activations of row s serve dy = -1, 0, +1 of output rows
 // s, s - 1, s - 2 (three MFMAs per LDS load).
-enum ConvMode : int { kGeneric = 0, kHidden = 2, kLast = 3, kBwd = 4 };
+enum ConvMode : int { kGeneric = 0, kFirst = 1, kHidden = 2, kLast = 3, kBwd = 4 };
 
 template <int kMode>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void cnn_conv_kernel(const ConvArgs a) {
-  constexpr bool kRelu = kMode == kHidden;
+  constexpr bool kRelu = kMode == kHidden || kMode == kFirst;
   constexpr bool kOutZ = kMode == kLast;
-  constexpr bool kOut16 = kMode == kHidden || kMode == kBwd;
+  constexpr bool kOut16 = kMode == kHidden || kMode == kFirst || kMode == kBwd;
+  constexpr bool kFeat = kMode == kFirst;
   if (a.live && !ld_coherent(a.live)) return;   // a device-steered solve has stopped
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int nn = nx * ny * nz;   // < 2^26 nodes
   const bool transpose = kMode == kBwd || (kMode == kGeneric && a.transpose);
-  const bool out_major = kMode == kHidden || kMode == kLast || (kMode == kGeneric && a.w_out_major);
+  const bool out_major = kMode == kHidden || kMode == kFirst || kMode == kLast || (kMode == kGeneric && a.w_out_major);
 
   // LDS: the A operands [pair][dy][quad][row][8 k] (a lane's 16 bytes of one
   // step are contiguous, a wave's 1 KB too), and the input tile with its halo
@@ -121,6 +124,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   }
   float scale = 0.f;
   if constexpr (kOutZ) scale = (float)ld_coherent(a.scale);
+  // feature scales: 1 / RMS of r / diag, r, diag and |grad R| (0 for a zero RMS)
+  float fs[4] = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (kFeat) {
+    const int slot[4] = {PC_RMS_Y, PC_RMS_R, PC_RMS_D, PC_RMS_G};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double sv = ld_coherent(a.fsc + slot[i]);
+      fs[i] = sv > 0.0 ? (float)(1.0 / sv) : 0.f;
+    }
+  }
   double zr = 0.0, zrp = 0.0;
 
   const int tnx = (nx + kTx - 1) / kTx, tny = (ny + kTy - 1) / kTy, tnz = (nz + kTz - 1) / kTz;
@@ -144,9 +157,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
         }
       }
     }
+    // network input of the halo nodes (kFirst): r, diag and |grad R| of node
+    // q = tid + 256 k, zero outside the grid
+    constexpr int kNodes = kHz * kHy * kHx, kNPer = (kNodes + 255) / 256;
+    float fin[kFeat ? kNPer : 1][7];
+    bool fok[kFeat ? kNPer : 1];
+    if constexpr (kFeat) {
+#pragma unroll
+      for (int k = 0; k < kNPer; ++k) {
+        const int q = tid + 256 * k;
+        const int lx = q % kHx, ly = (q / kHx) % kHy, lz = q / (kHx * kHy);
+        const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
+        fok[k] = q < kNodes && xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+#pragma unroll
+        for (int e = 0; e < 7; ++e) fin[k][e] = 0.f;
+        if (fok[k]) {
+          const int node = (zz * ny + yy) * nx + xx;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            fin[k][d] = a.fr[d * nn + node];
+            fin[k][3 + d] = a.fdiag[d * nn + node];
+          }
+          fin[k][6] = a.fgR[node];
+        }
+      }
+    }
     uint4 v[kXPer];
 #pragma unroll
-    for (int k = 0; k < kXPer; ++k) {
+    for (int k = 0; k < (kFeat ? 0 : kXPer); ++k) {
       const int q = tid + 256 * k;
       v[k] = make_uint4(0u, 0u, 0u, 0u);
       if (q < kXChunks) {
@@ -167,8 +205,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       }
     }
     first = false;
+    if constexpr (kFeat) {
+      // channels (r/diag)/rms_y [0..2], r/rms_r [3..5], diag/rms_d [6..8],
+      // |grad R|/rms_g [9], zero [10..15], rounded to bf16 (to nearest even)
 #pragma unroll
-    for (int k = 0; k < kXPer; ++k) {
+      for (int k = 0; k < kNPer; ++k) {
+        const int q = tid + 256 * k;
+        if (q < kNodes) {
+          uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = make_uint4(0u, 0u, 0u, 0u);
+          if (fok[k]) {
+            float f[10];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              f[d] = (fin[k][d] / fin[k][3 + d]) * fs[0];
+              f[3 + d] = fin[k][d] * fs[1];
+              f[6 + d] = fin[k][3 + d] * fs[2];
+            }
+            f[9] = fin[k][6] * fs[3];
+            auto pk = [](float u, float w) {
+              return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){u, w}, bf16x2));
+            };
+            lo = make_uint4(pk(f[0], f[1]), pk(f[2], f[3]), pk(f[4], f[5]), pk(f[6], f[7]));
+            hi = make_uint4(pk(f[8], f[9]), 0u, 0u, 0u);
+          }
+          const int lx = q % kHx, lyz = q / kHx;
+          *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * (lyz * 2 * kHx + lx)) = lo;
+          *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * ((lyz * 2 + 1) * kHx + lx)) = hi;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < (kFeat ? 0 : kXPer); ++k) {
       const int q = tid + 256 * k;
       if (q < kXChunks) {
         const int half = q & 1, rest = q >> 1;
@@ -298,12 +365,16 @@ hipError_t launch_cnn_conv(const ConvArgs& a, hipStream_t st) {
     if (!a.transpose && a.w_out_major && !a.mask) {
       if (a.x && a.relu && a.y16 && !a.z) mode = kHidden;
       else if (a.x && !a.relu && !a.y16 && a.z) mode = kLast;
+      else if (!a.x && a.fr && a.fdiag && a.fgR && a.fsc && a.relu && a.y16 && !a.z) mode = kFirst;
     }
   }
+  // the computed input exists only in its specialisation, every other mode reads x
+  if ((a.fr != nullptr) != (mode == kFirst) || (mode != kFirst && !a.x)) return hipErrorInvalidValue;
   if (a.transpose && a.mask && a.y16 && !a.y32 && !a.relu && !a.bias && !a.z) mode = kBwd;
   // the z output exists only in its specialisation
   if (a.z && mode != kLast) return hipErrorInvalidValue;
   switch (mode) {
+    case kFirst: hipLaunchKernelGGL(cnn_conv_kernel<kFirst>, dim3(blocks), dim3(256), 0, st, a); break;
     case kHidden: hipLaunchKernelGGL(cnn_conv_kernel<kHidden>, dim3(blocks), dim3(256), 0, st, a); break;
     case kLast: hipLaunchKernelGGL(cnn_conv_kernel<kLast>, dim3(blocks), dim3(256), 0, st, a); break;
     case kBwd: hipLaunchKernelGGL(cnn_conv_kernel<kBwd>, dim3(blocks), dim3(256), 0, st, a); break;

@@ -182,8 +182,11 @@ mfr_status gn_step(mfr_ctx* c, float* u, const mfr_gn_opts* o, mfr_gn_info* out)
 // learned preconditioner (pc.cpp) as used by the flexible CG of pcg_run
 mfr_status pc_begin_solve(mfr_pc* pc, const float* diag);
 // live (nullable): every kernel of the application does nothing while *live == 0.
+// keep_input: store the network input in h0 (a separate feature pass; training
+// needs it for the first layer's weight gradient).
 mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, bool scales_ready = false,
-                      const float* rprev = nullptr, double* zred = nullptr, const int* live = nullptr);
+                      const float* rprev = nullptr, double* zred = nullptr, const int* live = nullptr,
+                      bool keep_input = false);
 float* pc_scratch_vec(mfr_pc* pc);
 double* pc_red(mfr_pc* pc);
 double* pc_scalars(mfr_pc* pc);

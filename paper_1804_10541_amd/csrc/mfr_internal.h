@@ -370,6 +370,13 @@ struct ConvArgs {
   const float* rprev;   // with zred: per-group partials of z.r and z.rprev (2 per group)
   double* zred;
   const int* live;   // nullable: skip while *live == 0 (device-steered solve)
+  // first layer with its input computed while staging (x null): the network
+  // input of pc_features from r and diag (3 x n each), |grad R| (n) and the
+  // scalars at PC_RMS_Y, PC_RMS_R, PC_RMS_D, PC_RMS_G of fsc
+  const float* fr;
+  const float* fdiag;
+  const float* fgR;
+  const double* fsc;
 };
 
 struct AdamArgs {

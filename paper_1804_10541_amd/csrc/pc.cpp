@@ -148,7 +148,7 @@ mfr_status train_step(mfr_pc* pc, const float* u, const float* r, const mfr_pc_t
   HIP_TRY(launch_pc_jacobi(n3, r, pc->diag, pc->y, st));
   MFR_TRY(enqueue_hess_vec(c, u, pc->y, pc->Ay));
   // forward pass and A z
-  MFR_TRY(pc_forward(pc, r, pc->diag, pc->z, false, nullptr, nullptr));
+  MFR_TRY(pc_forward(pc, r, pc->diag, pc->z, false, nullptr, nullptr, nullptr, true));
   MFR_TRY(enqueue_hess_vec(c, u, pc->z, pc->Az));
   DotsArgs d{};
   DotsOut out{};
@@ -241,7 +241,7 @@ mfr_status pc_begin_solve(mfr_pc* pc, const float* diag) {
 // r and r/diag are already in the scalars (the flexible-CG update computes them).
 // zred: the final layer also leaves per-group partials of z.r and z.rprev there.
 mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, bool scales_ready,
-                      const float* rprev, double* zred, const int* live) {
+                      const float* rprev, double* zred, const int* live, bool keep_input) {
   hipStream_t st = st_of(pc);
   if (!scales_ready) {
     DotsArgs d{};
@@ -257,14 +257,22 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, b
     o.rms_scale[0] = o.rms_scale[1] = 1.0 / pc->n3;
     HIP_TRY(launch_pc_dots(d, o, pc->red, st));
   }
-  // the network input (kept for the first layer's weight gradient in training)
-  HIP_TRY(launch_pc_features(pc->n, r, diag, pc->gR, pc->sc, pc->h[0], st, live));
+  // the network input: stored for the first layer's weight gradient in
+  // training, else computed by the first layer itself while it stages a tile
+  if (keep_input) HIP_TRY(launch_pc_features(pc->n, r, diag, pc->gR, pc->sc, pc->h[0], st, live));
   for (int l = 0; l < kCnnLayers; ++l) {
     ConvArgs a{};
     a.nx = pc->nx;
     a.ny = pc->ny;
     a.nz = pc->nz;
-    a.x = pc->h[l];
+    if (l > 0 || keep_input) {
+      a.x = pc->h[l];
+    } else {
+      a.fr = r;
+      a.fdiag = diag;
+      a.fgR = pc->gR;
+      a.fsc = pc->sc;
+    }
     a.live = live;
     a.w = pc->w16 + (size_t)(kCnnLayers + l) * kCnnWeights;
     a.w_out_major = 1;
