@@ -288,12 +288,53 @@ def pc_leg(dev):
         return {"skipped": f"no trained weights at {os.path.relpath(pc_train.WEIGHTS, ROOT)}"}
     params = np.load(pc_train.WEIGHTS)
     out = {"weights": os.path.relpath(pc_train.WEIGHTS, ROOT), "rtol": 1e-3}
+    out["network_vs_hv"] = network_vs_hv(dev, params)
     for name, seeds, spec in (("128x128x96", [200], pc_train.workload_spec()),
                               ("512x512x128", [201], pc_train.c4_specs()[8])):
         rows = pc_train.evaluate(params, seeds, gn_iters=4, spec=spec, device=dev)
         summ = pc_train.summarize(rows)
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"[bench] learned preconditioner {name}: {out[name]}")
+    return out
+
+
+def network_vs_hv(dev, params, reps=50):
+    """One application of the learned preconditioner's network (its convolutions,
+    the input features computed by the first) against one Hessian-vector product
+    (voxel tiles and node pass) on the 128 x 128 x 96 / 65 x 65 x 49 workload:
+    mean times from HIP events on the context's stream (the library's timing)."""
+    import torch
+
+    from paper_1804_10541_amd import mfr, pc_train
+    from synth import ct_pair, smooth_field
+
+    spec = pc_train.workload_spec()
+    R, T, _, rng = ct_pair(210, spec.m, device=dev)
+    ctx = mfr.Context(spec, dev)
+    ctx.set_images(R, T)
+    pc = mfr.LearnedPC(ctx)
+    pc.set_params(params)
+    u = torch.from_numpy(smooth_field(rng, spec.my, 0.5).astype("float32")).to(dev)
+    r = torch.randn(u.shape, generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+    z, q = torch.empty_like(r), torch.empty_like(r)
+    for _ in range(3):
+        pc.apply(u, r, out=z)
+        ctx.hess_vec(u, r, out=q)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    for _ in range(reps):
+        pc.apply(u, r, out=z)
+    for _ in range(reps):
+        ctx.hess_vec(u, r, out=q)
+    pr = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    net_us = 1e3 * pr["pc_network"][1] / max(pr["pc_network"][0], 1)
+    hv_us = 1e3 * (pr["tile_hv"][1] + pr["node_pass"][1]) / reps
+    out = {"nodes": list(spec.my), "network_us": round(net_us, 2), "hv_us": round(hv_us, 2),
+           "network_per_hv": round(net_us / hv_us, 3)}
+    pc.close()
+    ctx.close()
+    log(f"[bench] learned preconditioner network vs Hv: {out}")
     return out
 
 

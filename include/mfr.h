@@ -480,11 +480,13 @@ mfr_status mfr_get_tile_config(mfr_tile_config* cfg);
  * kernels; mfr_profile_read synchronises the stream and returns the launch
  * counts and summed event times in milliseconds, per kernel:
  * [0] voxel-tile kernel, objective mode; [1] gradient mode; [2] Hessian-vector
- * mode; [3] Jacobi diagonal; [4] node pass (all modes).  Timing adds two event
- * records per launch; it is off after mfr_create. */
+ * mode; [3] Jacobi diagonal; [4] node pass (all modes); [5] the attached or
+ * applied learned preconditioner's network (its features and four
+ * convolutions, one record per application).  Timing adds two event records
+ * per launch; it is off after mfr_create. */
 typedef struct {
-  int32_t launches[5];
-  double ms[5];
+  int32_t launches[6];
+  double ms[6];
 } mfr_profile_stats;
 
 mfr_status mfr_profile_enable(mfr_ctx* ctx, int32_t enable);

@@ -885,22 +885,6 @@ hipEvent_t prof_event(mfr_ctx* c) {
   return e;
 }
 
-// Runs `launch` between two event records when timing is on (slot: kernel id).
-template <class F>
-hipError_t timed(mfr_ctx* c, int slot, F&& launch) {
-  if (!c->prof_on) return launch();
-  hipEvent_t a = prof_event(c), b = prof_event(c);
-  if (!a || !b) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(a, c->stream);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, c->stream);
-  if (e != hipSuccess) return e;
-  c->prof_pending.push_back({slot, {a, b}});
-  return hipSuccess;
-}
-
 hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag) {
   if (c->geo.dim == 2)
     return c->tiling.dg.on ? launch_diag_tile(c->dtp, u, diag, c->stream) : launch_plane_jacobi(c->dp, u, diag, c->stream);
@@ -1364,7 +1348,7 @@ mfr_status mfr_profile_read(mfr_ctx* c, mfr_profile_stats* st, int32_t reset) {
     c->prof_pool.push_back(p.second.second);
   }
   c->prof_pending.clear();
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < 6; ++k) {
     st->launches[k] = c->prof_launches[k];
     st->ms[k] = c->prof_ms[k];
     if (reset) {

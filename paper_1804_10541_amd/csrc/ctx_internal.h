@@ -152,8 +152,8 @@ struct mfr_ctx {
   bool prof_on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
   std::vector<hipEvent_t> prof_pool;
-  int prof_launches[5] = {0, 0, 0, 0, 0};
-  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int prof_launches[6] = {0, 0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
   ~mfr_ctx() {
     for (auto& p : prof_pending) {
       (void)hipEventDestroy(p.second.first);
@@ -166,6 +166,23 @@ struct mfr_ctx {
 namespace mfr {
 
 mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes);
+// Runs `launch` between two event records when timing is on (slot: kernel id).
+hipEvent_t prof_event(mfr_ctx* c);   // a timing event from the context's pool
+template <class F>
+hipError_t timed(mfr_ctx* c, int slot, F&& launch) {
+  if (!c->prof_on) return launch();
+  hipEvent_t a = prof_event(c), b = prof_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, c->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, c->stream);
+  if (e != hipSuccess) return e;
+  c->prof_pending.push_back({slot, {a, b}});
+  return hipSuccess;
+}
+
 hipError_t enqueue_diag(mfr_ctx* c, const float* u, float* diag);
 hipError_t enqueue_pcg_diag(mfr_ctx* c, const float* u, float* diag);   // zero entries -> 1
 int node_blocks(const mfr_ctx* c);   // work-groups (per component) of a node pass

@@ -257,39 +257,47 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, b
     o.rms_scale[0] = o.rms_scale[1] = 1.0 / pc->n3;
     HIP_TRY(launch_pc_dots(d, o, pc->red, st));
   }
-  // the network input: stored for the first layer's weight gradient in
-  // training, else computed by the first layer itself while it stages a tile
-  if (keep_input) HIP_TRY(launch_pc_features(pc->n, r, diag, pc->gR, pc->sc, pc->h[0], st, live));
-  for (int l = 0; l < kCnnLayers; ++l) {
-    ConvArgs a{};
-    a.nx = pc->nx;
-    a.ny = pc->ny;
-    a.nz = pc->nz;
-    if (l > 0 || keep_input) {
-      a.x = pc->h[l];
-    } else {
-      a.fr = r;
-      a.fdiag = diag;
-      a.fgR = pc->gR;
-      a.fsc = pc->sc;
+  // the network (timed as one record when the context's timing is on)
+  HIP_TRY(timed(pc->c, 5, [&]() -> hipError_t {
+    // the network input: stored for the first layer's weight gradient in
+    // training, else computed by the first layer itself while it stages a tile
+    if (keep_input) {
+      const hipError_t e = launch_pc_features(pc->n, r, diag, pc->gR, pc->sc, pc->h[0], st, live);
+      if (e != hipSuccess) return e;
     }
-    a.live = live;
-    a.w = pc->w16 + (size_t)(kCnnLayers + l) * kCnnWeights;
-    a.w_out_major = 1;
-    a.bias = pc->params + (size_t)l * kCnnLayerParams + kCnnWeights;
-    if (l < kCnnLayers - 1) {
-      a.relu = 1;
-      a.y16 = pc->h[l + 1];
-    } else {
-      a.z = z;
-      a.r = r;
-      a.diag = diag;
-      a.scale = pc->sc + PC_RMS_Y;
-      a.rprev = rprev;
-      a.zred = zred;
+    for (int l = 0; l < kCnnLayers; ++l) {
+      ConvArgs a{};
+      a.nx = pc->nx;
+      a.ny = pc->ny;
+      a.nz = pc->nz;
+      if (l > 0 || keep_input) {
+        a.x = pc->h[l];
+      } else {
+        a.fr = r;
+        a.fdiag = diag;
+        a.fgR = pc->gR;
+        a.fsc = pc->sc;
+      }
+      a.live = live;
+      a.w = pc->w16 + (size_t)(kCnnLayers + l) * kCnnWeights;
+      a.w_out_major = 1;
+      a.bias = pc->params + (size_t)l * kCnnLayerParams + kCnnWeights;
+      if (l < kCnnLayers - 1) {
+        a.relu = 1;
+        a.y16 = pc->h[l + 1];
+      } else {
+        a.z = z;
+        a.r = r;
+        a.diag = diag;
+        a.scale = pc->sc + PC_RMS_Y;
+        a.rprev = rprev;
+        a.zred = zred;
+      }
+      const hipError_t e = launch_cnn_conv(a, st);
+      if (e != hipSuccess) return e;
     }
-    HIP_TRY(launch_cnn_conv(a, st));
-  }
+    return hipSuccess;
+  }));
   return MFR_OK;
 }
 

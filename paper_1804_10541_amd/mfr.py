@@ -70,7 +70,7 @@ class CMlReport(ctypes.Structure):
 
 
 class CProfile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int32 * 5), ("ms", ctypes.c_double * 5)]
+    _fields_ = [("launches", ctypes.c_int32 * 6), ("ms", ctypes.c_double * 6)]
 
 
 class CTileConfig(ctypes.Structure):
@@ -111,7 +111,7 @@ class CLbfgsReport(ctypes.Structure):
                 ("J_final", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
-PROFILE_KERNELS = ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass")
+PROFILE_KERNELS = ("tile_obj", "tile_grad", "tile_hv", "jacobi_diag", "node_pass", "pc_network")
 
 _lib = None
 

@@ -132,6 +132,24 @@ def test_preconditioner_apply_matches_oracle():
     ctx.close()
 
 
+def test_network_application_is_timed_as_one_record():
+    print("[gpu-case] network timing record 40x36x28", flush=True)
+    spec, R, T, u, probes, ctx = _pc_case()
+    pc = mfr.LearnedPC(ctx)
+    tu, r = to_dev(u), to_dev(probes[0])
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    for _ in range(3):
+        pc.apply(tu, r)
+    ctx.hess_vec(tu, r)
+    pr = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    assert pr["pc_network"][0] == 3 and pr["pc_network"][1] > 0.0
+    assert pr["tile_hv"][0] == 1 and pr["jacobi_diag"][0] == 0
+    pc.close()
+    ctx.close()
+
+
 def test_flexible_cg_zero_network_matches_oracle_iterates():
     print("[gpu-case] flexible CG, zero network, 48x44x36", flush=True)
     spec, R, T, u, _, ctx = _pc_case(seed=6, m=(48, 44, 36), my=(13, 12, 10))
