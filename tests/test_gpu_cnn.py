@@ -127,7 +127,10 @@ def test_preconditioner_apply_matches_oracle():
     y = probes[0].astype(np.float64) / d64
     e = rel_l2(z - y, ref - y)
     print(f"[gpu-case] network part rel-L2 {e:.2e}", flush=True)
-    assert e <= 1e-2
+    # measured 1.0e-7 (fp32 accumulation against float64, both rounding the
+    # activations to bf16); 1e-4 leaves room for a few activations that round
+    # to the neighbouring bf16 value on one side only
+    assert e <= 1e-4
     pc.close()
     ctx.close()
 
