@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define MFR_ABI_VERSION 3
+#define MFR_ABI_VERSION 4
 
 /* Regularisers (mfr_grid.regulariser). */
 #define MFR_REG_CURVATURE 0   /* curvature, eq. CURV_discretized (the paper's)                  */
@@ -141,6 +141,17 @@ mfr_status mfr_gradient(mfr_ctx* ctx, const float* u, double* J, float* g);
  * nabla^2 S = 2 hbar^y L^T L (eq. curv_hessMult).
  * q must not alias u or p.  Asynchronous. */
 mfr_status mfr_hess_vec(mfr_ctx* ctx, const float* u, const float* p, float* q);
+
+/* Twins of mfr_objective and mfr_gradient for HIP graph capture (eq.
+ * discreteenergy, eq. gradNGF, as above): the same kernels, with the scalars
+ * written by the device into caller memory instead of returned, so nothing
+ * synchronises or reads back and the calls can be captured together with
+ * mfr_hess_vec and mfr_jacobi_diag.  out: device double[3] = {J, D, S}; J of
+ * mfr_gradient_async: device double[1] or NULL.  Values equal those of the
+ * synchronous calls bit for bit.  A non-finite J is written as it is (the
+ * synchronous calls return MFR_ENONFINITE for it).  Asynchronous. */
+mfr_status mfr_objective_async(mfr_ctx* ctx, const float* u, double* out);
+mfr_status mfr_gradient_async(mfr_ctx* ctx, const float* u, double* J, float* g);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the product

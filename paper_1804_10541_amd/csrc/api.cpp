@@ -1284,6 +1284,32 @@ mfr_status mfr_gradient(mfr_ctx* c, const float* u, double* J, float* g) {
   return MFR_OK;
 }
 
+// The scalars of the last objective or gradient into device memory.
+static mfr_status objective_out(mfr_ctx* c, double* out, int count) {
+  HIP_TRY(launch_objective_out(c->sc + SC_D, c->geo.hbar(), c->geo.s_mul(), c->geo.s_k(), c->geo.alpha, out, count,
+                               c->stream));
+  return MFR_OK;
+}
+
+mfr_status mfr_objective_async(mfr_ctx* c, const float* u, double* out) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  if (!out || reinterpret_cast<uintptr_t>(out) % 8 != 0) return fail(MFR_EINVAL, "out must be an 8-byte aligned device pointer");
+  MFR_TRY(enqueue_objective(c, u));
+  return objective_out(c, out, 3);
+}
+
+mfr_status mfr_gradient_async(mfr_ctx* c, const float* u, double* J, float* g) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(check_ptr(g, "g"));
+  if (g == u) return fail(MFR_EINVAL, "g must not alias u");
+  if (J && reinterpret_cast<uintptr_t>(J) % 8 != 0) return fail(MFR_EINVAL, "J must be an 8-byte aligned device pointer");
+  MFR_TRY(enqueue_gradient(c, u, g));
+  if (J) return objective_out(c, J, 1);
+  return MFR_OK;
+}
+
 mfr_status mfr_hess_vec(mfr_ctx* c, const float* u, const float* p, float* q) {
   MFR_TRY(need_images(c));
   MFR_TRY(check_ptr(u, "u"));

@@ -60,9 +60,9 @@ struct Geo {
   double reg_scale() const {
     return reg == MFR_REG_CURVATURE ? 2.0 * alpha * hybar() : alpha * hybar() * (reg == MFR_REG_ELASTIC ? lame_mu : 1.0);
   }
-  double s_value(double sum) const {
-    return reg == MFR_REG_CURVATURE ? hybar() * sum : 0.5 * hybar() * sum * (reg == MFR_REG_ELASTIC ? lame_mu : 1.0);
-  }
+  double s_mul() const { return reg == MFR_REG_CURVATURE ? hybar() : 0.5 * hybar(); }
+  double s_k() const { return reg == MFR_REG_ELASTIC ? lame_mu : 1.0; }
+  double s_value(double sum) const { return s_mul() * sum * s_k(); }
   double kappa() const { return reg == MFR_REG_ELASTIC ? (lame_lambda + lame_mu) / lame_mu : 0.0; }
 };
 
@@ -167,6 +167,11 @@ namespace mfr {
 
 mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, size_t ws_bytes);
 // Runs `launch` between two event records when timing is on (slot: kernel id).
+// out = {J, D, S} (count 3) or {J} (count 1) from the sums at sums[0] (distance)
+// and sums[1] (regulariser): D = dmul sums[0], S = (smul sums[1]) sk, J = D + alpha S,
+// rounded as Geo::s_value and the host evaluate them (node_kernels.hip)
+hipError_t launch_objective_out(const double* sums, double dmul, double smul, double sk, double alpha, double* out,
+                                int count, hipStream_t st);
 hipEvent_t prof_event(mfr_ctx* c);   // a timing event from the context's pool
 template <class F>
 hipError_t timed(mfr_ctx* c, int slot, F&& launch) {

@@ -279,6 +279,26 @@ hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Objective scalars into caller memory (the graph-capturable entry points):
+// D = dmul sums[0], S = (smul sums[1]) sk, J = D + alpha S; out = {J, D, S} (count
+// 3) or {J} (count 1).  Separate roundings, as the host evaluates them.
+__global__ void objective_out_kernel(const double* __restrict__ sums, double dmul, double smul, double sk,
+                                     double alpha, double* __restrict__ out, int count) {
+  if (threadIdx.x != 0) return;
+  const double D = __dmul_rn(dmul, sums[0]), S = __dmul_rn(__dmul_rn(smul, sums[1]), sk);
+  out[0] = __dadd_rn(D, __dmul_rn(alpha, S));
+  if (count == 3) {
+    out[1] = D;
+    out[2] = S;
+  }
+}
+
+hipError_t launch_objective_out(const double* sums, double dmul, double smul, double sk, double alpha, double* out,
+                                int count, hipStream_t st) {
+  hipLaunchKernelGGL(objective_out_kernel, dim3(1), dim3(64), 0, st, sums, dmul, smul, sk, alpha, out, count);
+  return hipGetLastError();
+}
+
 // Copy T into an (mx + 4) x (my + 4) x (mz + 2 bz) array with a two-cell zero
 // border in x and y and bz cells in z.
 __global__ void pad_template_kernel(const float* __restrict__ T, float* __restrict__ Tp, int mx, int my,

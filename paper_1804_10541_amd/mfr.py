@@ -127,6 +127,8 @@ SIGNATURES = {
     "mfr_objective": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mfr_gradient": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), _VP]),
     "mfr_hess_vec": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mfr_objective_async": (ctypes.c_int, [_VP, _VP, _VP]),
+    "mfr_gradient_async": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mfr_hess_vec_noalloc": (ctypes.c_int, [ctypes.POINTER(CGrid), _VP, _VP, _VP, _VP, _VP, _VP]),
     "mfr_jacobi_diag": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
@@ -250,6 +252,15 @@ def _dev_tensor(x, numel, name, device):
     return ctypes.c_void_p(x.data_ptr())
 
 
+def _f64_tensor(x, numel, name, device):
+    """A contiguous float64 device tensor of numel elements (scalars the device writes)."""
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 torch tensor")
+    if x.device != device or not x.is_contiguous() or x.numel() != numel:
+        raise ValueError(f"{name}: expected a contiguous tensor of {numel} elements on {device}")
+    return ctypes.c_void_p(x.data_ptr())
+
+
 def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -341,6 +352,23 @@ class Context:
                                      ctypes.byref(J) if want_J else None,
                                      _dev_tensor(out, self.nc * self.nbar, "g", self.device)))
         return out, (J.value if want_J else None)
+
+    def objective_async(self, u, out=None):
+        """(J, D, S) written by the device into `out` (float64 [3] on the device);
+        no synchronisation, so the call can be captured in a HIP graph."""
+        out = torch.empty(3, dtype=torch.float64, device=self.device) if out is None else out
+        _check(self.lib.mfr_objective_async(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                            _f64_tensor(out, 3, "out", self.device)))
+        return out
+
+    def gradient_async(self, u, out=None, J=None):
+        """The gradient into `out` and, if `J` (float64 [1] on the device) is
+        given, J(u) written by the device there; no synchronisation."""
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        _check(self.lib.mfr_gradient_async(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                           None if J is None else _f64_tensor(J, 1, "J", self.device),
+                                           _dev_tensor(out, self.nc * self.nbar, "g", self.device)))
+        return out
 
     def hess_vec(self, u, p, out=None):
         out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.mfr_abi_version() == 3
+    assert lib.mfr_abi_version() == 4
 
 
 def _ws(spec):
@@ -79,6 +79,8 @@ def test_null_arguments_rejected(lib):
     assert lib.mfr_workspace_size(None, None) == -1
     assert lib.mfr_objective(None, None, None, None, None) == -1
     assert lib.mfr_hess_vec(None, None, None, None) == -1
+    assert lib.mfr_objective_async(None, None, None) == -1
+    assert lib.mfr_gradient_async(None, None, None, None) == -1
 
 
 def test_distance_field_validation(lib):
