@@ -236,6 +236,8 @@ typedef struct {
  * Synchronises the stream. */
 mfr_status mfr_gn_step(mfr_ctx* ctx, float* u, const mfr_gn_opts* opts, mfr_gn_info* info);
 
+typedef struct mfr_pc mfr_pc;   /* learned preconditioner (see below) */
+
 typedef struct {
   int32_t levels;      /* pyramid levels, 1..8                                     */
   int32_t gn_iters;    /* Gauss-Newton iterations per level                        */
@@ -243,10 +245,18 @@ typedef struct {
   double pcg_rtol;     /* CG relative residual tolerance                            */
   double armijo_c1;    /* sufficient-decrease constant (e.g. 1e-4)                  */
   int32_t armijo_max;  /* step halvings before the line search gives up             */
-  int32_t precond;     /* 0 none, 1 Jacobi                                          */
+  int32_t precond;     /* 0 none, 1 Jacobi, 2 learned (flexible CG with pc)        */
   const float* u_init; /* device [3][n] displacement on the COARSEST deformation
                           grid (mfr_ml_level_grid level 0) the first level starts
                           from; NULL: u = 0 there                                    */
+  mfr_pc* pc;          /* precond 2 (three-dimensional problems): the learned
+                          preconditioner, bound to each level's context in turn,
+                          so its workspace must fit the finest grid; it is left
+                          unbound when the call returns, whatever the outcome
+                          (mfr_pc_bind before its next use).  Ignored for precond 0, 1; the batched path
+                          takes precond 0, 1 only.                                 */
+  int32_t fallback_iters; /* precond 2: CG iterations after which a solve that has
+                          not converged continues as Jacobi-PCG (0: never)         */
 } mfr_ml_opts;
 
 typedef struct {
@@ -411,7 +421,7 @@ mfr_status mfr_batch_register(mfr_batch* b, const mfr_ml_opts* opts, int32_t use
  * tap t = 9 (dz+1) + 3 (dy+1) + (dx+1), then 16 biases. */
 #define MFR_PC_PARAMS (4 * (27 * 16 * 16 + 16))
 
-typedef struct mfr_pc mfr_pc;   /* opaque, bound to one context (grid, stream, images) */
+/* mfr_pc (opaque, bound to one context: grid, stream, images) is declared before mfr_ml_opts. */
 
 /* Device workspace of a preconditioner for `grid`; train != 0 adds the
  * gradient, optimiser and backward buffers. */

@@ -1247,6 +1247,8 @@ mfr_status mfr_create(const mfr_grid* grid, void* hip_stream, void* workspace, s
 void mfr_destroy(mfr_ctx* ctx) {
   // pending copies may still read host memory the context owns
   if (ctx) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx)
+    for (mfr_pc* pc : ctx->bound_pcs) pc_release_context(pc);
   delete ctx;
 }
 
@@ -1484,8 +1486,10 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
   const auto t0 = std::chrono::steady_clock::now();
   if (!o) return fail(MFR_EINVAL, "opts is NULL");
   if (o->gn_iters < 0 || o->pcg_max < 0 || !(o->pcg_rtol >= 0) || !(o->armijo_c1 >= 0 && o->armijo_c1 < 1) ||
-      o->armijo_max < 1 || o->precond < 0 || o->precond > 1)
+      o->armijo_max < 1 || o->precond < 0 || o->precond > 2 || o->fallback_iters < 0)
     return fail(MFR_EINVAL, "invalid multilevel options");
+  if (o->precond == 2 && !o->pc) return fail(MFR_EINVAL, "precond 2 needs opts->pc");
+  if (o->precond == 2) pc_unbind(o->pc);   // unbound whatever the outcome of the call
   MFR_TRY(check_ptr(R, "R"));
   MFR_TRY(check_ptr(T, "T"));
   MFR_TRY(check_ptr(u, "u"));
@@ -1496,9 +1500,10 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
   size_t need = 0;
   MFR_TRY(ml_levels(finest, o->levels, &L, &need));
   if (ws_bytes < need) return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", ws_bytes, need);
+  const int nl = o->levels;
+  if (o->precond == 2) MFR_TRY(pc_check_grid(o->pc, L[nl - 1].geo));   // before any level runs
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace);
-  const int nl = o->levels;
   mfr_ml_report rep{};
 
   // image pyramid (finest level copies the caller's images)
@@ -1548,7 +1553,12 @@ mfr_status mfr_register_multilevel(const mfr_grid* finest, const mfr_ml_opts* o,
       ~Guard() { mfr_destroy(c); }
     } guard{c};
     MFR_TRY(mfr_set_images(c, at<float>(ws, L[l].off_R), at<float>(ws, L[l].off_T)));
-    mfr_gn_opts go{o->pcg_max, o->pcg_rtol, o->precond, o->armijo_c1, o->armijo_max, 0};
+    if (o->precond == 2) {   // unbound again when the level's context is destroyed
+      MFR_TRY(mfr_pc_bind(o->pc, c));
+      MFR_TRY(mfr_attach_pc(c, o->pc));
+    }
+    mfr_gn_opts go{o->pcg_max, o->pcg_rtol, o->precond, o->armijo_c1, o->armijo_max,
+                   o->precond == 2 ? o->fallback_iters : 0};
     int gn_done = 0, pcg_tot = 0, status = 0;
     double Jv = 0.0;
     MFR_TRY(mfr_objective(c, ul, &Jv, nullptr, nullptr));

@@ -144,6 +144,7 @@ struct mfr_ctx {
   int vec_blocks;
   int* ctrl;                     // device-steered CG: [0] active flag, [1..] PcgState
   mfr_pc* pc = nullptr;          // learned preconditioner used by precond = 2
+  std::vector<mfr_pc*> bound_pcs;   // preconditioners bound to this context (unbound when it is destroyed)
   unsigned image_version = 0;    // bumped by mfr_set_images
   // host copies of the L-BFGS initial-matrix tables (cosine matrices, their
   // transposes, eigenvalues); kept here so uploads need no synchronisation
@@ -210,6 +211,12 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, b
                       const float* rprev = nullptr, double* zred = nullptr, const int* live = nullptr,
                       bool keep_input = false);
 float* pc_scratch_vec(mfr_pc* pc);
+// The context of pc is being destroyed: pc is left unbound (mfr_pc_bind again before use).
+void pc_release_context(mfr_pc* pc);
+// Take pc off its context (detached too); mfr_pc_bind before its next use.
+void pc_unbind(mfr_pc* pc);
+// MFR_EINVAL / MFR_ENOMEM unless pc can be bound to a context of geometry g.
+mfr_status pc_check_grid(const mfr_pc* pc, const Geo& g);
 double* pc_red(mfr_pc* pc);
 double* pc_scalars(mfr_pc* pc);
 int pc_conv_blocks(const mfr_pc* pc);

@@ -207,6 +207,23 @@ mfr_status check_pc(const mfr_pc* pc) {
   return MFR_OK;
 }
 
+// A preconditioner whose context was destroyed has none until it is bound again.
+mfr_status check_bound(const mfr_pc* pc) {
+  MFR_TRY(check_pc(pc));
+  if (!pc->c) return fail(MFR_EINVAL, "the preconditioner's context was destroyed; bind it with mfr_pc_bind first");
+  return MFR_OK;
+}
+
+// Take pc off the context it is bound to (and attached to, if it is).
+void unlink_pc(mfr_pc* pc) {
+  mfr_ctx* c = pc->c;
+  if (!c) return;
+  if (c->pc == pc) c->pc = nullptr;
+  auto& v = c->bound_pcs;
+  v.erase(std::remove(v.begin(), v.end(), pc), v.end());
+  pc->c = nullptr;
+}
+
 mfr_status check_grid_dims(int nx, int ny, int nz) {
   if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz >= (1LL << 26))
     return fail(MFR_EINVAL, "node grid %d x %d x %d out of range", nx, ny, nz);
@@ -302,6 +319,18 @@ mfr_status pc_forward(mfr_pc* pc, const float* r, const float* diag, float* z, b
 }
 
 float* pc_scratch_vec(mfr_pc* pc) { return pc->vtmp; }
+void pc_release_context(mfr_pc* pc) { pc->c = nullptr; }
+void pc_unbind(mfr_pc* pc) { unlink_pc(pc); }
+
+mfr_status pc_check_grid(const mfr_pc* pc, const Geo& g) {
+  MFR_TRY(check_pc(pc));
+  if (g.dim == 2) return fail(MFR_EINVAL, "the learned preconditioner takes three-dimensional problems only");
+  const size_t need = pc_layout(g, pc->train).total;
+  if (pc->ws_bytes < need)
+    return fail(MFR_ENOMEM, "preconditioner workspace of %zu bytes is smaller than the %zu the grid needs", pc->ws_bytes,
+                need);
+  return MFR_OK;
+}
 double* pc_scalars(mfr_pc* pc) { return pc->sc; }
 int pc_conv_blocks(const mfr_pc* pc) { return cnn_conv_blocks(pc->nx, pc->ny, pc->nz); }
 double* pc_red(mfr_pc* pc) { return pc->red; }
@@ -331,9 +360,12 @@ mfr_status bind_pc(mfr_pc* pc, mfr_ctx* c) {
   const PcLayout L = pc_layout(g, pc->train);
   if (pc->ws_bytes < L.total)
     return fail(MFR_ENOMEM, "workspace of %zu bytes is smaller than the required %zu", pc->ws_bytes, L.total);
-  if (pc->c && pc->c != c && pc->c->pc == pc) pc->c->pc = nullptr;
+  if (pc->c != c) {
+    unlink_pc(pc);
+    c->bound_pcs.push_back(pc);
+    pc->c = c;
+  }
   char* ws = pc->ws;
-  pc->c = c;
   pc->nx = g.n[0];
   pc->ny = g.n[1];
   pc->nz = g.n[2];
@@ -434,12 +466,12 @@ mfr_status mfr_pc_bind(mfr_pc* pc, mfr_ctx* c) {
 }
 
 void mfr_pc_destroy(mfr_pc* pc) {
-  if (pc && pc->c && pc->c->pc == pc) pc->c->pc = nullptr;
+  if (pc) unlink_pc(pc);
   delete pc;
 }
 
 mfr_status mfr_pc_set_params(mfr_pc* pc, const float* params) {
-  MFR_TRY(check_pc(pc));
+  MFR_TRY(check_bound(pc));
   if (!params) return fail(MFR_EINVAL, "params is NULL");
   for (int i = 0; i < kCnnParams; ++i)
     if (!std::isfinite(params[i])) return fail(MFR_ENONFINITE, "parameter %d is not finite", i);
@@ -456,7 +488,7 @@ mfr_status mfr_pc_set_params(mfr_pc* pc, const float* params) {
 }
 
 mfr_status mfr_pc_get_params(mfr_pc* pc, float* params) {
-  MFR_TRY(check_pc(pc));
+  MFR_TRY(check_bound(pc));
   if (!params) return fail(MFR_EINVAL, "params is NULL");
   HIP_TRY(hipMemcpyAsync(params, pc->params, sizeof(float) * kCnnParams, hipMemcpyDeviceToHost, st_of(pc)));
   HIP_TRY(hipStreamSynchronize(st_of(pc)));
@@ -464,7 +496,7 @@ mfr_status mfr_pc_get_params(mfr_pc* pc, float* params) {
 }
 
 mfr_status mfr_pc_apply(mfr_pc* pc, const float* u, const float* r, float* z) {
-  MFR_TRY(check_pc(pc));
+  MFR_TRY(check_bound(pc));
   MFR_TRY(check_ptr(u, "u"));
   MFR_TRY(check_ptr(r, "r"));
   MFR_TRY(check_ptr(z, "z"));
@@ -476,7 +508,7 @@ mfr_status mfr_pc_apply(mfr_pc* pc, const float* u, const float* r, float* z) {
 
 mfr_status mfr_pc_train_system(mfr_pc* pc, const float* u, const float* b, const mfr_pc_train_opts* o,
                                mfr_pc_train_info* info) {
-  MFR_TRY(check_pc(pc));
+  MFR_TRY(check_bound(pc));
   if (!pc->train) return fail(MFR_EINVAL, "preconditioner was created without training buffers");
   MFR_TRY(check_ptr(u, "u"));
   MFR_TRY(check_ptr(b, "b"));

@@ -60,7 +60,8 @@ class CGnInfo(ctypes.Structure):
 class CMlOpts(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32), ("pcg_max", ctypes.c_int32),
                 ("pcg_rtol", ctypes.c_double), ("armijo_c1", ctypes.c_double), ("armijo_max", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("u_init", ctypes.c_void_p)]
+                ("precond", ctypes.c_int32), ("u_init", ctypes.c_void_p), ("pc", ctypes.c_void_p),
+                ("fallback_iters", ctypes.c_int32)]
 
 
 class CMlReport(ctypes.Structure):
@@ -456,9 +457,12 @@ def ml_level_grid(spec, levels, level):
 
 
 def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=1e-3, armijo_c1=1e-4,
-                        armijo_max=10, precond=1, u0=None, device="cuda:0"):
+                        armijo_max=10, precond=1, u0=None, device="cuda:0", pc=None, fallback_iters=0):
     """Coarse-to-fine Gauss-Newton registration; returns (u_finest, report dict).
-    ``u0``: initial displacement on the COARSEST deformation grid (None: 0)."""
+    ``u0``: initial displacement on the COARSEST deformation grid (None: 0).
+    ``pc`` (precond 2): a LearnedPC whose workspace fits the finest grid; the
+    library binds it to each level in turn and leaves it unbound (``pc.bind``
+    before its next use)."""
     lib = load()
     device = torch.device(device)
     g = make_grid(spec)
@@ -474,8 +478,12 @@ def register_multilevel(spec, R, T, levels=3, gn_iters=10, pcg_max=50, pcg_rtol=
     if u0 is not None:
         gc = ml_level_grid(spec, levels, 0)
         init = _dev_tensor(u0, node_count(gc.m, gc.my), "u0", device)
+    if int(precond) == 2 and pc is None:
+        raise ValueError("precond 2 needs a LearnedPC (pc=...)")
     opts = CMlOpts(int(levels), int(gn_iters), int(pcg_max), float(pcg_rtol), float(armijo_c1), int(armijo_max),
-                   int(precond), init)
+                   int(precond), init, None if pc is None else pc._h, int(fallback_iters))
+    if pc is not None and int(precond) == 2:
+        pc._unbind()   # the library moves it through the levels' contexts
     rep = CMlReport()
     _check(lib.mfr_register_multilevel(ctypes.byref(g), ctypes.byref(opts), _stream(device), ctypes.c_void_p(ptr),
                                        n.value, _dev_tensor(R, mbar, "R", device),
@@ -674,10 +682,21 @@ class LearnedPC:
 
     def bind(self, ctx):
         """Move to another context (parameters and optimiser state are kept)."""
-        if getattr(self.ctx, "_pc", None) is self:
+        if self.ctx is not None and getattr(self.ctx, "_pc", None) is self:
             self.ctx.attach_pc(None)
         _check(self.lib.mfr_pc_bind(self._h, ctx._h))
         self.ctx = ctx
+
+    def _bound_ctx(self):
+        if self.ctx is None:
+            raise MfrError(-1, "the preconditioner is not bound to a context; call bind(ctx) first")
+        return self.ctx
+
+    def _unbind(self):
+        # the library takes the preconditioner off its context (multilevel runs)
+        if self.ctx is not None and getattr(self.ctx, "_pc", None) is self:
+            self.ctx._pc = None
+        self.ctx = None
 
     def set_params(self, params):
         import numpy as np
@@ -695,7 +714,7 @@ class LearnedPC:
         return a
 
     def apply(self, u, r, out=None):
-        c = self.ctx
+        c = self._bound_ctx()
         out = torch.empty(c.node_shape(), dtype=torch.float32, device=c.device) if out is None else out
         _check(self.lib.mfr_pc_apply(self._h, _dev_tensor(u, 3 * c.nbar, "u", c.device),
                                      _dev_tensor(r, 3 * c.nbar, "r", c.device),
@@ -703,7 +722,7 @@ class LearnedPC:
         return out
 
     def train_system(self, u, b, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, pcg_iters=20, sample_every=4):
-        c = self.ctx
+        c = self._bound_ctx()
         opts = CPcTrainOpts(float(lr), float(beta1), float(beta2), float(eps), int(pcg_iters), int(sample_every))
         info = CPcTrainInfo()
         _check(self.lib.mfr_pc_train_system(self._h, _dev_tensor(u, 3 * c.nbar, "u", c.device),

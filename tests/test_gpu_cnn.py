@@ -211,3 +211,45 @@ def test_training_lowers_loss_and_fallback_switches():
     ctx.attach_pc(None)
     pc.close()
     ctx.close()
+
+
+
+def test_preconditioner_capacity_and_context_lifetime():
+    print("[gpu-case] preconditioner capacity / context lifetime 64x60x48 and 24x24x16", flush=True)
+    spec, R, T, u, _ = ct_case(12, (64, 60, 48), (17, 16, 13), amp=0.5, n_probes=0)
+    tR, tT = to_dev(R), to_dev(T)
+    ctx = mfr.Context(spec, DEV)
+    ctx.set_images(tR, tT)
+    # a workspace sized for a coarser grid is refused before any level runs
+    cspec, cR, cT, _, _ = ct_case(13, (24, 24, 16), (7, 7, 5), amp=0.5, n_probes=0)
+    cctx = mfr.Context(cspec, DEV)
+    cctx.set_images(to_dev(cR), to_dev(cT))
+    small = mfr.LearnedPC(cctx)
+    with pytest.raises(mfr.MfrError, match="ENOMEM"):
+        mfr.register_multilevel(spec, tR, tT, levels=3, gn_iters=1, precond=2, pc=small)
+    # the call leaves it unbound whatever its outcome; binding again restores it
+    cu, cr = to_dev(np.zeros((3, 5, 7, 7), np.float32)), to_dev(np.ones((3, 5, 7, 7), np.float32))
+    with pytest.raises(mfr.MfrError):
+        small.apply(cu, cr)
+    small.bind(cctx)
+    assert torch.equal(small.apply(cu, cr), cr / cctx.jacobi_diag(cu))
+    # destroying its context leaves a preconditioner unbound, not dangling
+    cctx.close()
+    with pytest.raises(mfr.MfrError, match="bind"):
+        _check_unbound_apply(small, cu, cr)
+    cctx2 = mfr.Context(cspec, DEV)
+    cctx2.set_images(to_dev(cR), to_dev(cT))
+    small.bind(cctx2)
+    assert torch.equal(small.apply(cu, cr), cr / cctx2.jacobi_diag(cu))
+    small.close()
+    cctx2.close()
+    ctx.close()
+
+
+def _check_unbound_apply(pc, u, r):
+    """mfr_pc_apply through the C ABI on a preconditioner whose context is gone."""
+    import ctypes
+    z = torch.empty_like(r)
+    st = pc.lib.mfr_pc_apply(pc._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                             ctypes.c_void_p(z.data_ptr()))
+    mfr._check(st)

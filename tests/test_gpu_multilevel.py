@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_cases import DEV, rel_l2
+from gpu_cases import DEV, ct_case, rel_l2, to_dev
 from oracle import Grid, interp, multilevel, solver
 from paper_1804_10541_amd import mfr
 from synth import GridSpec, config_c2
@@ -259,4 +259,54 @@ def test_config2_finest_level_first_three_pcg_iterates(c2_run):
         assert info["iters"] == k == oi["iters"]
         assert e <= 1e-4
         assert abs(info["relres"] - oi["relres"]) <= 1e-4 * oi["relres"]
+    ctx.close()
+
+
+def test_driver_with_learned_preconditioner_equals_public_calls():
+    """precond 2: the driver binds the preconditioner to each level's context
+    and runs flexible CG; the same public calls give the same result bit for bit."""
+    print("[gpu-case] multilevel precond 2, 3 levels, 64x60x48 / 17x16x13: driver and public calls", flush=True)
+    spec, R, T, _, _ = ct_case(12, (64, 60, 48), (17, 16, 13), amp=0.5, n_probes=0)
+    tR, tT = to_dev(R), to_dev(T)
+    ctx = mfr.Context(spec, DEV)
+    ctx.set_images(tR, tT)
+    pc = mfr.LearnedPC(ctx)
+    rng = np.random.default_rng(21)
+    params = (0.02 * rng.standard_normal(mfr.PC_PARAMS)).astype(np.float32)
+    pc.set_params(params)
+    opts = dict(pcg_max=40, pcg_rtol=1e-3, precond=2, armijo_c1=1e-4, armijo_max=10, fallback_iters=30)
+    levels, iters = 3, 4
+    u_drv, rep = mfr.register_multilevel(spec, tR, tT, levels=levels, gn_iters=iters, pc=pc, **opts)
+    grids = [mfr.ml_level_grid(spec, levels, lv) for lv in range(levels)]
+    Rs, Ts = [tR], [tT]
+    for _ in range(levels - 1):
+        Rs.append(mfr.restrict_image(Rs[-1]))
+        Ts.append(mfr.restrict_image(Ts[-1]))
+    Rs, Ts = Rs[::-1], Ts[::-1]
+    u, Jends, dones = None, [], []
+    for lv in range(levels):
+        g = grids[lv]
+        u = torch.zeros((3, g.my[2], g.my[1], g.my[0]), dtype=torch.float32, device=DEV) if u is None else \
+            mfr.prolong(u, grids[lv - 1], g)
+        c = mfr.Context(spec_of(g), DEV)
+        c.set_images(Rs[lv], Ts[lv])
+        pc.bind(c)
+        c.attach_pc(pc)
+        J, done = c.objective(u)[0], 0
+        for _ in range(iters):
+            info = c.gn_step(u, **opts)
+            if not info["accepted"]:
+                break
+            J, done = info["J_after"], done + 1
+        Jends.append(J)
+        dones.append(done)
+        c.attach_pc(None)
+        c.close()
+    torch.cuda.synchronize()
+    print(f"[gpu-case] per level J {rep['J_level']} gn {rep['gn_done']} pcg {rep['pcg_total']}", flush=True)
+    assert rep["gn_done"] == dones and rep["J_level"] == Jends
+    assert torch.equal(u_drv, u)
+    for lv in range(levels):
+        assert rep["J_level"][lv] < rep["J_start"][lv]
+    pc.close()
     ctx.close()
