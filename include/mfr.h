@@ -149,7 +149,9 @@ mfr_status mfr_hess_vec(mfr_ctx* ctx, const float* u, const float* p, float* q);
  * mfr_hess_vec and mfr_jacobi_diag.  out: device double[3] = {J, D, S}; J of
  * mfr_gradient_async: device double[1] or NULL.  Values equal those of the
  * synchronous calls bit for bit.  A non-finite J is written as it is (the
- * synchronous calls return MFR_ENONFINITE for it).  Asynchronous. */
+ * synchronous calls return MFR_ENONFINITE for it).  A captured graph uses the
+ * context's workspace: replay it on the context's stream (or ordered with
+ * it), never while other calls on the context run.  Asynchronous. */
 mfr_status mfr_objective_async(mfr_ctx* ctx, const float* u, double* out);
 mfr_status mfr_gradient_async(mfr_ctx* ctx, const float* u, double* J, float* g);
 

@@ -377,7 +377,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.dpart = take(dg.on ? sizeof(float) * (size_t)dg.grid() * 3 * dg.nzt * dg.nyt * dg.nxt : 0);
   L.red_tile = take(sizeof(double) * (size_t)t.grid());
   const size_t node_blocks = (g.nbar + kNodeBlock - 1) / kNodeBlock;
-  L.n_red_node = std::max<size_t>(3 * node_blocks, 2 * 1024);   // the node pass: one partial per block and component
+  L.n_red_node = std::max<size_t>(3 * node_blocks, 2 * 1024);   // node-pass partials (one per block) and others
   L.red_node = take(sizeof(double) * L.n_red_node);
   L.sc = take(sizeof(double) * SC_COUNT);
   L.vec = take(sizeof(float) * nc * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
@@ -902,7 +902,7 @@ hipError_t enqueue_pcg_diag(mfr_ctx* c, const float* u, float* diag) {
 }
 
 int node_blocks(const mfr_ctx* c) { return (int)((c->geo.nbar + kNodeBlock - 1) / kNodeBlock); }
-int node_parts(const mfr_ctx* c) { return c->geo.nc() * node_blocks(c); }
+int node_parts(const mfr_ctx* c) { return node_blocks(c); }   // one partial per block (all components)
 
 mfr_status check_ptr(const void* p, const char* name) {
   if (!p) return fail(MFR_EINVAL, "%s is NULL", name);

@@ -128,12 +128,13 @@ __device__ __forceinline__ void lap_body(const NodeParams& Q, const float* __res
   }
 }
 
-// One thread per node and component d (work-group row d): q_d = s_ngf * (sum of
-// the tile partials) + s_curv * (L L f_d).  Partials: red[d * nb + blk].
+// One thread per node, all its components d: q_d = s_ngf * (sum of the tile
+// partials of component d) + s_curv * (L L f_d).  The node's indices and the
+// walk over the tile slots that overlap it are formed once for all components.
+// Partials: red[blk] (the components summed in order within the thread).
 template <int MODE>
 __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float* __restrict__ f,
-                                               float* __restrict__ out, const int blk, const int nb, const int d,
-                                               double* sred) {
+                                               float* __restrict__ out, const int blk, double* sred) {
   const int n = blk * kNodeBlock + threadIdx.x;
   double local = 0.0;
   if (n < Q.nbar) {
@@ -141,56 +142,67 @@ __device__ __forceinline__ void node_pass_body(const NodeParams& Q, const float*
     const int j = (n / Q.nx) % Q.ny;
     const int k = n / (Q.nx * Q.ny);
     const int nxy = Q.nx * Q.ny;
-    const float* fd = f + (size_t)d * Q.nbar;
-    const float* Ld = Q.lap + (size_t)d * Q.nbar;
-    const float L0 = Ld[n];
-    const float Lxm = i > 0 ? Ld[n - 1] : L0;
-    const float Lxp = i < Q.nx - 1 ? Ld[n + 1] : L0;
-    const float Lym = j > 0 ? Ld[n - Q.nx] : L0;
-    const float Lyp = j < Q.ny - 1 ? Ld[n + Q.nx] : L0;
-    const float Lzm = k > 0 ? Ld[n - nxy] : L0;
-    const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
-    const float m2 = -2.0f * L0;
-    // curvature: L L f; diffusive: -L f (its Hessian is -hbar^y L); elastic: -L f + kappa (B^T B f)_d
-    float LL = Q.reg ? -L0 : fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
-    if (Q.reg == 2) {
-      const int cx = Q.nx - 1, cy = Q.ny - 1;
-      const int nd = d == 0 ? i : d == 1 ? j : k;
-      const float ih4 = 0.25f * sqrtf(d == 0 ? Q.ihy2x : d == 1 ? Q.ihy2y : Q.ihy2z);
-      float bt = 0.f;
-      for (int c = max(k - 1, 0); c <= min(k, Q.nz - 2); ++c)
-        for (int b = max(j - 1, 0); b <= min(j, Q.ny - 2); ++b)
-          for (int a = max(i - 1, 0); a <= min(i, Q.nx - 2); ++a) {
-            const int cd = d == 0 ? a : d == 1 ? b : c;
-            const float dv = Q.div[a + cx * (b + cy * c)];
-            bt += cd == nd - 1 ? dv : -dv;   // the node is the upper (+) or lower (-) corner along d
-          }
-      LL = fmaf(Q.kappa * ih4, bt, LL);
-    }
+    const size_t nb3 = (size_t)Q.nbar;
     // gather of the transposed conversion: every tile slot overlapping node n
     // (the groups overlapping a node have distinct slots: at most smx of them
     // along x, and so on)
     const Range1 rx = Q.ntx[i], ry = Q.nty[j], rz = Q.ntz[k];
-    float s = 0.0f;
-    for (int cz = rz.lo; cz <= rz.hi; ++cz) {
-      for (int cy = ry.lo; cy <= ry.hi; ++cy) {
-        for (int cx = rx.lo; cx <= rx.hi; ++cx) {
-          const size_t ps = ((size_t)(cz % Q.smz) * Q.smy + cy % Q.smy) * Q.smx + cx % Q.smx;
-          s += Q.part[(ps * 3 + d) * Q.nbar + n];
+    // slot indices c % sm advance with c (one remainder per axis)
+    float sg[3] = {0.0f, 0.0f, 0.0f};
+    const int sx0 = rx.lo % Q.smx, sy0 = ry.lo % Q.smy;
+    for (int cz = rz.lo, sz = rz.lo % Q.smz; cz <= rz.hi; ++cz, sz = sz + 1 == Q.smz ? 0 : sz + 1) {
+      for (int cy = ry.lo, sy = sy0; cy <= ry.hi; ++cy, sy = sy + 1 == Q.smy ? 0 : sy + 1) {
+        const size_t pzy = (size_t)sz * Q.smy + sy;
+        for (int cx = rx.lo, sx = sx0; cx <= rx.hi; ++cx, sx = sx + 1 == Q.smx ? 0 : sx + 1) {
+          const float* pp = Q.part + (pzy * Q.smx + sx) * 3 * nb3 + n;
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            if (d < Q.nc) sg[d] += pp[d * nb3];
         }
       }
     }
-    const float q = fmaf(Q.s_ngf, s, Q.s_curv * LL);
-    out[(size_t)d * Q.nbar + n] = q;
-    if (MODE == NP_GRAD) {
-      local = Q.reg ? (double)fwd_sq(fd, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z) : (double)L0 * (double)L0;
-      if (Q.reg == 2 && d == 0 && n < (Q.nx - 1) * (Q.ny - 1) * (Q.nz - 1))
-        local += (double)Q.kappa * (double)Q.div[n] * (double)Q.div[n];   // once per cell (component row 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d >= Q.nc) break;
+      const float* fd = f + (size_t)d * nb3;
+      const float* Ld = Q.lap + (size_t)d * nb3;
+      const float L0 = Ld[n];
+      const float Lxm = i > 0 ? Ld[n - 1] : L0;
+      const float Lxp = i < Q.nx - 1 ? Ld[n + 1] : L0;
+      const float Lym = j > 0 ? Ld[n - Q.nx] : L0;
+      const float Lyp = j < Q.ny - 1 ? Ld[n + Q.nx] : L0;
+      const float Lzm = k > 0 ? Ld[n - nxy] : L0;
+      const float Lzp = k < Q.nz - 1 ? Ld[n + nxy] : L0;
+      const float m2 = -2.0f * L0;
+      // curvature: L L f; diffusive: -L f (its Hessian is -hbar^y L); elastic: -L f + kappa (B^T B f)_d
+      float LL = Q.reg ? -L0 : fmaf(Lxm + Lxp + m2, Q.ihy2x, fmaf(Lym + Lyp + m2, Q.ihy2y, (Lzm + Lzp + m2) * Q.ihy2z));
+      if (Q.reg == 2) {
+        const int cx = Q.nx - 1, cy = Q.ny - 1;
+        const int nd = d == 0 ? i : d == 1 ? j : k;
+        const float ih4 = 0.25f * sqrtf(d == 0 ? Q.ihy2x : d == 1 ? Q.ihy2y : Q.ihy2z);
+        float bt = 0.f;
+        for (int c = max(k - 1, 0); c <= min(k, Q.nz - 2); ++c)
+          for (int b = max(j - 1, 0); b <= min(j, Q.ny - 2); ++b)
+            for (int a = max(i - 1, 0); a <= min(i, Q.nx - 2); ++a) {
+              const int cd = d == 0 ? a : d == 1 ? b : c;
+              const float dv = Q.div[a + cx * (b + cy * c)];
+              bt += cd == nd - 1 ? dv : -dv;   // the node is the upper (+) or lower (-) corner along d
+            }
+        LL = fmaf(Q.kappa * ih4, bt, LL);
+      }
+      const float q = fmaf(Q.s_ngf, sg[d], Q.s_curv * LL);
+      out[(size_t)d * nb3 + n] = q;
+      if (MODE == NP_GRAD) {
+        local += Q.reg ? (double)fwd_sq(fd, i, j, k, Q.nx, Q.ny, Q.nz, Q.ihy2x, Q.ihy2y, Q.ihy2z)
+                       : (double)L0 * (double)L0;
+        if (Q.reg == 2 && d == 0 && n < (Q.nx - 1) * (Q.ny - 1) * (Q.nz - 1))
+          local += (double)Q.kappa * (double)Q.div[n] * (double)Q.div[n];   // once per cell (component row 0)
+      }
+      if (MODE == NP_HV) local += (double)fd[n] * (double)q;
     }
-    if (MODE == NP_HV) local = (double)fd[n] * (double)q;
   }
   const double s = block_sum<kNodeBlock>(local, sred);
-  if (threadIdx.x == 0) Q.red[(size_t)d * nb + blk] = s;
+  if (threadIdx.x == 0) Q.red[blk] = s;
 }
 
 template <int MODE>
@@ -216,7 +228,7 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_kernel(const NodeParams 
                                                                float* __restrict__ out) {
   if (Q.live && !ld_coherent(Q.live)) return;   // a device-steered solve has stopped
   __shared__ double sred[kNodeBlock / 64];
-  node_pass_body<MODE>(Q, f, out, blockIdx.x, gridDim.x, blockIdx.y, sred);
+  node_pass_body<MODE>(Q, f, out, blockIdx.x, sred);
 }
 
 // The same per-node arithmetic for a table of problems (batched path).
@@ -227,8 +239,7 @@ __global__ __launch_bounds__(kNodeBlock) void node_pass_batch_kernel(const NodeJ
   while (pr + 1 < J.n && J.prefix[pr + 1] <= (int)blockIdx.x) ++pr;
   if (J.active && !ld_coherent(J.active + pr)) return;
   const NodeJob& jb = J.jobs[pr];
-  node_pass_body<MODE>(jb.q, jb.f, jb.out, blockIdx.x - J.prefix[pr], J.prefix[pr + 1] - J.prefix[pr], blockIdx.y,
-                       sred);
+  node_pass_body<MODE>(jb.q, jb.f, jb.out, blockIdx.x - J.prefix[pr], sred);
 }
 
 hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
@@ -241,9 +252,9 @@ hipError_t launch_node_pass_batch(int mode, const NodeJobs& j, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == NP_GRAD)
-    hipLaunchKernelGGL(node_pass_batch_kernel<NP_GRAD>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, j);
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
   else
-    hipLaunchKernelGGL(node_pass_batch_kernel<NP_HV>, dim3(blocks, 3), dim3(kNodeBlock), 0, st, j);
+    hipLaunchKernelGGL(node_pass_batch_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, j);
   return hipGetLastError();
 }
 
@@ -258,9 +269,9 @@ hipError_t launch_node_pass(int mode, const NodeParams& q, const float* f, float
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == NP_GRAD)
-    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks, q.nc), dim3(kNodeBlock), 0, st, q, f, out);
+    hipLaunchKernelGGL(node_pass_kernel<NP_GRAD>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
   else
-    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks, q.nc), dim3(kNodeBlock), 0, st, q, f, out);
+    hipLaunchKernelGGL(node_pass_kernel<NP_HV>, dim3(blocks), dim3(kNodeBlock), 0, st, q, f, out);
   return hipGetLastError();
 }
 

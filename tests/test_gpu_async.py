@@ -64,10 +64,11 @@ def test_captured_graph_replays_to_eager_results():
             tu.copy_(to_dev(u * (1.0 + 0.1 * k)))
             tp.copy_(to_dev(probes[k % 3] + 0.01 * rng.standard_normal(probes[0].shape).astype(np.float32)))
             sc.fill_(np.nan)
+            # on the context's stream: a replay on another stream would race with
+            # the eager calls below for the context's workspace
+            graph.replay()
+            got = (sc.clone(), g.clone(), q.clone(), d.clone())
         s.synchronize()
-        graph.replay()
-        s.synchronize()
-        got = (sc.clone(), g.clone(), q.clone(), d.clone())
         with torch.cuda.stream(s):
             J, D, S = ctx.objective(tu)
             g_ref, Jg = ctx.gradient(tu)
