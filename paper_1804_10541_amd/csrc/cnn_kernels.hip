@@ -97,6 +97,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   constexpr int kWPer = (kWChunks + 255) / 256;
   constexpr int kXChunks = kHz * kHy * kHx * 2;
   constexpr int kXPer = (kXChunks + 255) / 256;
+  constexpr unsigned kNowhere = 0x80000000u;   // past every array here (< 2^26 nodes of 32 bytes)
+  const __amdgpu_buffer_rsrc_t rx = raw_buffer(reinterpret_cast<const float*>(a.x), (unsigned)nn * 32u);
 
   // weight chunk q of this thread: its tap, or -1 for the zero half
   auto w_tap = [&](int q) {
@@ -139,6 +141,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   const int tnx = (nx + kTx - 1) / kTx, tny = (ny + kTy - 1) / kTy, tnz = (nz + kTz - 1) / kTz;
   const int tiles = tnx * tny * tnz;
   bool first = true;
+#pragma clang loop unroll(disable)
   for (int tile = xcd_block_id(); tile < tiles; tile += gridDim.x) {
     const int x0 = (tile % tnx) * kTx, y0 = ((tile / tnx) % tny) * kTy, z0 = (tile / (tnx * tny)) * kTz;
     // all loads first (the weights with the first tile), then the LDS stores:
@@ -152,8 +155,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
         if (q < kWChunks) {
           const int t = w_tap(q);
           if (t >= 0)
-            wv[k] = *reinterpret_cast<const uint4*>(a.w + (size_t)(transpose ? kTaps - 1 - t : t) * kCh * kCh +
-                                                    (q % 16) * kCh + 8 * ((q / 16) % 2));
+            wv[k] = *reinterpret_cast<const uint4*>(a.w + ((unsigned)(transpose ? kTaps - 1 - t : t) * kCh * kCh +
+                                                            (q % 16) * kCh + 8 * ((q / 16) % 2)));
         }
       }
     }
@@ -182,20 +185,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
         }
       }
     }
+    // halo chunks through a buffer descriptor: a chunk outside the grid gets an
+    // offset past the array's end, for which the hardware returns zeros
     uint4 v[kXPer];
 #pragma unroll
     for (int k = 0; k < (kFeat ? 0 : kXPer); ++k) {
       const int q = tid + 256 * k;
-      v[k] = make_uint4(0u, 0u, 0u, 0u);
-      if (q < kXChunks) {
-        const int half = q & 1, rest = q >> 1;
-        const int lx = rest % kHx, ly = (rest / kHx) % kHy, lz = rest / (kHx * kHy);
-        const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
-        if (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) {
-          const size_t node = ((size_t)zz * a.ny + yy) * a.nx + xx;
-          v[k] = *reinterpret_cast<const uint4*>(a.x + node * kCh + 8 * half);
-        }
-      }
+      const int half = q & 1, rest = q >> 1;
+      const int lx = rest % kHx, ly = (rest / kHx) % kHy, lz = rest / (kHx * kHy);
+      const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
+      const bool ok = q < kXChunks && (unsigned)xx < (unsigned)nx && (unsigned)yy < (unsigned)ny &&
+                      (unsigned)zz < (unsigned)nz;
+      const unsigned off = ok ? (unsigned)((zz * ny + yy) * nx + xx) * 32u + 16u * half : kNowhere;
+      v[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)off, 0, 0));
     }
     if (first && (transpose || out_major)) {
 #pragma unroll
@@ -244,9 +246,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       }
     }
     __syncthreads();
+    // row s first receives pair 0, dy = -1 at staged row s: that MFMA starts from 0
     f32x4 acc[kTy];
-#pragma unroll
-    for (int i = 0; i < kTy; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
       // this lane's (dz, dx): the first or second member of the pair; the zero
@@ -259,7 +261,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
 #pragma unroll
       for (int s = 0; s < kHy; ++s) {
         const uint4 b = *reinterpret_cast<const uint4*>(brow + s * (2 * kHx * 8));
-        if (s < kTy) acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a0), as_bf16x8(b), acc[s], 0, 0, 0);
+        if (s < kTy)
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a0), as_bf16x8(b), p == 0 ? zero4 : acc[s], 0, 0, 0);
         if (s >= 1 && s <= kTy)
           acc[s - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a1), as_bf16x8(b), acc[s - 1], 0, 0, 0);
         if (s >= 2)
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
       const int x = x0 + col, z = z0 + wave;
       const int rows = min(kTy, ny - y0);   // wave-uniform
       if (x < nx && z < nz) {
-        int node = (z * ny + y0) * nx + x;
+        unsigned node = (unsigned)((z * ny + y0) * nx + x);
 #pragma unroll
         for (int i = 0; i < kTy; ++i, node += nx) {
           if (i >= rows) break;
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
             if (kRelu || (kMode == kGeneric && a.relu)) v[r] = fmaxf(v[r], 0.f);
           }
           if (kMode == kBwd || (kMode == kGeneric && a.mask)) {
-            const uint2 mk = *reinterpret_cast<const uint2*>(a.mask + (size_t)node * kCh + 4 * quad);
+            const uint2 mk = *reinterpret_cast<const uint2*>(a.mask + (node * kCh + 4 * quad));
             const uint16_t mh[4] = {(uint16_t)(mk.x & 0xffff), (uint16_t)(mk.x >> 16), (uint16_t)(mk.y & 0xffff),
                                     (uint16_t)(mk.y >> 16)};
 #pragma unroll
@@ -326,11 +329,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
             // round to nearest even in hardware (the same rounding as f2bf for non-NaN values)
             const bf16x2 lo = __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2);
             const bf16x2 hi = __builtin_convertvector((f32x2){v[2], v[3]}, bf16x2);
-            *reinterpret_cast<uint2*>(a.y16 + (size_t)node * kCh + 4 * quad) =
+            *reinterpret_cast<uint2*>(a.y16 + (node * kCh + 4 * quad)) =
                 make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
           }
           if (kMode == kGeneric && a.y32)
-            *reinterpret_cast<float4*>(a.y32 + (size_t)node * kCh + 4 * quad) = make_float4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<float4*>(a.y32 + (node * kCh + 4 * quad)) = make_float4(v[0], v[1], v[2], v[3]);
         }
       }
     }
