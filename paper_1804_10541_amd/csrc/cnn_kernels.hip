@@ -22,6 +22,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
 typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+typedef short __attribute__((ext_vector_type(2))) s16x2;
 
 constexpr int kTaps = 27;
 constexpr int kCh = 16;
@@ -95,10 +96,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   __shared__ __align__(16) uint16_t xs[kHz][kHy][2][kHx][8];
   constexpr int kWChunks = kPairs * 3 * 4 * kCh;   // 16-byte chunks of wl
   constexpr int kWPer = (kWChunks + 255) / 256;
-  constexpr int kXChunks = kHz * kHy * kHx * 2;
-  constexpr int kXPer = (kXChunks + 255) / 256;
   constexpr unsigned kNowhere = 0x80000000u;   // past every array here (< 2^26 nodes of 32 bytes)
   const __amdgpu_buffer_rsrc_t rx = raw_buffer(reinterpret_cast<const float*>(a.x), (unsigned)nn * 32u);
+  // inputs of the first layer's features (r, diag: 3 x nn floats; |grad R|: nn)
+  __amdgpu_buffer_rsrc_t rr = rx, rd = rx, rg = rx;
+  if constexpr (kFeat) {
+    rr = raw_buffer(a.fr, (unsigned)nn * 12u);
+    rd = raw_buffer(a.fdiag, (unsigned)nn * 12u);
+    rg = raw_buffer(a.fgR, (unsigned)nn * 4u);
+  }
+  // halo staging by rows: 36 chunks of 16 bytes per staged x-row, 7 rows per pass
+  constexpr int kRowChunks = 2 * kHx, kRowStep = 256 / kRowChunks, kRows = kHz * kHy;
+  constexpr int kRowPasses = (kRows + kRowStep - 1) / kRowStep;
+  constexpr int kRowBytes = 2 * kHx * 16;
+  static_assert(kRowStep < kHy, "one carry per pass at most");
+  const int srow_r0 = tid / kRowChunks, srow_c = tid % kRowChunks;
+  const bool srow_ok = srow_r0 < kRowStep;   // the last 256 - 7 * 36 threads stage nothing
+  const int srow_x = srow_c >> 1;
+  const unsigned srow_half16 = 16u * (srow_c & 1);
+  unsigned char* const srow_lds = reinterpret_cast<unsigned char*>(&xs[0][0][0][0][0]) + srow_r0 * kRowBytes +
+                                  ((srow_c & 1) * kHx + srow_x) * 16;
 
   // weight chunk q of this thread: its tap, or -1 for the zero half
   auto w_tap = [&](int q) {
@@ -160,44 +177,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
         }
       }
     }
-    // network input of the halo nodes (kFirst): r, diag and |grad R| of node
-    // q = tid + 256 k, zero outside the grid
-    constexpr int kNodes = kHz * kHy * kHx, kNPer = (kNodes + 255) / 256;
-    float fin[kFeat ? kNPer : 1][7];
-    bool fok[kFeat ? kNPer : 1];
+    // network input of the halo nodes (kFirst): r, diag and |grad R| of node x
+    // = tid % 18 of the staged rows tid / 18, + 14, ... (zero outside the grid,
+    // where a node gets an offset past the arrays)
+    constexpr int kFStep = 256 / kHx, kFPasses = (kRows + kFStep - 1) / kFStep;
+    static_assert(kFStep < 2 * kHy, "at most two carries per pass");
+    float fin[kFeat ? kFPasses : 1][7];
+    bool fok[kFeat ? kFPasses : 1];
     if constexpr (kFeat) {
+      const int fr0 = tid / kHx, fx = tid % kHx;
+      const int fxx = x0 + fx - 1;
+      const bool fxok = fr0 < kFStep && (unsigned)fxx < (unsigned)nx;
 #pragma unroll
-      for (int k = 0; k < kNPer; ++k) {
-        const int q = tid + 256 * k;
-        const int lx = q % kHx, ly = (q / kHx) % kHy, lz = q / (kHx * kHy);
-        const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
-        fok[k] = q < kNodes && xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+      for (int j = 0, ly = fr0 % kHy, lz = fr0 / kHy; j < kFPasses; ++j) {
+        const int yy = y0 + ly - 1, zz = z0 + lz - 1;
+        fok[j] = fxok && lz < kHz && (unsigned)yy < (unsigned)ny && (unsigned)zz < (unsigned)nz;
+        const unsigned o = fok[j] ? 4u * (unsigned)((zz * ny + yy) * nx + fxx) : kNowhere;
 #pragma unroll
-        for (int e = 0; e < 7; ++e) fin[k][e] = 0.f;
-        if (fok[k]) {
-          const int node = (zz * ny + yy) * nx + xx;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            fin[k][d] = a.fr[d * nn + node];
-            fin[k][3 + d] = a.fdiag[d * nn + node];
-          }
-          fin[k][6] = a.fgR[node];
+        for (int d = 0; d < 3; ++d) {
+          fin[j][d] = buf_ld(rr, o, 4u * d * nn);
+          fin[j][3 + d] = buf_ld(rd, o, 4u * d * nn);
+        }
+        fin[j][6] = buf_ld(rg, o, 0u);
+        ly += kFStep % kHy;   // the next row of this thread: row + 14
+        lz += kFStep / kHy;
+        if (ly >= kHy) {
+          ly -= kHy;
+          ++lz;
         }
       }
     }
     // halo chunks through a buffer descriptor: a chunk outside the grid gets an
-    // offset past the array's end, for which the hardware returns zeros
-    uint4 v[kXPer];
+    // offset past the array's end, for which the hardware returns zeros.  Thread
+    // (r0, c) = (tid / 36, tid % 36) loads chunk c (x = c / 2, channel half c % 2)
+    // of the staged rows r0, r0 + 7, ... (row = lz * kHy + ly)
+    uint4 v[kRowPasses];
+    const int xx = x0 + srow_x - 1;
+    const bool xok = srow_ok && (unsigned)xx < (unsigned)nx;
 #pragma unroll
-    for (int k = 0; k < (kFeat ? 0 : kXPer); ++k) {
-      const int q = tid + 256 * k;
-      const int half = q & 1, rest = q >> 1;
-      const int lx = rest % kHx, ly = (rest / kHx) % kHy, lz = rest / (kHx * kHy);
-      const int xx = x0 + lx - 1, yy = y0 + ly - 1, zz = z0 + lz - 1;
-      const bool ok = q < kXChunks && (unsigned)xx < (unsigned)nx && (unsigned)yy < (unsigned)ny &&
-                      (unsigned)zz < (unsigned)nz;
-      const unsigned off = ok ? (unsigned)((zz * ny + yy) * nx + xx) * 32u + 16u * half : kNowhere;
-      v[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)off, 0, 0));
+    for (int j = 0, ly = srow_r0, lz = 0; j < (kFeat ? 0 : kRowPasses); ++j) {
+      const int yy = y0 + ly - 1, zz = z0 + lz - 1;
+      const bool ok = xok && lz < kHz && (unsigned)yy < (unsigned)ny && (unsigned)zz < (unsigned)nz;
+      const unsigned off = ok ? (unsigned)((zz * ny + yy) * nx + xx) * 32u + srow_half16 : kNowhere;
+      v[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)off, 0, 0));
+      ly += kRowStep;   // the next row of this thread: row + 7
+      if (ly >= kHy) {
+        ly -= kHy;
+        ++lz;
+      }
     }
     if (first && (transpose || out_major)) {
 #pragma unroll
@@ -210,40 +237,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
     if constexpr (kFeat) {
       // channels (r/diag)/rms_y [0..2], r/rms_r [3..5], diag/rms_d [6..8],
       // |grad R|/rms_g [9], zero [10..15], rounded to bf16 (to nearest even)
+      const int fr0 = tid / kHx, fx = tid % kHx;
 #pragma unroll
-      for (int k = 0; k < kNPer; ++k) {
-        const int q = tid + 256 * k;
-        if (q < kNodes) {
+      for (int j = 0; j < kFPasses; ++j) {
+        const int row = fr0 + kFStep * j;
+        if (fr0 < kFStep && row < kRows) {
           uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = make_uint4(0u, 0u, 0u, 0u);
-          if (fok[k]) {
+          if (fok[j]) {
             float f[10];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              f[d] = (fin[k][d] / fin[k][3 + d]) * fs[0];
-              f[3 + d] = fin[k][d] * fs[1];
-              f[6 + d] = fin[k][3 + d] * fs[2];
+              f[d] = (fin[j][d] / fin[j][3 + d]) * fs[0];
+              f[3 + d] = fin[j][d] * fs[1];
+              f[6 + d] = fin[j][3 + d] * fs[2];
             }
-            f[9] = fin[k][6] * fs[3];
+            f[9] = fin[j][6] * fs[3];
             auto pk = [](float u, float w) {
               return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){u, w}, bf16x2));
             };
             lo = make_uint4(pk(f[0], f[1]), pk(f[2], f[3]), pk(f[4], f[5]), pk(f[6], f[7]));
             hi = make_uint4(pk(f[8], f[9]), 0u, 0u, 0u);
           }
-          const int lx = q % kHx, lyz = q / kHx;
-          *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * (lyz * 2 * kHx + lx)) = lo;
-          *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * ((lyz * 2 + 1) * kHx + lx)) = hi;
+          *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * (row * 2 * kHx + fx)) = lo;
+          *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * ((row * 2 + 1) * kHx + fx)) = hi;
         }
       }
     }
+    if (srow_ok) {
 #pragma unroll
-    for (int k = 0; k < (kFeat ? 0 : kXPer); ++k) {
-      const int q = tid + 256 * k;
-      if (q < kXChunks) {
-        const int half = q & 1, rest = q >> 1;
-        const int lx = rest % kHx, lyz = rest / kHx;   // lyz = lz * kHy + ly
-        *reinterpret_cast<uint4*>(&xs[0][0][0][0][0] + 8 * ((lyz * 2 + half) * kHx + lx)) = v[k];
-      }
+      for (int j = 0; j < (kFeat ? 0 : kRowPasses); ++j)
+        if (srow_r0 + kRowStep * j < kRows) *reinterpret_cast<uint4*>(srow_lds + j * kRowStep * kRowBytes) = v[j];
     }
     __syncthreads();
     // row s first receives pair 0, dy = -1 at staged row s: that MFMA starts from 0
@@ -315,7 +338,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             v[r] = acc[i][r] + bias[r];
-            if (kRelu || (kMode == kGeneric && a.relu)) v[r] = fmaxf(v[r], 0.f);
+            if (kMode == kGeneric && a.relu) v[r] = fmaxf(v[r], 0.f);
           }
           if (kMode == kBwd || (kMode == kGeneric && a.mask)) {
             const uint2 mk = *reinterpret_cast<const uint2*>(a.mask + (node * kCh + 4 * quad));
@@ -327,8 +350,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
           }
           if (kOut16 || (kMode == kGeneric && a.y16)) {
             // round to nearest even in hardware (the same rounding as f2bf for non-NaN values)
-            const bf16x2 lo = __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2);
-            const bf16x2 hi = __builtin_convertvector((f32x2){v[2], v[3]}, bf16x2);
+            s16x2 lo = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2));
+            s16x2 hi = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){v[2], v[3]}, bf16x2));
+            if constexpr (kRelu) {
+              // ReLU on the rounded values, two per instruction: a bf16 pattern is
+              // negative exactly when it is negative as a 16-bit integer (NaN
+              // patterns with the sign clear pass through, as the reference's max)
+              const s16x2 z2 = {0, 0};
+              lo = __builtin_elementwise_max(lo, z2);
+              hi = __builtin_elementwise_max(hi, z2);
+            }
             *reinterpret_cast<uint2*>(a.y16 + (node * kCh + 4 * quad)) =
                 make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
           }
