@@ -210,6 +210,20 @@ typedef struct {
 mfr_status mfr_pcg_solve(mfr_ctx* ctx, const float* u, const float* b, float* s,
                          const mfr_pcg_opts* opts, mfr_pcg_info* info);
 
+/* Twin of mfr_pcg_solve for HIP graph capture (Sec. 2.3.1, as above), precond 0
+ * or 1: it enqueues the whole sequence of max_iter iterations with no host
+ * read; the convergence test runs on the device and the iterations after it
+ * has stopped the solve do nothing, so s equals that of mfr_pcg_solve bit for
+ * bit.  info: device double[3] = {iterations, relative residual, flag (0, 1,
+ * 2 as in mfr_pcg_info)}.  A right-hand side that is not finite shows as a
+ * non-finite relative residual (the synchronous call returns MFR_ENONFINITE);
+ * require_converged is refused.  Every launch of the sequence costs its launch
+ * latency even after convergence: max_iter bounds the work.  A captured graph
+ * uses the context's workspace (replay it on the context's stream).
+ * Asynchronous. */
+mfr_status mfr_pcg_solve_async(mfr_ctx* ctx, const float* u, const float* b, float* s, const mfr_pcg_opts* opts,
+                               double* info);
+
 typedef struct {
   int32_t pcg_max;     /* CG iterations                                              */
   double pcg_rtol;     /* CG relative residual tolerance (0: always pcg_max steps)   */

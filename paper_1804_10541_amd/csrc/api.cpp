@@ -981,7 +981,7 @@ constexpr int kSteerIters = 8;
 // at, with the same iterate (on a breakdown, p.q <= 0, the update of that
 // iteration is not applied).
 mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
-                           mfr_pcg_info* info) {
+                           mfr_pcg_info* info, double* info_dev) {
   float* diag = nullptr;
   if (o->precond >= 1) {
     diag = c->vec[4];
@@ -1015,6 +1015,20 @@ mfr_status pcg_run_steered(mfr_ctx* c, const float* u, const float* b, float* s_
   np.s_ngf = (float)c->geo.hess_scale();
   np.live = c->ctrl;
   int done = 0, active = 1;
+  if (info_dev) {
+    // the whole launch sequence with no host reads (graph capture): iterations
+    // after the device's convergence test has stopped the solve do nothing
+    for (int i = 0; i < o->max_iter; ++i) {
+      HIP_TRY(timed(c, 2, [&] { return launch_tiles(c, MODE_HV, tp, u, v.p); }));
+      HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_HV, np, v.p, v.q, node_blocks(c), c->stream); }));
+      HIP_TRY(launch_pcg_alpha_batch(V, c->stream));
+      HIP_TRY(launch_pcg_update_batch(V, c->stream));
+      HIP_TRY(launch_pcg_beta_batch(V, c->stream));
+      HIP_TRY(launch_pcg_direction_batch(V, c->stream));
+    }
+    HIP_TRY(launch_pcg_info_out(c->ctrl + 1, c->sc, info_dev, c->stream));
+    return MFR_OK;
+  }
   while (done < o->max_iter && active) {
     const int k = std::min(kSteerIters, o->max_iter - done);
     for (int i = 0; i < k; ++i) {
@@ -1157,7 +1171,7 @@ mfr_status pcg_run_flexible(mfr_ctx* c, const float* u, const float* b, float* s
 mfr_status pcg_run(mfr_ctx* c, const float* u, const float* b, float* s_out, const mfr_pcg_opts* o,
                    mfr_pcg_info* info) {
   if (o->precond == 2) return pcg_run_flexible(c, u, b, s_out, o, info);
-  return pcg_run_steered(c, u, b, s_out, o, info);
+  return pcg_run_steered(c, u, b, s_out, o, info, nullptr);
 }
 
 // One Gauss-Newton step (Sec. 2.3.1).  Vectors: vec[5] right-hand side -grad J,
@@ -1404,6 +1418,22 @@ mfr_status mfr_pcg_solve(mfr_ctx* c, const float* u, const float* b, float* s, c
     return fail(MFR_ENOTCONV, "CG stopped after %d iterations at relative residual %g > rtol %g", inf.iters,
                 inf.relres, opts->rtol);
   return MFR_OK;
+}
+
+mfr_status mfr_pcg_solve_async(mfr_ctx* c, const float* u, const float* b, float* s, const mfr_pcg_opts* opts,
+                               double* info) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  MFR_TRY(check_ptr(b, "b"));
+  MFR_TRY(check_ptr(s, "s"));
+  if (!opts) return fail(MFR_EINVAL, "opts is NULL");
+  if (opts->max_iter < 0 || !(opts->rtol >= 0) || opts->precond < 0 || opts->precond > 1)
+    return fail(MFR_EINVAL, "invalid PCG options (the capturable solve takes precond 0 or 1)");
+  if (opts->require_converged) return fail(MFR_EINVAL, "require_converged needs the synchronous solve");
+  if (s == u || s == b) return fail(MFR_EINVAL, "s must not alias u or b");
+  if (!info || reinterpret_cast<uintptr_t>(info) % 8 != 0)
+    return fail(MFR_EINVAL, "info must be an 8-byte aligned device pointer");
+  return pcg_run_steered(c, u, b, s, opts, nullptr, info);
 }
 
 // ---- multilevel ---------------------------------------------------------------

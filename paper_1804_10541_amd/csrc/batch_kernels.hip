@@ -158,6 +158,21 @@ __global__ __launch_bounds__(256) void pcg_init_finish_batch_kernel(const VecJob
   }
 }
 
+// The result of a device-steered solve into caller memory: {iterations,
+// relative residual, flag} (the capturable solve).
+__global__ void pcg_info_out_kernel(const int* __restrict__ state, const double* __restrict__ sc,
+                                    double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  out[0] = (double)state[ST_ITERS];
+  out[1] = sc[SC_RELRES];
+  out[2] = (double)state[ST_FLAG];
+}
+
+hipError_t launch_pcg_info_out(const int* state, const double* sc, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_info_out_kernel, dim3(1), dim3(64), 0, st, state, sc, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_pcg_init_batch(const VecJobs& j, hipStream_t st) {
   hipLaunchKernelGGL(pcg_init_batch_kernel, dim3(j.prefix[j.n]), dim3(kVecBlock), 0, st, j);
   hipError_t e = hipGetLastError();

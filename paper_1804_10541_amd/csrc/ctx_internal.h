@@ -173,6 +173,9 @@ mfr_status ctx_init(mfr_ctx* c, const mfr_grid* grid, void* stream, void* ws, si
 // rounded as Geo::s_value and the host evaluate them (node_kernels.hip)
 hipError_t launch_objective_out(const double* sums, double dmul, double smul, double sk, double alpha, double* out,
                                 int count, hipStream_t st);
+// out = {iterations, relative residual, flag} of a device-steered solve, from its
+// state array and scalars (batch_kernels.hip)
+hipError_t launch_pcg_info_out(const int* state, const double* sc, double* out, hipStream_t st);
 hipEvent_t prof_event(mfr_ctx* c);   // a timing event from the context's pool
 template <class F>
 hipError_t timed(mfr_ctx* c, int slot, F&& launch) {

@@ -133,6 +133,7 @@ SIGNATURES = {
     "mfr_hess_vec_noalloc": (ctypes.c_int, [ctypes.POINTER(CGrid), _VP, _VP, _VP, _VP, _VP, _VP]),
     "mfr_jacobi_diag": (ctypes.c_int, [_VP, _VP, _VP]),
     "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
+    "mfr_pcg_solve_async": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), _VP]),
     "mfr_gn_step": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(CGnOpts), ctypes.POINTER(CGnInfo)]),
     "mfr_ml_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_register_multilevel": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CMlOpts), _VP, _VP, _SZ,
@@ -440,6 +441,19 @@ class Context:
                                       _dev_tensor(out, self.nc * self.nbar, "s", self.device),
                                       ctypes.byref(opts), ctypes.byref(info)))
         return out, dict(iters=info.iters, relres=info.relres, flag=info.flag, used_fallback=info.used_fallback)
+
+    def pcg_solve_async(self, u, b, max_iter=50, rtol=1e-3, precond=1, out=None, info=None):
+        """The solve as one fixed launch sequence (capturable in a HIP graph): s into
+        `out`, (iterations, relative residual, flag) written by the device into
+        `info` (float64 [3] on the device); no synchronisation."""
+        out = torch.empty(self.node_shape(), dtype=torch.float32, device=self.device) if out is None else out
+        info = torch.empty(3, dtype=torch.float64, device=self.device) if info is None else info
+        opts = CPcgOpts(int(max_iter), float(rtol), int(precond), 0, 0)
+        _check(self.lib.mfr_pcg_solve_async(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                            _dev_tensor(b, self.nc * self.nbar, "b", self.device),
+                                            _dev_tensor(out, self.nc * self.nbar, "s", self.device),
+                                            ctypes.byref(opts), _f64_tensor(info, 3, "info", self.device)))
+        return out, info
 
     def attach_pc(self, pc):
         """Use a LearnedPC of this context for precond = 2 (None detaches)."""

@@ -1,7 +1,7 @@
-"""Graph-capturable twins of the objective and gradient (scalars written by the
-device into caller memory): equal to the synchronous calls bit for bit, and a
-HIP graph captured from objective, gradient, Hessian-vector product and Jacobi
-diagonal replays to the results of the same calls run eagerly."""
+"""Graph-capturable twins of the objective, gradient and CG solve (results
+written by the device into caller memory): equal to the synchronous calls bit
+for bit, and HIP graphs captured from them (with the Hessian-vector product and
+the Jacobi diagonal) replay to the results of the same calls run eagerly."""
 import numpy as np
 import pytest
 import torch
@@ -77,4 +77,38 @@ def test_captured_graph_replays_to_eager_results():
         s.synchronize()
         assert got[0].cpu().tolist() == [J, D, S, Jg], k
         assert torch.equal(got[1], g_ref) and torch.equal(got[2], q_ref) and torch.equal(got[3], d_ref), k
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_captured_cg_solve_replays_to_the_synchronous_solve(precond):
+    print(f"[gpu-case] graph capture of a CG solve (precond {precond}) 40x36x28", flush=True)
+    spec, R, T, u, probes = ct_case(5, (40, 36, 28), (11, 10, 8), amp=0.5, n_probes=3)
+    s = torch.cuda.Stream(DEV)
+    with torch.cuda.stream(s):
+        ctx = mfr.Context(spec, DEV)
+        ctx.set_images(to_dev(R), to_dev(T))
+        tu, tb = to_dev(u), to_dev(probes[0])
+        x = torch.empty_like(tu)
+        info = torch.empty(3, dtype=torch.float64, device=DEV)
+        # eager twin against the synchronous solve
+        x_ref, inf = ctx.pcg_solve(tu, tb, max_iter=60, rtol=1e-3, precond=precond)
+        ctx.pcg_solve_async(tu, tb, max_iter=60, rtol=1e-3, precond=precond, out=x, info=info)
+    s.synchronize()
+    assert torch.equal(x, x_ref)
+    assert info.cpu().tolist() == [inf["iters"], inf["relres"], inf["flag"]]
+    assert inf["flag"] == 0 and inf["iters"] < 60   # converged: the later launches did nothing
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        ctx.pcg_solve_async(tu, tb, max_iter=60, rtol=1e-3, precond=precond, out=x, info=info)
+    for k in range(3):
+        with torch.cuda.stream(s):
+            tb.copy_(to_dev(probes[k]))
+            info.fill_(np.nan)
+            graph.replay()
+            got_x, got_i = x.clone(), info.clone()
+            x_ref, inf = ctx.pcg_solve(tu, tb, max_iter=60, rtol=1e-3, precond=precond)
+        s.synchronize()
+        assert torch.equal(got_x, x_ref), k
+        assert got_i.cpu().tolist() == [inf["iters"], inf["relres"], inf["flag"]], k
     ctx.close()
