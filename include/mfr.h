@@ -252,6 +252,17 @@ typedef struct {
  * Synchronises the stream. */
 mfr_status mfr_gn_step(mfr_ctx* ctx, float* u, const mfr_gn_opts* opts, mfr_gn_info* info);
 
+/* Twin of mfr_gn_step for HIP graph capture (Sec. 2.3.1, as above), precond 0
+ * or 1: the gradient, the CG solve of mfr_pcg_solve_async and armijo_max line
+ * search trials are enqueued as one fixed sequence; the Armijo test runs on the
+ * device, the trials after an accepted one do nothing, and u is replaced by
+ * the accepted point on the device.  u and info equal those of mfr_gn_step bit
+ * for bit.  info: device double[9] = {J_before, J_after, eta, slope,
+ * pcg_iters, pcg_relres, pcg_flag, accepted, ls_trials} (the fields of
+ * mfr_gn_info in order).  A captured graph uses the context's workspace
+ * (replay it on the context's stream).  Asynchronous. */
+mfr_status mfr_gn_step_async(mfr_ctx* ctx, float* u, const mfr_gn_opts* opts, double* info);
+
 typedef struct mfr_pc mfr_pc;   /* learned preconditioner (see below) */
 
 typedef struct {

@@ -383,7 +383,7 @@ Layout make_layout(const Geo& g, const Tiling& t) {
   L.vec = take(sizeof(float) * nc * g.nbar * 8);   // PCG r z p q diag; GN rhs, trial, direction
   L.lap = take(sizeof(float) * nc * g.nbar);       // curvature Laplacian (node pass, first half)
   L.div = take(sizeof(float) * g.nbar);           // elastic: divergence per cell of the nodal grid
-  L.ctrl = take(sizeof(int) * (1 + ST_COUNT));    // device-steered CG: active flag, state
+  L.ctrl = take(sizeof(int) * (2 + ST_COUNT));    // device-steered CG: active flag, state; line-search flag
   L.total = o;
   return L;
 }
@@ -1417,6 +1417,52 @@ mfr_status mfr_pcg_solve(mfr_ctx* c, const float* u, const float* b, float* s, c
   if (opts->require_converged && inf.flag == 1)
     return fail(MFR_ENOTCONV, "CG stopped after %d iterations at relative residual %g > rtol %g", inf.iters,
                 inf.relres, opts->rtol);
+  return MFR_OK;
+}
+
+mfr_status mfr_gn_step_async(mfr_ctx* c, float* u, const mfr_gn_opts* o, double* info) {
+  MFR_TRY(need_images(c));
+  MFR_TRY(check_ptr(u, "u"));
+  if (!o) return fail(MFR_EINVAL, "opts is NULL");
+  if (o->pcg_max < 0 || !(o->pcg_rtol >= 0) || o->precond < 0 || o->precond > 1 ||
+      !(o->armijo_c1 >= 0 && o->armijo_c1 < 1) || o->armijo_max < 1 || o->fallback_iters < 0)
+    return fail(MFR_EINVAL, "invalid Gauss-Newton options (the capturable step takes precond 0 or 1)");
+  for (int k = 5; k < 8; ++k)
+    if (u == c->vec[k]) return fail(MFR_EINVAL, "u must not point into the context workspace");
+  if (!info || reinterpret_cast<uintptr_t>(info) % 8 != 0)
+    return fail(MFR_EINVAL, "info must be an 8-byte aligned device pointer");
+  // the steps of gn_step, with every decision taken on the device
+  const int n3 = (int)(c->geo.nc() * c->geo.nbar);
+  float* b = c->vec[5];
+  float* trial = c->vec[6];
+  float* dir = c->vec[7];
+  int* search = c->ctrl + 1 + ST_COUNT;
+  const double dmul = c->geo.hbar(), smul = c->geo.s_mul(), sk = c->geo.s_k(), alpha = c->geo.alpha;
+  MFR_TRY(enqueue_gradient(c, u, b));
+  HIP_TRY(launch_ls_begin(c->sc + SC_D, dmul, smul, sk, alpha, search, info, c->stream));
+  HIP_TRY(launch_axpy(n3, b, -2.0f, b, b, c->stream));   // b <- -grad J
+  mfr_pcg_opts po{o->pcg_max, o->pcg_rtol, o->precond, 0, 0};
+  MFR_TRY(pcg_run_steered(c, u, b, dir, &po, nullptr, info + 4));
+  HIP_TRY(launch_dot(n3, b, dir, c->red_node, c->vec_blocks, c->stream));
+  HIP_TRY(launch_sum(c->red_node, c->vec_blocks, c->sc + SC_DOT, c->stream));
+  HIP_TRY(launch_ls_slope(c->sc + SC_DOT, info, c->stream));
+  // Armijo trials eta = 1, 1/2, ...: each one's kernels do nothing once a step
+  // length has been accepted
+  TileParams tp = c->tp;
+  tp.live = search;
+  NodeParams q = c->np;
+  q.live = search;
+  double eta = 1.0;
+  for (int ls = 0; ls < o->armijo_max; ++ls) {
+    HIP_TRY(launch_ls_trial(n3, u, (float)eta, dir, trial, search, c->stream));
+    HIP_TRY(timed(c, 0, [&] { return launch_tiles(c, MODE_OBJ, tp, trial, nullptr); }));
+    HIP_TRY(launch_sum(c->red_tile, c->tiling.grid(), c->sc + SC_D, c->stream));
+    HIP_TRY(timed(c, 4, [&] { return launch_node_pass(NP_S, q, trial, nullptr, node_blocks(c), c->stream); }));
+    HIP_TRY(launch_sum(c->red_node, node_blocks(c), c->sc + SC_S, c->stream));
+    HIP_TRY(launch_ls_check(c->sc + SC_D, dmul, smul, sk, alpha, o->armijo_c1, eta, ls, search, info, c->stream));
+    eta *= 0.5;
+  }
+  HIP_TRY(launch_ls_commit(n3, trial, u, info, c->stream));
   return MFR_OK;
 }
 

@@ -176,6 +176,17 @@ hipError_t launch_objective_out(const double* sums, double dmul, double smul, do
 // out = {iterations, relative residual, flag} of a device-steered solve, from its
 // state array and scalars (batch_kernels.hip)
 hipError_t launch_pcg_info_out(const int* state, const double* sc, double* out, hipStream_t st);
+// The line search of the capturable Gauss-Newton step (node_kernels.hip):
+// info = {J_before, J_after, eta, slope, pcg iterations, pcg relative residual,
+// pcg flag, accepted, trials}; *search is 1 until a step length is accepted.
+hipError_t launch_ls_begin(const double* sums, double dmul, double smul, double sk, double alpha, int* search,
+                           double* info, hipStream_t st);
+hipError_t launch_ls_slope(const double* dot, double* info, hipStream_t st);
+hipError_t launch_ls_trial(int n, const float* u, float eta, const float* s, float* trial, const int* search,
+                           hipStream_t st);
+hipError_t launch_ls_check(const double* sums, double dmul, double smul, double sk, double alpha, double c1, double eta,
+                           int k, int* search, double* info, hipStream_t st);
+hipError_t launch_ls_commit(int n, const float* trial, float* u, const double* info, hipStream_t st);
 hipEvent_t prof_event(mfr_ctx* c);   // a timing event from the context's pool
 template <class F>
 hipError_t timed(mfr_ctx* c, int slot, F&& launch) {

@@ -669,6 +669,92 @@ __global__ void axpy_kernel(int n, const float* __restrict__ x, float eta, const
     y[i] = fmaf(eta, s[i], x[i]);
 }
 
+// ---- the line search of the capturable Gauss-Newton step ----------------------
+// info (device double[9]) = {J_before, J_after, eta, slope, pcg iterations, pcg
+// relative residual, pcg flag, accepted, line-search trials}; *search is 1 while
+// no step length has been accepted.  J = D + alpha S from the sums at sums[0]
+// (distance) and sums[1] (regulariser), rounded as the host evaluates it.
+__device__ __forceinline__ double objective_of(const double* sums, double dmul, double smul, double sk,
+                                               double alpha) {
+  const double D = __dmul_rn(dmul, sums[0]), S = __dmul_rn(__dmul_rn(smul, sums[1]), sk);
+  return __dadd_rn(D, __dmul_rn(alpha, S));
+}
+
+__global__ void ls_begin_kernel(const double* __restrict__ sums, double dmul, double smul, double sk, double alpha,
+                                int* __restrict__ search, double* __restrict__ info) {
+  if (threadIdx.x != 0) return;
+  const double J = objective_of(sums, dmul, smul, sk, alpha);
+  info[0] = J;
+  info[1] = J;
+  info[2] = 0.0;
+  info[7] = 0.0;
+  info[8] = 0.0;
+  *search = 1;
+}
+
+// slope = grad J . s = -(b . s), from the sum of b . s
+__global__ void ls_slope_kernel(const double* __restrict__ dot, double* __restrict__ info) {
+  if (threadIdx.x == 0) info[3] = -dot[0];
+}
+
+__global__ void ls_trial_kernel(int n, const float* __restrict__ u, float eta, const float* __restrict__ s,
+                                float* __restrict__ trial, const int* search) {
+  if (!ld_coherent(search)) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    trial[i] = fmaf(eta, s[i], u[i]);   // the arithmetic of axpy_kernel
+}
+
+// Armijo test of trial k at step length eta (J(u + eta s) <= J + c1 eta slope,
+// evaluated as the host does); a non-finite J is rejected
+__global__ void ls_check_kernel(const double* __restrict__ sums, double dmul, double smul, double sk, double alpha,
+                                double c1, double eta, int k, int* __restrict__ search, double* __restrict__ info) {
+  if (threadIdx.x != 0 || !ld_coherent(search)) return;
+  const double J = objective_of(sums, dmul, smul, sk, alpha);
+  info[8] = (double)(k + 1);
+  if (isfinite(J) && J <= __dadd_rn(info[0], __dmul_rn(__dmul_rn(c1, eta), info[3]))) {
+    info[1] = J;
+    info[2] = eta;
+    info[7] = 1.0;
+    *search = 0;
+  }
+}
+
+__global__ void ls_commit_kernel(int n, const float* __restrict__ trial, float* __restrict__ u,
+                                 const double* __restrict__ info) {
+  if (info[7] != 1.0) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) u[i] = trial[i];
+}
+
+hipError_t launch_ls_begin(const double* sums, double dmul, double smul, double sk, double alpha, int* search,
+                           double* info, hipStream_t st) {
+  hipLaunchKernelGGL(ls_begin_kernel, dim3(1), dim3(64), 0, st, sums, dmul, smul, sk, alpha, search, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_slope(const double* dot, double* info, hipStream_t st) {
+  hipLaunchKernelGGL(ls_slope_kernel, dim3(1), dim3(64), 0, st, dot, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_trial(int n, const float* u, float eta, const float* s, float* trial, const int* search,
+                           hipStream_t st) {
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(ls_trial_kernel, dim3(blocks), dim3(256), 0, st, n, u, eta, s, trial, search);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_check(const double* sums, double dmul, double smul, double sk, double alpha, double c1, double eta,
+                           int k, int* search, double* info, hipStream_t st) {
+  hipLaunchKernelGGL(ls_check_kernel, dim3(1), dim3(64), 0, st, sums, dmul, smul, sk, alpha, c1, eta, k, search, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_commit(int n, const float* trial, float* u, const double* info, hipStream_t st) {
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(ls_commit_kernel, dim3(blocks), dim3(256), 0, st, n, trial, u, info);
+  return hipGetLastError();
+}
+
 hipError_t launch_axpy(int n, const float* x, float eta, const float* s, float* y, hipStream_t st) {
   const int blocks = std::min((n + 255) / 256, 4096);
   hipLaunchKernelGGL(axpy_kernel, dim3(blocks), dim3(256), 0, st, n, x, eta, s, y);

@@ -135,6 +135,7 @@ SIGNATURES = {
     "mfr_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), ctypes.POINTER(CPcgInfo)]),
     "mfr_pcg_solve_async": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(CPcgOpts), _VP]),
     "mfr_gn_step": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(CGnOpts), ctypes.POINTER(CGnInfo)]),
+    "mfr_gn_step_async": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(CGnOpts), _VP]),
     "mfr_ml_workspace_size": (ctypes.c_int, [ctypes.POINTER(CGrid), _I, ctypes.POINTER(_SZ)]),
     "mfr_register_multilevel": (ctypes.c_int, [ctypes.POINTER(CGrid), ctypes.POINTER(CMlOpts), _VP, _VP, _SZ,
                                                _VP, _VP, _VP, ctypes.POINTER(CMlReport)]),
@@ -420,6 +421,16 @@ class Context:
         _check(self.lib.mfr_gn_step(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device), ctypes.byref(opts),
                                     ctypes.byref(info)))
         return {f[0]: getattr(info, f[0]) for f in CGnInfo._fields_}
+
+    def gn_step_async(self, u, pcg_max=50, pcg_rtol=1e-3, precond=1, armijo_c1=1e-4, armijo_max=10, info=None):
+        """One Gauss-Newton step as a fixed launch sequence (capturable in a HIP
+        graph): u updated in place on the device; the fields of gn_step's result
+        written by the device into `info` (float64 [9] on the device)."""
+        info = torch.empty(9, dtype=torch.float64, device=self.device) if info is None else info
+        opts = CGnOpts(int(pcg_max), float(pcg_rtol), int(precond), float(armijo_c1), int(armijo_max), 0)
+        _check(self.lib.mfr_gn_step_async(self._h, _dev_tensor(u, self.nc * self.nbar, "u", self.device),
+                                          ctypes.byref(opts), _f64_tensor(info, 9, "info", self.device)))
+        return info
 
     def profile(self, enable=True):
         """Turn kernel timing (HIP events on this context's stream) on or off."""

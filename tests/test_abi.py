@@ -82,6 +82,7 @@ def test_null_arguments_rejected(lib):
     assert lib.mfr_objective_async(None, None, None) == -1
     assert lib.mfr_gradient_async(None, None, None, None) == -1
     assert lib.mfr_pcg_solve_async(None, None, None, None, None, None) == -1
+    assert lib.mfr_gn_step_async(None, None, None, None) == -1
 
 
 def test_distance_field_validation(lib):

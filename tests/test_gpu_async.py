@@ -1,4 +1,4 @@
-"""Graph-capturable twins of the objective, gradient and CG solve (results
+"""Graph-capturable twins of the objective, gradient, CG solve and Gauss-Newton step (results
 written by the device into caller memory): equal to the synchronous calls bit
 for bit, and HIP graphs captured from them (with the Hessian-vector product and
 the Jacobi diagonal) replay to the results of the same calls run eagerly."""
@@ -111,4 +111,41 @@ def test_captured_cg_solve_replays_to_the_synchronous_solve(precond):
         s.synchronize()
         assert torch.equal(got_x, x_ref), k
         assert got_i.cpu().tolist() == [inf["iters"], inf["relres"], inf["flag"]], k
+    ctx.close()
+
+
+GN_FIELDS = ("J_before", "J_after", "eta", "slope", "pcg_iters", "pcg_relres", "pcg_flag", "accepted", "ls_trials")
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_captured_gauss_newton_steps_equal_the_synchronous_steps(precond):
+    print(f"[gpu-case] graph capture of a Gauss-Newton step (precond {precond}) 40x36x28", flush=True)
+    spec, R, T, u, _ = ct_case(6, (40, 36, 28), (11, 10, 8), amp=0.5, n_probes=0)
+    opts = dict(pcg_max=30, pcg_rtol=1e-3, precond=precond, armijo_c1=1e-4, armijo_max=6)
+    s = torch.cuda.Stream(DEV)
+    with torch.cuda.stream(s):
+        ctx = mfr.Context(spec, DEV)
+        ctx.set_images(to_dev(R), to_dev(T))
+        u_sync, u_async = to_dev(u), to_dev(u)
+        info = torch.empty(9, dtype=torch.float64, device=DEV)
+        # eager twin against the synchronous step
+        ref = ctx.gn_step(u_sync, **opts)
+        ctx.gn_step_async(u_async, info=info, **opts)
+    s.synchronize()
+    assert torch.equal(u_async, u_sync)
+    assert info.cpu().tolist() == [float(ref[k]) for k in GN_FIELDS]
+    assert ref["accepted"] == 1
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        ctx.gn_step_async(u_async, info=info, **opts)
+    # the capture ran nothing: u_async is still the state after one step
+    for k in range(3):
+        with torch.cuda.stream(s):
+            info.fill_(np.nan)
+            graph.replay()
+            got = info.clone()
+            ref = ctx.gn_step(u_sync, **opts)
+        s.synchronize()
+        assert torch.equal(u_async, u_sync), k
+        assert got.cpu().tolist() == [float(ref[k2]) for k2 in GN_FIELDS], k
     ctx.close()
