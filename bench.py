@@ -338,6 +338,33 @@ def network_vs_hv(dev, params, reps=50):
     return out
 
 
+def device_leg(dev):
+    """The device as the runtime reports it, and the bandwidth of a plain
+    streaming kernel measured on it (torch's neg over 1 GiB: 1 GiB read and
+    1 GiB written per launch, HIP events over 10 launches): the measured
+    counterpart of the 8 TB/s datasheet figure the roofline uses."""
+    import torch
+
+    props = torch.cuda.get_device_properties(dev)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del src, dst
+    out = {"name": props.name, "gcn_arch": getattr(props, "gcnArchName", None),
+           "compute_units": props.multi_processor_count, "memory_bytes": int(props.total_memory),
+           "copy_kernel_gbs": round(2 * (1 << 30) / (ms * 1e-3) / 1e9, 1), "copy_kernel_ms": round(ms, 4)}
+    log(f"[bench] device: {out}")
+    return out
+
+
 def memory_leg():
     """Device memory of the library at 512 x 512 x 900 and 512 x 512 x 450 voxels
     (same 129 x 129 node grid in x, y; 225 / 113 node planes): the workspace of
@@ -806,6 +833,7 @@ def main():
         "workspace_bytes": int(ctx.ws_bytes),
         "memory": memory_leg(),
         "tile_config": tile_cfg,
+        "device": device_leg(dev),
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the float64 oracle on a crop (cpu_baseline)")
